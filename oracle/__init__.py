@@ -1,0 +1,24 @@
+"""CPU oracle for the pCGMG compliance solve — TEST INFRASTRUCTURE ONLY.
+
+A plain, slow, FP64 reimplementation of what the HIP solver computes,
+written from the paper (Luu & Banh, "A novel preconditioned conjugate
+gradient multigrid method for multi-material topology optimization"):
+
+* ``fe``        — multi-phase SIMP modulus (Eq. 5), Q4 plane-stress element
+                  stiffness (Eqs. 7-9), assembly, clamped/traction boundary
+                  conditions (Eq. 10), compliance (Eq. 6) and its gradient.
+* ``linalg``    — dense Cholesky (Algorithm 3 with Eqs. 3-4), triangular
+                  substitution, damped Jacobi (Section 2.3) and
+                  preconditioned CG (Algorithm 2).
+* ``multigrid`` — bilinear prolongation, restriction as its transpose,
+                  Galerkin coarse operators and the gamma-cycle
+                  (Algorithm 1) used as a PCG preconditioner (Section 2.2).
+* ``solve``     — the plain definition u = K_ff^{-1} f_f by a direct solve,
+                  and the oracle's own MG-preconditioned CG.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the HIP path
+and never imports it.
+"""
+
+from . import fe, linalg, multigrid, solve  # noqa: F401
