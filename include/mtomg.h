@@ -1,0 +1,181 @@
+/*
+ * mtomg — pCGMG solver for the multi-material SIMP compliance problem on
+ * MI355X (gfx950).
+ *
+ * The library solves K(x) u = f for a 2D plane-stress wall meshed with
+ * nelx x nely square bilinear (Q4) elements, then returns the compliance
+ * c = f^T u and its gradient with respect to the phase densities x.  The
+ * method is the preconditioned conjugate gradient of Algorithm 2 with one
+ * multigrid V-cycle (Algorithm 1, gamma = 1) as the preconditioner, damped
+ * Jacobi smoothing (Section 2.3) and a direct Cholesky solve (Algorithm 3)
+ * on the coarsest grid; the stiffness follows Eqs. (5)-(10).
+ *
+ * Conventions shared by every entry point:
+ *   - Node (i, j), i = 0..nelx, j = 0..nely, stores its two displacement
+ *     components contiguously; nodal arrays are [nely+1][nelx+1][2]
+ *     row-major (x fastest).  Nodes with j = 0 are clamped (u = 0).
+ *   - Element (i, j) has phase densities x[j][i][0..m-1] (row-major).
+ *   - Pointers marked "device" are HIP device pointers owned by the
+ *     caller; the library keeps them (set_grid) or reads them during the
+ *     call, and never frees them.  Pointers marked "host" are read during
+ *     the call only.
+ *   - All device work is ordered on the HIP stream given to mtomg_create.
+ *     mtomg_solve blocks until the solve is finished; the other calls are
+ *     asynchronous with respect to the host.
+ *   - Every call returns MTOMG_OK (0) or a negative status; on failure
+ *     mtomg_last_error() describes the cause.  No C++ exception crosses
+ *     this interface.  A context is not thread-safe.
+ */
+#ifndef MTOMG_H
+#define MTOMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mtomg_ctx mtomg_ctx;
+
+enum {
+    MTOMG_OK = 0,
+    MTOMG_BAD_INPUT = -1,     /* invalid argument or size                        */
+    MTOMG_NOT_CONVERGED = -2, /* max_iter reached; U holds the last iterate      */
+    MTOMG_BREAKDOWN = -3,     /* p^T K p <= 0 or z^T r <= 0 inside PCG           */
+    MTOMG_NAN = -4,           /* non-finite residual                             */
+    MTOMG_WORKSPACE = -5,     /* workspace missing or too small                  */
+    MTOMG_HIP_ERROR = -6,     /* a HIP runtime call failed                       */
+    MTOMG_STATE = -7          /* call out of order (e.g. solve before set_grid)  */
+};
+
+/* Arithmetic of the multigrid preconditioner.  The outer CG recurrences
+ * (residual and iterate updates, dot products), the coarsest Cholesky
+ * factor and the compliance are FP64 in both modes. */
+enum { MTOMG_FP64 = 0, MTOMG_FP32MG = 1 };
+
+/* Per (design, load case) solve statistics. */
+typedef struct {
+    int32_t status;      /* MTOMG_OK / NOT_CONVERGED / BREAKDOWN / NAN        */
+    int32_t iters;       /* PCG iterations (updates of u)                      */
+    int32_t vcycles;     /* preconditioner applications                        */
+    int32_t n_dof;       /* 2 (nelx+1)(nely+1), clamped DOFs included          */
+    double relres_rec;   /* recursive ||r|| / ||f|| at exit                    */
+    double relres_true;  /* ||f - K u|| / ||f|| recomputed in FP64 at exit     */
+    double t_setup_ms;   /* device time of the last set_densities             */
+    double t_solve_ms;   /* device time of the solve of this design            */
+    double model_bytes;  /* algorithmic HBM bytes of one PCG iteration         */
+} mtomg_stats;
+
+/* Create a context for up to max_designs independent designs.
+ * hip_stream: a hipStream_t (NULL = the null stream) on which all work is
+ * ordered.  Returns BAD_INPUT if max_designs < 1, HIP_ERROR if no device. */
+int mtomg_create(mtomg_ctx **ctx, int max_designs, void *hip_stream);
+
+/* Release every device resource the library allocated.  Caller-owned
+ * buffers are untouched.  NULL is accepted. */
+int mtomg_destroy(mtomg_ctx *ctx);
+
+/* Describe design `design` (0 <= design < max_designs).
+ *   nelx, nely   element counts; both divisible by 2^(levels-1), and the
+ *                coarsest grid at most 32 x 32 elements
+ *                (its dense inverse is kept in device memory).
+ *   nu           Poisson ratio of the plane-stress law, Eq. (8), in [0, 0.5).
+ *   m, E_phase   number of solid phases and their moduli (host [m]), Eq. (5).
+ *   E_min        modulus of the void phase, > 0.
+ *   penal        SIMP exponent p >= 1 of Eq. (5).
+ *   levels       number of grids of the hierarchy (Algorithm 1), >= 1.
+ *   n_pre/n_post damped-Jacobi sweeps before/after the coarse correction
+ *                (theta_1, theta_2 of Algorithm 1), 0..8; equal values
+ *                keep the preconditioner symmetric (Section 2.2).
+ *   omega        damping of the Jacobi smoother (Section 2.3), in (0, 1].
+ *   precision    MTOMG_FP64 or MTOMG_FP32MG.
+ *   n_cases      number of load cases sharing this stiffness, 1..64.
+ *   F            device [n_cases][nely+1][nelx+1][2] FP64 nodal loads; read
+ *                at each solve.  Values on the clamped row are ignored.
+ *   U            device, same shape, FP64; receives the displacements (and
+ *                is the initial guess when solve is called with warm_start).
+ * Invalidates the workspace: call mtomg_workspace_bytes/set_workspace (or
+ * let the library allocate) before the next set_densities. */
+int mtomg_set_grid(mtomg_ctx *ctx, int design, int nelx, int nely, double nu, int m,
+                   const double *E_phase, double E_min, double penal, int levels,
+                   int n_pre, int n_post, double omega, int precision, int n_cases,
+                   const double *F, double *U);
+
+/* Bytes of device workspace needed by all designs described so far. */
+size_t mtomg_workspace_bytes(const mtomg_ctx *ctx);
+
+/* Hand the library a caller-owned device buffer of at least
+ * mtomg_workspace_bytes() bytes (256-byte aligned).  The caller keeps it
+ * alive until the next set_grid or destroy.  Without this call the library
+ * allocates its own workspace with hipMalloc at the first set_densities. */
+int mtomg_set_workspace(mtomg_ctx *ctx, void *dev, size_t bytes);
+
+/* Load phase densities for a design and build its preconditioner:
+ * element moduli by Eq. (5), Galerkin coarse operators for every level,
+ * and the coarsest Cholesky factor (Algorithm 3) turned into an explicit
+ * inverse.  x: device [nely][nelx][m] FP64 in [0, 1], read during the call
+ * (stream-ordered).  Returns BREAKDOWN (from the next solve) if the
+ * coarsest matrix is not positive definite. */
+int mtomg_set_densities(mtomg_ctx *ctx, int design, const double *x);
+
+/* Solve every load case of every design that has densities: PCG
+ * (Algorithm 2) from u = 0 (or from U when warm_start != 0), stopping when
+ * ||r||_2 <= rel_tol ||f||_2 over the free DOFs, or after max_iter
+ * iterations.  stats: host array of sum(n_cases) entries, filled in design
+ * then case order.  Blocks until done.  Returns the worst status. */
+int mtomg_solve(mtomg_ctx *ctx, double rel_tol, int max_iter, int warm_start,
+                mtomg_stats *stats);
+
+/* Compliance c_k = f_k^T u_k (Eq. 6) of every load case, and optionally
+ * its gradient dc_k/dx_{e,i} = -p x_{e,i}^(p-1) (E_i - E_min) u_e^T K^0 u_e
+ * (the sensitivity step of Section 4; compliance is self-adjoint).
+ *   c     device [n_cases] FP64.
+ *   dcdx  device [n_cases][nely][nelx][m] FP64, or NULL to skip.
+ * Uses the displacements of the last solve. */
+int mtomg_compliance_and_grad(mtomg_ctx *ctx, int design, double *c, double *dcdx);
+
+/* Static description of a status code. */
+const char *mtomg_status_string(int status);
+
+/* Message of the last failure on this context ("" if none). */
+const char *mtomg_last_error(const mtomg_ctx *ctx);
+
+/* Test hook: run one internal operator of level `level` (0 = coarsest,
+ * levels-1 = finest) of a design whose densities are set.  Vectors are
+ * nodal arrays of that level ([ny_l+1][nx_l+1][2]) in the multigrid
+ * precision (float for MTOMG_FP32MG, double otherwise) except
+ * MTOMG_OP_APPLY64, which is FP64.  `in` holds the listed inputs back to
+ * back; `out` receives one vector.  Both are device pointers.
+ *   APPLY     in: u           out: K_l u
+ *   APPLY64   in: u (FP64)    out: K u on the finest grid in FP64
+ *   DIAG      in: -           out: diag(K_l)
+ *   PRESMOOTH in: b           out: n_pre damped-Jacobi sweeps from u = 0
+ *   RESIDUAL_RESTRICT
+ *             in: b, u        out (level l-1): P_l^T (b - K_l u)
+ *   PROLONG_POSTSMOOTH
+ *             in: b, u, e_c   out: n_post sweeps from u + P_l e_c
+ *                               (e_c is a level l-1 vector)
+ *   SMOOTH    in: b, u        out: one damped-Jacobi sweep from u
+ *   COARSE_SOLVE (level 0)
+ *             in: b           out: K_0^{-1} b
+ *   VCYCLE    in: b           out: MG_1^l(0, b) (Algorithm 1)
+ */
+enum {
+    MTOMG_OP_APPLY = 0,
+    MTOMG_OP_APPLY64 = 1,
+    MTOMG_OP_DIAG = 2,
+    MTOMG_OP_PRESMOOTH = 3,
+    MTOMG_OP_RESIDUAL_RESTRICT = 4,
+    MTOMG_OP_PROLONG_POSTSMOOTH = 5,
+    MTOMG_OP_SMOOTH = 6,
+    MTOMG_OP_COARSE_SOLVE = 7,
+    MTOMG_OP_VCYCLE = 8
+};
+int mtomg_debug_apply(mtomg_ctx *ctx, int design, int level, int op, const void *in, void *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MTOMG_H */

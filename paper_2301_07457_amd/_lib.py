@@ -1,0 +1,160 @@
+"""ctypes binding of libmtomg.so: the C ABI of include/mtomg.h, same names.
+
+Argument marshalling only: every computation happens in the HIP library.
+Loading fails loudly (ImportError) when the library has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmtomg.so")
+
+MTOMG_OK = 0
+MTOMG_BAD_INPUT = -1
+MTOMG_NOT_CONVERGED = -2
+MTOMG_BREAKDOWN = -3
+MTOMG_NAN = -4
+MTOMG_WORKSPACE = -5
+MTOMG_HIP_ERROR = -6
+MTOMG_STATE = -7
+
+MTOMG_FP64 = 0
+MTOMG_FP32MG = 1
+
+OPS = dict(APPLY=0, APPLY64=1, DIAG=2, PRESMOOTH=3, RESIDUAL_RESTRICT=4, PROLONG_POSTSMOOTH=5,
+           SMOOTH=6, COARSE_SOLVE=7, VCYCLE=8)
+
+EXPORTS = ["mtomg_create", "mtomg_destroy", "mtomg_set_grid", "mtomg_workspace_bytes",
+           "mtomg_set_workspace", "mtomg_set_densities", "mtomg_solve",
+           "mtomg_compliance_and_grad", "mtomg_status_string", "mtomg_last_error",
+           "mtomg_debug_apply"]
+
+
+class mtomg_stats(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("iters", ctypes.c_int32),
+        ("vcycles", ctypes.c_int32),
+        ("n_dof", ctypes.c_int32),
+        ("relres_rec", ctypes.c_double),
+        ("relres_true", ctypes.c_double),
+        ("t_setup_ms", ctypes.c_double),
+        ("t_solve_ms", ctypes.c_double),
+        ("model_bytes", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class MtomgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"mtomg status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libmtomg.so (once).  Raises ImportError if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not found: build it with `python -m paper_2301_07457_amd.build` "
+                          "(the solver has no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    dp = ctypes.c_void_p
+    lib.mtomg_create.argtypes = [ctypes.POINTER(vp), i, vp]
+    lib.mtomg_destroy.argtypes = [vp]
+    lib.mtomg_set_grid.argtypes = [vp, i, i, i, d, i, ctypes.POINTER(d), d, d, i, i, i, d, i, i, dp, dp]
+    lib.mtomg_workspace_bytes.argtypes = [vp]
+    lib.mtomg_workspace_bytes.restype = sz
+    lib.mtomg_set_workspace.argtypes = [vp, vp, sz]
+    lib.mtomg_set_densities.argtypes = [vp, i, dp]
+    lib.mtomg_solve.argtypes = [vp, d, i, i, ctypes.POINTER(mtomg_stats)]
+    lib.mtomg_compliance_and_grad.argtypes = [vp, i, dp, dp]
+    lib.mtomg_status_string.argtypes = [i]
+    lib.mtomg_status_string.restype = ctypes.c_char_p
+    lib.mtomg_last_error.argtypes = [vp]
+    lib.mtomg_last_error.restype = ctypes.c_char_p
+    lib.mtomg_debug_apply.argtypes = [vp, i, i, i, dp, dp]
+    for name in EXPORTS:
+        if name not in ("mtomg_workspace_bytes", "mtomg_status_string", "mtomg_last_error"):
+            getattr(lib, name).restype = i
+    _lib = lib
+    return lib
+
+
+def check(ctx, status: int, allow=()):
+    """Raise MtomgError for a negative status not listed in `allow`."""
+    if status == MTOMG_OK or status in allow:
+        return status
+    lib = load()
+    msg = lib.mtomg_last_error(ctx).decode() if ctx else lib.mtomg_status_string(status).decode()
+    raise MtomgError(status, msg)
+
+
+# Thin same-name wrappers -----------------------------------------------------
+
+def mtomg_create(max_designs: int, stream: int = 0):
+    lib = load()
+    ctx = ctypes.c_void_p()
+    check(None, lib.mtomg_create(ctypes.byref(ctx), max_designs, ctypes.c_void_p(stream or None)))
+    return ctx
+
+
+def mtomg_destroy(ctx):
+    return load().mtomg_destroy(ctx)
+
+
+def mtomg_set_grid(ctx, design, nelx, nely, nu, E_phase, E_min, penal, levels, n_pre, n_post, omega,
+                   precision, n_cases, F_ptr, U_ptr):
+    lib = load()
+    m = len(E_phase)
+    arr = (ctypes.c_double * m)(*[float(e) for e in E_phase])
+    return check(ctx, lib.mtomg_set_grid(ctx, design, nelx, nely, nu, m, arr, E_min, penal, levels,
+                                         n_pre, n_post, omega, precision, n_cases,
+                                         ctypes.c_void_p(F_ptr), ctypes.c_void_p(U_ptr)))
+
+
+def mtomg_workspace_bytes(ctx) -> int:
+    return int(load().mtomg_workspace_bytes(ctx))
+
+
+def mtomg_set_workspace(ctx, ptr: int, nbytes: int):
+    return check(ctx, load().mtomg_set_workspace(ctx, ctypes.c_void_p(ptr), nbytes))
+
+
+def mtomg_set_densities(ctx, design, x_ptr):
+    return check(ctx, load().mtomg_set_densities(ctx, design, ctypes.c_void_p(x_ptr)))
+
+
+def mtomg_solve(ctx, rel_tol, max_iter, warm_start, n_systems):
+    stats = (mtomg_stats * n_systems)()
+    st = load().mtomg_solve(ctx, rel_tol, max_iter, int(warm_start), stats)
+    check(ctx, st, allow=(MTOMG_NOT_CONVERGED, MTOMG_BREAKDOWN, MTOMG_NAN))
+    return st, [s.as_dict() for s in stats]
+
+
+def mtomg_compliance_and_grad(ctx, design, c_ptr, dcdx_ptr):
+    return check(ctx, load().mtomg_compliance_and_grad(ctx, design, ctypes.c_void_p(c_ptr),
+                                                       ctypes.c_void_p(dcdx_ptr or None)))
+
+
+def mtomg_status_string(status: int) -> str:
+    return load().mtomg_status_string(status).decode()
+
+
+def mtomg_last_error(ctx) -> str:
+    return load().mtomg_last_error(ctx).decode()
+
+
+def mtomg_debug_apply(ctx, design, level, op, in_ptr, out_ptr):
+    return check(ctx, load().mtomg_debug_apply(ctx, design, level, op, ctypes.c_void_p(in_ptr or None),
+                                               ctypes.c_void_p(out_ptr)))

@@ -1,0 +1,207 @@
+// Device-side building blocks shared by the solver kernels (gfx950, wave64).
+//
+// Element operator.  Every level of the hierarchy is a grid of square
+// elements whose stiffness is the integral of E(xi, eta) B^T D B over the
+// element (Eq. 7), with bilinear B (Eq. 9) and the plane-stress D (Eq. 8),
+// in local coordinates xi, eta in [0, 1] (the 2D result does not depend on
+// the element size).  On the finest grid E is constant per element (Eq. 5);
+// on a coarse grid the Galerkin product P^T K P of the finer operator is,
+// element by element, the same integral with the coarse bilinear basis and
+// the fine modulus field E underneath it.  Because the strains of a bilinear
+// field are linear in xi and eta, that integral only sees the six moments
+//   M00 = int E, M10 = int E xi, M01 = int E eta,
+//   M20 = int E xi^2, M11 = int E xi eta, M02 = int E eta^2,
+// so one coarse element is stored as 6 numbers instead of an 8x8 matrix.
+// A fine element of modulus E has moments E * (1, 1/2, 1/2, 1/3, 1/4, 1/3).
+//
+// Local element nodes are 0 (0,0), 1 (1,0), 2 (1,1), 3 (0,1); element (i,j)
+// has nodes (i,j), (i+1,j), (i+1,j+1), (i,j+1).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mtomg {
+
+constexpr int WAVE = 64;
+constexpr int WAVES_PER_WG = 4;
+constexpr int WG_THREADS = WAVE * WAVES_PER_WG;
+
+template <typename T> struct V2 { T x, y; };
+
+template <typename T> struct Mom { T m00, m10, m01, m20, m11, m02; };
+
+// Material constants of Eq. (8) for unit modulus: c = 1/(1-nu^2),
+// cnu = c*nu, g = c*(1-nu)/2 (shear).
+template <typename T> struct Mat { T c, cnu, g, omega; };
+
+template <typename T>
+__device__ __forceinline__ Mom<T> mom_zero() { return Mom<T>{T(0), T(0), T(0), T(0), T(0), T(0)}; }
+
+template <typename T>
+__device__ __forceinline__ Mom<T> mom_const(T E) {
+    return Mom<T>{E, E * T(0.5), E * T(0.5), E * (T(1) / T(3)), E * T(0.25), E * (T(1) / T(3))};
+}
+
+// Nodal forces f = K_e u_e of one element from its moments.
+// The bilinear displacement has du_x/dxi = Ax + Bx eta, du_x/deta = Cx + Bx xi
+// (same for y); stresses sigma_xx, sigma_yy, tau are linear in (1, xi, eta)
+// and each nodal force integrates E * (linear shape derivative) * stress.
+template <typename T>
+__device__ __forceinline__ void elem_force(const Mom<T>& m, const Mat<T>& k,
+                                           const V2<T>& u0, const V2<T>& u1,
+                                           const V2<T>& u2, const V2<T>& u3,
+                                           V2<T>& f0, V2<T>& f1, V2<T>& f2, V2<T>& f3) {
+    const T Ax = u1.x - u0.x, Cx = u3.x - u0.x, Bx = (u0.x - u1.x) + (u2.x - u3.x);
+    const T Ay = u1.y - u0.y, Cy = u3.y - u0.y, By = (u0.y - u1.y) + (u2.y - u3.y);
+    // sigma_xx = s0 + s1 xi + s2 eta; sigma_yy = w0 + w1 xi + w2 eta; tau = t0 + t1 xi + t2 eta
+    const T s0 = k.c * Ax + k.cnu * Cy, s1 = k.cnu * By, s2 = k.c * Bx;
+    const T w0 = k.cnu * Ax + k.c * Cy, w1 = k.c * By, w2 = k.cnu * Bx;
+    const T t0 = k.g * (Cx + Ay), t1 = k.g * Bx, t2 = k.g * By;
+    const T Sxx = s0 * m.m00 + s1 * m.m10 + s2 * m.m01;   // int E sxx
+    const T Sxe = s0 * m.m01 + s1 * m.m11 + s2 * m.m02;   // int E sxx eta
+    const T Syy = w0 * m.m00 + w1 * m.m10 + w2 * m.m01;   // int E syy
+    const T Syx = w0 * m.m10 + w1 * m.m20 + w2 * m.m11;   // int E syy xi
+    const T Tt = t0 * m.m00 + t1 * m.m10 + t2 * m.m01;    // int E tau
+    const T Ttx = t0 * m.m10 + t1 * m.m20 + t2 * m.m11;   // int E tau xi
+    const T Tte = t0 * m.m01 + t1 * m.m11 + t2 * m.m02;   // int E tau eta
+    const T a = Sxx - Sxe, b = Tt - Ttx, c = Syy - Syx, d = Tt - Tte;
+    f0.x = -a - b;   f1.x = a - Ttx;  f2.x = Sxe + Ttx; f3.x = b - Sxe;
+    f0.y = -c - d;   f1.y = d - Syx;  f2.y = Syx + Tte; f3.y = c - Tte;
+}
+
+// Diagonal of K_e at the 8 local DOFs:
+// K[ax][ax] = int E (c (dN_a/dxi)^2 + g (dN_a/deta)^2), K[ay][ay] with c and g swapped.
+template <typename T>
+__device__ __forceinline__ void elem_diag(const Mom<T>& m, const Mat<T>& k,
+                                          V2<T>& d0, V2<T>& d1, V2<T>& d2, V2<T>& d3) {
+    const T P0 = m.m00 - T(2) * m.m01 + m.m02;  // int E (1-eta)^2
+    const T P1 = m.m02;                          // int E eta^2
+    const T Q0 = m.m00 - T(2) * m.m10 + m.m20;  // int E (1-xi)^2
+    const T Q1 = m.m20;                          // int E xi^2
+    d0.x = k.c * P0 + k.g * Q0; d0.y = k.c * Q0 + k.g * P0;
+    d1.x = k.c * P0 + k.g * Q1; d1.y = k.c * Q1 + k.g * P0;
+    d2.x = k.c * P1 + k.g * Q1; d2.y = k.c * Q1 + k.g * P1;
+    d3.x = k.c * P1 + k.g * Q0; d3.y = k.c * Q0 + k.g * P1;
+}
+
+// Moments of a parent element from its four children (s, t) in {0,1}^2,
+// each given in its own local coordinates: xi = (s + xi')/2, eta = (t + eta')/2,
+// d xi d eta = d xi' d eta' / 4.
+template <typename T>
+__device__ __forceinline__ void mom_accumulate_child(Mom<T>& P, const Mom<T>& c, int s, int t) {
+    const T S = T(s), U = T(t);
+    P.m00 += T(0.25) * c.m00;
+    P.m10 += T(0.125) * (S * c.m00 + c.m10);
+    P.m01 += T(0.125) * (U * c.m00 + c.m01);
+    P.m20 += T(0.0625) * (S * c.m00 + T(2) * S * c.m10 + c.m20);
+    P.m11 += T(0.0625) * (S * U * c.m00 + S * c.m01 + U * c.m10 + c.m11);
+    P.m02 += T(0.0625) * (U * c.m00 + T(2) * U * c.m01 + c.m02);
+}
+
+// ---------------------------------------------------------------------------
+// wave helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
+__device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
+
+// value of lane l-1 (lane 0 gets its own value)
+template <typename T> __device__ __forceinline__ T from_left(T v) { return __shfl_up(v, 1, WAVE); }
+// value of lane l+1 (lane 63 gets its own value)
+template <typename T> __device__ __forceinline__ T from_right(T v) { return __shfl_down(v, 1, WAVE); }
+
+template <typename T> __device__ __forceinline__ V2<T> from_left(V2<T> v) {
+    return V2<T>{from_left(v.x), from_left(v.y)};
+}
+template <typename T> __device__ __forceinline__ V2<T> from_right(V2<T> v) {
+    return V2<T>{from_right(v.x), from_right(v.y)};
+}
+
+template <typename T> __device__ __forceinline__ V2<T> operator+(V2<T> a, V2<T> b) { return V2<T>{a.x + b.x, a.y + b.y}; }
+template <typename T> __device__ __forceinline__ V2<T> operator-(V2<T> a, V2<T> b) { return V2<T>{a.x - b.x, a.y - b.y}; }
+
+// Fixed-order wave sum (tree over lane distance 32, 16, ..., 1); the result
+// is valid in lane 0.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, WAVE);
+    return v;
+}
+
+// Fixed-order workgroup sum of one double per thread (WG_THREADS threads);
+// every thread gets the result.  Requires all threads of the block to call.
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double red[WAVES_PER_WG];
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane_id() == 0) red[wave_id()] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < WAVES_PER_WG; ++w) s += red[w];
+    return s;
+}
+
+// Sum of n partials in a fixed order; identical in every block that calls it.
+__device__ __forceinline__ double sum_partials(const double* __restrict__ p, int n) {
+    double s = 0.0;
+    for (int k = threadIdx.x; k < n; k += WG_THREADS) s += p[k];
+    return block_sum(s);
+}
+
+// ---------------------------------------------------------------------------
+// tile mapping: consecutive tiles land on the same XCD (workgroups are
+// dispatched round-robin over the 8 XCDs), so vertical and horizontal halo
+// reads of neighbouring tiles hit the same L2.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int xcd_tile(int n_tiles) {
+    const int per = (n_tiles + 7) >> 3;
+    const int b = blockIdx.x;
+    return (b & 7) * per + (b >> 3);
+}
+
+// Nodal vector access with the clamped row (j = 0) and out-of-grid nodes read as 0.
+template <typename T>
+__device__ __forceinline__ V2<T> load_node(const T* __restrict__ v, int nx, int ny, int i, int j) {
+    if (i < 0 || i > nx || j < 1 || j > ny) return V2<T>{T(0), T(0)};
+    const size_t n = (size_t)j * (nx + 1) + i;
+    if constexpr (sizeof(T) == 4) {
+        const float2 w = reinterpret_cast<const float2*>(v)[n];
+        return V2<T>{w.x, w.y};
+    } else {
+        const double2 w = reinterpret_cast<const double2*>(v)[n];
+        return V2<T>{w.x, w.y};
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void store_node(T* __restrict__ v, int nx, int i, int j, V2<T> a) {
+    const size_t n = (size_t)j * (nx + 1) + i;
+    if constexpr (sizeof(T) == 4) {
+        reinterpret_cast<float2*>(v)[n] = make_float2(a.x, a.y);
+    } else {
+        reinterpret_cast<double2*>(v)[n] = make_double2(a.x, a.y);
+    }
+}
+
+// Operator data of one level: the finest grid stores E per element, a
+// coarse grid stores 6 moment planes (plane stride nx*ny).
+template <typename T> struct LevelOp {
+    int nx, ny;
+    const T* __restrict__ data;
+};
+
+template <typename T, bool FINE>
+__device__ __forceinline__ Mom<T> load_elem(const LevelOp<T>& L, int i, int j) {
+    if (i < 0 || i >= L.nx || j < 0 || j >= L.ny) return mom_zero<T>();
+    const size_t e = (size_t)j * L.nx + i;
+    if constexpr (FINE) {
+        return mom_const<T>(L.data[e]);
+    } else {
+        const size_t ps = (size_t)L.nx * L.ny;
+        return Mom<T>{L.data[e], L.data[ps + e], L.data[2 * ps + e], L.data[3 * ps + e],
+                      L.data[4 * ps + e], L.data[5 * ps + e]};
+    }
+}
+
+}  // namespace mtomg

@@ -1,0 +1,789 @@
+// Host side of the C ABI declared in include/mtomg.h: contexts, workspace
+// layout, preconditioner setup and the PCG driver (Algorithm 2 with the
+// multigrid cycle of Algorithm 1 as preconditioner).
+//
+// Solve loop.  All PCG scalars stay on the device: every kernel that needs
+// alpha = rho / p^T q or beta = rho_i / rho_{i-1} re-sums the per-workgroup
+// partial dot products of the kernel that produced them, in a fixed order,
+// so the run is deterministic and needs no host round trip.  Partial
+// buffers and the r / p vectors alternate by iteration parity.  A small
+// per-case state word carries convergence: 0 running, 1 converged (the last
+// x update is pending), 2 finished, 3 breakdown, 4 NaN; every kernel exits
+// at once when it is set, so the host can launch iterations in batches and
+// read the state only between batches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mtomg.h"
+#include "kernels.h"
+
+using namespace mtomg;
+
+namespace {
+
+constexpr int MAX_PHASES = 8;
+
+struct LevelBufs {
+    int nx = 0, ny = 0;
+    double* op64 = nullptr;   // E (finest) or 6 moment planes
+    float* op32 = nullptr;    // FP32 copy for the FP32 cycle
+    Sweep sw_apply{}, sw_pre{}, sw_res{}, sw_post{};
+    size_t nodes() const { return (size_t)(nx + 1) * (ny + 1); }
+};
+
+struct CaseBufs {
+    const double* F = nullptr;   // caller-owned load of this case
+    double* U = nullptr;         // caller-owned displacement of this case
+    double *r[2] = {nullptr, nullptr}, *p[2] = {nullptr, nullptr}, *q = nullptr;
+    void* z = nullptr;
+    float* r32 = nullptr;
+    std::vector<void*> b, u2, u4, e;   // per level, precision of the cycle
+    double *zr[2] = {nullptr, nullptr}, *pq[2] = {nullptr, nullptr}, *rr[2] = {nullptr, nullptr};
+    double *ff = nullptr, *trr = nullptr, *sums = nullptr, *cpart = nullptr;
+    int* state = nullptr;   // [0] conv, [1] iters
+};
+
+struct Design {
+    bool has_grid = false, has_dens = false;
+    int nelx = 0, nely = 0, m = 0, levels = 0, n_pre = 2, n_post = 2, precision = 0, n_cases = 1;
+    double nu = 0.3, E_min = 1e-9, penal = 3.0, omega = 0.6;
+    double E_phase[MAX_PHASES] = {};
+    const double* F = nullptr;
+    double* U = nullptr;
+    std::vector<LevelBufs> lev;   // 0 = coarsest
+    int n0 = 0;
+    double *A0 = nullptr, *W0 = nullptr, *Ainv = nullptr;
+    int* chol_status = nullptr;
+    std::vector<CaseBufs> cases;
+    const double* x_dev = nullptr;
+    float t_setup_ms = 0.f;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    int fine() const { return levels - 1; }
+    bool mixed() const { return precision == MTOMG_FP32MG; }
+};
+
+}  // namespace
+
+struct mtomg_ctx {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::vector<Design> d;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    bool ws_owned = false;
+    bool laid_out = false;
+    std::string err;
+    int* host_state = nullptr;    // pinned
+    double* host_sums = nullptr;  // pinned
+    int batch = 8;
+};
+
+namespace {
+
+int fail(mtomg_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(ctx, MTOMG_HIP_ERROR, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define LAUNCHCHK(ctx)                                                                      \
+    do {                                                                                    \
+        hipError_t e_ = hipGetLastError();                                                  \
+        if (e_ != hipSuccess)                                                               \
+            return fail(ctx, MTOMG_HIP_ERROR, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+// ----------------------------------------------------------------------------
+// launch geometry
+// ----------------------------------------------------------------------------
+int pick_rows(int strips, int rows_total) {
+    // enough waves to fill 256 CUs a few times over, at least 4 rows per wave
+    int R = 32;
+    while (R > 4 && (long)strips * ((rows_total + R - 1) / R) < 4096) R >>= 1;
+    return R;
+}
+
+Sweep make_sweep(int cols, int wout, int rows_total, int R = 0) {
+    Sweep s;
+    s.n_strips = (cols + wout - 1) / wout;
+    s.rows = R > 0 ? R : pick_rows(s.n_strips, rows_total);
+    const int chunks = (rows_total + s.rows - 1) / s.rows;
+    s.n_tiles = s.n_strips * ((chunks + WAVES_PER_WG - 1) / WAVES_PER_WG);
+    return s;
+}
+
+void plan_level(LevelBufs& L) {
+    L.sw_apply = make_sweep(L.nx + 1, 62, L.ny + 1);
+    L.sw_post = L.sw_apply;
+    L.sw_pre = make_sweep(L.nx + 1, 61, L.ny + 1);
+    if (L.nx % 2 == 0 && L.ny % 2 == 0)
+        L.sw_res = make_sweep(L.nx / 2 + 1, 30, L.ny / 2 + 1);
+}
+
+// ----------------------------------------------------------------------------
+// workspace layout (bump allocation; a null base only measures)
+// ----------------------------------------------------------------------------
+struct Bump {
+    char* base;
+    size_t off = 0;
+    template <typename T> T* take(size_t n) {
+        off = (off + 255) & ~(size_t)255;
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += n * sizeof(T);
+        return p;
+    }
+};
+
+void layout_design(Design& d, Bump& B) {
+    const bool mx = d.mixed();
+    const size_t tsz = mx ? sizeof(float) : sizeof(double);
+    for (int l = 0; l < d.levels; ++l) {
+        LevelBufs& L = d.lev[l];
+        const size_t ne = (size_t)L.nx * L.ny;
+        const bool fine = l == d.fine();
+        L.op64 = B.take<double>(fine ? ne : 6 * ne);
+        L.op32 = mx ? B.take<float>(fine ? ne : 6 * ne) : nullptr;
+    }
+    d.A0 = B.take<double>((size_t)d.n0 * d.n0);
+    d.W0 = B.take<double>((size_t)d.n0 * d.n0);
+    d.Ainv = B.take<double>((size_t)d.n0 * d.n0);
+    d.chol_status = B.take<int>(4);
+    const LevelBufs& Lf = d.lev[d.fine()];
+    const size_t nf = Lf.nodes() * 2;
+    const int np = std::max({Lf.sw_apply.n_tiles, Lf.sw_pre.n_tiles, Lf.sw_post.n_tiles, 1});
+    for (size_t ci = 0; ci < d.cases.size(); ++ci) {
+        CaseBufs& c = d.cases[ci];
+        c.F = d.F + ci * nf;
+        c.U = d.U + ci * nf;
+        for (int k = 0; k < 2; ++k) {
+            c.r[k] = B.take<double>(nf);
+            c.p[k] = B.take<double>(nf);
+            c.zr[k] = B.take<double>(np);
+            c.pq[k] = B.take<double>(np);
+            c.rr[k] = B.take<double>(np);
+        }
+        c.q = B.take<double>(nf);
+        c.z = B.take<char>(nf * tsz);
+        c.r32 = mx ? B.take<float>(nf) : nullptr;
+        c.ff = B.take<double>(np);
+        c.trr = B.take<double>(np);
+        c.cpart = B.take<double>(256);
+        c.sums = B.take<double>(8);
+        c.state = B.take<int>(4);
+        c.b.assign(d.levels, nullptr);
+        c.u2.assign(d.levels, nullptr);
+        c.u4.assign(d.levels, nullptr);
+        c.e.assign(d.levels, nullptr);
+        for (int l = 0; l < d.levels; ++l) {
+            const size_t n = d.lev[l].nodes() * 2 * tsz;
+            if (l != d.fine()) {
+                c.b[l] = B.take<char>(n);
+                c.e[l] = B.take<char>(n);
+            }
+            if (l != 0) {
+                c.u2[l] = B.take<char>(n);
+                c.u4[l] = B.take<char>(n);
+            }
+        }
+    }
+}
+
+size_t layout_all(mtomg_ctx* c, char* base) {
+    Bump B{base};
+    for (Design& d : c->d)
+        if (d.has_grid) layout_design(d, B);
+    return B.off + 256;
+}
+
+int ensure_workspace(mtomg_ctx* c) {
+    if (c->laid_out) return MTOMG_OK;
+    const size_t need = layout_all(c, nullptr);
+    if (c->ws && c->ws_bytes < need)
+        return fail(c, MTOMG_WORKSPACE, "workspace smaller than mtomg_workspace_bytes()");
+    if (!c->ws) {
+        HIPCHK(c, hipMalloc(&c->ws, need));
+        c->ws_bytes = need;
+        c->ws_owned = true;
+    }
+    layout_all(c, reinterpret_cast<char*>(c->ws));
+    c->laid_out = true;
+    return MTOMG_OK;
+}
+
+template <typename T> Mat<T> make_mat(const Design& d, double omega) {
+    const double cc = 1.0 / (1.0 - d.nu * d.nu);
+    return Mat<T>{(T)cc, (T)(cc * d.nu), (T)(cc * (1.0 - d.nu) / 2.0), (T)omega};
+}
+
+template <typename T> LevelOp<T> level_op(const Design& d, int l) {
+    const LevelBufs& L = d.lev[l];
+    if constexpr (sizeof(T) == 4) return LevelOp<T>{L.nx, L.ny, L.op32};
+    else return LevelOp<T>{L.nx, L.ny, L.op64};
+}
+
+Phases phases_of(const Design& d) {
+    Phases ph{};
+    for (int k = 0; k < d.m; ++k) ph.dE[k] = d.E_phase[k] - d.E_min;
+    ph.m = d.m;
+    ph.E_min = d.E_min;
+    ph.penal = d.penal;
+    return ph;
+}
+
+// ----------------------------------------------------------------------------
+// multigrid cycle on one case
+// ----------------------------------------------------------------------------
+template <typename T> struct CycleCtx {
+    Design* d;
+    CaseBufs* c;
+    hipStream_t st;
+    const int* conv;   // nullable (debug use)
+};
+
+// n sweeps of the post-smoother chain; returns the buffer holding the result
+template <typename T>
+void post_chain(CycleCtx<T>& cx, int l, const T* u_cur, const T* ec, const T* b, T* out, T* t0, T* t1,
+                bool dot, const double* r64, double* zr_out) {
+    Design& d = *cx.d;
+    const bool fine = l == d.fine();
+    const LevelOp<T> op = level_op<T>(d, l);
+    const LevelBufs& L = d.lev[l];
+    const int n = d.n_post;
+    if (n == 0) {
+        launch_post<T>(cx.st, fine, true, dot, op, make_mat<T>(d, 0.0), L.sw_post, u_cur, ec, b, out, r64, zr_out, cx.conv);
+        return;
+    }
+    const T* in = u_cur;
+    for (int k = 1; k <= n; ++k) {
+        T* dst = (k == n) ? out : ((in == t0) ? t1 : t0);
+        launch_post<T>(cx.st, fine, k == 1, dot && k == n, op, make_mat<T>(d, d.omega), L.sw_post, in,
+                       k == 1 ? ec : nullptr, b, dst, r64, zr_out, cx.conv);
+        in = dst;
+    }
+}
+
+// Extra pre-smoothing sweeps after the fused first two; returns current buffer.
+template <typename T>
+T* pre_chain_extra(CycleCtx<T>& cx, int l, T* cur, const T* b, T* t0, T* t1) {
+    Design& d = *cx.d;
+    const bool fine = l == d.fine();
+    for (int k = 3; k <= d.n_pre; ++k) {
+        T* dst = (cur == t0) ? t1 : t0;
+        launch_post<T>(cx.st, fine, false, false, level_op<T>(d, l), make_mat<T>(d, d.omega), d.lev[l].sw_post,
+                       cur, nullptr, b, dst, nullptr, nullptr, cx.conv);
+        cur = dst;
+    }
+    return cur;
+}
+
+// Levels l-1 .. 0 of Algorithm 1 given the restricted right-hand side in
+// c.b[l-1]; leaves the coarse correction in c.e[l-1].
+template <typename T>
+void coarse_cycle(CycleCtx<T>& cx, int top) {
+    Design& d = *cx.d;
+    CaseBufs& c = *cx.c;
+    ConvCheck nochk{};
+    CgRhs nocg{};
+    for (int l = top; l >= 1; --l) {
+        T* b = (T*)c.b[l];
+        T* t0 = (T*)c.u2[l];
+        T* t1 = (T*)c.u4[l];
+        T* cur = t0;
+        if (d.n_pre > 0) {
+            launch_presmooth<T>(cx.st, false, false, level_op<T>(d, l), make_mat<T>(d, d.omega), d.lev[l].sw_pre,
+                                b, t0, std::min(d.n_pre, 2), nocg, cx.conv);
+            cur = pre_chain_extra<T>(cx, l, cur, b, t0, t1);
+        }
+        launch_restrict<T>(cx.st, false, false, level_op<T>(d, l), make_mat<T>(d, d.omega), d.lev[l].sw_res, b,
+                           d.n_pre > 0 ? cur : nullptr, (T*)c.b[l - 1], nochk, cx.conv);
+        // remember which buffer holds the pre-smoothed iterate
+        if (cur != t0) std::swap(c.u2[l], c.u4[l]);
+    }
+    launch_coarse_solve<T>(cx.st, d.Ainv, d.n0, d.lev[0].nx, (const T*)c.b[0], (T*)c.e[0], cx.conv);
+    for (int l = 1; l <= top; ++l) {
+        T* t0 = (T*)c.u2[l];
+        T* t1 = (T*)c.u4[l];
+        post_chain<T>(cx, l, d.n_pre > 0 ? t0 : nullptr, (const T*)c.e[l - 1], (const T*)c.b[l], (T*)c.e[l], t1,
+                      t0, false, nullptr, nullptr);
+    }
+}
+
+// One preconditioner application on the finest grid inside PCG.
+//   it < 0: initial cycle on r_0 (no residual update, writes rho_0)
+//   it >= 0: iteration it: r_{it+1} = r_it - alpha q, then z_{it+1} = M^-1 r_{it+1}
+template <typename T>
+void fine_cycle(CycleCtx<T>& cx, int it, double tol2) {
+    Design& d = *cx.d;
+    CaseBufs& c = *cx.c;
+    const int f = d.fine();
+    const int par = it < 0 ? 0 : (it & 1);
+    const int nxt = it < 0 ? 0 : 1 - par;
+    const LevelBufs& L = d.lev[f];
+    CgRhs cg{};
+    cg.r_old = c.r[par];
+    cg.q = c.q;
+    cg.r_new = c.r[nxt];
+    cg.r32 = c.r32;
+    cg.zr = c.zr[par];
+    cg.n_zr = L.sw_post.n_tiles;
+    cg.pq = c.pq[par];
+    cg.n_pq = L.sw_apply.n_tiles;
+    cg.rr_out = c.rr[nxt];
+    cg.update = it >= 0;
+    cg.conv_rw = c.state;
+    cg.iters = c.state + 1;
+    T* t0 = (T*)c.u2[f];
+    T* t1 = (T*)c.u4[f];
+    const T* bfine = d.mixed() ? (const T*)(void*)c.r32 : (const T*)(void*)c.r[nxt];
+    launch_presmooth<T>(cx.st, true, true, level_op<T>(d, f), make_mat<T>(d, d.omega), L.sw_pre, nullptr, t0,
+                        std::min(d.n_pre, 2), cg, cx.conv);
+    T* cur = pre_chain_extra<T>(cx, f, t0, bfine, t0, t1);
+    ConvCheck chk{};
+    chk.rr = c.rr[nxt];
+    chk.n_rr = it < 0 ? L.sw_apply.n_tiles : L.sw_pre.n_tiles;
+    chk.ff = c.ff;
+    chk.n_ff = L.sw_apply.n_tiles;
+    chk.tol2 = tol2;
+    chk.conv_rw = c.state;
+    launch_restrict<T>(cx.st, true, true, level_op<T>(d, f), make_mat<T>(d, d.omega), L.sw_res, bfine,
+                       d.n_pre > 0 ? cur : nullptr, (T*)c.b[f - 1], chk, cx.conv);
+    if (cur != t0) std::swap(c.u2[f], c.u4[f]);
+    coarse_cycle<T>(cx, f - 1);
+    post_chain<T>(cx, f, d.n_pre > 0 ? (T*)c.u2[f] : nullptr, (const T*)c.e[f - 1], bfine, (T*)c.z,
+                  (T*)c.u4[f], (T*)c.u2[f], true, c.r[nxt], c.zr[it < 0 ? 0 : nxt]);
+}
+
+template <typename T>
+void cg_step(Design& d, CaseBufs& c, hipStream_t st, int it, int mode) {
+    const LevelBufs& L = d.lev[d.fine()];
+    const int par = it & 1, prv = 1 - par;
+    launch_cg_apply<T>(st, level_op<double>(d, d.fine()), make_mat<double>(d, d.omega), L.sw_apply,
+                       (const T*)c.z, c.p[prv], c.p[par], c.U, c.q, c.zr[par], c.zr[prv], L.sw_post.n_tiles,
+                       c.pq[prv], L.sw_apply.n_tiles, c.pq[par], c.state, mode);
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+namespace {
+
+// One V-cycle M^-1 b from a zero iterate on `level` (test hook).
+template <typename T>
+int debug_vcycle(mtomg_ctx* ctx, Design& d, CaseBufs& cb, hipStream_t st, int level, const T* vin, T* vout) {
+    const bool fine = level == d.fine();
+    const size_t n = 2 * d.lev[level].nodes();
+    T* bl = fine ? (T*)(d.mixed() ? (void*)cb.r32 : (void*)cb.r[0]) : (T*)cb.b[level];
+    HIPCHK(ctx, hipMemcpyAsync(bl, vin, n * sizeof(T), hipMemcpyDeviceToDevice, st));
+    const LevelOp<T> opT = level_op<T>(d, level);
+    const Mat<T> mat = make_mat<T>(d, d.omega);
+    CgRhs nocg{};
+    ConvCheck nochk{};
+    CycleCtx<T> cx{&d, &cb, st, nullptr};
+    T* t0 = (T*)cb.u2[level];
+    T* t1 = (T*)cb.u4[level];
+    T* cur = t0;
+    if (d.n_pre > 0) {
+        launch_presmooth<T>(st, fine, false, opT, mat, d.lev[level].sw_pre, bl, t0, std::min(d.n_pre, 2), nocg, nullptr);
+        cur = pre_chain_extra<T>(cx, level, cur, bl, t0, t1);
+    }
+    launch_restrict<T>(st, fine, false, opT, mat, d.lev[level].sw_res, bl, d.n_pre > 0 ? cur : nullptr,
+                       (T*)cb.b[level - 1], nochk, nullptr);
+    if (cur != t0) std::swap(cb.u2[level], cb.u4[level]);
+    coarse_cycle<T>(cx, level - 1);
+    post_chain<T>(cx, level, d.n_pre > 0 ? (T*)cb.u2[level] : nullptr, (const T*)cb.e[level - 1], bl, vout,
+                  (T*)cb.u4[level], (T*)cb.u2[level], false, nullptr, nullptr);
+    return MTOMG_OK;
+}
+
+int check_design(mtomg_ctx* c, int design, bool need_dens) {
+    if (!c) return MTOMG_BAD_INPUT;
+    if (design < 0 || design >= (int)c->d.size()) return fail(c, MTOMG_BAD_INPUT, "design index out of range");
+    if (!c->d[design].has_grid) return fail(c, MTOMG_STATE, "set_grid not called for this design");
+    if (need_dens && !c->d[design].has_dens) return fail(c, MTOMG_STATE, "set_densities not called for this design");
+    return MTOMG_OK;
+}
+
+template <typename T>
+int solve_case(mtomg_ctx* ctx, Design& d, CaseBufs& c, double rel_tol, int max_iter, int warm, mtomg_stats* out) {
+    hipStream_t st = ctx->stream;
+    const LevelBufs& L = d.lev[d.fine()];
+    const LevelOp<double> op64 = level_op<double>(d, d.fine());
+    const Mat<double> mat64 = make_mat<double>(d, d.omega);
+    const double tol2 = rel_tol * rel_tol;
+    HIPCHK(ctx, hipEventRecord(d.ev[0], st));
+    launch_fill<int>(st, c.state, 4, 0);
+    launch_residual(st, op64, mat64, L.sw_apply, c.F, c.U, warm ? 1 : 0, c.r[0], c.rr[0], c.ff);
+    CycleCtx<T> cx{&d, &c, st, c.state};
+    fine_cycle<T>(cx, -1, tol2);
+    LAUNCHCHK(ctx);
+    int it = 0;
+    int done = 0;
+    int batch = std::max(2, ctx->batch);
+    while (it < max_iter) {
+        const int nb = std::min(batch, max_iter - it);
+        for (int k = 0; k < nb; ++k) {
+            cg_step<T>(d, c, st, it + k, (it + k == 0) ? 1 : 0);
+            fine_cycle<T>(cx, it + k, tol2);
+        }
+        LAUNCHCHK(ctx);
+        it += nb;
+        HIPCHK(ctx, hipMemcpyAsync(ctx->host_state, c.state, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(ctx, hipStreamSynchronize(st));
+        done = ctx->host_state[0];
+        if (done != 0) break;
+        // next batch: a few more than the iterations done so far
+        batch = std::max(2, std::min(it, 16));
+    }
+    if (done == 0 && max_iter > 0) {
+        // pending x update of the last iteration
+        cg_step<T>(d, c, st, it, 2);
+    } else if (done == 1 && it > 0) {
+        // converged in the last launched iteration: the pending update
+        cg_step<T>(d, c, st, it, 0);
+    }
+    launch_residual(st, op64, mat64, L.sw_apply, c.F, c.U, 1, nullptr, c.trr, nullptr);
+    HIPCHK(ctx, hipMemcpyAsync(ctx->host_state, c.state, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    const int iters = ctx->host_state[1];
+    SumJob job{};
+    job.p[0] = c.ff; job.n[0] = L.sw_apply.n_tiles;
+    job.p[1] = c.rr[iters & 1]; job.n[1] = iters == 0 ? L.sw_apply.n_tiles : L.sw_pre.n_tiles;
+    job.p[2] = c.trr; job.n[2] = L.sw_apply.n_tiles;
+    job.count = 3;
+    launch_sums(st, job, c.sums);
+    LAUNCHCHK(ctx);
+    HIPCHK(ctx, hipEventRecord(d.ev[1], st));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->host_sums, c.sums, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->host_state, c.state, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    float ms = 0.f;
+    HIPCHK(ctx, hipEventElapsedTime(&ms, d.ev[0], d.ev[1]));
+    const double ff = ctx->host_sums[0];
+    const int cv = ctx->host_state[0];
+    out->status = (cv == 1 || cv == 2) ? MTOMG_OK : cv == 3 ? MTOMG_BREAKDOWN : cv == 4 ? MTOMG_NAN : MTOMG_NOT_CONVERGED;
+    out->iters = ctx->host_state[1];
+    out->vcycles = out->iters + 1;
+    out->n_dof = (int)(2 * L.nodes());
+    out->relres_rec = ff > 0 ? std::sqrt(ctx->host_sums[1] / ff) : 0.0;
+    out->relres_true = ff > 0 ? std::sqrt(ctx->host_sums[2] / ff) : 0.0;
+    out->t_setup_ms = d.t_setup_ms;
+    out->t_solve_ms = ms;
+    // algorithmic bytes of one iteration (each array touched once per kernel)
+    double bytes = 0.0;
+    const double t = sizeof(T);
+    for (int l = 0; l < d.levels; ++l) {
+        const double n = (double)d.lev[l].nodes(), ne = (double)d.lev[l].nx * d.lev[l].ny;
+        if (l == d.fine()) {
+            bytes += n * 16 * 6 + ne * 8;                      // cg_apply: z,p_old,x in; p,q,x out; E
+            bytes += n * 16 * 3 + (d.mixed() ? n * 8 : 0);     // r, q in; r out (+ r32)
+            bytes += n * 2 * t * 5 + ne * t * 4 + n * 16;      // smoothing/transfer sweeps + r for dot
+        } else if (l > 0) {
+            bytes += n * 2 * t * 7 + ne * 6 * t * 4;
+        } else {
+            bytes += 8.0 * d.n0 * d.n0 + n * 2 * t * 2;
+        }
+    }
+    out->model_bytes = bytes;
+    return out->status;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mtomg_create(mtomg_ctx** ctx, int max_designs, void* hip_stream) {
+    if (!ctx || max_designs < 1) return MTOMG_BAD_INPUT;
+    *ctx = nullptr;
+    mtomg_ctx* c = new (std::nothrow) mtomg_ctx();
+    if (!c) return MTOMG_BAD_INPUT;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return MTOMG_HIP_ERROR;
+    }
+    c->d.resize(max_designs);
+    if (hipHostMalloc((void**)&c->host_state, 16 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&c->host_sums, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return MTOMG_HIP_ERROR;
+    }
+    *ctx = c;
+    return MTOMG_OK;
+}
+
+int mtomg_destroy(mtomg_ctx* c) {
+    if (!c) return MTOMG_OK;
+    hipStreamSynchronize(c->stream);
+    for (Design& d : c->d)
+        for (hipEvent_t& e : d.ev)
+            if (e) hipEventDestroy(e);
+    if (c->ws_owned && c->ws) hipFree(c->ws);
+    if (c->host_state) hipHostFree(c->host_state);
+    if (c->host_sums) hipHostFree(c->host_sums);
+    delete c;
+    return MTOMG_OK;
+}
+
+int mtomg_set_grid(mtomg_ctx* c, int design, int nelx, int nely, double nu, int m, const double* E_phase,
+                   double E_min, double penal, int levels, int n_pre, int n_post, double omega, int precision,
+                   int n_cases, const double* F, double* U) {
+    if (!c) return MTOMG_BAD_INPUT;
+    if (design < 0 || design >= (int)c->d.size()) return fail(c, MTOMG_BAD_INPUT, "design index out of range");
+    if (levels < 2 || levels > 14) return fail(c, MTOMG_BAD_INPUT, "levels must be in [2, 14]");
+    const int s = 1 << (levels - 1);
+    if (nelx < s || nely < s || nelx % s || nely % s)
+        return fail(c, MTOMG_BAD_INPUT, "nelx and nely must be positive multiples of 2^(levels-1)");
+    if (nelx / s > 32 || nely / s > 32)
+        return fail(c, MTOMG_BAD_INPUT, "coarsest grid larger than 32 x 32 elements; add levels");
+    if ((long)(nelx + 1) * (nely + 1) > (1L << 30)) return fail(c, MTOMG_BAD_INPUT, "grid too large");
+    if (!(nu >= 0.0 && nu < 0.5)) return fail(c, MTOMG_BAD_INPUT, "nu must be in [0, 0.5)");
+    if (m < 1 || m > MAX_PHASES || !E_phase) return fail(c, MTOMG_BAD_INPUT, "m must be in [1, 8] with E_phase given");
+    if (!(E_min > 0.0)) return fail(c, MTOMG_BAD_INPUT, "E_min must be > 0");
+    for (int k = 0; k < m; ++k)
+        if (!(E_phase[k] >= E_min) || !std::isfinite(E_phase[k])) return fail(c, MTOMG_BAD_INPUT, "E_phase must be finite and >= E_min");
+    if (!(penal >= 1.0)) return fail(c, MTOMG_BAD_INPUT, "penal must be >= 1");
+    if (n_pre < 0 || n_pre > 8 || n_post < 0 || n_post > 8) return fail(c, MTOMG_BAD_INPUT, "n_pre, n_post must be in [0, 8]");
+    if (!(omega > 0.0 && omega <= 1.0)) return fail(c, MTOMG_BAD_INPUT, "omega must be in (0, 1]");
+    if (precision != MTOMG_FP64 && precision != MTOMG_FP32MG) return fail(c, MTOMG_BAD_INPUT, "unknown precision");
+    if (n_cases < 1 || n_cases > 64) return fail(c, MTOMG_BAD_INPUT, "n_cases must be in [1, 64]");
+    if (!F || !U) return fail(c, MTOMG_BAD_INPUT, "F and U must be device pointers");
+    Design& d = c->d[design];
+    d = Design();
+    d.nelx = nelx; d.nely = nely; d.nu = nu; d.m = m; d.E_min = E_min; d.penal = penal; d.levels = levels;
+    d.n_pre = n_pre; d.n_post = n_post; d.omega = omega; d.precision = precision; d.n_cases = n_cases;
+    d.F = F; d.U = U;
+    for (int k = 0; k < m; ++k) d.E_phase[k] = E_phase[k];
+    d.lev.resize(levels);
+    for (int l = 0; l < levels; ++l) {
+        const int sh = levels - 1 - l;
+        d.lev[l].nx = nelx >> sh;
+        d.lev[l].ny = nely >> sh;
+        plan_level(d.lev[l]);
+    }
+    d.n0 = 2 * (d.lev[0].nx + 1) * d.lev[0].ny;
+    d.cases.assign(n_cases, CaseBufs());
+    HIPCHK(c, hipEventCreate(&d.ev[0]));
+    HIPCHK(c, hipEventCreate(&d.ev[1]));
+    d.has_grid = true;
+    // the layout changes: drop an owned workspace, forget a borrowed one
+    if (c->ws_owned && c->ws) {
+        hipStreamSynchronize(c->stream);
+        hipFree(c->ws);
+    }
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+    c->ws_owned = false;
+    c->laid_out = false;
+    for (Design& o : c->d) o.has_dens = false;
+    return MTOMG_OK;
+}
+
+size_t mtomg_workspace_bytes(const mtomg_ctx* c) {
+    if (!c) return 0;
+    return layout_all(const_cast<mtomg_ctx*>(c), nullptr);
+}
+
+int mtomg_set_workspace(mtomg_ctx* c, void* dev, size_t bytes) {
+    if (!c) return MTOMG_BAD_INPUT;
+    if (!dev || (reinterpret_cast<uintptr_t>(dev) & 255)) return fail(c, MTOMG_BAD_INPUT, "workspace must be a 256-byte aligned device pointer");
+    const size_t need = layout_all(c, nullptr);
+    if (bytes < need) return fail(c, MTOMG_WORKSPACE, "workspace smaller than mtomg_workspace_bytes()");
+    if (c->ws_owned && c->ws) {
+        hipStreamSynchronize(c->stream);
+        hipFree(c->ws);
+    }
+    c->ws = dev;
+    c->ws_bytes = bytes;
+    c->ws_owned = false;
+    c->laid_out = false;
+    for (Design& o : c->d) o.has_dens = false;
+    return ensure_workspace(c);
+}
+
+int mtomg_set_densities(mtomg_ctx* c, int design, const double* x) {
+    int rc = check_design(c, design, false);
+    if (rc) return rc;
+    if (!x) return fail(c, MTOMG_BAD_INPUT, "x must be a device pointer");
+    rc = ensure_workspace(c);
+    if (rc) return rc;
+    Design& d = c->d[design];
+    hipStream_t st = c->stream;
+    HIPCHK(c, hipEventRecord(d.ev[0], st));
+    const int f = d.fine();
+    LevelBufs& Lf = d.lev[f];
+    launch_interp(st, x, phases_of(d), Lf.nx * Lf.ny, Lf.op64, d.mixed() ? Lf.op32 : nullptr);
+    for (int l = f - 1; l >= 0; --l) {
+        LevelBufs& L = d.lev[l];
+        LevelBufs& P = d.lev[l + 1];
+        if (l + 1 == f) launch_moments_from_fine(st, P.op64, P.nx, P.ny, L.op64, d.mixed() ? L.op32 : nullptr);
+        else launch_moments_coarsen(st, P.op64, P.nx, P.ny, L.op64, d.mixed() ? L.op32 : nullptr);
+    }
+    launch_fill<double>(st, d.A0, (size_t)d.n0 * d.n0, 0.0);
+    launch_fill<int>(st, d.chol_status, 4, 0);
+    launch_assemble_dense(st, false, level_op<double>(d, 0), make_mat<double>(d, d.omega), d.A0);
+    launch_cholesky(st, d.A0, d.n0, d.chol_status);
+    launch_trinv(st, d.A0, d.W0, d.n0);
+    launch_gram(st, d.W0, d.Ainv, d.n0);
+    LAUNCHCHK(c);
+    HIPCHK(c, hipEventRecord(d.ev[1], st));
+    HIPCHK(c, hipMemcpyAsync(c->host_state + 8, d.chol_status, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    HIPCHK(c, hipEventElapsedTime(&d.t_setup_ms, d.ev[0], d.ev[1]));
+    if (c->host_state[8] != 0) {
+        d.has_dens = false;
+        return fail(c, MTOMG_BREAKDOWN, "coarsest matrix is not positive definite");
+    }
+    d.x_dev = x;
+    d.has_dens = true;
+    return MTOMG_OK;
+}
+
+int mtomg_solve(mtomg_ctx* c, double rel_tol, int max_iter, int warm_start, mtomg_stats* stats) {
+    if (!c || !stats) return MTOMG_BAD_INPUT;
+    if (!(rel_tol >= 0.0) || max_iter < 0) return fail(c, MTOMG_BAD_INPUT, "rel_tol must be >= 0 and max_iter >= 0");
+    int worst = MTOMG_OK, k = 0, any = 0;
+    for (Design& d : c->d) {
+        if (!d.has_grid) continue;
+        if (!d.has_dens) continue;
+        any = 1;
+        for (CaseBufs& cb : d.cases) {
+            mtomg_stats& s = stats[k++];
+            std::memset(&s, 0, sizeof(s));
+            int rc = d.mixed() ? solve_case<float>(c, d, cb, rel_tol, max_iter, warm_start, &s)
+                               : solve_case<double>(c, d, cb, rel_tol, max_iter, warm_start, &s);
+            if (rc == MTOMG_HIP_ERROR) return rc;
+            if (rc < worst) worst = rc;
+        }
+    }
+    if (!any) return fail(c, MTOMG_STATE, "no design has densities");
+    if (worst != MTOMG_OK) c->err = mtomg_status_string(worst);
+    return worst;
+}
+
+int mtomg_compliance_and_grad(mtomg_ctx* c, int design, double* cout, double* dcdx) {
+    int rc = check_design(c, design, true);
+    if (rc) return rc;
+    if (!cout) return fail(c, MTOMG_BAD_INPUT, "c must be a device pointer");
+    Design& d = c->d[design];
+    hipStream_t st = c->stream;
+    const LevelBufs& L = d.lev[d.fine()];
+    const size_t nf = 2 * L.nodes();
+    for (int k = 0; k < d.n_cases; ++k) {
+        CaseBufs& cb = d.cases[k];
+        launch_dot_partials(st, cb.F, cb.U, nf, cb.cpart, 256);
+        launch_sum_to(st, cb.cpart, 256, cout + k);
+        if (dcdx)
+            launch_grad(st, cb.U, d.x_dev, phases_of(d), make_mat<double>(d, d.omega), L.nx, L.ny,
+                        dcdx + (size_t)k * L.nx * L.ny * d.m);
+    }
+    LAUNCHCHK(c);
+    return MTOMG_OK;
+}
+
+const char* mtomg_status_string(int s) {
+    switch (s) {
+        case MTOMG_OK: return "ok";
+        case MTOMG_BAD_INPUT: return "bad input";
+        case MTOMG_NOT_CONVERGED: return "not converged (max_iter reached)";
+        case MTOMG_BREAKDOWN: return "breakdown (p^T K p <= 0 or z^T r <= 0, or coarsest matrix not SPD)";
+        case MTOMG_NAN: return "non-finite residual";
+        case MTOMG_WORKSPACE: return "workspace missing or too small";
+        case MTOMG_HIP_ERROR: return "HIP runtime error";
+        case MTOMG_STATE: return "call out of order";
+        default: return "unknown status";
+    }
+}
+
+const char* mtomg_last_error(const mtomg_ctx* c) { return c ? c->err.c_str() : ""; }
+
+int mtomg_debug_apply(mtomg_ctx* c, int design, int level, int op, const void* in, void* out) {
+    int rc = check_design(c, design, true);
+    if (rc) return rc;
+    Design& d = c->d[design];
+    if (level < 0 || level >= d.levels) return fail(c, MTOMG_BAD_INPUT, "level out of range");
+    if (!out) return fail(c, MTOMG_BAD_INPUT, "out must be a device pointer");
+    hipStream_t st = c->stream;
+    const LevelBufs& L = d.lev[level];
+    const bool fine = level == d.fine();
+    const size_t n = 2 * L.nodes();
+    auto run = [&](auto tag) -> int {
+        using T = decltype(tag);
+        const T* vin = (const T*)in;
+        T* vout = (T*)out;
+        const LevelOp<T> opT = level_op<T>(d, level);
+        const Mat<T> mat = make_mat<T>(d, d.omega);
+        CaseBufs& cb = d.cases[0];
+        CgRhs nocg{};
+        ConvCheck nochk{};
+        switch (op) {
+            case MTOMG_OP_APPLY: launch_apply<T>(st, fine, false, opT, mat, L.sw_apply, vin, vout); break;
+            case MTOMG_OP_DIAG: launch_apply<T>(st, fine, true, opT, mat, L.sw_apply, nullptr, vout); break;
+            case MTOMG_OP_PRESMOOTH: {
+                if (level == 0) return fail(c, MTOMG_BAD_INPUT, "no smoother on the coarsest level");
+                T* t0 = (T*)cb.u2[level];
+                T* t1 = (T*)cb.u4[level];
+                CycleCtx<T> cx{&d, &cb, st, nullptr};
+                if (d.n_pre == 0) { launch_fill<T>(st, vout, n, T(0)); break; }
+                launch_presmooth<T>(st, fine, false, opT, mat, L.sw_pre, vin, t0, std::min(d.n_pre, 2), nocg, nullptr);
+                T* cur = pre_chain_extra<T>(cx, level, t0, vin, t0, t1);
+                HIPCHK(c, hipMemcpyAsync(vout, cur, n * sizeof(T), hipMemcpyDeviceToDevice, st));
+                break;
+            }
+            case MTOMG_OP_RESIDUAL_RESTRICT:
+                if (level == 0) return fail(c, MTOMG_BAD_INPUT, "no restriction from the coarsest level");
+                launch_restrict<T>(st, fine, false, opT, mat, L.sw_res, vin, vin + n, vout, nochk, nullptr);
+                break;
+            case MTOMG_OP_PROLONG_POSTSMOOTH: {
+                if (level == 0) return fail(c, MTOMG_BAD_INPUT, "no prolongation onto the coarsest level");
+                CycleCtx<T> cx{&d, &cb, st, nullptr};
+                post_chain<T>(cx, level, vin + n, vin + 2 * n, vin, vout, (T*)cb.u2[level], (T*)cb.u4[level], false,
+                              nullptr, nullptr);
+                break;
+            }
+            case MTOMG_OP_SMOOTH:
+                if (level == 0) return fail(c, MTOMG_BAD_INPUT, "no smoother on the coarsest level");
+                launch_post<T>(st, fine, false, false, opT, mat, L.sw_post, vin + n, nullptr, vin, vout, nullptr, nullptr, nullptr);
+                break;
+            case MTOMG_OP_COARSE_SOLVE:
+                if (level != 0) return fail(c, MTOMG_BAD_INPUT, "coarse solve is on level 0");
+                launch_coarse_solve<T>(st, d.Ainv, d.n0, L.nx, vin, vout, nullptr);
+                break;
+            case MTOMG_OP_VCYCLE:
+                if (level == 0) launch_coarse_solve<T>(st, d.Ainv, d.n0, L.nx, vin, vout, nullptr);
+                else {
+                    const int r2 = debug_vcycle<T>(c, d, cb, st, level, vin, vout);
+                    if (r2) return r2;
+                }
+                break;
+            default: return fail(c, MTOMG_BAD_INPUT, "unknown op");
+        }
+        return MTOMG_OK;
+    };
+    if (op == MTOMG_OP_APPLY64) {
+        if (!fine) return fail(c, MTOMG_BAD_INPUT, "APPLY64 is on the finest level");
+        launch_apply<double>(st, true, false, level_op<double>(d, level), make_mat<double>(d, d.omega), L.sw_apply,
+                             (const double*)in, (double*)out);
+        LAUNCHCHK(c);
+        return MTOMG_OK;
+    }
+    rc = d.mixed() ? run(float()) : run(double());
+    if (rc) return rc;
+    LAUNCHCHK(c);
+    return MTOMG_OK;
+}
+
+}  // extern "C"

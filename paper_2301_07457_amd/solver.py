@@ -1,0 +1,134 @@
+"""Torch-facing wrapper of the pCGMG library: device memory and stream only.
+
+``PCGMGSolver`` owns the torch tensors the C ABI works on (loads F,
+displacements U, the workspace) and forwards every call to libmtomg.so on
+the current torch stream.  ``ComplianceFn`` is the differentiable compliance
+c(x) of Eq. (6): forward = set_densities + solve + compliance_and_grad,
+backward = the adjoint gradient computed by the library (compliance is
+self-adjoint, so no second solve is needed).
+"""
+
+from __future__ import annotations
+
+from typing import Dict, List, Optional, Sequence
+
+import torch
+
+from . import _lib
+
+PRECISION = {"fp64": _lib.MTOMG_FP64, "fp32mg": _lib.MTOMG_FP32MG}
+
+
+def _stream_ptr(device) -> int:
+    return int(torch.cuda.current_stream(device).cuda_stream)
+
+
+class PCGMGSolver:
+    """One or more square-wall designs solved by the HIP pCGMG library.
+
+    Parameters mirror ``mtomg_set_grid``.  ``F`` is a CUDA float64 tensor
+    [n_cases, nely+1, nelx+1, 2].  Several designs are added with
+    ``add_design``; the constructor describes design 0.
+    """
+
+    def __init__(self, max_designs: int = 1, device="cuda:0"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("PCGMGSolver needs a ROCm GPU (no CPU fallback)")
+        self.device = torch.device(device)
+        with torch.cuda.device(self.device):
+            self.ctx = _lib.mtomg_create(max_designs, _stream_ptr(self.device))
+        self.designs: Dict[int, dict] = {}
+        self.workspace: Optional[torch.Tensor] = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "ctx", None) is not None:
+                _lib.mtomg_destroy(self.ctx)
+                self.ctx = None
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------
+    def add_design(self, design: int, nelx: int, nely: int, F: torch.Tensor, E_phase: Sequence[float],
+                   E_min: float = 1e-9, penal: float = 3.0, nu: float = 0.3, levels: int = 3,
+                   n_pre: int = 2, n_post: int = 2, omega: float = 0.6, precision: str = "fp64"):
+        F = F.to(self.device, torch.float64).contiguous()
+        if F.dim() == 3:
+            F = F.unsqueeze(0)
+        if tuple(F.shape[1:]) != (nely + 1, nelx + 1, 2):
+            raise ValueError(f"F must be [n_cases, {nely + 1}, {nelx + 1}, 2], got {tuple(F.shape)}")
+        U = torch.zeros_like(F)
+        _lib.mtomg_set_grid(self.ctx, design, nelx, nely, nu, list(E_phase), E_min, penal, levels,
+                            n_pre, n_post, omega, PRECISION[precision], F.shape[0], F.data_ptr(),
+                            U.data_ptr())
+        self.designs[design] = dict(nelx=nelx, nely=nely, F=F, U=U, m=len(E_phase), x=None,
+                                    precision=precision, levels=levels)
+        self.workspace = None
+        return self
+
+    def _ensure_workspace(self):
+        if self.workspace is None:
+            nb = _lib.mtomg_workspace_bytes(self.ctx)
+            self.workspace = torch.empty(nb, dtype=torch.uint8, device=self.device)
+            _lib.mtomg_set_workspace(self.ctx, self.workspace.data_ptr(), nb)
+            # set_workspace drops densities of every design: reload them
+            for d, info in self.designs.items():
+                if info["x"] is not None:
+                    _lib.mtomg_set_densities(self.ctx, d, info["x"].data_ptr())
+
+    def set_densities(self, design: int, x: torch.Tensor):
+        info = self.designs[design]
+        x = x.to(self.device, torch.float64).contiguous()
+        if tuple(x.shape) != (info["nely"], info["nelx"], info["m"]):
+            raise ValueError("x must be [nely, nelx, m]")
+        info["x"] = x
+        self._ensure_workspace()
+        _lib.mtomg_set_densities(self.ctx, design, x.data_ptr())
+
+    def solve(self, rel_tol: float = 1e-8, max_iter: int = 1000, warm_start: bool = False) -> List[dict]:
+        n = sum(info["F"].shape[0] for info in self.designs.values() if info["x"] is not None)
+        _, stats = _lib.mtomg_solve(self.ctx, rel_tol, max_iter, warm_start, n)
+        return stats
+
+    def compliance_and_grad(self, design: int, grad: bool = True):
+        info = self.designs[design]
+        c = torch.empty(info["F"].shape[0], dtype=torch.float64, device=self.device)
+        dc = None
+        if grad:
+            dc = torch.empty((info["F"].shape[0], info["nely"], info["nelx"], info["m"]),
+                             dtype=torch.float64, device=self.device)
+        _lib.mtomg_compliance_and_grad(self.ctx, design, c.data_ptr(), dc.data_ptr() if dc is not None else 0)
+        return c, dc
+
+    def U(self, design: int = 0) -> torch.Tensor:
+        return self.designs[design]["U"]
+
+    def debug_apply(self, design: int, level: int, op: str, inp: Optional[torch.Tensor],
+                    out_shape, dtype) -> torch.Tensor:
+        out = torch.empty(out_shape, dtype=dtype, device=self.device)
+        ptr = inp.contiguous().data_ptr() if inp is not None else 0
+        _lib.mtomg_debug_apply(self.ctx, design, level, _lib.OPS[op], ptr, out.data_ptr())
+        return out
+
+
+class ComplianceFn(torch.autograd.Function):
+    """c_k(x) for every load case of one design; gradient from the adjoint kernel."""
+
+    @staticmethod
+    def forward(ctx, x: torch.Tensor, solver: PCGMGSolver, design: int = 0, rel_tol: float = 1e-8,
+                max_iter: int = 1000):
+        solver.set_densities(design, x.detach())
+        stats = solver.solve(rel_tol, max_iter)
+        bad = [s for s in stats if s["status"] != 0]
+        if bad:
+            raise _lib.MtomgError(bad[0]["status"], f"solve failed: {bad[0]}")
+        c, dc = solver.compliance_and_grad(design, grad=True)
+        ctx.save_for_backward(dc)
+        ctx.stats = stats
+        return c
+
+    @staticmethod
+    def backward(ctx, grad_c: torch.Tensor):
+        (dc,) = ctx.saved_tensors
+        g = torch.einsum("k,kjim->jim", grad_c.to(dc.dtype), dc)
+        return g, None, None, None, None

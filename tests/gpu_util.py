@@ -1,0 +1,48 @@
+"""Helpers shared by the GPU parity tests: oracle operators in the nodal layout."""
+
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from oracle import fe, multigrid, solve
+
+
+def free_of(v: np.ndarray, nx: int) -> np.ndarray:
+    """Free-DOF vector (rows j >= 1) of a nodal array [ny+1][nx+1][2]."""
+    return np.ravel(v)[2 * (nx + 1):]
+
+
+def nodal_of(vf: np.ndarray, nx: int, ny: int) -> np.ndarray:
+    out = np.zeros((ny + 1) * (nx + 1) * 2)
+    out[2 * (nx + 1):] = vf
+    return out.reshape(ny + 1, nx + 1, 2)
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    d = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (d if d > 0 else 1.0)
+
+
+class OracleLevels:
+    """Oracle hierarchy of a design (levels[0] coarsest), all FP64."""
+
+    def __init__(self, nelx, nely, x, E_phase, E_min, penal, nu, levels):
+        E, K, Kff, free = solve.system(nelx, nely, x, E_phase, E_min, penal, nu)
+        self.H = multigrid.Hierarchy(nelx, nely, Kff, levels)
+        self.levels = levels
+
+    def dims(self, l):
+        L = self.H.levels[l]
+        return L.nelx, L.nely
+
+
+def gpu_solver(prob, precision="fp64", levels=None, n_pre=2, n_post=2):
+    from paper_2301_07457_amd import PCGMGSolver
+    s = PCGMGSolver(max_designs=1)
+    s.add_design(0, prob.nelx, prob.nely, torch.from_numpy(prob.F), list(prob.E_phase), prob.E_min,
+                 prob.penal, prob.nu, levels or prob.levels, n_pre, n_post, prob.omega, precision)
+    s.set_densities(0, torch.from_numpy(prob.x))
+    return s

@@ -1,0 +1,146 @@
+"""Operator-by-operator parity of the HIP hierarchy with the oracle (Sections 2.1-2.3).
+
+Every internal operator of every level is run through mtomg_debug_apply on
+random inputs and compared element by element with the oracle's explicit
+sparse operators: Galerkin K_l = P^T K P, its diagonal, damped Jacobi
+sweeps, P^T (b - K u), u + P e followed by post-smoothing, the coarsest
+Cholesky solve and one full V-cycle.  Grid sizes span several strips and
+row tiles with ragged tails (125 and 129 node columns against 62-column
+strips, odd coarsest sizes).
+FP64 bar: 1e-12 relative (2e-11 for the V-cycle and coarse solve, whose
+explicit inverse adds kappa * eps).  FP32 bar: 1e-5 relative.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import linalg, multigrid
+from tests.gpu_util import OracleLevels, free_of, gpu_solver, nodal_of, rel
+from workloads import Problem, load_top_traction
+
+pytestmark = pytest.mark.gpu
+
+GRIDS = [(128, 96, 3), (124, 60, 3), (64, 64, 4)]
+
+
+def make_prob(nx, ny, L, seed, contrast=False):
+    rng = np.random.default_rng(seed)
+    if contrast:
+        x = np.zeros((ny, nx, 3))
+        solid = rng.random((ny, nx)) < 0.6
+        solid[0] = solid[-1] = True
+        ph = rng.integers(0, 3, (ny, nx))
+        jj, ii = np.nonzero(solid)
+        x[jj, ii, ph[jj, ii]] = 1.0
+    else:
+        x = rng.uniform(0.05, 1.0, (ny, nx, 3)) / 3
+    return Problem("rand", nx, ny, x, np.array([1.0, 0.6, 0.2]), 1e-9, 3.0, 0.3,
+                   load_top_traction(nx, ny)[None], L)
+
+
+def rnd_nodal(rng, nx, ny):
+    v = rng.standard_normal((ny + 1, nx + 1, 2))
+    v[0] = 0.0
+    return v
+
+
+@pytest.fixture(scope="module", params=[(g, prec, c) for g in GRIDS for prec in ("fp64", "fp32mg")
+                                        for c in (False, True)],
+                ids=lambda p: f"{p[0][0]}x{p[0][1]}L{p[0][2]}-{p[1]}-{'contrast' if p[2] else 'smooth'}")
+def setup(request):
+    (nx, ny, L), prec, contrast = request.param
+    prob = make_prob(nx, ny, L, nx + ny + L, contrast)
+    print(f"[component setup] {nx}x{ny} L={L} {prec} contrast={contrast}", flush=True)
+    s = gpu_solver(prob, prec)
+    o = OracleLevels(nx, ny, prob.x, prob.E_phase, prob.E_min, prob.penal, prob.nu, L)
+    return prob, prec, s, o
+
+
+def tol(prec, fp64=1e-12):
+    return fp64 if prec == "fp64" else 1e-5
+
+
+def run(s, prec, level, op, inp, shape):
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    t = None if inp is None else torch.from_numpy(np.concatenate([np.ravel(a) for a in inp])).to("cuda", dt)
+    out = s.debug_apply(0, level, op, t, shape, dt)
+    torch.cuda.synchronize()
+    return out.double().cpu().numpy()
+
+
+def test_apply_and_diag_every_level(setup):
+    prob, prec, s, o = setup
+    rng = np.random.default_rng(1)
+    for l in range(o.levels):
+        nx, ny = o.dims(l)
+        K = o.H.levels[l].K
+        u = rnd_nodal(rng, nx, ny)
+        q = run(s, prec, l, "APPLY", [u], (ny + 1, nx + 1, 2))
+        assert np.all(q[0] == 0)
+        assert rel(free_of(q, nx), K @ free_of(u, nx)) < tol(prec), f"level {l}"
+        d = run(s, prec, l, "DIAG", None, (ny + 1, nx + 1, 2))
+        assert rel(free_of(d, nx), K.diagonal()) < tol(prec), f"level {l}"
+
+
+def test_fp64_outer_apply(setup):
+    prob, prec, s, o = setup
+    rng = np.random.default_rng(2)
+    l = o.levels - 1
+    nx, ny = o.dims(l)
+    u = rnd_nodal(rng, nx, ny)
+    t = torch.from_numpy(u).cuda()
+    q = s.debug_apply(0, l, "APPLY64", t, (ny + 1, nx + 1, 2), torch.float64).cpu().numpy()
+    assert rel(free_of(q, nx), o.H.levels[l].K @ free_of(u, nx)) < 1e-13
+
+
+def test_smoothers(setup):
+    prob, prec, s, o = setup
+    rng = np.random.default_rng(3)
+    for l in range(1, o.levels):
+        nx, ny = o.dims(l)
+        lev = o.H.levels[l]
+        b = rnd_nodal(rng, nx, ny)
+        u = rnd_nodal(rng, nx, ny)
+        want = linalg.damped_jacobi(lev.K, free_of(b, nx), np.zeros(lev.K.shape[0]), prob.omega, prob.n_pre)
+        got = run(s, prec, l, "PRESMOOTH", [b], (ny + 1, nx + 1, 2))
+        assert rel(free_of(got, nx), want) < tol(prec), f"presmooth level {l}"
+        want = linalg.damped_jacobi(lev.K, free_of(b, nx), free_of(u, nx), prob.omega, 1)
+        got = run(s, prec, l, "SMOOTH", [b, u], (ny + 1, nx + 1, 2))
+        assert rel(free_of(got, nx), want) < tol(prec), f"smooth level {l}"
+
+
+def test_transfers(setup):
+    prob, prec, s, o = setup
+    rng = np.random.default_rng(4)
+    for l in range(1, o.levels):
+        nx, ny = o.dims(l)
+        cx, cy = o.dims(l - 1)
+        lev = o.H.levels[l]
+        b = rnd_nodal(rng, nx, ny)
+        u = rnd_nodal(rng, nx, ny)
+        want = lev.P.T @ (free_of(b, nx) - lev.K @ free_of(u, nx))
+        got = run(s, prec, l, "RESIDUAL_RESTRICT", [b, u], (cy + 1, cx + 1, 2))
+        assert np.all(got[0] == 0)
+        assert rel(free_of(got, cx), want) < tol(prec), f"restrict level {l}"
+        ec = rnd_nodal(rng, cx, cy)
+        v = free_of(u, nx) + lev.P @ free_of(ec, cx)
+        want = linalg.damped_jacobi(lev.K, free_of(b, nx), v, prob.omega, prob.n_post)
+        got = run(s, prec, l, "PROLONG_POSTSMOOTH", [b, u, ec], (ny + 1, nx + 1, 2))
+        assert rel(free_of(got, nx), want) < tol(prec), f"prolong level {l}"
+
+
+def test_coarse_solve_and_vcycle(setup):
+    prob, prec, s, o = setup
+    rng = np.random.default_rng(5)
+    nx, ny = o.dims(0)
+    b = rnd_nodal(rng, nx, ny)
+    want = linalg.cholesky_solve(o.H.levels[0].chol, free_of(b, nx))
+    got = run(s, prec, 0, "COARSE_SOLVE", [b], (ny + 1, nx + 1, 2))
+    assert rel(free_of(got, nx), want) < tol(prec, 2e-11)
+    for l in range(1, o.levels):
+        nx, ny = o.dims(l)
+        b = rnd_nodal(rng, nx, ny)
+        want = multigrid.cycle(o.H, l, free_of(b, nx), None, prob.omega, prob.n_pre, prob.n_post)
+        got = run(s, prec, l, "VCYCLE", [b], (ny + 1, nx + 1, 2))
+        assert rel(free_of(got, nx), want) < tol(prec, 2e-11), f"vcycle level {l}"

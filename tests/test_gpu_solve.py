@@ -1,0 +1,145 @@
+"""End-to-end parity of the HIP pCGMG solve with the oracle (Algorithm 2 + Algorithm 1).
+
+The bar (FP64 CG in both precisions): true relative residual <= 1e-8 and
+||u - u_oracle|| / ||u_oracle|| <= 1e-6; compliance to 1e-7 relative and
+the gradient to 1e-5 relative against the oracle's direct solve.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import fe, solve
+from tests.gpu_util import gpu_solver, rel
+from workloads import Problem, load_top_traction, make_problem
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle_direct(p):
+    return solve.solve_direct(p.nelx, p.nely, p.x, p.E_phase, p.E_min, p.penal, p.nu, p.F)
+
+
+def rand_prob(nx, ny, L, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0.05, 1.0, (ny, nx, 3)) / 3
+    return Problem("rand", nx, ny, x, np.array([1.0, 0.6, 0.2]), 1e-9, 3.0, 0.3,
+                   load_top_traction(nx, ny)[None], L)
+
+
+CASES = [("wall64", "fp64"), ("wall64", "fp32mg"), ("rand124x60", "fp64"), ("rand124x60", "fp32mg"),
+         ("rand256x128", "fp32mg")]
+
+
+def get_prob(name):
+    if name == "wall64":
+        return make_problem("wall64")
+    if name == "rand124x60":
+        return rand_prob(124, 60, 3, 7)
+    if name == "rand256x128":
+        return rand_prob(256, 128, 4, 8)
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name,prec", CASES)
+def test_solve_matches_oracle(name, prec):
+    p = get_prob(name)
+    print(f"[solve] {name} {prec}", flush=True)
+    ref = oracle_direct(p)
+    s = gpu_solver(p, prec)
+    st = s.solve(1e-8, 1000)[0]
+    assert st["status"] == 0, st
+    assert st["relres_true"] <= 1e-8 * 1.05, st
+    U = s.U(0).cpu().numpy()
+    assert rel(U, ref.U) <= 1e-6
+    c, dc = s.compliance_and_grad(0)
+    c = c.cpu().numpy()
+    dc = dc.cpu().numpy()
+    np.testing.assert_allclose(c, ref.c, rtol=1e-7)
+    assert rel(dc, ref.dcdx) <= 1e-5
+    # the oracle's own energy identity on the GPU displacements
+    E = fe.interpolate_modulus(p.x, p.E_phase, p.E_min, p.penal)
+    energy = np.sum(E * fe.element_energies(U[0], p.nelx, p.nely, p.nu))
+    assert c[0] == pytest.approx(energy, rel=1e-7)
+
+
+def test_iteration_count_matches_oracle_pcgmg():
+    p = make_problem("wall64")
+    o = solve.solve_mgpcg(p.nelx, p.nely, p.x, p.E_phase, p.E_min, p.penal, p.nu, p.F, p.levels,
+                          rel_tol=1e-8, grad=False)
+    s = gpu_solver(p, "fp64")
+    st = s.solve(1e-8, 1000)[0]
+    assert abs(st["iters"] - o.iters[0]) <= 1, (st, o.iters)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32mg"])
+def test_deterministic(prec):
+    p = rand_prob(124, 60, 3, 9)
+    s = gpu_solver(p, prec)
+    s.solve(1e-8, 1000)
+    a = s.U(0).clone()
+    s.solve(1e-8, 1000)
+    assert torch.equal(a, s.U(0))
+
+
+def test_warm_start_and_status_paths():
+    p = rand_prob(64, 64, 3, 10)
+    s = gpu_solver(p, "fp64")
+    st = s.solve(1e-8, 1000)[0]
+    assert st["status"] == 0
+    st2 = s.solve(1e-8, 1000, warm_start=True)[0]
+    assert st2["status"] == 0 and st2["iters"] <= 1
+    st3 = s.solve(1e-8, 1)[0]
+    assert st3["status"] == -2 and st3["iters"] == 1
+    assert st3["relres_true"] > 1e-8
+    st4 = s.solve(1e-8, 0)[0]
+    assert st4["status"] == -2 and st4["iters"] == 0
+    assert torch.count_nonzero(s.U(0)) == 0
+
+
+def test_zero_load_gives_zero_displacement():
+    p = rand_prob(32, 32, 2, 11)
+    p.F[:] = 0.0
+    s = gpu_solver(p, "fp64")
+    st = s.solve(1e-8, 100)[0]
+    assert st["status"] == 0 and st["iters"] == 0
+    assert torch.count_nonzero(s.U(0)) == 0
+
+
+def test_multiple_load_cases():
+    from workloads.square_wall import four_load_cases
+    p = rand_prob(64, 32, 3, 12)
+    p.F = four_load_cases(64, 32)
+    ref = oracle_direct(p)
+    s = gpu_solver(p, "fp32mg")
+    stats = s.solve(1e-8, 1000)
+    assert all(st["status"] == 0 and st["relres_true"] <= 1.05e-8 for st in stats)
+    assert rel(s.U(0).cpu().numpy(), ref.U) <= 1e-6
+    c, dc = s.compliance_and_grad(0)
+    np.testing.assert_allclose(c.cpu().numpy(), ref.c, rtol=1e-7)
+    assert rel(dc.cpu().numpy(), ref.dcdx) <= 1e-5
+
+
+def test_bad_inputs_are_rejected():
+    from paper_2301_07457_amd import PCGMGSolver
+    from paper_2301_07457_amd._lib import MtomgError
+    s = PCGMGSolver()
+    F = torch.zeros((1, 33, 33, 2), dtype=torch.float64)
+    with pytest.raises(MtomgError):
+        s.add_design(0, 32, 32, F, [1.0], levels=7)       # 32 not divisible by 64
+    with pytest.raises(MtomgError):
+        s.add_design(0, 32, 32, F, [1.0], E_min=0.0)      # E_min must be > 0
+    with pytest.raises(MtomgError):
+        s.add_design(0, 256, 256, torch.zeros((1, 257, 257, 2)), [1.0], levels=2)  # coarsest too big
+
+
+def test_autograd_function_matches_oracle_gradient():
+    from paper_2301_07457_amd import ComplianceFn
+    p = rand_prob(64, 64, 3, 13)
+    ref = oracle_direct(p)
+    s = gpu_solver(p, "fp64")
+    x = torch.from_numpy(p.x).cuda().requires_grad_(True)
+    c = ComplianceFn.apply(x, s, 0, 1e-10, 1000)
+    c.sum().backward()
+    assert c.item() == pytest.approx(ref.c[0], rel=1e-9)
+    assert rel(x.grad.cpu().numpy(), ref.dcdx[0]) <= 1e-6
