@@ -141,6 +141,42 @@ const char *mtomg_status_string(int status);
 /* Message of the last failure on this context ("" if none). */
 const char *mtomg_last_error(const mtomg_ctx *ctx);
 
+/* Options of a context.
+ *   MTOMG_OPT_GRAPHS (default 1): replay the PCG iteration body from a
+ *     captured HIP graph (two iterations per replay) instead of launching
+ *     its kernels one by one; results are identical either way.
+ *   MTOMG_OPT_BATCH (default 8, 1..1000): iterations launched before the
+ *     host first reads the convergence state; later solves start from the
+ *     previous iteration count instead.  Setting it clears that history.
+ *   MTOMG_OPT_ROWS_FINE / MTOMG_OPT_ROWS_COARSE (default 0 = automatic;
+ *     1, 2, 4 or 8): node rows each wave marches through in the sweeps of
+ *     the finest grid / of the coarse grids (a tuning knob).  Changing it
+ *     re-plans every design: a workspace given with set_workspace must be
+ *     given again (the size may change) and densities set again. */
+enum { MTOMG_OPT_GRAPHS = 0, MTOMG_OPT_BATCH = 1, MTOMG_OPT_ROWS_FINE = 2, MTOMG_OPT_ROWS_COARSE = 3 };
+int mtomg_set_option(mtomg_ctx *ctx, int option, int value);
+
+/* Profiling: bracket every launch of one solver kernel with HIP events on
+ * the solve stream during the following solves, so its device time can be
+ * read back (two event records per launch; kernel = MTOMG_KERNEL_NONE
+ * switches it off).  At most 4096 launches are timed between reads.
+ * mtomg_profile_read synchronises the stream, writes the duration in ms of
+ * each timed launch since the last read, in launch order, to ms[0..cap-1]
+ * (host) and their count to *launches (host), then starts a new record.
+ * Launches that found the solve already converged exit at once and show as
+ * near-zero durations. */
+enum {
+    MTOMG_KERNEL_NONE = 0,
+    MTOMG_KERNEL_CG_APPLY = 1,        /* FP64 p update + K p + p.q (outer CG)      */
+    MTOMG_KERNEL_FINE_PRESMOOTH = 2,  /* r update + two Jacobi sweeps, finest grid */
+    MTOMG_KERNEL_FINE_RESTRICT = 3,   /* residual + restriction, finest grid       */
+    MTOMG_KERNEL_FINE_POST = 4,       /* prolongation + Jacobi sweep, finest grid  */
+    MTOMG_KERNEL_FINE_POST_DOT = 5,   /* last Jacobi sweep + z.r, finest grid      */
+    MTOMG_KERNEL_COARSE_SOLVE = 6     /* explicit-inverse coarsest solve           */
+};
+int mtomg_profile_kernel(mtomg_ctx *ctx, int kernel);
+int mtomg_profile_read(mtomg_ctx *ctx, double *ms, int cap, int *launches);
+
 /* Test hook: run one internal operator of level `level` (0 = coarsest,
  * levels-1 = finest) of a design whose densities are set.  Vectors are
  * nodal arrays of that level ([ny_l+1][nx_l+1][2]) in the multigrid

@@ -30,7 +30,13 @@ OPS = dict(APPLY=0, APPLY64=1, DIAG=2, PRESMOOTH=3, RESIDUAL_RESTRICT=4, PROLONG
 EXPORTS = ["mtomg_create", "mtomg_destroy", "mtomg_set_grid", "mtomg_workspace_bytes",
            "mtomg_set_workspace", "mtomg_set_densities", "mtomg_solve",
            "mtomg_compliance_and_grad", "mtomg_status_string", "mtomg_last_error",
-           "mtomg_debug_apply"]
+           "mtomg_debug_apply", "mtomg_profile_kernel", "mtomg_profile_read",
+           "mtomg_set_option"]
+
+OPTIONS = dict(GRAPHS=0, BATCH=1, ROWS_FINE=2, ROWS_COARSE=3)
+
+KERNELS = dict(NONE=0, CG_APPLY=1, FINE_PRESMOOTH=2, FINE_RESTRICT=3, FINE_POST=4, FINE_POST_DOT=5,
+               COARSE_SOLVE=6)
 
 
 class mtomg_stats(ctypes.Structure):
@@ -84,6 +90,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mtomg_last_error.argtypes = [vp]
     lib.mtomg_last_error.restype = ctypes.c_char_p
     lib.mtomg_debug_apply.argtypes = [vp, i, i, i, dp, dp]
+    lib.mtomg_profile_kernel.argtypes = [vp, i]
+    lib.mtomg_set_option.argtypes = [vp, i, i]
+    lib.mtomg_profile_read.argtypes = [vp, ctypes.POINTER(d), i, ctypes.POINTER(i)]
     for name in EXPORTS:
         if name not in ("mtomg_workspace_bytes", "mtomg_status_string", "mtomg_last_error"):
             getattr(lib, name).restype = i
@@ -158,3 +167,19 @@ def mtomg_last_error(ctx) -> str:
 def mtomg_debug_apply(ctx, design, level, op, in_ptr, out_ptr):
     return check(ctx, load().mtomg_debug_apply(ctx, design, level, op, ctypes.c_void_p(in_ptr or None),
                                                ctypes.c_void_p(out_ptr)))
+
+
+def mtomg_profile_kernel(ctx, kernel: str):
+    return check(ctx, load().mtomg_profile_kernel(ctx, KERNELS[kernel]))
+
+
+def mtomg_profile_read(ctx, cap: int = 4096):
+    """Per-launch durations (ms) of the profiled kernel since the last read."""
+    buf = (ctypes.c_double * cap)()
+    n = ctypes.c_int(0)
+    check(ctx, load().mtomg_profile_read(ctx, buf, cap, ctypes.byref(n)))
+    return [buf[k] for k in range(min(n.value, cap))]
+
+
+def mtomg_set_option(ctx, option: str, value: int):
+    return check(ctx, load().mtomg_set_option(ctx, OPTIONS[option], int(value)))

@@ -47,6 +47,9 @@ struct CaseBufs {
     double *zr[2] = {nullptr, nullptr}, *pq[2] = {nullptr, nullptr}, *rr[2] = {nullptr, nullptr};
     double *ff = nullptr, *trr = nullptr, *sums = nullptr, *cpart = nullptr;
     int* state = nullptr;   // [0] conv, [1] iters
+    hipGraphExec_t pair_exec = nullptr;   // two PCG iterations (parities 1, 0), captured
+    double pair_tol2 = -1.0;
+    int last_iters = 0;                   // iterations of the previous solve (batch hint)
 };
 
 struct Design {
@@ -57,8 +60,8 @@ struct Design {
     const double* F = nullptr;
     double* U = nullptr;
     std::vector<LevelBufs> lev;   // 0 = coarsest
-    int n0 = 0;
-    double *A0 = nullptr, *W0 = nullptr, *Ainv = nullptr;
+    int n0 = 0, np0 = 0;   // coarsest free DOFs, padded to the block size
+    double *A0 = nullptr, *W0 = nullptr, *Ainv = nullptr, *Dinv = nullptr;
     int* chol_status = nullptr;
     std::vector<CaseBufs> cases;
     const double* x_dev = nullptr;
@@ -68,9 +71,26 @@ struct Design {
     bool mixed() const { return precision == MTOMG_FP32MG; }
 };
 
+// Event brackets around the launches of one kernel (profiling hook).
+struct Prof {
+    int kernel = 0;
+    std::vector<hipEvent_t> ev;
+    int used = 0;
+    void begin(int id, hipStream_t st) {
+        if (id != kernel || used + 2 > (int)ev.size()) return;
+        hipEventRecord(ev[used], st);
+    }
+    void end(int id, hipStream_t st) {
+        if (id != kernel || used + 2 > (int)ev.size()) return;
+        hipEventRecord(ev[used + 1], st);
+        used += 2;
+    }
+};
+
 }  // namespace
 
 struct mtomg_ctx {
+    Prof prof;
     hipStream_t stream = nullptr;
     int device = 0;
     std::vector<Design> d;
@@ -81,7 +101,10 @@ struct mtomg_ctx {
     std::string err;
     int* host_state = nullptr;    // pinned
     double* host_sums = nullptr;  // pinned
-    int batch = 8;
+    int batch = 8;                // iterations between host checks (first solve)
+    bool use_graphs = true;
+    int rows_fine = 0, rows_coarse = 0;   // rows per wave overrides (0 = automatic)
+    hipStream_t cap_stream = nullptr;  // capture stream (default priority)
 };
 
 namespace {
@@ -89,6 +112,16 @@ namespace {
 int fail(mtomg_ctx* c, int code, const std::string& msg) {
     if (c) c->err = msg;
     return code;
+}
+
+void drop_graphs(mtomg_ctx* c) {
+    for (Design& d : c->d)
+        for (CaseBufs& cb : d.cases)
+            if (cb.pair_exec) {
+                hipGraphExecDestroy(cb.pair_exec);
+                cb.pair_exec = nullptr;
+                cb.pair_tol2 = -1.0;
+            }
 }
 
 #define HIPCHK(ctx, call)                                                                   \
@@ -109,9 +142,10 @@ int fail(mtomg_ctx* c, int code, const std::string& msg) {
 // launch geometry
 // ----------------------------------------------------------------------------
 int pick_rows(int strips, int rows_total) {
-    // enough waves to fill 256 CUs a few times over, at least 4 rows per wave
-    int R = 32;
-    while (R > 4 && (long)strips * ((rows_total + R - 1) / R) < 4096) R >>= 1;
+    // rows per wave in {1, 2, 4, 8}: the largest that still gives enough
+    // waves to fill 256 CUs a few times over
+    int R = 8;
+    while (R > 1 && (long)strips * ((rows_total + R - 1) / R) < 4096) R >>= 1;
     return R;
 }
 
@@ -124,13 +158,15 @@ Sweep make_sweep(int cols, int wout, int rows_total, int R = 0) {
     return s;
 }
 
-void plan_level(LevelBufs& L) {
-    L.sw_apply = make_sweep(L.nx + 1, 62, L.ny + 1);
+void plan_level(LevelBufs& L, int R = 0) {
+    L.sw_apply = make_sweep(L.nx + 1, 62, L.ny + 1, R);
     L.sw_post = L.sw_apply;
-    L.sw_pre = make_sweep(L.nx + 1, 61, L.ny + 1);
+    L.sw_pre = make_sweep(L.nx + 1, 61, L.ny + 1, R);
     if (L.nx % 2 == 0 && L.ny % 2 == 0)
-        L.sw_res = make_sweep(L.nx / 2 + 1, 30, L.ny / 2 + 1);
+        L.sw_res = make_sweep(L.nx / 2 + 1, 30, L.ny / 2 + 1, R);
 }
+
+
 
 // ----------------------------------------------------------------------------
 // workspace layout (bump allocation; a null base only measures)
@@ -156,9 +192,10 @@ void layout_design(Design& d, Bump& B) {
         L.op64 = B.take<double>(fine ? ne : 6 * ne);
         L.op32 = mx ? B.take<float>(fine ? ne : 6 * ne) : nullptr;
     }
-    d.A0 = B.take<double>((size_t)d.n0 * d.n0);
-    d.W0 = B.take<double>((size_t)d.n0 * d.n0);
-    d.Ainv = B.take<double>((size_t)d.n0 * d.n0);
+    d.A0 = B.take<double>((size_t)d.np0 * d.np0);
+    d.W0 = B.take<double>((size_t)d.np0 * d.np0);
+    d.Ainv = B.take<double>((size_t)d.np0 * d.np0);
+    d.Dinv = B.take<double>((size_t)d.np0 * COARSE_NB);
     d.chol_status = B.take<int>(4);
     const LevelBufs& Lf = d.lev[d.fine()];
     const size_t nf = Lf.nodes() * 2;
@@ -250,6 +287,9 @@ template <typename T> struct CycleCtx {
     CaseBufs* c;
     hipStream_t st;
     const int* conv;   // nullable (debug use)
+    Prof* prof = nullptr;
+    void begin(int id) { if (prof) prof->begin(id, st); }
+    void end(int id) { if (prof) prof->end(id, st); }
 };
 
 // n sweeps of the post-smoother chain; returns the buffer holding the result
@@ -268,8 +308,11 @@ void post_chain(CycleCtx<T>& cx, int l, const T* u_cur, const T* ec, const T* b,
     const T* in = u_cur;
     for (int k = 1; k <= n; ++k) {
         T* dst = (k == n) ? out : ((in == t0) ? t1 : t0);
+        const int pid = !fine ? 0 : (k == n ? MTOMG_KERNEL_FINE_POST_DOT : MTOMG_KERNEL_FINE_POST);
+        cx.begin(pid);
         launch_post<T>(cx.st, fine, k == 1, dot && k == n, op, make_mat<T>(d, d.omega), L.sw_post, in,
                        k == 1 ? ec : nullptr, b, dst, r64, zr_out, cx.conv);
+        cx.end(pid);
         in = dst;
     }
 }
@@ -289,13 +332,16 @@ T* pre_chain_extra(CycleCtx<T>& cx, int l, T* cur, const T* b, T* t0, T* t1) {
 }
 
 // Levels l-1 .. 0 of Algorithm 1 given the restricted right-hand side in
-// c.b[l-1]; leaves the coarse correction in c.e[l-1].
+// c.b[top]; leaves the coarse correction in c.e[top].  The pre-smoothed
+// iterate of each level stays in u2 or u4 (which one depends on the number
+// of sweeps only), so a captured launch sequence is the same every time.
 template <typename T>
 void coarse_cycle(CycleCtx<T>& cx, int top) {
     Design& d = *cx.d;
     CaseBufs& c = *cx.c;
     ConvCheck nochk{};
     CgRhs nocg{};
+    T* pre[16] = {};
     for (int l = top; l >= 1; --l) {
         T* b = (T*)c.b[l];
         T* t0 = (T*)c.u2[l];
@@ -308,15 +354,15 @@ void coarse_cycle(CycleCtx<T>& cx, int top) {
         }
         launch_restrict<T>(cx.st, false, false, level_op<T>(d, l), make_mat<T>(d, d.omega), d.lev[l].sw_res, b,
                            d.n_pre > 0 ? cur : nullptr, (T*)c.b[l - 1], nochk, cx.conv);
-        // remember which buffer holds the pre-smoothed iterate
-        if (cur != t0) std::swap(c.u2[l], c.u4[l]);
+        pre[l] = cur;
     }
-    launch_coarse_solve<T>(cx.st, d.Ainv, d.n0, d.lev[0].nx, (const T*)c.b[0], (T*)c.e[0], cx.conv);
+    cx.begin(MTOMG_KERNEL_COARSE_SOLVE);
+    launch_coarse_solve<T>(cx.st, d.Ainv, d.n0, d.np0, d.lev[0].nx, (const T*)c.b[0], (T*)c.e[0], cx.conv);
+    cx.end(MTOMG_KERNEL_COARSE_SOLVE);
     for (int l = 1; l <= top; ++l) {
-        T* t0 = (T*)c.u2[l];
-        T* t1 = (T*)c.u4[l];
-        post_chain<T>(cx, l, d.n_pre > 0 ? t0 : nullptr, (const T*)c.e[l - 1], (const T*)c.b[l], (T*)c.e[l], t1,
-                      t0, false, nullptr, nullptr);
+        T* other = pre[l] == (T*)c.u2[l] ? (T*)c.u4[l] : (T*)c.u2[l];
+        post_chain<T>(cx, l, d.n_pre > 0 ? pre[l] : nullptr, (const T*)c.e[l - 1], (const T*)c.b[l], (T*)c.e[l],
+                      other, pre[l], false, nullptr, nullptr);
     }
 }
 
@@ -347,8 +393,10 @@ void fine_cycle(CycleCtx<T>& cx, int it, double tol2) {
     T* t0 = (T*)c.u2[f];
     T* t1 = (T*)c.u4[f];
     const T* bfine = d.mixed() ? (const T*)(void*)c.r32 : (const T*)(void*)c.r[nxt];
+    cx.begin(MTOMG_KERNEL_FINE_PRESMOOTH);
     launch_presmooth<T>(cx.st, true, true, level_op<T>(d, f), make_mat<T>(d, d.omega), L.sw_pre, nullptr, t0,
                         std::min(d.n_pre, 2), cg, cx.conv);
+    cx.end(MTOMG_KERNEL_FINE_PRESMOOTH);
     T* cur = pre_chain_extra<T>(cx, f, t0, bfine, t0, t1);
     ConvCheck chk{};
     chk.rr = c.rr[nxt];
@@ -357,21 +405,24 @@ void fine_cycle(CycleCtx<T>& cx, int it, double tol2) {
     chk.n_ff = L.sw_apply.n_tiles;
     chk.tol2 = tol2;
     chk.conv_rw = c.state;
+    cx.begin(MTOMG_KERNEL_FINE_RESTRICT);
     launch_restrict<T>(cx.st, true, true, level_op<T>(d, f), make_mat<T>(d, d.omega), L.sw_res, bfine,
                        d.n_pre > 0 ? cur : nullptr, (T*)c.b[f - 1], chk, cx.conv);
-    if (cur != t0) std::swap(c.u2[f], c.u4[f]);
+    cx.end(MTOMG_KERNEL_FINE_RESTRICT);
     coarse_cycle<T>(cx, f - 1);
-    post_chain<T>(cx, f, d.n_pre > 0 ? (T*)c.u2[f] : nullptr, (const T*)c.e[f - 1], bfine, (T*)c.z,
-                  (T*)c.u4[f], (T*)c.u2[f], true, c.r[nxt], c.zr[it < 0 ? 0 : nxt]);
+    post_chain<T>(cx, f, d.n_pre > 0 ? cur : nullptr, (const T*)c.e[f - 1], bfine, (T*)c.z, cur == t0 ? t1 : t0,
+                  cur, true, c.r[nxt], c.zr[it < 0 ? 0 : nxt]);
 }
 
 template <typename T>
-void cg_step(Design& d, CaseBufs& c, hipStream_t st, int it, int mode) {
+void cg_step(Design& d, CaseBufs& c, hipStream_t st, int it, int mode, Prof* prof = nullptr) {
     const LevelBufs& L = d.lev[d.fine()];
     const int par = it & 1, prv = 1 - par;
+    if (prof) prof->begin(MTOMG_KERNEL_CG_APPLY, st);
     launch_cg_apply<T>(st, level_op<double>(d, d.fine()), make_mat<double>(d, d.omega), L.sw_apply,
                        (const T*)c.z, c.p[prv], c.p[par], c.U, c.q, c.zr[par], c.zr[prv], L.sw_post.n_tiles,
                        c.pq[prv], L.sw_apply.n_tiles, c.pq[par], c.state, mode);
+    if (prof) prof->end(MTOMG_KERNEL_CG_APPLY, st);
 }
 
 }  // namespace
@@ -402,10 +453,9 @@ int debug_vcycle(mtomg_ctx* ctx, Design& d, CaseBufs& cb, hipStream_t st, int le
     }
     launch_restrict<T>(st, fine, false, opT, mat, d.lev[level].sw_res, bl, d.n_pre > 0 ? cur : nullptr,
                        (T*)cb.b[level - 1], nochk, nullptr);
-    if (cur != t0) std::swap(cb.u2[level], cb.u4[level]);
     coarse_cycle<T>(cx, level - 1);
-    post_chain<T>(cx, level, d.n_pre > 0 ? (T*)cb.u2[level] : nullptr, (const T*)cb.e[level - 1], bl, vout,
-                  (T*)cb.u4[level], (T*)cb.u2[level], false, nullptr, nullptr);
+    post_chain<T>(cx, level, d.n_pre > 0 ? cur : nullptr, (const T*)cb.e[level - 1], bl, vout, cur == t0 ? t1 : t0,
+                  cur, false, nullptr, nullptr);
     return MTOMG_OK;
 }
 
@@ -417,6 +467,33 @@ int check_design(mtomg_ctx* c, int design, bool need_dens) {
     return MTOMG_OK;
 }
 
+// Capture iterations 1 and 2 (parities 1, 0) of the PCG loop into a graph;
+// replaying it runs any later pair of iterations.
+template <typename T>
+int capture_pair(mtomg_ctx* ctx, Design& d, CaseBufs& c, double tol2) {
+    if (c.pair_exec) {
+        HIPCHK(ctx, hipGraphExecDestroy(c.pair_exec));
+        c.pair_exec = nullptr;
+    }
+    hipStream_t cs = ctx->cap_stream;
+    HIPCHK(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    CycleCtx<T> cx{&d, &c, cs, c.state, nullptr};
+    for (int k = 1; k <= 2; ++k) {
+        cg_step<T>(d, c, cs, k, 0, nullptr);
+        fine_cycle<T>(cx, k, tol2);
+    }
+    hipGraph_t g = nullptr;
+    HIPCHK(ctx, hipStreamEndCapture(cs, &g));
+    const hipError_t e = hipGraphInstantiate(&c.pair_exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        c.pair_exec = nullptr;
+        return fail(ctx, MTOMG_HIP_ERROR, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    c.pair_tol2 = tol2;
+    return MTOMG_OK;
+}
+
 template <typename T>
 int solve_case(mtomg_ctx* ctx, Design& d, CaseBufs& c, double rel_tol, int max_iter, int warm, mtomg_stats* out) {
     hipStream_t st = ctx->stream;
@@ -424,29 +501,48 @@ int solve_case(mtomg_ctx* ctx, Design& d, CaseBufs& c, double rel_tol, int max_i
     const LevelOp<double> op64 = level_op<double>(d, d.fine());
     const Mat<double> mat64 = make_mat<double>(d, d.omega);
     const double tol2 = rel_tol * rel_tol;
+    const bool graphs = ctx->use_graphs && ctx->prof.kernel == MTOMG_KERNEL_NONE;
     HIPCHK(ctx, hipEventRecord(d.ev[0], st));
     launch_fill<int>(st, c.state, 4, 0);
     launch_residual(st, op64, mat64, L.sw_apply, c.F, c.U, warm ? 1 : 0, c.r[0], c.rr[0], c.ff);
-    CycleCtx<T> cx{&d, &c, st, c.state};
+    CycleCtx<T> cx{&d, &c, st, c.state, &ctx->prof};
     fine_cycle<T>(cx, -1, tol2);
     LAUNCHCHK(ctx);
-    int it = 0;
-    int done = 0;
-    int batch = std::max(2, ctx->batch);
-    while (it < max_iter) {
-        const int nb = std::min(batch, max_iter - it);
-        for (int k = 0; k < nb; ++k) {
-            cg_step<T>(d, c, st, it + k, (it + k == 0) ? 1 : 0);
-            fine_cycle<T>(cx, it + k, tol2);
+    // iterations [from, from + count): pairs starting at an odd index replay the graph
+    auto launch_iters = [&](int from, int count) -> int {
+        int k = from;
+        const int end = from + count;
+        while (k < end) {
+            if (graphs && (k & 1) && end - k >= 2) {
+                if (!c.pair_exec || c.pair_tol2 != tol2) {
+                    const int rc = capture_pair<T>(ctx, d, c, tol2);
+                    if (rc) return rc;
+                }
+                HIPCHK(ctx, hipGraphLaunch(c.pair_exec, st));
+                k += 2;
+            } else {
+                cg_step<T>(d, c, st, k, k == 0 ? 1 : 0, &ctx->prof);
+                fine_cycle<T>(cx, k, tol2);
+                ++k;
+            }
         }
         LAUNCHCHK(ctx);
+        return MTOMG_OK;
+    };
+    int it = 0;
+    int done = 0;
+    // first batch: the previous solve's count (a design loop changes slowly), then small steps
+    int batch = c.last_iters > 0 ? c.last_iters + 1 : std::max(2, ctx->batch);
+    while (it < max_iter) {
+        const int nb = std::min(batch, max_iter - it);
+        const int rc = launch_iters(it, nb);
+        if (rc) return rc;
         it += nb;
         HIPCHK(ctx, hipMemcpyAsync(ctx->host_state, c.state, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(ctx, hipStreamSynchronize(st));
         done = ctx->host_state[0];
         if (done != 0) break;
-        // next batch: a few more than the iterations done so far
-        batch = std::max(2, std::min(it, 16));
+        batch = std::max(2, std::min(it / 2, 16));
     }
     if (done == 0 && max_iter > 0) {
         // pending x update of the last iteration
@@ -477,6 +573,7 @@ int solve_case(mtomg_ctx* ctx, Design& d, CaseBufs& c, double rel_tol, int max_i
     out->status = (cv == 1 || cv == 2) ? MTOMG_OK : cv == 3 ? MTOMG_BREAKDOWN : cv == 4 ? MTOMG_NAN : MTOMG_NOT_CONVERGED;
     out->iters = ctx->host_state[1];
     out->vcycles = out->iters + 1;
+    c.last_iters = out->iters;
     out->n_dof = (int)(2 * L.nodes());
     out->relres_rec = ff > 0 ? std::sqrt(ctx->host_sums[1] / ff) : 0.0;
     out->relres_true = ff > 0 ? std::sqrt(ctx->host_sums[2] / ff) : 0.0;
@@ -516,6 +613,10 @@ int mtomg_create(mtomg_ctx** ctx, int max_designs, void* hip_stream) {
         return MTOMG_HIP_ERROR;
     }
     c->d.resize(max_designs);
+    if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return MTOMG_HIP_ERROR;
+    }
     if (hipHostMalloc((void**)&c->host_state, 16 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&c->host_sums, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
         delete c;
@@ -528,12 +629,16 @@ int mtomg_create(mtomg_ctx** ctx, int max_designs, void* hip_stream) {
 int mtomg_destroy(mtomg_ctx* c) {
     if (!c) return MTOMG_OK;
     hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     for (Design& d : c->d)
         for (hipEvent_t& e : d.ev)
             if (e) hipEventDestroy(e);
     if (c->ws_owned && c->ws) hipFree(c->ws);
     if (c->host_state) hipHostFree(c->host_state);
     if (c->host_sums) hipHostFree(c->host_sums);
+    for (hipEvent_t& e : c->prof.ev)
+        if (e) hipEventDestroy(e);
     delete c;
     return MTOMG_OK;
 }
@@ -562,6 +667,10 @@ int mtomg_set_grid(mtomg_ctx* c, int design, int nelx, int nely, double nu, int 
     if (n_cases < 1 || n_cases > 64) return fail(c, MTOMG_BAD_INPUT, "n_cases must be in [1, 64]");
     if (!F || !U) return fail(c, MTOMG_BAD_INPUT, "F and U must be device pointers");
     Design& d = c->d[design];
+    hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    for (hipEvent_t& e : d.ev)
+        if (e) hipEventDestroy(e);
     d = Design();
     d.nelx = nelx; d.nely = nely; d.nu = nu; d.m = m; d.E_min = E_min; d.penal = penal; d.levels = levels;
     d.n_pre = n_pre; d.n_post = n_post; d.omega = omega; d.precision = precision; d.n_cases = n_cases;
@@ -572,9 +681,10 @@ int mtomg_set_grid(mtomg_ctx* c, int design, int nelx, int nely, double nu, int 
         const int sh = levels - 1 - l;
         d.lev[l].nx = nelx >> sh;
         d.lev[l].ny = nely >> sh;
-        plan_level(d.lev[l]);
+        plan_level(d.lev[l], l == levels - 1 ? c->rows_fine : c->rows_coarse);
     }
     d.n0 = 2 * (d.lev[0].nx + 1) * d.lev[0].ny;
+    d.np0 = (d.n0 + COARSE_NB - 1) / COARSE_NB * COARSE_NB;
     d.cases.assign(n_cases, CaseBufs());
     HIPCHK(c, hipEventCreate(&d.ev[0]));
     HIPCHK(c, hipEventCreate(&d.ev[1]));
@@ -602,10 +712,9 @@ int mtomg_set_workspace(mtomg_ctx* c, void* dev, size_t bytes) {
     if (!dev || (reinterpret_cast<uintptr_t>(dev) & 255)) return fail(c, MTOMG_BAD_INPUT, "workspace must be a 256-byte aligned device pointer");
     const size_t need = layout_all(c, nullptr);
     if (bytes < need) return fail(c, MTOMG_WORKSPACE, "workspace smaller than mtomg_workspace_bytes()");
-    if (c->ws_owned && c->ws) {
-        hipStreamSynchronize(c->stream);
-        hipFree(c->ws);
-    }
+    hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    if (c->ws_owned && c->ws) hipFree(c->ws);
     c->ws = dev;
     c->ws_bytes = bytes;
     c->ws_owned = false;
@@ -632,12 +741,10 @@ int mtomg_set_densities(mtomg_ctx* c, int design, const double* x) {
         if (l + 1 == f) launch_moments_from_fine(st, P.op64, P.nx, P.ny, L.op64, d.mixed() ? L.op32 : nullptr);
         else launch_moments_coarsen(st, P.op64, P.nx, P.ny, L.op64, d.mixed() ? L.op32 : nullptr);
     }
-    launch_fill<double>(st, d.A0, (size_t)d.n0 * d.n0, 0.0);
+    launch_fill<double>(st, d.A0, (size_t)d.np0 * d.np0, 0.0);
     launch_fill<int>(st, d.chol_status, 4, 0);
-    launch_assemble_dense(st, false, level_op<double>(d, 0), make_mat<double>(d, d.omega), d.A0);
-    launch_cholesky(st, d.A0, d.n0, d.chol_status);
-    launch_trinv(st, d.A0, d.W0, d.n0);
-    launch_gram(st, d.W0, d.Ainv, d.n0);
+    launch_assemble_dense(st, false, level_op<double>(d, 0), make_mat<double>(d, d.omega), d.A0, d.np0);
+    launch_coarse_factor(st, d.A0, d.n0, d.np0, d.Dinv, d.W0, d.Ainv, d.chol_status);
     LAUNCHCHK(c);
     HIPCHK(c, hipEventRecord(d.ev[1], st));
     HIPCHK(c, hipMemcpyAsync(c->host_state + 8, d.chol_status, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -710,6 +817,64 @@ const char* mtomg_status_string(int s) {
 
 const char* mtomg_last_error(const mtomg_ctx* c) { return c ? c->err.c_str() : ""; }
 
+int mtomg_set_option(mtomg_ctx* c, int option, int value) {
+    if (!c) return MTOMG_BAD_INPUT;
+    switch (option) {
+        case MTOMG_OPT_GRAPHS:
+            c->use_graphs = value != 0;
+            return MTOMG_OK;
+        case MTOMG_OPT_ROWS_FINE:
+        case MTOMG_OPT_ROWS_COARSE: {
+            if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8)
+                return fail(c, MTOMG_BAD_INPUT, "rows per wave must be 0 (automatic), 1, 2, 4 or 8");
+            (option == MTOMG_OPT_ROWS_FINE ? c->rows_fine : c->rows_coarse) = value;
+            hipStreamSynchronize(c->stream);
+            drop_graphs(c);
+            for (Design& d : c->d)
+                for (int l = 0; l < d.levels; ++l) plan_level(d.lev[l], l == d.levels - 1 ? c->rows_fine : c->rows_coarse);
+            // partial-sum buffers are sized by the tile counts: re-lay out the workspace
+            c->laid_out = false;
+            for (Design& d : c->d) d.has_dens = false;
+            if (c->ws_owned && c->ws) { hipFree(c->ws); c->ws = nullptr; c->ws_owned = false; c->ws_bytes = 0; }
+            return MTOMG_OK;
+        }
+        case MTOMG_OPT_BATCH:
+            if (value < 1 || value > 1000) return fail(c, MTOMG_BAD_INPUT, "batch must be in [1, 1000]");
+            c->batch = value;
+            for (Design& d : c->d)
+                for (CaseBufs& cb : d.cases) cb.last_iters = 0;
+            return MTOMG_OK;
+        default:
+            return fail(c, MTOMG_BAD_INPUT, "unknown option");
+    }
+}
+
+int mtomg_profile_kernel(mtomg_ctx* c, int kernel) {
+    if (!c) return MTOMG_BAD_INPUT;
+    if (kernel < MTOMG_KERNEL_NONE || kernel > MTOMG_KERNEL_COARSE_SOLVE) return fail(c, MTOMG_BAD_INPUT, "unknown kernel id");
+    if (kernel != MTOMG_KERNEL_NONE && c->prof.ev.empty()) {
+        c->prof.ev.resize(8192, nullptr);
+        for (hipEvent_t& e : c->prof.ev) HIPCHK(c, hipEventCreate(&e));
+    }
+    c->prof.kernel = kernel;
+    c->prof.used = 0;
+    return MTOMG_OK;
+}
+
+int mtomg_profile_read(mtomg_ctx* c, double* ms_out, int cap, int* launches) {
+    if (!c || !launches || (cap > 0 && !ms_out)) return MTOMG_BAD_INPUT;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k + 1 < c->prof.used; k += 2) {
+        if (k / 2 >= cap) break;
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->prof.ev[k], c->prof.ev[k + 1]));
+        ms_out[k / 2] = ms;
+    }
+    *launches = c->prof.used / 2;
+    c->prof.used = 0;
+    return MTOMG_OK;
+}
+
 int mtomg_debug_apply(mtomg_ctx* c, int design, int level, int op, const void* in, void* out) {
     int rc = check_design(c, design, true);
     if (rc) return rc;
@@ -760,10 +925,10 @@ int mtomg_debug_apply(mtomg_ctx* c, int design, int level, int op, const void* i
                 break;
             case MTOMG_OP_COARSE_SOLVE:
                 if (level != 0) return fail(c, MTOMG_BAD_INPUT, "coarse solve is on level 0");
-                launch_coarse_solve<T>(st, d.Ainv, d.n0, L.nx, vin, vout, nullptr);
+                launch_coarse_solve<T>(st, d.Ainv, d.n0, d.np0, L.nx, vin, vout, nullptr);
                 break;
             case MTOMG_OP_VCYCLE:
-                if (level == 0) launch_coarse_solve<T>(st, d.Ainv, d.n0, L.nx, vin, vout, nullptr);
+                if (level == 0) launch_coarse_solve<T>(st, d.Ainv, d.n0, d.np0, L.nx, vin, vout, nullptr);
                 else {
                     const int r2 = debug_vcycle<T>(c, d, cb, st, level, vin, vout);
                     if (r2) return r2;

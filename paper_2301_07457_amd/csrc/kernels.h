@@ -61,7 +61,7 @@ template <typename T>
 void launch_apply(hipStream_t st, bool fine, bool diag, LevelOp<T> op, Mat<T> mat, Sweep sw, const T* u,
                   T* q);
 template <typename T>
-void launch_coarse_solve(hipStream_t st, const double* Ainv, int n0, int nx0, const T* b, T* e,
+void launch_coarse_solve(hipStream_t st, const double* Ainv, int n0, int ld, int nx0, const T* b, T* e,
                          const int* conv);
 
 // setup
@@ -75,10 +75,12 @@ void launch_moments_from_fine(hipStream_t st, const double* E64, int nxf, int ny
                               float* mom32);
 void launch_moments_coarsen(hipStream_t st, const double* momf, int nxf, int nyf, double* mom64,
                             float* mom32);
-void launch_assemble_dense(hipStream_t st, bool fine, LevelOp<double> op, Mat<double> mat, double* A);
-void launch_cholesky(hipStream_t st, double* A, int n, int* status);
-void launch_trinv(hipStream_t st, const double* L, double* W, int n);
-void launch_gram(hipStream_t st, const double* W, double* Ainv, int n);
+constexpr int COARSE_NB = 32;   // block size of the coarse factorisation
+void launch_assemble_dense(hipStream_t st, bool fine, LevelOp<double> op, Mat<double> mat, double* A, int ld);
+// A (np x np, n0 used, identity padding written here) -> L in place,
+// Dinv = inverses of the diagonal blocks, W = L^{-1}, Ainv = A^{-1}.
+void launch_coarse_factor(hipStream_t st, double* A, int n0, int np, double* Dinv, double* W, double* Ainv,
+                          int* status);
 template <typename T>
 void launch_fill(hipStream_t st, T* p, size_t n, T v);
 void launch_cast_f32(hipStream_t st, const double* a, float* b, size_t n);

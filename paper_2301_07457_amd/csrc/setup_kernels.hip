@@ -2,8 +2,8 @@
 //  * element moduli from phase densities (Eq. 5, implicit void phase);
 //  * Galerkin coarse operators as six moments per coarse element, computed
 //    exactly by a 2x2 -> 1 recursion (FP64 accumulation);
-//  * dense coarsest matrix, its Cholesky factor (Algorithm 3, right-looking)
-//    and the explicit inverse K_0^{-1} = L^-T L^-1 used by the coarse solve;
+//  * dense coarsest matrix, its blocked Cholesky factor (Algorithm 3) and the
+//    explicit inverse K_0^{-1} = L^-T L^-1 used by the coarse solve;
 //  * compliance gradient dc/dx = -p x^(p-1) (E_i - E_min) u_e^T K^0 u_e and
 //    fixed-order reductions.
 #include "device_common.h"
@@ -66,9 +66,8 @@ __global__ void k_moments_coarsen(const double* __restrict__ mf, int nxf, int ny
 // its 9 neighbours); each computes the 2x2 block as the sum over the shared
 // elements of element responses to unit displacements.
 template <bool FINE>
-__global__ void k_assemble_dense(LevelOp<double> op, Mat<double> mat, double* __restrict__ A) {
+__global__ void k_assemble_dense(LevelOp<double> op, Mat<double> mat, double* __restrict__ A, int ld) {
     const int nx = op.nx, ny = op.ny;
-    const int n0 = 2 * (nx + 1) * ny;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int node = t / 9, o = t % 9;
     if (node >= (nx + 1) * ny) return;
@@ -95,86 +94,200 @@ __global__ void k_assemble_dense(LevelOp<double> op, Mat<double> mat, double* __
         }
     const int rn = 2 * ((j - 1) * (nx + 1) + i), cm = 2 * ((mj - 1) * (nx + 1) + mi);
     for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) A[(size_t)(rn + a) * n0 + cm + b] = blk[a][b];
+        for (int b = 0; b < 2; ++b) A[(size_t)(rn + a) * ld + cm + b] = blk[a][b];
 }
 
-// In-place Cholesky A = L L^T of the lower triangle (Algorithm 3: pivot
-// square root, column scaling, trailing outer-product update), one
-// workgroup.  status = 1 if a pivot is not positive.
-__global__ __launch_bounds__(1024) void k_cholesky(double* __restrict__ A, int n, int* __restrict__ status) {
-    extern __shared__ double col[];
-    __shared__ double piv;
-    const int tid = threadIdx.x, nth = blockDim.x;
-    const int lane = tid & 63, wv = tid >> 6, nw = nth >> 6;
-    for (int k = 0; k < n; ++k) {
-        if (tid == 0) {
-            const double a = A[(size_t)k * n + k];
-            if (a > 0.0) {
-                piv = sqrt(a);
-                A[(size_t)k * n + k] = piv;
-            } else {
-                piv = -1.0;
-                *status = 1;
+// ---------------------------------------------------------------------------
+// Coarsest solve setup: blocked Cholesky (Algorithm 3 carried out on 32 x 32
+// blocks) and the explicit inverse K_0^{-1} = W^T W with W = L^{-1}.
+// The matrix is padded to a multiple of the block size with an identity
+// tail, so every block is full; row-major, leading dimension np.
+// ---------------------------------------------------------------------------
+constexpr int NB = 32;
+
+// Each of the 256 threads owns one row r and four columns c4..c4+3 of a block.
+__device__ __forceinline__ void blk_coords(int& r, int& c4) {
+    r = threadIdx.x >> 3;
+    c4 = (threadIdx.x & 7) * 4;
+}
+
+__device__ __forceinline__ void blk_load(double (*S)[NB + 1], const double* __restrict__ A, int np, int bi, int bj) {
+    for (int k = threadIdx.x; k < NB * NB; k += 256) {
+        const int r = k / NB, c = k % NB;
+        S[r][c] = A[(size_t)(bi * NB + r) * np + bj * NB + c];
+    }
+}
+
+// Unblocked Cholesky of a block held in LDS (lower triangle), then its
+// inverse Li (lower).  Returns false if a pivot is not positive.
+__device__ bool blk_potrf_inv(double (*L)[NB + 1], double (*Li)[NB + 1]) {
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    for (int k = 0; k < NB; ++k) {
+        if (threadIdx.x == 0) {
+            const double a = L[k][k];
+            if (a > 0.0) L[k][k] = sqrt(a);
+            else bad = 1;
+        }
+        __syncthreads();
+        if (bad) return false;
+        const double piv = L[k][k];
+        if (threadIdx.x > k && threadIdx.x < NB) L[threadIdx.x][k] /= piv;
+        __syncthreads();
+        for (int t = threadIdx.x; t < NB * NB; t += 256) {
+            const int r = t / NB, c = t % NB;
+            if (c > k && r >= c) L[r][c] -= L[r][k] * L[c][k];
+        }
+        __syncthreads();
+    }
+    // Li = L^{-1}: thread c solves column c by forward substitution
+    if (threadIdx.x < NB) {
+        const int c = threadIdx.x;
+        for (int r = 0; r < NB; ++r) {
+            if (r < c) { Li[r][c] = 0.0; continue; }
+            double s = (r == c) ? 1.0 : 0.0;
+            for (int t = c; t < r; ++t) s -= L[r][t] * Li[t][c];
+            Li[r][c] = s / L[r][r];
+        }
+    }
+    __syncthreads();
+    return true;
+}
+
+// Left-looking block column kb: workgroup b updates block row ib = kb + b,
+// A[ib,kb] -= sum_{t<kb} L[ib,t] L[kb,t]^T, factors the (identically
+// updated) diagonal block itself and forms L[ib,kb] = A[ib,kb] L_kk^{-T}.
+// Workgroup 0 writes the inverse of L_kk (Dinv[kb]).
+__global__ __launch_bounds__(256) void k_chol_col(double* __restrict__ A, int np, int kb, double* __restrict__ Dinv,
+                                                  int* __restrict__ status) {
+    __shared__ double Lk[NB][NB + 1], Lt[NB][NB + 1], Akk[NB][NB + 1], Aik[NB][NB + 1], Li[NB][NB + 1];
+    const int ib = kb + blockIdx.x;
+    int r, c4;
+    blk_coords(r, c4);
+    double akk[4] = {0, 0, 0, 0}, aik[4] = {0, 0, 0, 0};
+    for (int t = 0; t < kb; ++t) {
+        blk_load(Lk, A, np, kb, t);
+        blk_load(Lt, A, np, ib, t);
+        __syncthreads();
+        for (int s = 0; s < NB; ++s) {
+            const double lr = Lk[r][s], tr = Lt[r][s];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                akk[q] += lr * Lk[c4 + q][s];
+                aik[q] += tr * Lk[c4 + q][s];
             }
         }
         __syncthreads();
-        if (!(piv > 0.0)) return;
-        const double inv = 1.0 / piv;
-        for (int r = k + 1 + tid; r < n; r += nth) {
-            const double v = A[(size_t)r * n + k] * inv;
-            A[(size_t)r * n + k] = v;
-            col[r] = v;
-        }
-        __syncthreads();
-        for (int r = k + 1 + wv; r < n; r += nw) {
-            const double lr = col[r];
-            double* row = A + (size_t)r * n;
-            for (int c = k + 1 + lane; c <= r; c += 64) row[c] -= lr * col[c];
-        }
-        __syncthreads();
     }
-}
-
-// W = L^{-1} by forward substitution, one wave per column c (two waves per
-// block); the running column lives in LDS.  W row-major, lower triangular.
-__global__ __launch_bounds__(128) void k_trinv(const double* __restrict__ L, double* __restrict__ W, int n) {
-    extern __shared__ double wl[];
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int c = blockIdx.x * 2 + wv;
-    if (c >= n) return;
-    double* w = wl + (size_t)wv * n;
-    for (int r = lane; r < n; r += 64) w[r] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        Akk[r][c4 + q] = A[(size_t)(kb * NB + r) * np + kb * NB + c4 + q] - akk[q];
+        Aik[r][c4 + q] = A[(size_t)(ib * NB + r) * np + kb * NB + c4 + q] - aik[q];
+    }
     __syncthreads();
-    for (int r = c; r < n; ++r) {
-        const double* Lr = L + (size_t)r * n;
-        double s = 0.0;
-        for (int t = c + lane; t < r; t += 64) s += Lr[t] * w[t];
-        s = wave_sum(s);
-        s = __shfl(s, 0, 64);
-        const double v = ((r == c ? 1.0 : 0.0) - s) / Lr[r];
-        if (lane == 0) w[r] = v;
-        __builtin_amdgcn_s_waitcnt(0);
-        __builtin_amdgcn_wave_barrier();
+    if (!blk_potrf_inv(Akk, Li)) {
+        if (threadIdx.x == 0) *status = 1;
+        return;
     }
-    for (int r = lane; r < n; r += 64) W[(size_t)r * n + c] = w[r];
+    if (blockIdx.x == 0) {
+        // The factored diagonal block is not stored: other workgroups of this
+        // launch still read the unfactored A[kb,kb], and later steps only use
+        // off-diagonal blocks of L and the block inverses.
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Dinv[(size_t)kb * NB * NB + r * NB + c4 + q] = Li[r][c4 + q];
+        return;
+    }
+    // L[ib,kb] = Aik Li^T
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int c = c4 + q;
+        double s = 0.0;
+        for (int t = 0; t <= c; ++t) s += Aik[r][t] * Li[c][t];
+        A[(size_t)(ib * NB + r) * np + kb * NB + c] = s;
+    }
 }
 
-// K_0^{-1} = W^T W, W = L^{-1}: one wave per output row a, lanes over
-// columns; the sum runs over t ascending, so the result is bitwise symmetric.
-__global__ __launch_bounds__(256) void k_gram(const double* __restrict__ W, double* __restrict__ Ainv, int n) {
-    const int a = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (a >= n) return;
-    for (int b0 = 0; b0 < n; b0 += 64) {
-        const int b = b0 + lane;
-        double s = 0.0;
-        const int t0 = a;
-        for (int t = t0; t < n; ++t) {
-            const double wa = W[(size_t)t * n + a];
-            if (b < n) s += wa * W[(size_t)t * n + b];
+// W = L^{-1} by block forward substitution, one workgroup per block column jb:
+// W[jb,jb] = L_jj^{-1}; W[ib,jb] = -L_ii^{-1} sum_{t=jb}^{ib-1} L[ib,t] W[t,jb].
+__global__ __launch_bounds__(256) void k_trinv_blk(const double* __restrict__ A, const double* __restrict__ Dinv,
+                                                   double* __restrict__ W, int np) {
+    __shared__ double La[NB][NB + 1], Wb[NB][NB + 1], S[NB][NB + 1], Di[NB][NB + 1];
+    const int nblk = np / NB;
+    const int jb = blockIdx.x;
+    int r, c4;
+    blk_coords(r, c4);
+    // diagonal block
+#pragma unroll
+    for (int q = 0; q < 4; ++q) W[(size_t)(jb * NB + r) * np + jb * NB + c4 + q] = Dinv[(size_t)jb * NB * NB + r * NB + c4 + q];
+    // blocks above the diagonal are zero
+    for (int ib = 0; ib < jb; ++ib)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) W[(size_t)(ib * NB + r) * np + jb * NB + c4 + q] = 0.0;
+    __threadfence();
+    __syncthreads();
+    for (int ib = jb + 1; ib < nblk; ++ib) {
+        double acc[4] = {0, 0, 0, 0};
+        for (int t = jb; t < ib; ++t) {
+            blk_load(La, A, np, ib, t);
+            blk_load(Wb, W, np, t, jb);
+            __syncthreads();
+            for (int s = 0; s < NB; ++s) {
+                const double lr = La[r][s];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q] += lr * Wb[s][c4 + q];
+            }
+            __syncthreads();
         }
-        if (b < n) Ainv[(size_t)a * n + b] = s;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) S[r][c4 + q] = acc[q];
+        for (int k = threadIdx.x; k < NB * NB; k += 256) Di[k / NB][k % NB] = Dinv[(size_t)ib * NB * NB + k];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = c4 + q;
+            double s = 0.0;
+            for (int t = 0; t <= r; ++t) s += Di[r][t] * S[t][c];
+            W[(size_t)(ib * NB + r) * np + jb * NB + c] = -s;
+        }
+        __threadfence();
+        __syncthreads();
     }
+}
+
+// K_0^{-1} = W^T W: one workgroup per lower block (ib >= jb), mirrored to
+// the upper block so the inverse is exactly symmetric.
+__global__ __launch_bounds__(256) void k_gram_blk(const double* __restrict__ W, double* __restrict__ Ainv, int np) {
+    __shared__ double Wi[NB][NB + 1], Wj[NB][NB + 1];
+    const int nblk = np / NB;
+    int ib = 0, rem = blockIdx.x;
+    while (rem > ib) { rem -= ib + 1; ++ib; }
+    const int jb = rem;   // 0 <= jb <= ib
+    int r, c4;
+    blk_coords(r, c4);
+    double acc[4] = {0, 0, 0, 0};
+    for (int t = ib; t < nblk; ++t) {
+        blk_load(Wi, W, np, t, ib);
+        blk_load(Wj, W, np, t, jb);
+        __syncthreads();
+        for (int s = 0; s < NB; ++s) {
+            const double wr = Wi[s][r];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] += wr * Wj[s][c4 + q];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int c = c4 + q;
+        Ainv[(size_t)(ib * NB + r) * np + jb * NB + c] = acc[q];
+        Ainv[(size_t)(jb * NB + c) * np + ib * NB + r] = acc[q];
+    }
+}
+
+__global__ void k_pad_identity(double* __restrict__ A, int n0, int np) {
+    const int k = n0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < np) A[(size_t)k * np + k] = 1.0;
 }
 
 template <typename T>
@@ -237,19 +350,20 @@ void launch_moments_coarsen(hipStream_t st, const double* mf, int nxf, int nyf, 
     const int n = (nxf / 2) * (nyf / 2);
     hipLaunchKernelGGL(k_moments_coarsen, dim3(blocks_for(n, 256)), dim3(256), 0, st, mf, nxf, nyf, m64, m32);
 }
-void launch_assemble_dense(hipStream_t st, bool fine, LevelOp<double> op, Mat<double> mat, double* A) {
+void launch_assemble_dense(hipStream_t st, bool fine, LevelOp<double> op, Mat<double> mat, double* A, int ld) {
     const int n = 9 * (op.nx + 1) * op.ny;
-    if (fine) hipLaunchKernelGGL(k_assemble_dense<true>, dim3(blocks_for(n, 256)), dim3(256), 0, st, op, mat, A);
-    else hipLaunchKernelGGL(k_assemble_dense<false>, dim3(blocks_for(n, 256)), dim3(256), 0, st, op, mat, A);
+    if (fine) hipLaunchKernelGGL(k_assemble_dense<true>, dim3(blocks_for(n, 256)), dim3(256), 0, st, op, mat, A, ld);
+    else hipLaunchKernelGGL(k_assemble_dense<false>, dim3(blocks_for(n, 256)), dim3(256), 0, st, op, mat, A, ld);
 }
-void launch_cholesky(hipStream_t st, double* A, int n, int* status) {
-    hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(1024), n * sizeof(double), st, A, n, status);
-}
-void launch_trinv(hipStream_t st, const double* L, double* W, int n) {
-    hipLaunchKernelGGL(k_trinv, dim3((n + 1) / 2), dim3(128), 2 * n * sizeof(double), st, L, W, n);
-}
-void launch_gram(hipStream_t st, const double* W, double* Ainv, int n) {
-    hipLaunchKernelGGL(k_gram, dim3((n + 3) / 4), dim3(256), 0, st, W, Ainv, n);
+void launch_coarse_factor(hipStream_t st, double* A, int n0, int np, double* Dinv, double* W, double* Ainv,
+                          int* status) {
+    if (np > n0)
+        hipLaunchKernelGGL(k_pad_identity, dim3(blocks_for(np - n0, 256)), dim3(256), 0, st, A, n0, np);
+    const int nblk = np / NB;
+    for (int kb = 0; kb < nblk; ++kb)
+        hipLaunchKernelGGL(k_chol_col, dim3(nblk - kb), dim3(256), 0, st, A, np, kb, Dinv, status);
+    hipLaunchKernelGGL(k_trinv_blk, dim3(nblk), dim3(256), 0, st, A, Dinv, W, np);
+    hipLaunchKernelGGL(k_gram_blk, dim3(nblk * (nblk + 1) / 2), dim3(256), 0, st, W, Ainv, np);
 }
 template <typename T>
 void launch_fill(hipStream_t st, T* p, size_t n, T v) {

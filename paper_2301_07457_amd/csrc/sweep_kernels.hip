@@ -25,14 +25,15 @@ struct TileInfo {
     bool block_ok;
 };
 
+template <int R>
 __device__ __forceinline__ TileInfo tile_info(const Sweep& s, int n_rows) {
     TileInfo t;
     t.tile = xcd_tile(s.n_tiles);
     t.block_ok = t.tile < s.n_tiles;
     t.strip = t.tile % s.n_strips;
     const int chunk = (t.tile / s.n_strips) * WAVES_PER_WG + wave_id();
-    t.j0 = chunk * s.rows;
-    t.j1 = min(t.j0 + s.rows, n_rows);
+    t.j0 = chunk * R;
+    t.j1 = min(t.j0 + R, n_rows);
     return t;
 }
 
@@ -42,7 +43,7 @@ __device__ __forceinline__ TileInfo tile_info(const Sweep& s, int n_rows) {
 // mode 2: only the pending x update (after the last iteration).
 // Geometry: H_L = 1, H_R = 1, 62 output columns per strip.
 // ===========================================================================
-template <typename TZ>
+template <typename TZ, int R>
 __global__ __launch_bounds__(WG_THREADS) void k_cg_apply(
     LevelOp<double> op, Mat<double> mat, Sweep sw, const TZ* __restrict__ z,
     const double* __restrict__ p_old, double* __restrict__ p_new, double* __restrict__ x,
@@ -54,7 +55,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_cg_apply(
     if (mode == 1 && cst != 0) return;
     if (mode == 0 && cst != 0 && cst != 1) return;
     const int nx = op.nx, ny = op.ny;
-    const TileInfo t = tile_info(sw, ny + 1);
+    const TileInfo t = tile_info<R>(sw, ny + 1);
     if (!t.block_ok) return;
     constexpr int HL = 1, WOUT = 62;
     const int lane = lane_id();
@@ -109,13 +110,15 @@ __global__ __launch_bounds__(WG_THREADS) void k_cg_apply(
         V2<double> f0, f1, f2, f3;
         elem_force(load_elem<double, true>(op, i, t.j0 - 1), mat, pa, pa_r, pb_r, pb, f0, f1, f2, f3);
         V2<double> carry = f3 + from_left(f2);
-        for (int j = t.j0; j < t.j1; ++j) {
+#pragma unroll
+        for (int s = 0; s < R; ++s) {
+            const int j = t.j0 + s;
             pa = pb; pa_r = pb_r;
             pb = getp(j + 1); pb_r = from_right(pb);
             elem_force(load_elem<double, true>(op, i, j), mat, pa, pa_r, pb_r, pb, f0, f1, f2, f3);
             const V2<double> qv = carry + f0 + from_left(f1);
             carry = f3 + from_left(f2);
-            if (out_lane) {
+            if (out_lane && j < t.j1) {
                 if (j >= 1) {
                     store_node(q, nx, i, j, qv);
                     dot += pa.x * qv.x + pa.y * qv.y;
@@ -136,12 +139,13 @@ __global__ __launch_bounds__(WG_THREADS) void k_cg_apply(
 // ||r||^2 and ||f||^2 over free DOFs.  Also used for the true residual
 // (then r may be null).  Geometry as k_cg_apply.
 // ===========================================================================
+template <int R>
 __global__ __launch_bounds__(WG_THREADS) void k_residual(
     LevelOp<double> op, Mat<double> mat, Sweep sw, const double* __restrict__ f,
     double* __restrict__ x, int use_x, double* __restrict__ r, double* __restrict__ rr_out,
     double* __restrict__ ff_out) {
     const int nx = op.nx, ny = op.ny;
-    const TileInfo t = tile_info(sw, ny + 1);
+    const TileInfo t = tile_info<R>(sw, ny + 1);
     if (!t.block_ok) return;
     constexpr int HL = 1, WOUT = 62;
     const int lane = lane_id();
@@ -158,13 +162,15 @@ __global__ __launch_bounds__(WG_THREADS) void k_residual(
         V2<double> f0, f1, f2, f3;
         elem_force(load_elem<double, true>(op, i, t.j0 - 1), mat, xa, xa_r, xb_r, xb, f0, f1, f2, f3);
         V2<double> carry = f3 + from_left(f2);
-        for (int j = t.j0; j < t.j1; ++j) {
+#pragma unroll
+        for (int s = 0; s < R; ++s) {
+            const int j = t.j0 + s;
             xa = xb; xa_r = xb_r;
             xb = getx(j + 1); xb_r = from_right(xb);
             elem_force(load_elem<double, true>(op, i, j), mat, xa, xa_r, xb_r, xb, f0, f1, f2, f3);
             const V2<double> kx = carry + f0 + from_left(f1);
             carry = f3 + from_left(f2);
-            if (out_lane) {
+            if (out_lane && j < t.j1) {
                 if (j >= 1) {
                     const V2<double> fv = load_node(f, nx, ny, i, j);
                     const V2<double> rv = fv - kx;
@@ -196,7 +202,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_residual(
 // Geometry: H_L = 2, H_R = 1, 61 output columns per strip.  The diagonal
 // stage runs one element row ahead of the force stage.
 // ===========================================================================
-template <typename T, bool FINE, bool CG>
+template <typename T, bool FINE, bool CG, int R>
 __global__ __launch_bounds__(WG_THREADS) void k_presmooth(
     LevelOp<T> op, Mat<T> mat, Sweep sw, const T* __restrict__ b, T* __restrict__ u_out,
     int sweeps, CgRhs cg, const int* conv) {
@@ -207,7 +213,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_presmooth(
     }
     if (cst != 0) return;
     const int nx = op.nx, ny = op.ny;
-    const TileInfo t = tile_info(sw, ny + 1);
+    const TileInfo t = tile_info<R>(sw, ny + 1);
     if (!t.block_ok) return;
     constexpr int HL = 2, WOUT = 61;
     const int lane = lane_id();
@@ -267,7 +273,9 @@ __global__ __launch_bounds__(WG_THREADS) void k_presmooth(
         V2<T> fcarry{T(0), T(0)};
         Mom<T> m_prev = mom_zero<T>();
         V2<T> u1_prev{T(0), T(0)}, u1r_prev{T(0), T(0)}, b_prev{T(0), T(0)}, D_prev{T(1), T(1)};
-        for (int k = t.j0 - 1; k <= t.j1; ++k) {
+#pragma unroll
+        for (int s = 0; s < R + 2; ++s) {
+            const int k = t.j0 - 1 + s;
             const Mom<T> mk = load_elem<T, FINE>(op, i, k);
             elem_diag(mk, mat, d0, d1, d2, d3);
             const V2<T> D = dcarry + d0 + from_left(d1);
@@ -279,14 +287,14 @@ __global__ __launch_bounds__(WG_THREADS) void k_presmooth(
                 u1.y = mat.omega * bk.y / D.y;
             }
             const V2<T> u1r = from_right(u1);
-            if (k >= t.j0) {
+            if (s >= 1) {
                 // force stage for element row k-1 -> node row k-1 complete
                 V2<T> f0, f1, f2, f3;
                 elem_force(m_prev, mat, u1_prev, u1r_prev, u1r, u1, f0, f1, f2, f3);
                 const V2<T> fs = fcarry + f0 + from_left(f1);
                 fcarry = f3 + from_left(f2);
                 const int jr = k - 1;
-                if (jr >= t.j0 && jr >= 1 && out_lane) {
+                if (jr >= t.j0 && jr < t.j1 && jr >= 1 && out_lane) {
                     V2<T> uo = sweeps == 0 ? V2<T>{T(0), T(0)} : u1_prev;
                     if (sweeps >= 2) {
                         uo.x = u1_prev.x + mat.omega * (b_prev.x - fs.x) / D_prev.x;
@@ -319,7 +327,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_presmooth(
 // Geometry: H_L = 2, 60 fine columns (30 coarse) per strip; the chunk is in
 // coarse rows.
 // ===========================================================================
-template <typename T, bool FINE, bool CHECK>
+template <typename T, bool FINE, bool CHECK, int R>
 __global__ __launch_bounds__(WG_THREADS) void k_restrict(
     LevelOp<T> op, Mat<T> mat, Sweep sw, const T* __restrict__ b, const T* __restrict__ u,
     T* __restrict__ rc, ConvCheck chk, const int* conv) {
@@ -328,7 +336,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_restrict(
     if (cst != 0) return;
     const int nx = op.nx, ny = op.ny;
     const int ncx = nx / 2, ncy = ny / 2;
-    const TileInfo t = tile_info(sw, ncy + 1);
+    const TileInfo t = tile_info<R>(sw, ncy + 1);
     if (!t.block_ok) return;
     if constexpr (CHECK) {
         const double rr = sum_partials(chk.rr, chk.n_rr);
@@ -354,14 +362,16 @@ __global__ __launch_bounds__(WG_THREADS) void k_restrict(
         if (!u) return V2<T>{T(0), T(0)};
         return load_node(u, nx, ny, i, jj);
     };
-    const int jf0 = 2 * t.j0 - 1, jf1 = 2 * t.j1 - 1;   // fine rows computed: [jf0, jf1]
+    const int jf0 = 2 * t.j0 - 1;   // fine rows computed: jf0 .. jf0 + 2R
     V2<T> ua = getu(jf0 - 1), ua_r = from_right(ua);
     V2<T> ub = getu(jf0), ub_r = from_right(ub);
     V2<T> f0, f1, f2, f3;
     elem_force(load_elem<T, FINE>(op, i, jf0 - 1), mat, ua, ua_r, ub_r, ub, f0, f1, f2, f3);
     V2<T> carry = f3 + from_left(f2);
     V2<T> h_m2{T(0), T(0)}, h_m1{T(0), T(0)};
-    for (int j = jf0; j <= jf1; ++j) {
+#pragma unroll
+    for (int s = 0; s <= 2 * R; ++s) {
+        const int j = jf0 + s;
         ua = ub; ua_r = ub_r;
         ub = getu(j + 1); ub_r = from_right(ub);
         elem_force(load_elem<T, FINE>(op, i, j), mat, ua, ua_r, ub_r, ub, f0, f1, f2, f3);
@@ -371,9 +381,9 @@ __global__ __launch_bounds__(WG_THREADS) void k_restrict(
         if (node_col && j >= 1 && j <= ny) rr = load_node(b, nx, ny, i, j) - ku;
         const V2<T> rl = from_left(rr), rrt = from_right(rr);
         const V2<T> h{rr.x + T(0.5) * (rl.x + rrt.x), rr.y + T(0.5) * (rl.y + rrt.y)};
-        if ((j & 1) && j >= jf0 + 2) {
+        if ((s & 1) == 0 && s >= 2) {
             const int J = (j - 1) >> 1;
-            if (out_lane) {
+            if (out_lane && J < t.j1) {
                 V2<T> v{h_m1.x + T(0.5) * (h_m2.x + h.x), h_m1.y + T(0.5) * (h_m2.y + h.y)};
                 if (J == 0) v = V2<T>{T(0), T(0)};
                 store_node(rc, ncx, I, J, v);
@@ -392,7 +402,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_restrict(
 // free DOFs, r being the FP64 residual.
 // Geometry: H_L = 1, H_R = 1, 62 output columns per strip.
 // ===========================================================================
-template <typename T, bool FINE, bool PROLONG, bool DOT>
+template <typename T, bool FINE, bool PROLONG, bool DOT, int R>
 __global__ __launch_bounds__(WG_THREADS) void k_post(
     LevelOp<T> op, Mat<T> mat, Sweep sw, const T* __restrict__ u_in, const T* __restrict__ ec,
     const T* __restrict__ b, T* __restrict__ u_out, const double* __restrict__ r64,
@@ -402,7 +412,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_post(
     if (cst != 0) return;
     const int nx = op.nx, ny = op.ny;
     const int ncx = nx / 2, ncy = ny / 2;
-    const TileInfo t = tile_info(sw, ny + 1);
+    const TileInfo t = tile_info<R>(sw, ny + 1);
     if (!t.block_ok) return;
     constexpr int HL = 1, WOUT = 62;
     const int lane = lane_id();
@@ -436,7 +446,9 @@ __global__ __launch_bounds__(WG_THREADS) void k_post(
         }
         V2<T> fcarry = f3 + from_left(f2);
         V2<T> dcarry = d3 + from_left(d2);
-        for (int j = t.j0; j < t.j1; ++j) {
+#pragma unroll
+        for (int s = 0; s < R; ++s) {
+            const int j = t.j0 + s;
             va = vb; va_r = vb_r;
             vb = getv(j + 1); vb_r = from_right(vb);
             const Mom<T> m = load_elem<T, FINE>(op, i, j);
@@ -446,7 +458,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_post(
             const V2<T> D = dcarry + d0 + from_left(d1);
             fcarry = f3 + from_left(f2);
             dcarry = d3 + from_left(d2);
-            if (out_lane) {
+            if (out_lane && j < t.j1) {
                 if (j >= 1) {
                     const V2<T> bv = load_node(b, nx, ny, i, j);
                     V2<T> uo;
@@ -473,11 +485,11 @@ __global__ __launch_bounds__(WG_THREADS) void k_post(
 // Plain stiffness apply q = K_l u in the level precision (test hook and
 // building block): Geometry as k_cg_apply.
 // ===========================================================================
-template <typename T, bool FINE, bool DIAG>
+template <typename T, bool FINE, bool DIAG, int R>
 __global__ __launch_bounds__(WG_THREADS) void k_apply(LevelOp<T> op, Mat<T> mat, Sweep sw,
                                                       const T* __restrict__ u, T* __restrict__ q) {
     const int nx = op.nx, ny = op.ny;
-    const TileInfo t = tile_info(sw, ny + 1);
+    const TileInfo t = tile_info<R>(sw, ny + 1);
     if (!t.block_ok) return;
     constexpr int HL = 1, WOUT = 62;
     const int lane = lane_id();
@@ -494,7 +506,9 @@ __global__ __launch_bounds__(WG_THREADS) void k_apply(LevelOp<T> op, Mat<T> mat,
         else elem_force(m, mat, ua, ua_r, ub_r, ub, f0, f1, f2, f3);
     }
     V2<T> carry = f3 + from_left(f2);
-    for (int j = t.j0; j < t.j1; ++j) {
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+        const int j = t.j0 + s;
         ua = ub; ua_r = ub_r;
         ub = getu(j + 1); ub_r = from_right(ub);
         const Mom<T> m = load_elem<T, FINE>(op, i, j);
@@ -502,7 +516,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_apply(LevelOp<T> op, Mat<T> mat,
         else elem_force(m, mat, ua, ua_r, ub_r, ub, f0, f1, f2, f3);
         V2<T> qv = carry + f0 + from_left(f1);
         carry = f3 + from_left(f2);
-        if (out_lane) {
+        if (out_lane && j < t.j1) {
             if (j < 1) qv = V2<T>{T(0), T(0)};
             store_node(q, nx, i, j, qv);
         }
@@ -516,7 +530,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_apply(LevelOp<T> op, Mat<T> mat,
 // ===========================================================================
 template <typename T>
 __global__ __launch_bounds__(WG_THREADS) void k_coarse_solve(const double* __restrict__ Ainv, int n0,
-                                                             int nx0, const T* __restrict__ b,
+                                                             int ld, int nx0, const T* __restrict__ b,
                                                              T* __restrict__ e, const int* conv) {
     if (conv && *conv != 0) return;
     extern __shared__ double sb[];
@@ -528,7 +542,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_coarse_solve(const double* __res
     __syncthreads();
     const int row = blockIdx.x * WAVES_PER_WG + wave_id();
     if (row >= n0) return;
-    const double* a = Ainv + (size_t)row * n0;
+    const double* a = Ainv + (size_t)row * ld;
     double s = 0.0;
     for (int k = lane_id(); k < n0; k += WAVE) s += a[k] * sb[k];
     s = wave_sum(s);
@@ -536,17 +550,27 @@ __global__ __launch_bounds__(WG_THREADS) void k_coarse_solve(const double* __res
 }
 
 // ===========================================================================
-// launchers
+// launchers: the rows per wave (a compile-time loop length, so all loads of
+// a wave can be issued together) is chosen per level on the host.
 // ===========================================================================
 static inline dim3 grid_of(const Sweep& s) { return dim3(8 * ((s.n_tiles + 7) / 8)); }
+
+#define MTOMG_ROWS_SWITCH(R_, CALL)               \
+    switch (R_) {                                 \
+        case 1: { constexpr int RR = 1; CALL; } break; \
+        case 2: { constexpr int RR = 2; CALL; } break; \
+        case 4: { constexpr int RR = 4; CALL; } break; \
+        default: { constexpr int RR = 8; CALL; } break; \
+    }
 
 template <typename TZ>
 void launch_cg_apply(hipStream_t st, LevelOp<double> op, Mat<double> mat, Sweep sw, const TZ* z,
                      const double* p_old, double* p_new, double* x, double* q, const double* zr_cur,
                      const double* zr_prev, int n_zr, const double* pq_prev, int n_pq,
                      double* pq_out, const int* conv, int mode) {
-    hipLaunchKernelGGL(k_cg_apply<TZ>, grid_of(sw), dim3(WG_THREADS), 0, st, op, mat, sw, z, p_old,
-                       p_new, x, q, zr_cur, zr_prev, n_zr, pq_prev, n_pq, pq_out, conv, mode);
+    MTOMG_ROWS_SWITCH(sw.rows, hipLaunchKernelGGL((k_cg_apply<TZ, RR>), grid_of(sw), dim3(WG_THREADS), 0, st, op,
+                                                   mat, sw, z, p_old, p_new, x, q, zr_cur, zr_prev, n_zr, pq_prev,
+                                                   n_pq, pq_out, conv, mode))
 }
 template void launch_cg_apply<float>(hipStream_t, LevelOp<double>, Mat<double>, Sweep, const float*,
                                      const double*, double*, double*, double*, const double*,
@@ -557,53 +581,47 @@ template void launch_cg_apply<double>(hipStream_t, LevelOp<double>, Mat<double>,
 
 void launch_residual(hipStream_t st, LevelOp<double> op, Mat<double> mat, Sweep sw, const double* f,
                      double* x, int use_x, double* r, double* rr_out, double* ff_out) {
-    hipLaunchKernelGGL(k_residual, grid_of(sw), dim3(WG_THREADS), 0, st, op, mat, sw, f, x, use_x, r,
-                       rr_out, ff_out);
+    MTOMG_ROWS_SWITCH(sw.rows, hipLaunchKernelGGL((k_residual<RR>), grid_of(sw), dim3(WG_THREADS), 0, st, op, mat,
+                                                   sw, f, x, use_x, r, rr_out, ff_out))
 }
 
 template <typename T>
 void launch_presmooth(hipStream_t st, bool fine, bool cgmode, LevelOp<T> op, Mat<T> mat, Sweep sw,
                       const T* b, T* u_out, int sweeps, const CgRhs& cg, const int* conv) {
-    if (cgmode) {
-        hipLaunchKernelGGL((k_presmooth<T, true, true>), grid_of(sw), dim3(WG_THREADS), 0, st, op, mat,
-                           sw, b, u_out, sweeps, cg, conv);
-    } else if (fine) {
-        hipLaunchKernelGGL((k_presmooth<T, true, false>), grid_of(sw), dim3(WG_THREADS), 0, st, op, mat,
-                           sw, b, u_out, sweeps, cg, conv);
-    } else {
-        hipLaunchKernelGGL((k_presmooth<T, false, false>), grid_of(sw), dim3(WG_THREADS), 0, st, op, mat,
-                           sw, b, u_out, sweeps, cg, conv);
-    }
+#define MTOMG_PRE(F, C)                                                                              \
+    MTOMG_ROWS_SWITCH(sw.rows, hipLaunchKernelGGL((k_presmooth<T, F, C, RR>), grid_of(sw), dim3(WG_THREADS), 0, \
+                                                   st, op, mat, sw, b, u_out, sweeps, cg, conv))
+    if (cgmode) MTOMG_PRE(true, true)
+    else if (fine) MTOMG_PRE(true, false)
+    else MTOMG_PRE(false, false)
+#undef MTOMG_PRE
 }
 
 template <typename T>
 void launch_restrict(hipStream_t st, bool fine, bool check, LevelOp<T> op, Mat<T> mat, Sweep sw,
                      const T* b, const T* u, T* rc, const ConvCheck& chk, const int* conv) {
-    if (check) {
-        hipLaunchKernelGGL((k_restrict<T, true, true>), grid_of(sw), dim3(WG_THREADS), 0, st, op, mat, sw,
-                           b, u, rc, chk, conv);
-    } else if (fine) {
-        hipLaunchKernelGGL((k_restrict<T, true, false>), grid_of(sw), dim3(WG_THREADS), 0, st, op, mat,
-                           sw, b, u, rc, chk, conv);
-    } else {
-        hipLaunchKernelGGL((k_restrict<T, false, false>), grid_of(sw), dim3(WG_THREADS), 0, st, op, mat,
-                           sw, b, u, rc, chk, conv);
-    }
+#define MTOMG_RES(F, C)                                                                              \
+    MTOMG_ROWS_SWITCH(sw.rows, hipLaunchKernelGGL((k_restrict<T, F, C, RR>), grid_of(sw), dim3(WG_THREADS), 0, \
+                                                   st, op, mat, sw, b, u, rc, chk, conv))
+    if (check) MTOMG_RES(true, true)
+    else if (fine) MTOMG_RES(true, false)
+    else MTOMG_RES(false, false)
+#undef MTOMG_RES
 }
 
 template <typename T>
 void launch_post(hipStream_t st, bool fine, bool prolong, bool dot, LevelOp<T> op, Mat<T> mat, Sweep sw,
                  const T* u_in, const T* ec, const T* b, T* u_out, const double* r64, double* zr_out,
                  const int* conv) {
-#define MTOMG_POST(F, P, D)                                                                        \
-    hipLaunchKernelGGL((k_post<T, F, P, D>), grid_of(sw), dim3(WG_THREADS), 0, st, op, mat, sw, u_in, \
-                       ec, b, u_out, r64, zr_out, conv)
+#define MTOMG_POST(F, P, D)                                                                          \
+    MTOMG_ROWS_SWITCH(sw.rows, hipLaunchKernelGGL((k_post<T, F, P, D, RR>), grid_of(sw), dim3(WG_THREADS), 0, \
+                                                   st, op, mat, sw, u_in, ec, b, u_out, r64, zr_out, conv))
     if (fine) {
-        if (prolong) { if (dot) MTOMG_POST(true, true, true); else MTOMG_POST(true, true, false); }
-        else { if (dot) MTOMG_POST(true, false, true); else MTOMG_POST(true, false, false); }
+        if (prolong) { if (dot) MTOMG_POST(true, true, true) else MTOMG_POST(true, true, false) }
+        else { if (dot) MTOMG_POST(true, false, true) else MTOMG_POST(true, false, false) }
     } else {
-        if (prolong) MTOMG_POST(false, true, false);
-        else MTOMG_POST(false, false, false);
+        if (prolong) MTOMG_POST(false, true, false)
+        else MTOMG_POST(false, false, false)
     }
 #undef MTOMG_POST
 }
@@ -611,21 +629,20 @@ void launch_post(hipStream_t st, bool fine, bool prolong, bool dot, LevelOp<T> o
 template <typename T>
 void launch_apply(hipStream_t st, bool fine, bool diag, LevelOp<T> op, Mat<T> mat, Sweep sw, const T* u,
                   T* q) {
-    if (fine) {
-        if (diag) hipLaunchKernelGGL((k_apply<T, true, true>), grid_of(sw), dim3(WG_THREADS), 0, st, op, mat, sw, u, q);
-        else hipLaunchKernelGGL((k_apply<T, true, false>), grid_of(sw), dim3(WG_THREADS), 0, st, op, mat, sw, u, q);
-    } else {
-        if (diag) hipLaunchKernelGGL((k_apply<T, false, true>), grid_of(sw), dim3(WG_THREADS), 0, st, op, mat, sw, u, q);
-        else hipLaunchKernelGGL((k_apply<T, false, false>), grid_of(sw), dim3(WG_THREADS), 0, st, op, mat, sw, u, q);
-    }
+#define MTOMG_APP(F, D)                                                                              \
+    MTOMG_ROWS_SWITCH(sw.rows, hipLaunchKernelGGL((k_apply<T, F, D, RR>), grid_of(sw), dim3(WG_THREADS), 0, st, \
+                                                   op, mat, sw, u, q))
+    if (fine) { if (diag) MTOMG_APP(true, true) else MTOMG_APP(true, false) }
+    else { if (diag) MTOMG_APP(false, true) else MTOMG_APP(false, false) }
+#undef MTOMG_APP
 }
 
 template <typename T>
-void launch_coarse_solve(hipStream_t st, const double* Ainv, int n0, int nx0, const T* b, T* e,
+void launch_coarse_solve(hipStream_t st, const double* Ainv, int n0, int ld, int nx0, const T* b, T* e,
                          const int* conv) {
     const int nblk = (n0 + WAVES_PER_WG - 1) / WAVES_PER_WG;
     hipLaunchKernelGGL((k_coarse_solve<T>), dim3(nblk), dim3(WG_THREADS), n0 * sizeof(double), st, Ainv,
-                       n0, nx0, b, e, conv);
+                       n0, ld, nx0, b, e, conv);
 }
 
 #define MTOMG_INST(T)                                                                              \
@@ -636,7 +653,7 @@ void launch_coarse_solve(hipStream_t st, const double* Ainv, int n0, int nx0, co
     template void launch_post<T>(hipStream_t, bool, bool, bool, LevelOp<T>, Mat<T>, Sweep, const T*,  \
                                  const T*, const T*, T*, const double*, double*, const int*);      \
     template void launch_apply<T>(hipStream_t, bool, bool, LevelOp<T>, Mat<T>, Sweep, const T*, T*);  \
-    template void launch_coarse_solve<T>(hipStream_t, const double*, int, int, const T*, T*, const int*);
+    template void launch_coarse_solve<T>(hipStream_t, const double*, int, int, int, const T*, T*, const int*);
 MTOMG_INST(float)
 MTOMG_INST(double)
 #undef MTOMG_INST

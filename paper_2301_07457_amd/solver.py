@@ -66,6 +66,13 @@ class PCGMGSolver:
         self.workspace = None
         return self
 
+    def set_option(self, name: str, value: int):
+        """mtomg_set_option; re-plans the workspace when the launch geometry changes."""
+        _lib.mtomg_set_option(self.ctx, name, value)
+        if name in ("ROWS_FINE", "ROWS_COARSE"):
+            self.workspace = None
+            self._ensure_workspace()
+
     def _ensure_workspace(self):
         if self.workspace is None:
             nb = _lib.mtomg_workspace_bytes(self.ctx)
