@@ -160,17 +160,24 @@ __device__ __forceinline__ int xcd_tile(int n_tiles) {
     return (b & 7) * per + (b >> 3);
 }
 
-// Nodal vector access with the clamped row (j = 0) and out-of-grid nodes read as 0.
+// Nodal vector access with the clamped row (j = 0) and out-of-grid nodes read
+// as 0.  The index is clamped into the grid and the load is always issued,
+// then masked: no branch, so the loads of consecutive rows can be batched.
 template <typename T>
 __device__ __forceinline__ V2<T> load_node(const T* __restrict__ v, int nx, int ny, int i, int j) {
-    if (i < 0 || i > nx || j < 1 || j > ny) return V2<T>{T(0), T(0)};
-    const size_t n = (size_t)j * (nx + 1) + i;
+    const bool ok = (i >= 0) & (i <= nx) & (j >= 1) & (j <= ny);
+    const int ic = min(max(i, 0), nx), jc = min(max(j, 1), ny);
+    const size_t n = (size_t)jc * (nx + 1) + ic;
+    // the clamped address always holds finite data, so multiplying by the
+    // 0/1 mask zeroes it exactly; the value is used unconditionally, which
+    // keeps the load out of any branch
+    const T msk = ok ? T(1) : T(0);
     if constexpr (sizeof(T) == 4) {
         const float2 w = reinterpret_cast<const float2*>(v)[n];
-        return V2<T>{w.x, w.y};
+        return V2<T>{w.x * msk, w.y * msk};
     } else {
         const double2 w = reinterpret_cast<const double2*>(v)[n];
-        return V2<T>{w.x, w.y};
+        return V2<T>{w.x * msk, w.y * msk};
     }
 }
 
@@ -193,14 +200,16 @@ template <typename T> struct LevelOp {
 
 template <typename T, bool FINE>
 __device__ __forceinline__ Mom<T> load_elem(const LevelOp<T>& L, int i, int j) {
-    if (i < 0 || i >= L.nx || j < 0 || j >= L.ny) return mom_zero<T>();
-    const size_t e = (size_t)j * L.nx + i;
+    const bool ok = (i >= 0) & (i < L.nx) & (j >= 0) & (j < L.ny);
+    const int ic = min(max(i, 0), L.nx - 1), jc = min(max(j, 0), L.ny - 1);
+    const size_t e = (size_t)jc * L.nx + ic;
+    const T msk = ok ? T(1) : T(0);   // see load_node
     if constexpr (FINE) {
-        return mom_const<T>(L.data[e]);
+        return mom_const<T>(L.data[e] * msk);
     } else {
         const size_t ps = (size_t)L.nx * L.ny;
-        return Mom<T>{L.data[e], L.data[ps + e], L.data[2 * ps + e], L.data[3 * ps + e],
-                      L.data[4 * ps + e], L.data[5 * ps + e]};
+        return Mom<T>{L.data[e] * msk, L.data[ps + e] * msk, L.data[2 * ps + e] * msk,
+                      L.data[3 * ps + e] * msk, L.data[4 * ps + e] * msk, L.data[5 * ps + e] * msk};
     }
 }
 

@@ -142,9 +142,10 @@ void drop_graphs(mtomg_ctx* c) {
 // launch geometry
 // ----------------------------------------------------------------------------
 int pick_rows(int strips, int rows_total) {
-    // rows per wave in {1, 2, 4, 8}: the largest that still gives enough
-    // waves to fill 256 CUs a few times over
-    int R = 8;
+    // rows per wave in {1, 2, 4}: the largest that still gives enough waves
+    // to fill 256 CUs a few times over (8 only on request: its register
+    // footprint lowers occupancy)
+    int R = 4;
     while (R > 1 && (long)strips * ((rows_total + R - 1) / R) < 4096) R >>= 1;
     return R;
 }

@@ -42,6 +42,8 @@ __device__ __forceinline__ TileInfo tile_info(const Sweep& s, int n_rows) {
 // mode 0: iteration i >= 1; mode 1: first iteration (beta = 0, no x update);
 // mode 2: only the pending x update (after the last iteration).
 // Geometry: H_L = 1, H_R = 1, 62 output columns per strip.
+// Every kernel first issues all loads of its rows (masked, branch-free),
+// then marches through the rows from registers.
 // ===========================================================================
 template <typename TZ, int R>
 __global__ __launch_bounds__(WG_THREADS) void k_cg_apply(
@@ -81,50 +83,61 @@ __global__ __launch_bounds__(WG_THREADS) void k_cg_apply(
     }
     if (mode == 0) beta = sum_partials(zr_cur, n_zr) / rho_prev;
 
-    auto getp = [&](int jj) -> V2<double> {
-        if (i < 0 || i > nx || jj < 1 || jj > ny) return V2<double>{0.0, 0.0};
-        const V2<TZ> zv = load_node(z, nx, ny, i, jj);
-        V2<double> pv{(double)zv.x, (double)zv.y};
-        V2<double> po{0.0, 0.0};
-        if (mode == 0) {
-            po = load_node(p_old, nx, ny, i, jj);
-            pv.x += beta * po.x;
-            pv.y += beta * po.y;
-        }
-        if (out_lane && jj >= t.j0 && jj < t.j1) {
-            store_node(p_new, nx, i, jj, pv);
-            if (mode == 0) {
-                V2<double> xv = load_node(x, nx, ny, i, jj);
-                xv.x += alpha_prev * po.x;
-                xv.y += alpha_prev * po.y;
-                store_node(x, nx, i, jj, xv);
-            }
-        }
-        return pv;
-    };
-
     double dot = 0.0;
     if (t.j0 < t.j1) {
-        V2<double> pa = getp(t.j0 - 1), pa_r = from_right(pa);
-        V2<double> pb = getp(t.j0), pb_r = from_right(pb);
+        // rows j0-1 .. j0+R of z and p_old, element rows j0-1 .. j0+R-1, x of rows j0 .. j0+R-1
+        V2<TZ> zr[R + 2];
+        V2<double> po[R + 2], xr[R];
+        Mom<double> me[R + 1];
+#pragma unroll
+        for (int s = 0; s < R + 2; ++s) zr[s] = load_node(z, nx, ny, i, t.j0 - 1 + s);
+        if (mode == 0) {
+#pragma unroll
+            for (int s = 0; s < R + 2; ++s) po[s] = load_node(p_old, nx, ny, i, t.j0 - 1 + s);
+#pragma unroll
+            for (int s = 0; s < R; ++s) xr[s] = load_node(x, nx, ny, i, t.j0 + s);
+        } else {
+#pragma unroll
+            for (int s = 0; s < R + 2; ++s) po[s] = V2<double>{0.0, 0.0};
+        }
+#pragma unroll
+        for (int s = 0; s < R + 1; ++s) me[s] = load_elem<double, true>(op, i, t.j0 - 1 + s);
+
+        V2<double> p[R + 2];
+#pragma unroll
+        for (int s = 0; s < R + 2; ++s) {
+            p[s] = V2<double>{(double)zr[s].x + beta * po[s].x, (double)zr[s].y + beta * po[s].y};
+            const int jj = t.j0 - 1 + s;
+            if (s >= 1 && s <= R && out_lane && jj < t.j1) {
+                if (jj >= 1) {
+                    store_node(p_new, nx, i, jj, p[s]);
+                    if (mode == 0) {
+                        const V2<double> xv{xr[s - 1].x + alpha_prev * po[s].x, xr[s - 1].y + alpha_prev * po[s].y};
+                        store_node(x, nx, i, jj, xv);
+                    }
+                } else {
+                    store_node(p_new, nx, i, jj, V2<double>{0.0, 0.0});
+                }
+            }
+        }
         V2<double> f0, f1, f2, f3;
-        elem_force(load_elem<double, true>(op, i, t.j0 - 1), mat, pa, pa_r, pb_r, pb, f0, f1, f2, f3);
+        V2<double> pr_lo = from_right(p[0]), pr_hi = from_right(p[1]);
+        elem_force(me[0], mat, p[0], pr_lo, pr_hi, p[1], f0, f1, f2, f3);
         V2<double> carry = f3 + from_left(f2);
 #pragma unroll
         for (int s = 0; s < R; ++s) {
             const int j = t.j0 + s;
-            pa = pb; pa_r = pb_r;
-            pb = getp(j + 1); pb_r = from_right(pb);
-            elem_force(load_elem<double, true>(op, i, j), mat, pa, pa_r, pb_r, pb, f0, f1, f2, f3);
+            pr_lo = pr_hi;
+            pr_hi = from_right(p[s + 2]);
+            elem_force(me[s + 1], mat, p[s + 1], pr_lo, pr_hi, p[s + 2], f0, f1, f2, f3);
             const V2<double> qv = carry + f0 + from_left(f1);
             carry = f3 + from_left(f2);
             if (out_lane && j < t.j1) {
                 if (j >= 1) {
                     store_node(q, nx, i, j, qv);
-                    dot += pa.x * qv.x + pa.y * qv.y;
+                    dot += p[s + 1].x * qv.x + p[s + 1].y * qv.y;
                 } else {
                     store_node(q, nx, i, j, V2<double>{0.0, 0.0});
-                    store_node(p_new, nx, i, j, V2<double>{0.0, 0.0});
                 }
             }
         }
@@ -151,33 +164,40 @@ __global__ __launch_bounds__(WG_THREADS) void k_residual(
     const int lane = lane_id();
     const int i = t.strip * WOUT - HL + lane;
     const bool out_lane = lane >= HL && lane < HL + WOUT && i <= nx;
-    auto getx = [&](int jj) -> V2<double> {
-        if (!use_x) return V2<double>{0.0, 0.0};
-        return load_node(x, nx, ny, i, jj);
-    };
     double rr = 0.0, ff = 0.0;
     if (t.j0 < t.j1) {
-        V2<double> xa = getx(t.j0 - 1), xa_r = from_right(xa);
-        V2<double> xb = getx(t.j0), xb_r = from_right(xb);
+        V2<double> xr[R + 2], fr[R];
+        Mom<double> me[R + 1];
+        if (use_x) {
+#pragma unroll
+            for (int s = 0; s < R + 2; ++s) xr[s] = load_node(x, nx, ny, i, t.j0 - 1 + s);
+        } else {
+#pragma unroll
+            for (int s = 0; s < R + 2; ++s) xr[s] = V2<double>{0.0, 0.0};
+        }
+#pragma unroll
+        for (int s = 0; s < R; ++s) fr[s] = load_node(f, nx, ny, i, t.j0 + s);
+#pragma unroll
+        for (int s = 0; s < R + 1; ++s) me[s] = load_elem<double, true>(op, i, t.j0 - 1 + s);
         V2<double> f0, f1, f2, f3;
-        elem_force(load_elem<double, true>(op, i, t.j0 - 1), mat, xa, xa_r, xb_r, xb, f0, f1, f2, f3);
+        V2<double> xr_lo = from_right(xr[0]), xr_hi = from_right(xr[1]);
+        elem_force(me[0], mat, xr[0], xr_lo, xr_hi, xr[1], f0, f1, f2, f3);
         V2<double> carry = f3 + from_left(f2);
 #pragma unroll
         for (int s = 0; s < R; ++s) {
             const int j = t.j0 + s;
-            xa = xb; xa_r = xb_r;
-            xb = getx(j + 1); xb_r = from_right(xb);
-            elem_force(load_elem<double, true>(op, i, j), mat, xa, xa_r, xb_r, xb, f0, f1, f2, f3);
+            xr_lo = xr_hi;
+            xr_hi = from_right(xr[s + 2]);
+            elem_force(me[s + 1], mat, xr[s + 1], xr_lo, xr_hi, xr[s + 2], f0, f1, f2, f3);
             const V2<double> kx = carry + f0 + from_left(f1);
             carry = f3 + from_left(f2);
             if (out_lane && j < t.j1) {
                 if (j >= 1) {
-                    const V2<double> fv = load_node(f, nx, ny, i, j);
-                    const V2<double> rv = fv - kx;
+                    const V2<double> rv = fr[s] - kx;
                     if (r) store_node(r, nx, i, j, rv);
                     if (!use_x) store_node(x, nx, i, j, V2<double>{0.0, 0.0});
                     rr += rv.x * rv.x + rv.y * rv.y;
-                    ff += fv.x * fv.x + fv.y * fv.y;
+                    ff += fr[s].x * fr[s].x + fr[s].y * fr[s].y;
                 } else {
                     if (r) store_node(r, nx, i, j, V2<double>{0.0, 0.0});
                     store_node(x, nx, i, j, V2<double>{0.0, 0.0});
@@ -235,62 +255,69 @@ __global__ __launch_bounds__(WG_THREADS) void k_presmooth(
         }
     }
     double rr = 0.0;
-    auto getb = [&](int jj) -> V2<T> {
-        if (!node_col || jj < 1 || jj > ny) return V2<T>{T(0), T(0)};
-        if constexpr (CG) {
-            V2<double> rv = load_node(cg.r_old, nx, ny, i, jj);
-            if (cg.update) {
-                const V2<double> qv = load_node(cg.q, nx, ny, i, jj);
-                rv.x -= alpha * qv.x;
-                rv.y -= alpha * qv.y;
-            }
-            if (out_lane && jj >= t.j0 && jj < t.j1) {
-                if (cg.update) {
-                    store_node(cg.r_new, nx, i, jj, rv);
-                    rr += rv.x * rv.x + rv.y * rv.y;
-                }
-                if constexpr (sizeof(T) == 4) store_node(cg.r32, nx, i, jj, V2<float>{(float)rv.x, (float)rv.y});
-            }
-            return V2<T>{(T)rv.x, (T)rv.y};
-        } else {
-            return load_node(b, nx, ny, i, jj);
-        }
-    };
-
     if (t.j0 < t.j1) {
-        // zero the clamped row of the outputs
-        if (t.j0 == 0 && out_lane) {
-            store_node(u_out, nx, i, 0, V2<T>{T(0), T(0)});
-            if constexpr (CG) {
-                if (cg.update) store_node(cg.r_new, nx, i, 0, V2<double>{0.0, 0.0});
-                if constexpr (sizeof(T) == 4) store_node(cg.r32, nx, i, 0, V2<float>{0.f, 0.f});
+        // right-hand side rows j0-1 .. j0+R, element rows j0-2 .. j0+R
+        V2<T> br[R + 2];
+        Mom<T> me[R + 3];
+        if constexpr (CG) {
+            V2<double> ro[R + 2], qr[R + 2];
+#pragma unroll
+            for (int s = 0; s < R + 2; ++s) ro[s] = load_node(cg.r_old, nx, ny, i, t.j0 - 1 + s);
+            if (cg.update) {
+#pragma unroll
+                for (int s = 0; s < R + 2; ++s) qr[s] = load_node(cg.q, nx, ny, i, t.j0 - 1 + s);
             }
+#pragma unroll
+            for (int s = 0; s < R + 3; ++s) me[s] = load_elem<T, FINE>(op, i, t.j0 - 2 + s);
+#pragma unroll
+            for (int s = 0; s < R + 2; ++s) {
+                V2<double> rv = ro[s];
+                if (cg.update) {
+                    rv.x -= alpha * qr[s].x;
+                    rv.y -= alpha * qr[s].y;
+                }
+                const int jj = t.j0 - 1 + s;
+                if (out_lane && jj >= t.j0 && jj < t.j1) {
+                    if (jj >= 1) {
+                        if (cg.update) {
+                            store_node(cg.r_new, nx, i, jj, rv);
+                            rr += rv.x * rv.x + rv.y * rv.y;
+                        }
+                        if constexpr (sizeof(T) == 4) store_node(cg.r32, nx, i, jj, V2<float>{(float)rv.x, (float)rv.y});
+                    } else {
+                        if (cg.update) store_node(cg.r_new, nx, i, jj, V2<double>{0.0, 0.0});
+                        if constexpr (sizeof(T) == 4) store_node(cg.r32, nx, i, jj, V2<float>{0.f, 0.f});
+                    }
+                }
+                br[s] = V2<T>{(T)rv.x, (T)rv.y};
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < R + 2; ++s) br[s] = load_node(b, nx, ny, i, t.j0 - 1 + s);
+#pragma unroll
+            for (int s = 0; s < R + 3; ++s) me[s] = load_elem<T, FINE>(op, i, t.j0 - 2 + s);
         }
+        if (t.j0 == 0 && out_lane) store_node(u_out, nx, i, 0, V2<T>{T(0), T(0)});
+
         V2<T> d0, d1, d2, d3;
-        // diagonal carry from element row j0-2
-        elem_diag(load_elem<T, FINE>(op, i, t.j0 - 2), mat, d0, d1, d2, d3);
+        elem_diag(me[0], mat, d0, d1, d2, d3);
         V2<T> dcarry = d3 + from_left(d2);
         V2<T> fcarry{T(0), T(0)};
-        Mom<T> m_prev = mom_zero<T>();
         V2<T> u1_prev{T(0), T(0)}, u1r_prev{T(0), T(0)}, b_prev{T(0), T(0)}, D_prev{T(1), T(1)};
 #pragma unroll
         for (int s = 0; s < R + 2; ++s) {
-            const int k = t.j0 - 1 + s;
-            const Mom<T> mk = load_elem<T, FINE>(op, i, k);
-            elem_diag(mk, mat, d0, d1, d2, d3);
+            const int k = t.j0 - 1 + s;   // node row completed by the diagonal stage
+            elem_diag(me[s + 1], mat, d0, d1, d2, d3);
             const V2<T> D = dcarry + d0 + from_left(d1);
             dcarry = d3 + from_left(d2);
-            const V2<T> bk = getb(k);
-            V2<T> u1{T(0), T(0)};
-            if (node_col && k >= 1 && k <= ny) {
-                u1.x = mat.omega * bk.x / D.x;
-                u1.y = mat.omega * bk.y / D.y;
-            }
+            const V2<T> bk = br[s];
+            const bool kok = node_col && k >= 1 && k <= ny;
+            const V2<T> u1{kok ? mat.omega * bk.x / D.x : T(0), kok ? mat.omega * bk.y / D.y : T(0)};
             const V2<T> u1r = from_right(u1);
             if (s >= 1) {
                 // force stage for element row k-1 -> node row k-1 complete
                 V2<T> f0, f1, f2, f3;
-                elem_force(m_prev, mat, u1_prev, u1r_prev, u1r, u1, f0, f1, f2, f3);
+                elem_force(me[s], mat, u1_prev, u1r_prev, u1r, u1, f0, f1, f2, f3);
                 const V2<T> fs = fcarry + f0 + from_left(f1);
                 fcarry = f3 + from_left(f2);
                 const int jr = k - 1;
@@ -303,7 +330,6 @@ __global__ __launch_bounds__(WG_THREADS) void k_presmooth(
                     store_node(u_out, nx, i, jr, uo);
                 }
             }
-            m_prev = mk;
             u1_prev = u1;
             u1r_prev = u1r;
             b_prev = bk;
@@ -358,27 +384,36 @@ __global__ __launch_bounds__(WG_THREADS) void k_restrict(
     const bool out_lane = lane >= HL && lane < HL + WOUT && !(lane & 1) && I <= ncx;
     const bool node_col = i >= 0 && i <= nx;
     if (t.j0 >= t.j1) return;
-    auto getu = [&](int jj) -> V2<T> {
-        if (!u) return V2<T>{T(0), T(0)};
-        return load_node(u, nx, ny, i, jj);
-    };
-    const int jf0 = 2 * t.j0 - 1;   // fine rows computed: jf0 .. jf0 + 2R
-    V2<T> ua = getu(jf0 - 1), ua_r = from_right(ua);
-    V2<T> ub = getu(jf0), ub_r = from_right(ub);
+    constexpr int NF = 2 * R + 1;              // fine rows jf0 .. jf0 + 2R
+    const int jf0 = 2 * t.j0 - 1;
+    V2<T> ur[NF + 2], br[NF];
+    Mom<T> me[NF + 1];
+    if (u) {
+#pragma unroll
+        for (int s = 0; s < NF + 2; ++s) ur[s] = load_node(u, nx, ny, i, jf0 - 1 + s);
+    } else {
+#pragma unroll
+        for (int s = 0; s < NF + 2; ++s) ur[s] = V2<T>{T(0), T(0)};
+    }
+#pragma unroll
+    for (int s = 0; s < NF; ++s) br[s] = load_node(b, nx, ny, i, jf0 + s);
+#pragma unroll
+    for (int s = 0; s < NF + 1; ++s) me[s] = load_elem<T, FINE>(op, i, jf0 - 1 + s);
     V2<T> f0, f1, f2, f3;
-    elem_force(load_elem<T, FINE>(op, i, jf0 - 1), mat, ua, ua_r, ub_r, ub, f0, f1, f2, f3);
+    V2<T> ur_lo = from_right(ur[0]), ur_hi = from_right(ur[1]);
+    elem_force(me[0], mat, ur[0], ur_lo, ur_hi, ur[1], f0, f1, f2, f3);
     V2<T> carry = f3 + from_left(f2);
     V2<T> h_m2{T(0), T(0)}, h_m1{T(0), T(0)};
 #pragma unroll
-    for (int s = 0; s <= 2 * R; ++s) {
+    for (int s = 0; s < NF; ++s) {
         const int j = jf0 + s;
-        ua = ub; ua_r = ub_r;
-        ub = getu(j + 1); ub_r = from_right(ub);
-        elem_force(load_elem<T, FINE>(op, i, j), mat, ua, ua_r, ub_r, ub, f0, f1, f2, f3);
+        ur_lo = ur_hi;
+        ur_hi = from_right(ur[s + 2]);
+        elem_force(me[s + 1], mat, ur[s + 1], ur_lo, ur_hi, ur[s + 2], f0, f1, f2, f3);
         const V2<T> ku = carry + f0 + from_left(f1);
         carry = f3 + from_left(f2);
-        V2<T> rr{T(0), T(0)};
-        if (node_col && j >= 1 && j <= ny) rr = load_node(b, nx, ny, i, j) - ku;
+        const bool jok = node_col && j >= 1 && j <= ny;
+        const V2<T> rr{jok ? br[s].x - ku.x : T(0), jok ? br[s].y - ku.y : T(0)};
         const V2<T> rl = from_left(rr), rrt = from_right(rr);
         const V2<T> h{rr.x + T(0.5) * (rl.x + rrt.x), rr.y + T(0.5) * (rl.y + rrt.y)};
         if ((s & 1) == 0 && s >= 2) {
@@ -391,6 +426,33 @@ __global__ __launch_bounds__(WG_THREADS) void k_restrict(
         }
         h_m2 = h_m1;
         h_m1 = h;
+    }
+}
+
+// v(i, jj) += (P e_c)(i, jj) for the fine rows jj = j0-1 .. j0+R of one
+// lane (bilinear weights; nodes off the grid or on the clamped row get 0).
+// With j0 = 2h + PAR, the coarse rows needed are h-1 .. h-1+NC-1 and the
+// coarse row below/above fine row j0-1+s is at offset ((PAR-1+s)>>1)+1 /
+// ((PAR+s)>>1)+1, both compile-time constants.
+template <typename T, int R, int PAR>
+__device__ __forceinline__ void add_prolongation(V2<T>* vr, const T* __restrict__ ec, int ncx, int ncy, int I0,
+                                                 int I1, int j0, bool node_col, int ny) {
+    constexpr int NC = R / 2 + 3;
+    const int Jb = ((j0 - PAR) >> 1) - 1;
+    V2<T> c0[NC], c1[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        c0[k] = load_node(ec, ncx, ncy, I0, Jb + k);
+        c1[k] = load_node(ec, ncx, ncy, I1, Jb + k);
+    }
+#pragma unroll
+    for (int s = 0; s < R + 2; ++s) {
+        const int k0 = ((PAR - 1 + s) >> 1) + 1, k1 = ((PAR + s) >> 1) + 1;
+        const int jj = j0 - 1 + s;
+        const bool ok = node_col && jj >= 1 && jj <= ny;
+        const T w = ok ? T(0.25) : T(0);
+        vr[s].x += w * ((c0[k0].x + c1[k0].x) + (c0[k1].x + c1[k1].x));
+        vr[s].y += w * ((c0[k0].y + c1[k0].y) + (c0[k1].y + c1[k1].y));
     }
 }
 
@@ -420,55 +482,58 @@ __global__ __launch_bounds__(WG_THREADS) void k_post(
     const bool out_lane = lane >= HL && lane < HL + WOUT && i <= nx;
     const bool node_col = i >= 0 && i <= nx;
     const int I0 = i >> 1, I1 = (i + 1) >> 1;
-    auto getv = [&](int jj) -> V2<T> {
-        if (!node_col || jj < 1 || jj > ny) return V2<T>{T(0), T(0)};
-        V2<T> v = u_in ? load_node(u_in, nx, ny, i, jj) : V2<T>{T(0), T(0)};
-        if constexpr (PROLONG) {
-            const int J0 = jj >> 1, J1 = (jj + 1) >> 1;
-            const V2<T> a = load_node(ec, ncx, ncy, I0, J0);
-            const V2<T> bb = load_node(ec, ncx, ncy, I1, J0);
-            const V2<T> c = load_node(ec, ncx, ncy, I0, J1);
-            const V2<T> d = load_node(ec, ncx, ncy, I1, J1);
-            v.x += T(0.25) * ((a.x + bb.x) + (c.x + d.x));
-            v.y += T(0.25) * ((a.y + bb.y) + (c.y + d.y));
-        }
-        return v;
-    };
     double dot = 0.0;
     if (t.j0 < t.j1) {
-        V2<T> va = getv(t.j0 - 1), va_r = from_right(va);
-        V2<T> vb = getv(t.j0), vb_r = from_right(vb);
-        V2<T> f0, f1, f2, f3, d0, d1, d2, d3;
-        {
-            const Mom<T> m = load_elem<T, FINE>(op, i, t.j0 - 1);
-            elem_force(m, mat, va, va_r, vb_r, vb, f0, f1, f2, f3);
-            elem_diag(m, mat, d0, d1, d2, d3);
+        // v rows j0-1 .. j0+R, element rows j0-1 .. j0+R-1, b (and r) rows j0 .. j0+R-1
+        V2<T> vr[R + 2], br[R];
+        Mom<T> me[R + 1];
+        V2<double> rr64[DOT ? R : 1];
+        if (u_in) {
+#pragma unroll
+            for (int s = 0; s < R + 2; ++s) vr[s] = load_node(u_in, nx, ny, i, t.j0 - 1 + s);
+        } else {
+#pragma unroll
+            for (int s = 0; s < R + 2; ++s) vr[s] = V2<T>{T(0), T(0)};
         }
+        if constexpr (PROLONG) {
+            // the parity of j0 is uniform over the wave: one branch, then
+            // compile-time indices into the coarse rows held in registers
+            if (t.j0 & 1) add_prolongation<T, R, 1>(vr, ec, ncx, ncy, I0, I1, t.j0, node_col, ny);
+            else add_prolongation<T, R, 0>(vr, ec, ncx, ncy, I0, I1, t.j0, node_col, ny);
+        }
+#pragma unroll
+        for (int s = 0; s < R; ++s) br[s] = load_node(b, nx, ny, i, t.j0 + s);
+        if constexpr (DOT) {
+#pragma unroll
+            for (int s = 0; s < R; ++s) rr64[s] = load_node(r64, nx, ny, i, t.j0 + s);
+        }
+#pragma unroll
+        for (int s = 0; s < R + 1; ++s) me[s] = load_elem<T, FINE>(op, i, t.j0 - 1 + s);
+
+        V2<T> f0, f1, f2, f3, d0, d1, d2, d3;
+        V2<T> vr_lo = from_right(vr[0]), vr_hi = from_right(vr[1]);
+        elem_force(me[0], mat, vr[0], vr_lo, vr_hi, vr[1], f0, f1, f2, f3);
+        elem_diag(me[0], mat, d0, d1, d2, d3);
         V2<T> fcarry = f3 + from_left(f2);
         V2<T> dcarry = d3 + from_left(d2);
 #pragma unroll
         for (int s = 0; s < R; ++s) {
             const int j = t.j0 + s;
-            va = vb; va_r = vb_r;
-            vb = getv(j + 1); vb_r = from_right(vb);
-            const Mom<T> m = load_elem<T, FINE>(op, i, j);
-            elem_force(m, mat, va, va_r, vb_r, vb, f0, f1, f2, f3);
-            elem_diag(m, mat, d0, d1, d2, d3);
+            vr_lo = vr_hi;
+            vr_hi = from_right(vr[s + 2]);
+            elem_force(me[s + 1], mat, vr[s + 1], vr_lo, vr_hi, vr[s + 2], f0, f1, f2, f3);
+            elem_diag(me[s + 1], mat, d0, d1, d2, d3);
             const V2<T> fs = fcarry + f0 + from_left(f1);
             const V2<T> D = dcarry + d0 + from_left(d1);
             fcarry = f3 + from_left(f2);
             dcarry = d3 + from_left(d2);
             if (out_lane && j < t.j1) {
                 if (j >= 1) {
-                    const V2<T> bv = load_node(b, nx, ny, i, j);
                     V2<T> uo;
-                    uo.x = va.x + mat.omega * (bv.x - fs.x) / D.x;
-                    uo.y = va.y + mat.omega * (bv.y - fs.y) / D.y;
+                    uo.x = vr[s + 1].x + mat.omega * (br[s].x - fs.x) / D.x;
+                    uo.y = vr[s + 1].y + mat.omega * (br[s].y - fs.y) / D.y;
                     store_node(u_out, nx, i, j, uo);
-                    if constexpr (DOT) {
-                        const V2<double> rv = load_node(r64, nx, ny, i, j);
-                        dot += (double)uo.x * rv.x + (double)uo.y * rv.y;
-                    }
+                    if constexpr (DOT) dot += (double)uo.x * rr64[s].x + (double)uo.y * rr64[s].y;
                 } else {
                     store_node(u_out, nx, i, j, V2<T>{T(0), T(0)});
                 }
@@ -482,8 +547,8 @@ __global__ __launch_bounds__(WG_THREADS) void k_post(
 }
 
 // ===========================================================================
-// Plain stiffness apply q = K_l u in the level precision (test hook and
-// building block): Geometry as k_cg_apply.
+// Plain stiffness apply q = K_l u (or its diagonal) in the level precision
+// (test hook and building block).  Geometry as k_cg_apply.
 // ===========================================================================
 template <typename T, bool FINE, bool DIAG, int R>
 __global__ __launch_bounds__(WG_THREADS) void k_apply(LevelOp<T> op, Mat<T> mat, Sweep sw,
@@ -496,24 +561,24 @@ __global__ __launch_bounds__(WG_THREADS) void k_apply(LevelOp<T> op, Mat<T> mat,
     const int i = t.strip * WOUT - HL + lane;
     const bool out_lane = lane >= HL && lane < HL + WOUT && i <= nx;
     if (t.j0 >= t.j1) return;
-    auto getu = [&](int jj) -> V2<T> { return DIAG ? V2<T>{T(0), T(0)} : load_node(u, nx, ny, i, jj); };
-    V2<T> ua = getu(t.j0 - 1), ua_r = from_right(ua);
-    V2<T> ub = getu(t.j0), ub_r = from_right(ub);
+    V2<T> ur[R + 2];
+    Mom<T> me[R + 1];
+#pragma unroll
+    for (int s = 0; s < R + 2; ++s) ur[s] = DIAG ? V2<T>{T(0), T(0)} : load_node(u, nx, ny, i, t.j0 - 1 + s);
+#pragma unroll
+    for (int s = 0; s < R + 1; ++s) me[s] = load_elem<T, FINE>(op, i, t.j0 - 1 + s);
     V2<T> f0, f1, f2, f3;
-    {
-        const Mom<T> m = load_elem<T, FINE>(op, i, t.j0 - 1);
-        if (DIAG) elem_diag(m, mat, f0, f1, f2, f3);
-        else elem_force(m, mat, ua, ua_r, ub_r, ub, f0, f1, f2, f3);
-    }
+    V2<T> ur_lo = from_right(ur[0]), ur_hi = from_right(ur[1]);
+    if (DIAG) elem_diag(me[0], mat, f0, f1, f2, f3);
+    else elem_force(me[0], mat, ur[0], ur_lo, ur_hi, ur[1], f0, f1, f2, f3);
     V2<T> carry = f3 + from_left(f2);
 #pragma unroll
     for (int s = 0; s < R; ++s) {
         const int j = t.j0 + s;
-        ua = ub; ua_r = ub_r;
-        ub = getu(j + 1); ub_r = from_right(ub);
-        const Mom<T> m = load_elem<T, FINE>(op, i, j);
-        if (DIAG) elem_diag(m, mat, f0, f1, f2, f3);
-        else elem_force(m, mat, ua, ua_r, ub_r, ub, f0, f1, f2, f3);
+        ur_lo = ur_hi;
+        ur_hi = from_right(ur[s + 2]);
+        if (DIAG) elem_diag(me[s + 1], mat, f0, f1, f2, f3);
+        else elem_force(me[s + 1], mat, ur[s + 1], ur_lo, ur_hi, ur[s + 2], f0, f1, f2, f3);
         V2<T> qv = carry + f0 + from_left(f1);
         carry = f3 + from_left(f2);
         if (out_lane && j < t.j1) {
