@@ -77,10 +77,10 @@ void launch_moments_coarsen(hipStream_t st, const double* momf, int nxf, int nyf
                             float* mom32);
 constexpr int COARSE_NB = 32;   // block size of the coarse factorisation
 void launch_assemble_dense(hipStream_t st, bool fine, LevelOp<double> op, Mat<double> mat, double* A, int ld);
-// A (np x np, n0 used, identity padding written here) -> L in place,
-// Dinv = inverses of the diagonal blocks, W = L^{-1}, Ainv = A^{-1}.
+// A (np x np, n0 used, identity padding written here; overwritten) ->
+// Dinv = inverses of the diagonal blocks of L, W = L^{-1}, Ainv = A^{-1}.
 void launch_coarse_factor(hipStream_t st, double* A, int n0, int np, double* Dinv, double* W, double* Ainv,
-                          int* status);
+                          int* status, double* scratch /* np x np */);
 template <typename T>
 void launch_fill(hipStream_t st, T* p, size_t n, T v);
 void launch_cast_f32(hipStream_t st, const double* a, float* b, size_t n);

@@ -11,12 +11,24 @@
 
 namespace mtomg {
 
+// x^p; repeated multiplication when p is a small whole number (the usual
+// SIMP exponents), pow otherwise.
+__device__ __forceinline__ double powp(double x, double p) {
+    const int n = (int)p;
+    if ((double)n == p && n >= 0 && n <= 8) {
+        double r = 1.0;
+        for (int k = 0; k < n; ++k) r *= x;
+        return r;
+    }
+    return pow(x, p);
+}
+
 __global__ void k_interp(const double* __restrict__ x, Phases ph, int n_e, double* __restrict__ E64,
                          float* __restrict__ E32) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n_e) return;
     double E = ph.E_min;
-    for (int k = 0; k < ph.m; ++k) E += pow(x[(size_t)e * ph.m + k], ph.penal) * ph.dE[k];
+    for (int k = 0; k < ph.m; ++k) E += powp(x[(size_t)e * ph.m + k], ph.penal) * ph.dE[k];
     E64[e] = E;
     if (E32) E32[e] = (float)E;
 }
@@ -118,140 +130,179 @@ __device__ __forceinline__ void blk_load(double (*S)[NB + 1], const double* __re
     }
 }
 
-// Unblocked Cholesky of a block held in LDS (lower triangle), then its
-// inverse Li (lower).  Returns false if a pivot is not positive.
-__device__ bool blk_potrf_inv(double (*L)[NB + 1], double (*Li)[NB + 1]) {
-    __shared__ int bad;
-    if (threadIdx.x == 0) bad = 0;
-    __syncthreads();
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// Cholesky of a 32x32 SPD block (read from LDS, lower triangle) and the
+// inverse of its factor, by one wave with the block in registers: lane r
+// holds row r, column values are broadcast with readlane.  Writes the
+// inverse to Li (LDS).  Returns false if a pivot is not positive.
+__device__ bool wave_potrf_inv(double (*S)[NB + 1], double (*Li)[NB + 1]) {
+    const int lane = threadIdx.x & 63;
+    const int r = lane & (NB - 1);
+    double a[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) a[c] = S[r][c];
+    bool ok = true;
+#pragma unroll
     for (int k = 0; k < NB; ++k) {
-        if (threadIdx.x == 0) {
-            const double a = L[k][k];
-            if (a > 0.0) L[k][k] = sqrt(a);
-            else bad = 1;
-        }
-        __syncthreads();
-        if (bad) return false;
-        const double piv = L[k][k];
-        if (threadIdx.x > k && threadIdx.x < NB) L[threadIdx.x][k] /= piv;
-        __syncthreads();
-        for (int t = threadIdx.x; t < NB * NB; t += 256) {
-            const int r = t / NB, c = t % NB;
-            if (c > k && r >= c) L[r][c] -= L[r][k] * L[c][k];
-        }
-        __syncthreads();
-    }
-    // Li = L^{-1}: thread c solves column c by forward substitution
-    if (threadIdx.x < NB) {
-        const int c = threadIdx.x;
-        for (int r = 0; r < NB; ++r) {
-            if (r < c) { Li[r][c] = 0.0; continue; }
-            double s = (r == c) ? 1.0 : 0.0;
-            for (int t = c; t < r; ++t) s -= L[r][t] * Li[t][c];
-            Li[r][c] = s / L[r][r];
+        const double d = readlane_d(a[k], k);
+        ok = ok && (d > 0.0);
+        const double piv = sqrt(d > 0.0 ? d : 1.0);
+        a[k] = (r == k) ? piv : ((r > k) ? a[k] / piv : a[k]);
+#pragma unroll
+        for (int c = k + 1; c < NB; ++c) {
+            const double lck = readlane_d(a[k], c);
+            a[c] = (r >= c) ? a[c] - a[k] * lck : a[c];
         }
     }
-    __syncthreads();
+    if (!ok) return false;
+    // column c = r of L^{-1} by forward substitution; lane r (< 32) keeps its
+    // column in Li and only ever reads back its own entries
+#pragma unroll
+    for (int rr = 0; rr < NB; ++rr) {
+        double s = (rr == r) ? 1.0 : 0.0;
+#pragma unroll
+        for (int t = 0; t < rr; ++t) s -= readlane_d(a[t], rr) * Li[t][r];
+        const double v = s / readlane_d(a[rr], rr);
+        if (lane < NB) Li[rr][r] = v;
+    }
+    __builtin_amdgcn_wave_barrier();
     return true;
 }
 
-// Left-looking block column kb: workgroup b updates block row ib = kb + b,
-// A[ib,kb] -= sum_{t<kb} L[ib,t] L[kb,t]^T, factors the (identically
-// updated) diagonal block itself and forms L[ib,kb] = A[ib,kb] L_kk^{-T}.
-// Workgroup 0 writes the inverse of L_kk (Dinv[kb]).
-__global__ __launch_bounds__(256) void k_chol_col(double* __restrict__ A, int np, int kb, double* __restrict__ Dinv,
-                                                  int* __restrict__ status) {
-    __shared__ double Lk[NB][NB + 1], Lt[NB][NB + 1], Akk[NB][NB + 1], Aik[NB][NB + 1], Li[NB][NB + 1];
-    const int ib = kb + blockIdx.x;
+// C (LDS) = X Y^T for 32x32 blocks in LDS; thread (r, c4..c4+3).
+__device__ __forceinline__ void blk_gemm_nt(double (*C)[NB + 1], double (*X)[NB + 1], double (*Y)[NB + 1]) {
     int r, c4;
     blk_coords(r, c4);
-    double akk[4] = {0, 0, 0, 0}, aik[4] = {0, 0, 0, 0};
-    for (int t = 0; t < kb; ++t) {
-        blk_load(Lk, A, np, kb, t);
-        blk_load(Lt, A, np, ib, t);
-        __syncthreads();
-        for (int s = 0; s < NB; ++s) {
-            const double lr = Lk[r][s], tr = Lt[r][s];
+    double acc[4] = {0, 0, 0, 0};
+    for (int s = 0; s < NB; ++s) {
+        const double xr = X[r][s];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                akk[q] += lr * Lk[c4 + q][s];
-                aik[q] += tr * Lk[c4 + q][s];
+        for (int q = 0; q < 4; ++q) acc[q] += xr * Y[c4 + q][s];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) C[r][c4 + q] = acc[q];
+}
+
+// Right-looking blocked Cholesky, launch k (k >= 1): workgroup (ib, jb),
+// ib >= jb >= k, forms L[ib,k-1] = A[ib,k-1] Linv_{k-1}^T and L[jb,k-1],
+// applies A[ib,jb] -= L[ib,k-1] L[jb,k-1]^T; workgroups with jb == k store
+// L[ib,k-1]; the one with ib == jb == k then factors the finished diagonal
+// block k (Dinv[k] = its factor's inverse).  Launch 0 only factors block 0.
+// Every block read in a launch is written by an earlier launch.
+__global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ A, int np, int k, double* __restrict__ Dinv,
+                                                   double* __restrict__ Lbuf, int* __restrict__ status) {
+    __shared__ double Ai[NB][NB + 1], Aj[NB][NB + 1], Dk[NB][NB + 1], Pi[NB][NB + 1], Pj[NB][NB + 1];
+    const int nblk = np / NB;
+    int r, c4;
+    blk_coords(r, c4);
+    if (k == 0) {
+        blk_load(Ai, A, np, 0, 0);
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            if (!wave_potrf_inv(Ai, Pi)) {
+                if (threadIdx.x == 0) *status = 1;
             }
         }
         __syncthreads();
-    }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        Akk[r][c4 + q] = A[(size_t)(kb * NB + r) * np + kb * NB + c4 + q] - akk[q];
-        Aik[r][c4 + q] = A[(size_t)(ib * NB + r) * np + kb * NB + c4 + q] - aik[q];
+        for (int q = 0; q < 4; ++q) Dinv[r * NB + c4 + q] = Pi[r][c4 + q];
+        return;
     }
+    // triangular index -> (ib, jb) over the trailing blocks k..nblk-1
+    int a = 0, rem = blockIdx.x;
+    while (rem > a) { rem -= a + 1; ++a; }
+    const int ib = k + a, jb = k + rem;
+    blk_load(Ai, A, np, ib, k - 1);
+    if (jb != ib) blk_load(Aj, A, np, jb, k - 1);
+    for (int t = threadIdx.x; t < NB * NB; t += 256) Dk[t / NB][t % NB] = Dinv[(size_t)(k - 1) * NB * NB + t];
     __syncthreads();
-    if (!blk_potrf_inv(Akk, Li)) {
-        if (threadIdx.x == 0) *status = 1;
-        return;
-    }
-    if (blockIdx.x == 0) {
-        // The factored diagonal block is not stored: other workgroups of this
-        // launch still read the unfactored A[kb,kb], and later steps only use
-        // off-diagonal blocks of L and the block inverses.
+    blk_gemm_nt(Pi, Ai, Dk);
+    if (jb != ib) blk_gemm_nt(Pj, Aj, Dk);
+    __syncthreads();
+    double (*Lj)[NB + 1] = (jb != ib) ? Pj : Pi;
+    if (jb == k) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Dinv[(size_t)kb * NB * NB + r * NB + c4 + q] = Li[r][c4 + q];
+        for (int q = 0; q < 4; ++q) Lbuf[(size_t)(ib * NB + r) * np + (k - 1) * NB + c4 + q] = Pi[r][c4 + q];
+    }
+    double upd[4] = {0, 0, 0, 0};
+    for (int s = 0; s < NB; ++s) {
+        const double lr = Pi[r][s];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) upd[q] += lr * Lj[c4 + q][s];
+    }
+    double* blk = A + (size_t)(ib * NB + r) * np + jb * NB + c4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) blk[q] -= upd[q];
+    if (ib == k && jb == k) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Ai[r][c4 + q] = blk[q];
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            if (!wave_potrf_inv(Ai, Dk)) {
+                if (threadIdx.x == 0) *status = 1;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Dinv[(size_t)k * NB * NB + r * NB + c4 + q] = Dk[r][c4 + q];
+    }
+}
+
+// W = L^{-1} by right-looking block substitution.  Launch t: workgroup
+// (i, j), i > t >= j: S[i,j] += L[i,t] W[t,j]; for i == t+1 the sum is
+// complete and W[t+1,j] = -L_{t+1}^{-1} S[t+1,j].  W's diagonal blocks are
+// the block inverses, set beforehand; S starts at zero.
+__global__ __launch_bounds__(256) void k_trinv_step(const double* __restrict__ Lbuf, const double* __restrict__ Dinv,
+                                                    double* __restrict__ W, double* __restrict__ S, int np, int t) {
+    __shared__ double La[NB][NB + 1], Wb[NB][NB + 1], Di[NB][NB + 1], Sb[NB][NB + 1];
+    const int nblk = np / NB;
+    const int j = blockIdx.x % (t + 1);
+    const int i = t + 1 + blockIdx.x / (t + 1);
+    if (i >= nblk) return;
+    int r, c4;
+    blk_coords(r, c4);
+    blk_load(La, Lbuf, np, i, t);
+    blk_load(Wb, W, np, t, j);
+    __syncthreads();
+    double acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = S[(size_t)(i * NB + r) * np + j * NB + c4 + q];
+    for (int s = 0; s < NB; ++s) {
+        const double lr = La[r][s];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] += lr * Wb[s][c4 + q];
+    }
+    if (i != t + 1) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) S[(size_t)(i * NB + r) * np + j * NB + c4 + q] = acc[q];
         return;
     }
-    // L[ib,kb] = Aik Li^T
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Sb[r][c4 + q] = acc[q];
+    for (int x = threadIdx.x; x < NB * NB; x += 256) Di[x / NB][x % NB] = Dinv[(size_t)i * NB * NB + x];
+    __syncthreads();
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int c = c4 + q;
         double s = 0.0;
-        for (int t = 0; t <= c; ++t) s += Aik[r][t] * Li[c][t];
-        A[(size_t)(ib * NB + r) * np + kb * NB + c] = s;
+        for (int u = 0; u <= r; ++u) s += Di[r][u] * Sb[u][c];
+        W[(size_t)(i * NB + r) * np + j * NB + c] = -s;
     }
 }
 
-// W = L^{-1} by block forward substitution, one workgroup per block column jb:
-// W[jb,jb] = L_jj^{-1}; W[ib,jb] = -L_ii^{-1} sum_{t=jb}^{ib-1} L[ib,t] W[t,jb].
-__global__ __launch_bounds__(256) void k_trinv_blk(const double* __restrict__ A, const double* __restrict__ Dinv,
-                                                   double* __restrict__ W, int np) {
-    __shared__ double La[NB][NB + 1], Wb[NB][NB + 1], S[NB][NB + 1], Di[NB][NB + 1];
-    const int nblk = np / NB;
-    const int jb = blockIdx.x;
-    int r, c4;
-    blk_coords(r, c4);
-    // diagonal block
-#pragma unroll
-    for (int q = 0; q < 4; ++q) W[(size_t)(jb * NB + r) * np + jb * NB + c4 + q] = Dinv[(size_t)jb * NB * NB + r * NB + c4 + q];
-    // blocks above the diagonal are zero
-    for (int ib = 0; ib < jb; ++ib)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) W[(size_t)(ib * NB + r) * np + jb * NB + c4 + q] = 0.0;
-    __threadfence();
-    __syncthreads();
-    for (int ib = jb + 1; ib < nblk; ++ib) {
-        double acc[4] = {0, 0, 0, 0};
-        for (int t = jb; t < ib; ++t) {
-            blk_load(La, A, np, ib, t);
-            blk_load(Wb, W, np, t, jb);
-            __syncthreads();
-            for (int s = 0; s < NB; ++s) {
-                const double lr = La[r][s];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) acc[q] += lr * Wb[s][c4 + q];
-            }
-            __syncthreads();
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) S[r][c4 + q] = acc[q];
-        for (int k = threadIdx.x; k < NB * NB; k += 256) Di[k / NB][k % NB] = Dinv[(size_t)ib * NB * NB + k];
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int c = c4 + q;
-            double s = 0.0;
-            for (int t = 0; t <= r; ++t) s += Di[r][t] * S[t][c];
-            W[(size_t)(ib * NB + r) * np + jb * NB + c] = -s;
-        }
-        __threadfence();
-        __syncthreads();
+// W diagonal blocks = block inverses, everything above them zero.
+__global__ void k_trinv_init(const double* __restrict__ Dinv, double* __restrict__ W, int np) {
+    const size_t n = (size_t)np * np;
+    for (size_t x = blockIdx.x * (size_t)blockDim.x + threadIdx.x; x < n; x += (size_t)gridDim.x * blockDim.x) {
+        const int row = (int)(x / np), col = (int)(x % np);
+        const int bi = row / NB, bj = col / NB;
+        W[x] = (bi == bj) ? Dinv[(size_t)bi * NB * NB + (row % NB) * NB + (col % NB)] : 0.0;
     }
 }
 
@@ -314,7 +365,7 @@ __global__ void k_grad(const double* __restrict__ U, const double* __restrict__ 
                      (u2.x * f2.x + u2.y * f2.y) + (u3.x * f3.x + u3.y * f3.y);
     for (int k = 0; k < ph.m; ++k) {
         const double xv = x[(size_t)e * ph.m + k];
-        dcdx[(size_t)e * ph.m + k] = -ph.penal * pow(xv, ph.penal - 1.0) * ph.dE[k] * w;
+        dcdx[(size_t)e * ph.m + k] = -ph.penal * powp(xv, ph.penal - 1.0) * ph.dE[k] * w;
     }
 }
 
@@ -356,13 +407,23 @@ void launch_assemble_dense(hipStream_t st, bool fine, LevelOp<double> op, Mat<do
     else hipLaunchKernelGGL(k_assemble_dense<false>, dim3(blocks_for(n, 256)), dim3(256), 0, st, op, mat, A, ld);
 }
 void launch_coarse_factor(hipStream_t st, double* A, int n0, int np, double* Dinv, double* W, double* Ainv,
-                          int* status) {
+                          int* status, double* scratch) {
     if (np > n0)
         hipLaunchKernelGGL(k_pad_identity, dim3(blocks_for(np - n0, 256)), dim3(256), 0, st, A, n0, np);
     const int nblk = np / NB;
-    for (int kb = 0; kb < nblk; ++kb)
-        hipLaunchKernelGGL(k_chol_col, dim3(nblk - kb), dim3(256), 0, st, A, np, kb, Dinv, status);
-    hipLaunchKernelGGL(k_trinv_blk, dim3(nblk), dim3(256), 0, st, A, Dinv, W, np);
+    double* Lbuf = scratch;   // np x np: off-diagonal blocks of L, then reused as the S accumulator
+    for (int k = 0; k < nblk; ++k) {
+        const int m = nblk - k;
+        hipLaunchKernelGGL(k_chol_step, dim3(k == 0 ? 1 : m * (m + 1) / 2), dim3(256), 0, st, A, np, k, Dinv, Lbuf,
+                           status);
+    }
+    // A is free now: it accumulates the sums S of the block substitution
+    hipLaunchKernelGGL(k_trinv_init, dim3(std::min<size_t>(blocks_for((size_t)np * np, 256), 2048)), dim3(256), 0, st,
+                       Dinv, W, np);
+    hipLaunchKernelGGL(k_fill<double>, dim3(std::min<size_t>(blocks_for((size_t)np * np, 256), 2048)), dim3(256), 0,
+                       st, A, (size_t)np * np, 0.0);
+    for (int t = 0; t + 1 < nblk; ++t)
+        hipLaunchKernelGGL(k_trinv_step, dim3((nblk - 1 - t) * (t + 1)), dim3(256), 0, st, Lbuf, Dinv, W, A, np, t);
     hipLaunchKernelGGL(k_gram_blk, dim3(nblk * (nblk + 1) / 2), dim3(256), 0, st, W, Ainv, np);
 }
 template <typename T>
