@@ -1,0 +1,173 @@
+"""Parity at the full workload sizes, in the configuration bench.py times.
+
+* 256 x 256, binary 1e9 contrast (5 levels, FP64): against the oracle's
+  direct solve element by element, and the adjoint gradient against central
+  finite differences on 64 solid (element, phase) pairs plus 8 pairs whose
+  gradient is ~0.  At this contrast the residual 1e-8 leaves an error of
+  ~6e-6 in u (condition number ~1e9), so the u comparison solves to 1e-10.
+* 1024 x 1024 smooth field (7 levels, FP32 cycle) and 2048 x 2048
+  near-binary 4-phase field (8 levels, FP32 cycle): against oracle samples
+  written by tests/golden/make_golden.py (compliance, u at 512 nodes,
+  gradient at 64 pairs), and properties that hold at any size: the
+  oracle's energy identity c = sum_e E_e u_e^T K0 u_e on the GPU field, the
+  oracle's nodal residual at sampled nodes, FP32-cycle and FP64-cycle
+  solutions agreeing.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import fe, solve
+from tests.gpu_util import gpu_solver, rel
+from workloads import make_problem
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------------------
+# 256 x 256 high contrast
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def wall256():
+    p = make_problem("wall256")
+    print("[wall256] oracle direct solve", flush=True)
+    ref = solve.solve_direct(p.nelx, p.nely, p.x, p.E_phase, p.E_min, p.penal, p.nu, p.F)
+    return p, ref
+
+
+def test_wall256_fp64_matches_direct_solve(wall256):
+    p, ref = wall256
+    s = gpu_solver(p, "fp64")
+    st = s.solve(1e-8, 20000)[0]
+    assert st["status"] == 0 and st["relres_true"] <= 1.05e-8, st
+    st = s.solve(1e-10, 20000)[0]
+    assert st["status"] == 0, st
+    U = s.U(0).cpu().numpy()
+    assert rel(U, ref.U) <= 1e-6
+    c, dc = s.compliance_and_grad(0)
+    assert c.item() == pytest.approx(ref.c[0], rel=1e-7)
+    assert rel(dc.cpu().numpy(), ref.dcdx) <= 1e-5
+    print(f"[wall256] iters={st['iters']} relres={st['relres_true']:.2e} err={rel(U, ref.U):.2e}")
+
+
+def test_wall256_fp32_cycle_converges(wall256):
+    p, ref = wall256
+    s = gpu_solver(p, "fp32mg")
+    st = s.solve(1e-8, 20000)[0]
+    assert st["status"] == 0 and st["relres_true"] <= 1.05e-8, st
+    c, _ = s.compliance_and_grad(0, grad=False)
+    assert c.item() == pytest.approx(ref.c[0], rel=1e-6)
+
+
+@pytest.mark.parametrize("chunk", range(9))
+def test_wall256_gradient_central_differences(wall256, chunk):
+    p, _ = wall256
+    pairs = np.concatenate([p.fd_elements, p.fd_zero_pairs])[chunk * 8:(chunk + 1) * 8]
+    h = 1e-6
+    s = gpu_solver(p, "fp64")
+    s.solve(1e-10, 20000)
+    _, g = s.compliance_and_grad(0)
+    g = g[0].cpu().numpy().reshape(-1, p.m)
+    gmax = np.abs(g).max()
+    KE = fe.element_stiffness(p.nu)
+    dofs = fe.element_dof_map(p.nelx, p.nely)
+    for e, ph in pairs:
+        out = []
+        for sign in (+1, -1):
+            x = p.x.copy()
+            x.reshape(-1, p.m)[e, ph] += sign * h
+            s.set_densities(0, torch.from_numpy(x))
+            st = s.solve(1e-10, 20000)[0]
+            assert st["status"] == 0, st
+            c, _ = s.compliance_and_grad(0, grad=False)
+            E = fe.interpolate_modulus(x.reshape(-1, p.m)[e], p.E_phase, p.E_min, p.penal)
+            out.append((c.item(), E, s.U(0).cpu().numpy().ravel()[dofs[e]]))
+        (cp, Ep, up), (cm, Em, um) = out
+        # exact difference for a symmetric K changed in one element:
+        # c+ - c- = -(E+ - E-) u-_e^T K0 u+_e  (no cancellation)
+        fd = -(Ep - Em) * (um @ KE @ up) / (2 * h)
+        naive = (cp - cm) / (2 * h)
+        tol = 1e-5 * max(abs(g[e, ph]), 1e-6 * gmax)
+        assert abs(fd - g[e, ph]) <= tol, (e, ph, fd, g[e, ph], naive)
+        print(f"[fd] e={e} ph={ph} grad={g[e, ph]:.6e} fd={fd:.6e} naive={naive:.6e}")
+
+
+# ---------------------------------------------------------------------------
+# 1024 x 1024 and 2048 x 2048 against stored oracle samples
+# ---------------------------------------------------------------------------
+def _samples(name):
+    path = os.path.join(GOLD, f"{name}_samples.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated (tests/golden/make_golden.py)")
+    return json.load(open(path))
+
+
+def _nodal_residual(p, U, nodes):
+    """Oracle f - K u at the given nodes, element by element (free DOFs)."""
+    KE = fe.element_stiffness(p.nu)
+    E = fe.interpolate_modulus(p.x, p.E_phase, p.E_min, p.penal)
+    nx = p.nelx
+    Uf = U.ravel()
+    res = []
+    for n in nodes:
+        i, j = n % (nx + 1), n // (nx + 1)
+        if j == 0:
+            continue
+        r = p.F[0].reshape(-1, 2)[n].copy()
+        for ej in (j - 1, j):
+            for ei in (i - 1, i):
+                if 0 <= ei < nx and 0 <= ej < p.nely:
+                    n0 = ej * (nx + 1) + ei
+                    gn = [n0, n0 + 1, n0 + nx + 2, n0 + nx + 1]
+                    ue = np.concatenate([Uf[2 * q:2 * q + 2] for q in gn])
+                    loc = gn.index(n)
+                    r -= E[ej, ei] * (KE[2 * loc:2 * loc + 2] @ ue)
+        res.append(r)
+    return np.array(res)
+
+
+@pytest.mark.parametrize("name", ["wall1024", "wall2048"])
+def test_fullsize_fp32_cycle_against_oracle_samples(name):
+    gold = _samples(name)
+    p = make_problem(name)
+    print(f"[{name}] gpu solve (FP32 cycle)", flush=True)
+    s = gpu_solver(p, "fp32mg")
+    st = s.solve(1e-8, 1000)[0]
+    assert st["status"] == 0 and st["relres_true"] <= 1.05e-8, st
+    U = s.U(0).cpu().numpy()
+    Uf = U.reshape(-1, 2)
+    un = np.array(gold["u_nodes"])
+    assert rel(Uf[gold["nodes"]], un) <= 1e-6
+    assert np.linalg.norm(U) == pytest.approx(gold["u_norm"], rel=1e-6)
+    c, dc = s.compliance_and_grad(0)
+    assert c.item() == pytest.approx(gold["compliance"], rel=1e-7)
+    g = dc[0].cpu().numpy().reshape(-1, p.m)[gold["grad_elems"], gold["grad_phases"]]
+    assert rel(g, gold["grad"]) <= 1e-5
+    # oracle energy identity on the GPU displacements
+    E = fe.interpolate_modulus(p.x, p.E_phase, p.E_min, p.penal)
+    energy = np.sum(E * fe.element_energies(U[0], p.nelx, p.nely, p.nu))
+    assert c.item() == pytest.approx(energy, rel=1e-7)
+    # oracle nodal residual at 2000 sampled nodes is within the global bound
+    nodes = np.random.default_rng(7).choice((p.nelx + 1) * (p.nely + 1), 2000, replace=False)
+    r = _nodal_residual(p, U[0], nodes)
+    assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(p.F[0])
+    print(f"[{name}] iters={st['iters']} solve_ms={st['t_solve_ms']:.2f} relres={st['relres_true']:.2e} "
+          f"c={c.item():.12g} (oracle {gold['compliance']:.12g})")
+
+
+def test_wall1024_fp32_cycle_agrees_with_fp64_cycle():
+    p = make_problem("wall1024")
+    s32 = gpu_solver(p, "fp32mg")
+    s64 = gpu_solver(p, "fp64")
+    st32 = s32.solve(1e-8, 1000)[0]
+    st64 = s64.solve(1e-8, 1000)[0]
+    assert st32["status"] == 0 and st64["status"] == 0
+    d = float(torch.linalg.norm(s32.U(0) - s64.U(0)) / torch.linalg.norm(s64.U(0)))
+    assert d <= 1e-6
+    print(f"[wall1024] fp32 cycle {st32['iters']} it {st32['t_solve_ms']:.2f} ms; "
+          f"fp64 cycle {st64['iters']} it {st64['t_solve_ms']:.2f} ms; rel diff {d:.2e}")
