@@ -61,7 +61,7 @@ struct Design {
     double* U = nullptr;
     std::vector<LevelBufs> lev;   // 0 = coarsest
     int n0 = 0, np0 = 0;   // coarsest free DOFs, padded to the block size
-    double *A0 = nullptr, *W0 = nullptr, *Ainv = nullptr, *Dinv = nullptr, *Lbuf = nullptr;
+    double *A0 = nullptr, *W0 = nullptr, *Ainv = nullptr, *Dinv = nullptr, *Lbuf = nullptr, *Sacc = nullptr;
     int* chol_status = nullptr;
     std::vector<CaseBufs> cases;
     const double* x_dev = nullptr;
@@ -198,6 +198,7 @@ void layout_design(Design& d, Bump& B) {
     d.Ainv = B.take<double>((size_t)d.np0 * d.np0);
     d.Dinv = B.take<double>((size_t)d.np0 * COARSE_NB);
     d.Lbuf = B.take<double>((size_t)d.np0 * d.np0);
+    d.Sacc = B.take<double>((size_t)d.np0 * d.np0);
     d.chol_status = B.take<int>(4);
     const LevelBufs& Lf = d.lev[d.fine()];
     const size_t nf = Lf.nodes() * 2;
@@ -746,7 +747,7 @@ int mtomg_set_densities(mtomg_ctx* c, int design, const double* x) {
     launch_fill<double>(st, d.A0, (size_t)d.np0 * d.np0, 0.0);
     launch_fill<int>(st, d.chol_status, 4, 0);
     launch_assemble_dense(st, false, level_op<double>(d, 0), make_mat<double>(d, d.omega), d.A0, d.np0);
-    launch_coarse_factor(st, d.A0, d.n0, d.np0, d.Dinv, d.W0, d.Ainv, d.chol_status, d.Lbuf);
+    launch_coarse_factor(st, d.A0, d.n0, d.np0, d.Dinv, d.W0, d.Ainv, d.chol_status, d.Lbuf, d.Sacc);
     LAUNCHCHK(c);
     HIPCHK(c, hipEventRecord(d.ev[1], st));
     HIPCHK(c, hipMemcpyAsync(c->host_state + 8, d.chol_status, sizeof(int), hipMemcpyDeviceToHost, st));

@@ -80,7 +80,7 @@ void launch_assemble_dense(hipStream_t st, bool fine, LevelOp<double> op, Mat<do
 // A (np x np, n0 used, identity padding written here; overwritten) ->
 // Dinv = inverses of the diagonal blocks of L, W = L^{-1}, Ainv = A^{-1}.
 void launch_coarse_factor(hipStream_t st, double* A, int n0, int np, double* Dinv, double* W, double* Ainv,
-                          int* status, double* scratch /* np x np */);
+                          int* status, double* Lbuf /* np x np */, double* Sacc /* np x np */);
 template <typename T>
 void launch_fill(hipStream_t st, T* p, size_t n, T v);
 void launch_cast_f32(hipStream_t st, const double* a, float* b, size_t n);

@@ -130,47 +130,77 @@ __device__ __forceinline__ void blk_load(double (*S)[NB + 1], const double* __re
     }
 }
 
-__device__ __forceinline__ double readlane_d(double v, int lane) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
-    return __hiloint2double(hi, lo);
+// Lower-triangle elements of a 32x32 block owned by thread t: indices
+// t, t+256, t+512 (< 528) of the row-major lower triangle.
+struct TriOwn {
+    int n, r[3], c[3];
+};
+__device__ __forceinline__ TriOwn tri_own() {
+    TriOwn o;
+    o.n = 0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const int idx = threadIdx.x + 256 * q;
+        const int ic = min(idx, NB * (NB + 1) / 2 - 1);
+        int r = (int)((sqrtf(8.0f * ic + 1.0f) - 1.0f) * 0.5f);
+        while (r * (r + 1) / 2 > ic) --r;
+        while ((r + 1) * (r + 2) / 2 <= ic) ++r;
+        o.r[q] = r;
+        o.c[q] = ic - r * (r + 1) / 2;
+        if (idx < NB * (NB + 1) / 2) o.n = q + 1;
+    }
+    return o;
 }
 
-// Cholesky of a 32x32 SPD block (read from LDS, lower triangle) and the
-// inverse of its factor, by one wave with the block in registers: lane r
-// holds row r, column values are broadcast with readlane.  Writes the
-// inverse to Li (LDS).  Returns false if a pivot is not positive.
-__device__ bool wave_potrf_inv(double (*S)[NB + 1], double (*Li)[NB + 1]) {
-    const int lane = threadIdx.x & 63;
-    const int r = lane & (NB - 1);
-    double a[NB];
+// Cholesky factor L of the SPD block S (LDS, lower triangle; S is used as
+// work space) and Li = L^{-1}, by all 256 threads with one barrier per step.
+// Right-looking: step k scales column k into L and updates the trailing
+// part of S; no element is read and written in the same step.  The inverse
+// is formed row by row, each thread finishing its own entries of row r and
+// adding row r-1's contribution to the rows below.  Acc is scratch.
+// Returns false (uniformly) if a pivot is not positive.
+__device__ bool block_potrf_inv(double (*S)[NB + 1], double (*L)[NB + 1], double (*Li)[NB + 1],
+                                double (*Acc)[NB + 1]) {
+    const TriOwn o = tri_own();
 #pragma unroll
-    for (int c = 0; c < NB; ++c) a[c] = S[r][c];
-    bool ok = true;
-#pragma unroll
+    for (int q = 0; q < 3; ++q)
+        if (q < o.n) Acc[o.r[q]][o.c[q]] = 0.0;
     for (int k = 0; k < NB; ++k) {
-        const double d = readlane_d(a[k], k);
-        ok = ok && (d > 0.0);
-        const double piv = sqrt(d > 0.0 ? d : 1.0);
-        a[k] = (r == k) ? piv : ((r > k) ? a[k] / piv : a[k]);
+        __syncthreads();
+        const double d = S[k][k];
+        if (!(d > 0.0)) return false;
+        const double sq = sqrt(d), inv = 1.0 / sq;
 #pragma unroll
-        for (int c = k + 1; c < NB; ++c) {
-            const double lck = readlane_d(a[k], c);
-            a[c] = (r >= c) ? a[c] - a[k] * lck : a[c];
+        for (int q = 0; q < 3; ++q) {
+            if (q >= o.n) continue;
+            const int r = o.r[q], c = o.c[q];
+            if (c == k) L[r][k] = (r == k) ? sq : S[r][k] * inv;
+            else if (c > k) S[r][c] -= (S[r][k] * inv) * (S[c][k] * inv);
         }
     }
-    if (!ok) return false;
-    // column c = r of L^{-1} by forward substitution; lane r (< 32) keeps its
-    // column in Li and only ever reads back its own entries
+    __syncthreads();
+    for (int r = 0; r < NB; ++r) {
 #pragma unroll
-    for (int rr = 0; rr < NB; ++rr) {
-        double s = (rr == r) ? 1.0 : 0.0;
-#pragma unroll
-        for (int t = 0; t < rr; ++t) s -= readlane_d(a[t], rr) * Li[t][r];
-        const double v = s / readlane_d(a[rr], rr);
-        if (lane < NB) Li[rr][r] = v;
+        for (int q = 0; q < 3; ++q) {
+            if (q >= o.n) continue;
+            const int i = o.r[q], c = o.c[q];
+            if (i == r) {
+                double s = (c == r) ? 1.0 : 0.0;
+                s -= Acc[r][c];
+                if (r >= 1 && c <= r - 1) s -= L[r][r - 1] * Li[r - 1][c];
+                Li[r][c] = s / L[r][r];
+            } else if (i > r && r >= 1 && c <= r - 1) {
+                Acc[i][c] += L[i][r - 1] * Li[r - 1][c];
+            }
+        }
+        __syncthreads();
     }
-    __builtin_amdgcn_wave_barrier();
+    // zero the strict upper part of Li (it is read as a full block)
+    for (int x = threadIdx.x; x < NB * NB; x += 256) {
+        const int r = x / NB, c = x % NB;
+        if (c > r) Li[r][c] = 0.0;
+    }
+    __syncthreads();
     return true;
 }
 
@@ -188,121 +218,116 @@ __device__ __forceinline__ void blk_gemm_nt(double (*C)[NB + 1], double (*X)[NB 
     for (int q = 0; q < 4; ++q) C[r][c4 + q] = acc[q];
 }
 
-// Right-looking blocked Cholesky, launch k (k >= 1): workgroup (ib, jb),
-// ib >= jb >= k, forms L[ib,k-1] = A[ib,k-1] Linv_{k-1}^T and L[jb,k-1],
-// applies A[ib,jb] -= L[ib,k-1] L[jb,k-1]^T; workgroups with jb == k store
-// L[ib,k-1]; the one with ib == jb == k then factors the finished diagonal
-// block k (Dinv[k] = its factor's inverse).  Launch 0 only factors block 0.
-// Every block read in a launch is written by an earlier launch.
-__global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ A, int np, int k, double* __restrict__ Dinv,
-                                                   double* __restrict__ Lbuf, int* __restrict__ status) {
-    __shared__ double Ai[NB][NB + 1], Aj[NB][NB + 1], Dk[NB][NB + 1], Pi[NB][NB + 1], Pj[NB][NB + 1];
+// One launch of the coarsest factorisation, k = 0 .. nblk (np = 32 nblk):
+//  * Cholesky part (k < nblk): workgroup (ib, jb), ib >= jb >= k, forms
+//    L[ib,k-1] = A[ib,k-1] Linv_{k-1}^T and L[jb,k-1], applies
+//    A[ib,jb] -= L[ib,k-1] L[jb,k-1]^T; workgroups with jb == k store
+//    L[ib,k-1]; the one with ib == jb == k then factors the finished
+//    diagonal block k: Dinv[k] = L_kk^{-1}, also written as W's diagonal
+//    block.  For k = 0 a single workgroup factors block 0.
+//  * W = L^{-1} part, step t = k - 2 (0 <= t <= nblk-2): workgroup (i, j),
+//    i > t >= j: S[i,j] (+)= L[i,t] W[t,j] (W[t,t] = Dinv[t]); for i == t+1
+//    the sum is complete and W[t+1,j] = -Dinv[t+1] S[t+1,j].
+// Every block a launch reads was written by an earlier launch.
+__global__ __launch_bounds__(256) void k_factor_step(double* __restrict__ A, int np, int k, double* __restrict__ Dinv,
+                                                     double* __restrict__ Lbuf, double* __restrict__ W,
+                                                     double* __restrict__ Sacc, int* __restrict__ status) {
+    __shared__ double B0[NB][NB + 1], B1[NB][NB + 1], B2[NB][NB + 1], B3[NB][NB + 1], B4[NB][NB + 1];
     const int nblk = np / NB;
     int r, c4;
     blk_coords(r, c4);
-    if (k == 0) {
-        blk_load(Ai, A, np, 0, 0);
-        __syncthreads();
-        if (threadIdx.x < 64) {
-            if (!wave_potrf_inv(Ai, Pi)) {
-                if (threadIdx.x == 0) *status = 1;
-            }
+    const int n_chol = (k >= nblk) ? 0 : (k == 0 ? 1 : (nblk - k) * (nblk - k + 1) / 2);
+    if ((int)blockIdx.x >= n_chol) {
+        // ---- W = L^{-1}, step t
+        const int t = k - 2;
+        const int b = blockIdx.x - n_chol;
+        const int j = b % (t + 1);
+        const int i = t + 1 + b / (t + 1);
+        blk_load(B0, Lbuf, np, i, t);
+        if (j == t) {
+            for (int x = threadIdx.x; x < NB * NB; x += 256) B1[x / NB][x % NB] = Dinv[(size_t)t * NB * NB + x];
+        } else {
+            blk_load(B1, W, np, t, j);
         }
         __syncthreads();
+        double acc[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Dinv[r * NB + c4 + q] = Pi[r][c4 + q];
+        for (int q = 0; q < 4; ++q) acc[q] = (j == t) ? 0.0 : Sacc[(size_t)(i * NB + r) * np + j * NB + c4 + q];
+        for (int s = 0; s < NB; ++s) {
+            const double lr = B0[r][s];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] += lr * B1[s][c4 + q];
+        }
+        if (i != t + 1) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Sacc[(size_t)(i * NB + r) * np + j * NB + c4 + q] = acc[q];
+            return;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) B2[r][c4 + q] = acc[q];
+        for (int x = threadIdx.x; x < NB * NB; x += 256) B3[x / NB][x % NB] = Dinv[(size_t)i * NB * NB + x];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = c4 + q;
+            double s = 0.0;
+            for (int u = 0; u <= r; ++u) s += B3[r][u] * B2[u][c];
+            W[(size_t)(i * NB + r) * np + j * NB + c] = -s;
+        }
         return;
     }
-    // triangular index -> (ib, jb) over the trailing blocks k..nblk-1
+    // ---- Cholesky
+    auto finish_diag = [&](int kk) {
+        // B0 holds the finished diagonal block kk
+        if (!block_potrf_inv(B0, B1, B2, B3)) {
+            if (threadIdx.x == 0) *status = 1;
+            return;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double v = B2[r][c4 + q];
+            Dinv[(size_t)kk * NB * NB + r * NB + c4 + q] = v;
+            W[(size_t)(kk * NB + r) * np + kk * NB + c4 + q] = v;
+        }
+    };
+    if (k == 0) {
+        blk_load(B0, A, np, 0, 0);
+        finish_diag(0);
+        return;
+    }
     int a = 0, rem = blockIdx.x;
     while (rem > a) { rem -= a + 1; ++a; }
     const int ib = k + a, jb = k + rem;
-    blk_load(Ai, A, np, ib, k - 1);
-    if (jb != ib) blk_load(Aj, A, np, jb, k - 1);
-    for (int t = threadIdx.x; t < NB * NB; t += 256) Dk[t / NB][t % NB] = Dinv[(size_t)(k - 1) * NB * NB + t];
+    blk_load(B0, A, np, ib, k - 1);
+    if (jb != ib) blk_load(B1, A, np, jb, k - 1);
+    for (int x = threadIdx.x; x < NB * NB; x += 256) B2[x / NB][x % NB] = Dinv[(size_t)(k - 1) * NB * NB + x];
     __syncthreads();
-    blk_gemm_nt(Pi, Ai, Dk);
-    if (jb != ib) blk_gemm_nt(Pj, Aj, Dk);
+    blk_gemm_nt(B3, B0, B2);
+    if (jb != ib) blk_gemm_nt(B4, B1, B2);
     __syncthreads();
-    double (*Lj)[NB + 1] = (jb != ib) ? Pj : Pi;
+    double (*Lj)[NB + 1] = (jb != ib) ? B4 : B3;
     if (jb == k) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Lbuf[(size_t)(ib * NB + r) * np + (k - 1) * NB + c4 + q] = Pi[r][c4 + q];
+        for (int q = 0; q < 4; ++q) Lbuf[(size_t)(ib * NB + r) * np + (k - 1) * NB + c4 + q] = B3[r][c4 + q];
     }
     double upd[4] = {0, 0, 0, 0};
     for (int s = 0; s < NB; ++s) {
-        const double lr = Pi[r][s];
+        const double lr = B3[r][s];
 #pragma unroll
         for (int q = 0; q < 4; ++q) upd[q] += lr * Lj[c4 + q][s];
     }
     double* blk = A + (size_t)(ib * NB + r) * np + jb * NB + c4;
+    double nv[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) blk[q] -= upd[q];
+    for (int q = 0; q < 4; ++q) {
+        nv[q] = blk[q] - upd[q];
+        blk[q] = nv[q];
+    }
     if (ib == k && jb == k) {
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Ai[r][c4 + q] = blk[q];
-        __syncthreads();
-        if (threadIdx.x < 64) {
-            if (!wave_potrf_inv(Ai, Dk)) {
-                if (threadIdx.x == 0) *status = 1;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < 4; ++q) Dinv[(size_t)k * NB * NB + r * NB + c4 + q] = Dk[r][c4 + q];
-    }
-}
-
-// W = L^{-1} by right-looking block substitution.  Launch t: workgroup
-// (i, j), i > t >= j: S[i,j] += L[i,t] W[t,j]; for i == t+1 the sum is
-// complete and W[t+1,j] = -L_{t+1}^{-1} S[t+1,j].  W's diagonal blocks are
-// the block inverses, set beforehand; S starts at zero.
-__global__ __launch_bounds__(256) void k_trinv_step(const double* __restrict__ Lbuf, const double* __restrict__ Dinv,
-                                                    double* __restrict__ W, double* __restrict__ S, int np, int t) {
-    __shared__ double La[NB][NB + 1], Wb[NB][NB + 1], Di[NB][NB + 1], Sb[NB][NB + 1];
-    const int nblk = np / NB;
-    const int j = blockIdx.x % (t + 1);
-    const int i = t + 1 + blockIdx.x / (t + 1);
-    if (i >= nblk) return;
-    int r, c4;
-    blk_coords(r, c4);
-    blk_load(La, Lbuf, np, i, t);
-    blk_load(Wb, W, np, t, j);
-    __syncthreads();
-    double acc[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = S[(size_t)(i * NB + r) * np + j * NB + c4 + q];
-    for (int s = 0; s < NB; ++s) {
-        const double lr = La[r][s];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] += lr * Wb[s][c4 + q];
-    }
-    if (i != t + 1) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) S[(size_t)(i * NB + r) * np + j * NB + c4 + q] = acc[q];
-        return;
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) Sb[r][c4 + q] = acc[q];
-    for (int x = threadIdx.x; x < NB * NB; x += 256) Di[x / NB][x % NB] = Dinv[(size_t)i * NB * NB + x];
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int c = c4 + q;
-        double s = 0.0;
-        for (int u = 0; u <= r; ++u) s += Di[r][u] * Sb[u][c];
-        W[(size_t)(i * NB + r) * np + j * NB + c] = -s;
-    }
-}
-
-// W diagonal blocks = block inverses, everything above them zero.
-__global__ void k_trinv_init(const double* __restrict__ Dinv, double* __restrict__ W, int np) {
-    const size_t n = (size_t)np * np;
-    for (size_t x = blockIdx.x * (size_t)blockDim.x + threadIdx.x; x < n; x += (size_t)gridDim.x * blockDim.x) {
-        const int row = (int)(x / np), col = (int)(x % np);
-        const int bi = row / NB, bj = col / NB;
-        W[x] = (bi == bj) ? Dinv[(size_t)bi * NB * NB + (row % NB) * NB + (col % NB)] : 0.0;
+        for (int q = 0; q < 4; ++q) B0[r][c4 + q] = nv[q];
+        finish_diag(k);
     }
 }
 
@@ -407,23 +432,19 @@ void launch_assemble_dense(hipStream_t st, bool fine, LevelOp<double> op, Mat<do
     else hipLaunchKernelGGL(k_assemble_dense<false>, dim3(blocks_for(n, 256)), dim3(256), 0, st, op, mat, A, ld);
 }
 void launch_coarse_factor(hipStream_t st, double* A, int n0, int np, double* Dinv, double* W, double* Ainv,
-                          int* status, double* scratch) {
+                          int* status, double* Lbuf, double* Sacc) {
     if (np > n0)
         hipLaunchKernelGGL(k_pad_identity, dim3(blocks_for(np - n0, 256)), dim3(256), 0, st, A, n0, np);
     const int nblk = np / NB;
-    double* Lbuf = scratch;   // np x np: off-diagonal blocks of L, then reused as the S accumulator
-    for (int k = 0; k < nblk; ++k) {
+    for (int k = 0; k <= nblk; ++k) {
         const int m = nblk - k;
-        hipLaunchKernelGGL(k_chol_step, dim3(k == 0 ? 1 : m * (m + 1) / 2), dim3(256), 0, st, A, np, k, Dinv, Lbuf,
+        const int n_chol = (k >= nblk) ? 0 : (k == 0 ? 1 : m * (m + 1) / 2);
+        const int t = k - 2;
+        const int n_inv = (t >= 0 && t <= nblk - 2) ? (nblk - 1 - t) * (t + 1) : 0;
+        if (n_chol + n_inv == 0) continue;
+        hipLaunchKernelGGL(k_factor_step, dim3(n_chol + n_inv), dim3(256), 0, st, A, np, k, Dinv, Lbuf, W, Sacc,
                            status);
     }
-    // A is free now: it accumulates the sums S of the block substitution
-    hipLaunchKernelGGL(k_trinv_init, dim3(std::min<size_t>(blocks_for((size_t)np * np, 256), 2048)), dim3(256), 0, st,
-                       Dinv, W, np);
-    hipLaunchKernelGGL(k_fill<double>, dim3(std::min<size_t>(blocks_for((size_t)np * np, 256), 2048)), dim3(256), 0,
-                       st, A, (size_t)np * np, 0.0);
-    for (int t = 0; t + 1 < nblk; ++t)
-        hipLaunchKernelGGL(k_trinv_step, dim3((nblk - 1 - t) * (t + 1)), dim3(256), 0, st, Lbuf, Dinv, W, A, np, t);
     hipLaunchKernelGGL(k_gram_blk, dim3(nblk * (nblk + 1) / 2), dim3(256), 0, st, W, Ainv, np);
 }
 template <typename T>
