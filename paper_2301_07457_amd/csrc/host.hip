@@ -2,15 +2,26 @@
 // layout, preconditioner setup and the PCG driver (Algorithm 2 with the
 // multigrid cycle of Algorithm 1 as preconditioner).
 //
+// Batching.  Designs with the same grid, hierarchy, smoother, material law
+// and number of load cases form a group; every (design, load case) pair of
+// a group is one system.  Each system's vectors live in a case slab and
+// each design's operators in a design slab, all slabs of a group the same
+// size, so one launch serves every system of the group (blockIdx.y picks
+// the system and the kernels shift their pointers by whole slabs).  All
+// groups iterate in lockstep in one solve, and two PCG iterations of every
+// group are captured in one HIP graph.  The coarsest factorisation of the
+// designs whose densities changed runs at the start of the next solve, one
+// launch sequence per group.
+//
 // Solve loop.  All PCG scalars stay on the device: every kernel that needs
 // alpha = rho / p^T q or beta = rho_i / rho_{i-1} re-sums the per-workgroup
 // partial dot products of the kernel that produced them, in a fixed order,
 // so the run is deterministic and needs no host round trip.  Partial
 // buffers and the r / p vectors alternate by iteration parity.  A small
-// per-case state word carries convergence: 0 running, 1 converged (the last
-// x update is pending), 2 finished, 3 breakdown, 4 NaN; every kernel exits
-// at once when it is set, so the host can launch iterations in batches and
-// read the state only between batches.
+// per-system state word carries convergence: 0 running, 1 converged (the
+// last x update is pending), 2 finished, 3 breakdown, 4 NaN, 5 not part of
+// this solve; every kernel exits at once when it is set, so the host can
+// launch iterations in batches and read the states only between batches.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,6 +39,7 @@ using namespace mtomg;
 namespace {
 
 constexpr int MAX_PHASES = 8;
+constexpr int ST_INACTIVE = 5;
 
 struct LevelBufs {
     int nx = 0, ny = 0;
@@ -46,14 +58,13 @@ struct CaseBufs {
     std::vector<void*> b, u2, u4, e;   // per level, precision of the cycle
     double *zr[2] = {nullptr, nullptr}, *pq[2] = {nullptr, nullptr}, *rr[2] = {nullptr, nullptr};
     double *ff = nullptr, *trr = nullptr, *sums = nullptr, *cpart = nullptr;
-    int* state = nullptr;   // [0] conv, [1] iters
-    hipGraphExec_t pair_exec = nullptr;   // two PCG iterations (parities 1, 0), captured
-    double pair_tol2 = -1.0;
-    int last_iters = 0;                   // iterations of the previous solve (batch hint)
+    int* state = nullptr;   // [0] state word, [1] iterations
 };
 
 struct Design {
     bool has_grid = false, has_dens = false;
+    bool needs_factor = false;   // densities set since the last factorisation
+    bool fac_failed = false;     // coarsest matrix not positive definite
     int nelx = 0, nely = 0, m = 0, levels = 0, n_pre = 2, n_post = 2, precision = 0, n_cases = 1;
     double nu = 0.3, E_min = 1e-9, penal = 3.0, omega = 0.6;
     double E_phase[MAX_PHASES] = {};
@@ -62,13 +73,34 @@ struct Design {
     std::vector<LevelBufs> lev;   // 0 = coarsest
     int n0 = 0, np0 = 0;   // coarsest free DOFs, padded to the block size
     double *A0 = nullptr, *W0 = nullptr, *Ainv = nullptr, *Dinv = nullptr, *Lbuf = nullptr, *Sacc = nullptr;
-    int* chol_status = nullptr;
+    int* chol_status = nullptr;   // [0] not positive definite, [1] factor pending
     std::vector<CaseBufs> cases;
     const double* x_dev = nullptr;
+    int group = -1, gidx = 0;     // group and position in it
     float t_setup_ms = 0.f;
-    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};   // around the last set_densities
+    hipEvent_t fev[2] = {nullptr, nullptr};  // around the last factorisation of its group (group lead)
     int fine() const { return levels - 1; }
     bool mixed() const { return precision == MTOMG_FP32MG; }
+};
+
+// Designs solved together (same shape); see the file comment.
+struct Group {
+    std::vector<int> designs;
+    int cpd = 1, n_sys = 0;
+    long long cs = 0, ds = 0;   // case / design slab bytes
+    const double** Ftab = nullptr;   // device [n_sys]
+    double** Utab = nullptr;         // device [n_sys]
+    Batch batch() const {
+        Batch b;
+        b.cs = cs;
+        b.ds = ds;
+        b.cpd = cpd;
+        b.n = n_sys;
+        b.F = Ftab;
+        b.U = Utab;
+        return b;
+    }
 };
 
 // Event brackets around the launches of one kernel (profiling hook).
@@ -94,17 +126,24 @@ struct mtomg_ctx {
     hipStream_t stream = nullptr;
     int device = 0;
     std::vector<Design> d;
+    std::vector<Group> groups;
     void* ws = nullptr;
     size_t ws_bytes = 0;
     bool ws_owned = false;
     bool laid_out = false;
     std::string err;
-    int* host_state = nullptr;    // pinned
-    double* host_sums = nullptr;  // pinned
+    int* host_state = nullptr;    // pinned [cap][4]
+    double* host_sums = nullptr;  // pinned [cap][4]
+    int host_cap = 0;
     int batch = 8;                // iterations between host checks (first solve)
+    int last_iters = 0;           // most iterations of the previous solve (batch hint)
     bool use_graphs = true;
     int rows_fine = 0, rows_coarse = 0;   // rows per wave overrides (0 = automatic)
-    hipStream_t cap_stream = nullptr;  // capture stream (default priority)
+    hipStream_t cap_stream = nullptr;     // capture stream (default priority)
+    hipGraphExec_t pair_exec = nullptr;   // two PCG iterations (parities 1, 0) of the groups below
+    double pair_tol2 = -1.0;
+    std::vector<int> pair_groups;
+    hipEvent_t ev_solve[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -115,13 +154,12 @@ int fail(mtomg_ctx* c, int code, const std::string& msg) {
 }
 
 void drop_graphs(mtomg_ctx* c) {
-    for (Design& d : c->d)
-        for (CaseBufs& cb : d.cases)
-            if (cb.pair_exec) {
-                hipGraphExecDestroy(cb.pair_exec);
-                cb.pair_exec = nullptr;
-                cb.pair_tol2 = -1.0;
-            }
+    if (c->pair_exec) {
+        hipGraphExecDestroy(c->pair_exec);
+        c->pair_exec = nullptr;
+    }
+    c->pair_tol2 = -1.0;
+    c->pair_groups.clear();
 }
 
 #define HIPCHK(ctx, call)                                                                   \
@@ -183,9 +221,9 @@ struct Bump {
     }
 };
 
-void layout_design(Design& d, Bump& B) {
+// operators and the coarsest factorisation of one design
+void layout_design_slab(Design& d, Bump& B) {
     const bool mx = d.mixed();
-    const size_t tsz = mx ? sizeof(float) : sizeof(double);
     for (int l = 0; l < d.levels; ++l) {
         LevelBufs& L = d.lev[l];
         const size_t ne = (size_t)L.nx * L.ny;
@@ -200,56 +238,121 @@ void layout_design(Design& d, Bump& B) {
     d.Lbuf = B.take<double>((size_t)d.np0 * d.np0);
     d.Sacc = B.take<double>((size_t)d.np0 * d.np0);
     d.chol_status = B.take<int>(4);
+}
+
+// vectors, partial sums and state of one load case
+void layout_case_slab(const Design& d, CaseBufs& c, Bump& B) {
+    const bool mx = d.mixed();
+    const size_t tsz = mx ? sizeof(float) : sizeof(double);
     const LevelBufs& Lf = d.lev[d.fine()];
     const size_t nf = Lf.nodes() * 2;
     const int np = std::max({Lf.sw_apply.n_tiles, Lf.sw_pre.n_tiles, Lf.sw_post.n_tiles, 1});
-    for (size_t ci = 0; ci < d.cases.size(); ++ci) {
-        CaseBufs& c = d.cases[ci];
-        c.F = d.F + ci * nf;
-        c.U = d.U + ci * nf;
-        for (int k = 0; k < 2; ++k) {
-            c.r[k] = B.take<double>(nf);
-            c.p[k] = B.take<double>(nf);
-            c.zr[k] = B.take<double>(np);
-            c.pq[k] = B.take<double>(np);
-            c.rr[k] = B.take<double>(np);
+    for (int k = 0; k < 2; ++k) {
+        c.r[k] = B.take<double>(nf);
+        c.p[k] = B.take<double>(nf);
+        c.zr[k] = B.take<double>(np);
+        c.pq[k] = B.take<double>(np);
+        c.rr[k] = B.take<double>(np);
+    }
+    c.q = B.take<double>(nf);
+    c.z = B.take<char>(nf * tsz);
+    c.r32 = mx ? B.take<float>(nf) : nullptr;
+    c.ff = B.take<double>(np);
+    c.trr = B.take<double>(np);
+    c.cpart = B.take<double>(256);
+    c.sums = B.take<double>(8);
+    c.state = B.take<int>(4);
+    c.b.assign(d.levels, nullptr);
+    c.u2.assign(d.levels, nullptr);
+    c.u4.assign(d.levels, nullptr);
+    c.e.assign(d.levels, nullptr);
+    for (int l = 0; l < d.levels; ++l) {
+        const size_t n = d.lev[l].nodes() * 2 * tsz;
+        if (l != d.fine()) {
+            c.b[l] = B.take<char>(n);
+            c.e[l] = B.take<char>(n);
         }
-        c.q = B.take<double>(nf);
-        c.z = B.take<char>(nf * tsz);
-        c.r32 = mx ? B.take<float>(nf) : nullptr;
-        c.ff = B.take<double>(np);
-        c.trr = B.take<double>(np);
-        c.cpart = B.take<double>(256);
-        c.sums = B.take<double>(8);
-        c.state = B.take<int>(4);
-        c.b.assign(d.levels, nullptr);
-        c.u2.assign(d.levels, nullptr);
-        c.u4.assign(d.levels, nullptr);
-        c.e.assign(d.levels, nullptr);
-        for (int l = 0; l < d.levels; ++l) {
-            const size_t n = d.lev[l].nodes() * 2 * tsz;
-            if (l != d.fine()) {
-                c.b[l] = B.take<char>(n);
-                c.e[l] = B.take<char>(n);
-            }
-            if (l != 0) {
-                c.u2[l] = B.take<char>(n);
-                c.u4[l] = B.take<char>(n);
-            }
+        if (l != 0) {
+            c.u2[l] = B.take<char>(n);
+            c.u4[l] = B.take<char>(n);
         }
     }
 }
 
-size_t layout_all(mtomg_ctx* c, char* base) {
+bool same_shape(const Design& a, const Design& b) {
+    return a.nelx == b.nelx && a.nely == b.nely && a.levels == b.levels && a.precision == b.precision &&
+           a.n_pre == b.n_pre && a.n_post == b.n_post && a.nu == b.nu && a.omega == b.omega &&
+           a.n_cases == b.n_cases;
+}
+
+void form_groups(std::vector<Design>& D, std::vector<Group>& G) {
+    G.clear();
+    for (int i = 0; i < (int)D.size(); ++i) {
+        if (!D[i].has_grid) continue;
+        int gi = -1;
+        for (int k = 0; k < (int)G.size(); ++k)
+            if (same_shape(D[G[k].designs[0]], D[i])) {
+                gi = k;
+                break;
+            }
+        if (gi < 0) {
+            G.emplace_back();
+            gi = (int)G.size() - 1;
+            G[gi].cpd = D[i].n_cases;
+        }
+        D[i].group = gi;
+        D[i].gidx = (int)G[gi].designs.size();
+        G[gi].designs.push_back(i);
+        G[gi].n_sys += D[i].n_cases;
+    }
+}
+
+// Groups, then per group: F/U tables, design slabs, case slabs.  Returns
+// the bytes used; with a null base only sizes are computed (on copies).
+size_t layout_into(std::vector<Design>& D, std::vector<Group>& G, char* base) {
+    form_groups(D, G);
     Bump B{base};
-    for (Design& d : c->d)
-        if (d.has_grid) layout_design(d, B);
+    for (Group& g : G) {
+        {
+            Design tmp = D[g.designs[0]];
+            Bump m{nullptr};
+            layout_design_slab(tmp, m);
+            g.ds = (long long)((m.off + 255) & ~(size_t)255);
+            CaseBufs cb;
+            Bump mc{nullptr};
+            layout_case_slab(tmp, cb, mc);
+            g.cs = (long long)((mc.off + 255) & ~(size_t)255);
+        }
+        g.Ftab = B.take<const double*>(g.n_sys);
+        g.Utab = B.take<double*>(g.n_sys);
+        char* dbase = B.take<char>((size_t)g.ds * g.designs.size());
+        char* cbase = B.take<char>((size_t)g.cs * g.n_sys);
+        for (size_t gi = 0; gi < g.designs.size(); ++gi) {
+            Design& d = D[g.designs[gi]];
+            Bump bd{base ? dbase + gi * g.ds : nullptr};
+            layout_design_slab(d, bd);
+            const size_t nf = 2 * d.lev[d.fine()].nodes();
+            for (int k = 0; k < d.n_cases; ++k) {
+                CaseBufs& cb = d.cases[k];
+                Bump bc{base ? cbase + (gi * g.cpd + k) * g.cs : nullptr};
+                layout_case_slab(d, cb, bc);
+                cb.F = d.F + k * nf;
+                cb.U = d.U + k * nf;
+            }
+        }
+    }
     return B.off + 256;
+}
+
+size_t measure_workspace(const mtomg_ctx* c) {
+    std::vector<Design> D = c->d;
+    std::vector<Group> G;
+    return layout_into(D, G, nullptr);
 }
 
 int ensure_workspace(mtomg_ctx* c) {
     if (c->laid_out) return MTOMG_OK;
-    const size_t need = layout_all(c, nullptr);
+    const size_t need = measure_workspace(c);
     if (c->ws && c->ws_bytes < need)
         return fail(c, MTOMG_WORKSPACE, "workspace smaller than mtomg_workspace_bytes()");
     if (!c->ws) {
@@ -257,7 +360,32 @@ int ensure_workspace(mtomg_ctx* c) {
         c->ws_bytes = need;
         c->ws_owned = true;
     }
-    layout_all(c, reinterpret_cast<char*>(c->ws));
+    drop_graphs(c);
+    layout_into(c->d, c->groups, reinterpret_cast<char*>(c->ws));
+    int total = 0;
+    for (Group& g : c->groups) {
+        std::vector<const double*> F;
+        std::vector<double*> U;
+        for (int di : g.designs)
+            for (const CaseBufs& cb : c->d[di].cases) {
+                F.push_back(cb.F);
+                U.push_back(cb.U);
+            }
+        HIPCHK(c, hipMemcpyAsync(g.Ftab, F.data(), F.size() * sizeof(F[0]), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(g.Utab, U.data(), U.size() * sizeof(U[0]), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        total += g.n_sys;
+    }
+    if (total > c->host_cap) {
+        if (c->host_state) hipHostFree(c->host_state);
+        if (c->host_sums) hipHostFree(c->host_sums);
+        c->host_state = nullptr;
+        c->host_sums = nullptr;
+        c->host_cap = 0;
+        HIPCHK(c, hipHostMalloc((void**)&c->host_state, (size_t)total * 4 * sizeof(int), hipHostMallocDefault));
+        HIPCHK(c, hipHostMalloc((void**)&c->host_sums, (size_t)total * 4 * sizeof(double), hipHostMallocDefault));
+        c->host_cap = total;
+    }
     c->laid_out = true;
     return MTOMG_OK;
 }
@@ -291,6 +419,7 @@ template <typename T> struct CycleCtx {
     hipStream_t st;
     const int* conv;   // nullable (debug use)
     Prof* prof = nullptr;
+    Batch bt{};        // systems of every launch (pointers above are system 0's)
     void begin(int id) { if (prof) prof->begin(id, st); }
     void end(int id) { if (prof) prof->end(id, st); }
 };
@@ -305,7 +434,8 @@ void post_chain(CycleCtx<T>& cx, int l, const T* u_cur, const T* ec, const T* b,
     const LevelBufs& L = d.lev[l];
     const int n = d.n_post;
     if (n == 0) {
-        launch_post<T>(cx.st, fine, true, dot, op, make_mat<T>(d, 0.0), L.sw_post, u_cur, ec, b, out, r64, zr_out, cx.conv);
+        launch_post<T>(cx.st, fine, true, dot, op, make_mat<T>(d, 0.0), L.sw_post, u_cur, ec, b, out, r64, zr_out, cx.conv,
+                       cx.bt);
         return;
     }
     const T* in = u_cur;
@@ -314,7 +444,7 @@ void post_chain(CycleCtx<T>& cx, int l, const T* u_cur, const T* ec, const T* b,
         const int pid = !fine ? 0 : (k == n ? MTOMG_KERNEL_FINE_POST_DOT : MTOMG_KERNEL_FINE_POST);
         cx.begin(pid);
         launch_post<T>(cx.st, fine, k == 1, dot && k == n, op, make_mat<T>(d, d.omega), L.sw_post, in,
-                       k == 1 ? ec : nullptr, b, dst, r64, zr_out, cx.conv);
+                       k == 1 ? ec : nullptr, b, dst, r64, zr_out, cx.conv, cx.bt);
         cx.end(pid);
         in = dst;
     }
@@ -328,7 +458,7 @@ T* pre_chain_extra(CycleCtx<T>& cx, int l, T* cur, const T* b, T* t0, T* t1) {
     for (int k = 3; k <= d.n_pre; ++k) {
         T* dst = (cur == t0) ? t1 : t0;
         launch_post<T>(cx.st, fine, false, false, level_op<T>(d, l), make_mat<T>(d, d.omega), d.lev[l].sw_post,
-                       cur, nullptr, b, dst, nullptr, nullptr, cx.conv);
+                       cur, nullptr, b, dst, nullptr, nullptr, cx.conv, cx.bt);
         cur = dst;
     }
     return cur;
@@ -352,15 +482,15 @@ void coarse_cycle(CycleCtx<T>& cx, int top) {
         T* cur = t0;
         if (d.n_pre > 0) {
             launch_presmooth<T>(cx.st, false, false, level_op<T>(d, l), make_mat<T>(d, d.omega), d.lev[l].sw_pre,
-                                b, t0, std::min(d.n_pre, 2), nocg, cx.conv);
+                                b, t0, std::min(d.n_pre, 2), nocg, cx.conv, cx.bt);
             cur = pre_chain_extra<T>(cx, l, cur, b, t0, t1);
         }
         launch_restrict<T>(cx.st, false, false, level_op<T>(d, l), make_mat<T>(d, d.omega), d.lev[l].sw_res, b,
-                           d.n_pre > 0 ? cur : nullptr, (T*)c.b[l - 1], nochk, cx.conv);
+                           d.n_pre > 0 ? cur : nullptr, (T*)c.b[l - 1], nochk, cx.conv, cx.bt);
         pre[l] = cur;
     }
     cx.begin(MTOMG_KERNEL_COARSE_SOLVE);
-    launch_coarse_solve<T>(cx.st, d.Ainv, d.n0, d.np0, d.lev[0].nx, (const T*)c.b[0], (T*)c.e[0], cx.conv);
+    launch_coarse_solve<T>(cx.st, d.Ainv, d.n0, d.np0, d.lev[0].nx, (const T*)c.b[0], (T*)c.e[0], cx.conv, cx.bt);
     cx.end(MTOMG_KERNEL_COARSE_SOLVE);
     for (int l = 1; l <= top; ++l) {
         T* other = pre[l] == (T*)c.u2[l] ? (T*)c.u4[l] : (T*)c.u2[l];
@@ -398,7 +528,7 @@ void fine_cycle(CycleCtx<T>& cx, int it, double tol2) {
     const T* bfine = d.mixed() ? (const T*)(void*)c.r32 : (const T*)(void*)c.r[nxt];
     cx.begin(MTOMG_KERNEL_FINE_PRESMOOTH);
     launch_presmooth<T>(cx.st, true, true, level_op<T>(d, f), make_mat<T>(d, d.omega), L.sw_pre, nullptr, t0,
-                        std::min(d.n_pre, 2), cg, cx.conv);
+                        std::min(d.n_pre, 2), cg, cx.conv, cx.bt);
     cx.end(MTOMG_KERNEL_FINE_PRESMOOTH);
     T* cur = pre_chain_extra<T>(cx, f, t0, bfine, t0, t1);
     ConvCheck chk{};
@@ -410,7 +540,7 @@ void fine_cycle(CycleCtx<T>& cx, int it, double tol2) {
     chk.conv_rw = c.state;
     cx.begin(MTOMG_KERNEL_FINE_RESTRICT);
     launch_restrict<T>(cx.st, true, true, level_op<T>(d, f), make_mat<T>(d, d.omega), L.sw_res, bfine,
-                       d.n_pre > 0 ? cur : nullptr, (T*)c.b[f - 1], chk, cx.conv);
+                       d.n_pre > 0 ? cur : nullptr, (T*)c.b[f - 1], chk, cx.conv, cx.bt);
     cx.end(MTOMG_KERNEL_FINE_RESTRICT);
     coarse_cycle<T>(cx, f - 1);
     post_chain<T>(cx, f, d.n_pre > 0 ? cur : nullptr, (const T*)c.e[f - 1], bfine, (T*)c.z, cur == t0 ? t1 : t0,
@@ -418,14 +548,16 @@ void fine_cycle(CycleCtx<T>& cx, int it, double tol2) {
 }
 
 template <typename T>
-void cg_step(Design& d, CaseBufs& c, hipStream_t st, int it, int mode, Prof* prof = nullptr) {
+void cg_step(CycleCtx<T>& cx, int it, int mode) {
+    Design& d = *cx.d;
+    CaseBufs& c = *cx.c;
     const LevelBufs& L = d.lev[d.fine()];
     const int par = it & 1, prv = 1 - par;
-    if (prof) prof->begin(MTOMG_KERNEL_CG_APPLY, st);
-    launch_cg_apply<T>(st, level_op<double>(d, d.fine()), make_mat<double>(d, d.omega), L.sw_apply,
+    cx.begin(MTOMG_KERNEL_CG_APPLY);
+    launch_cg_apply<T>(cx.st, level_op<double>(d, d.fine()), make_mat<double>(d, d.omega), L.sw_apply,
                        (const T*)c.z, c.p[prv], c.p[par], c.U, c.q, c.zr[par], c.zr[prv], L.sw_post.n_tiles,
-                       c.pq[prv], L.sw_apply.n_tiles, c.pq[par], c.state, mode);
-    if (prof) prof->end(MTOMG_KERNEL_CG_APPLY, st);
+                       c.pq[prv], L.sw_apply.n_tiles, c.pq[par], c.state, mode, cx.bt);
+    cx.end(MTOMG_KERNEL_CG_APPLY);
 }
 
 }  // namespace
@@ -470,121 +602,10 @@ int check_design(mtomg_ctx* c, int design, bool need_dens) {
     return MTOMG_OK;
 }
 
-// Capture iterations 1 and 2 (parities 1, 0) of the PCG loop into a graph;
-// replaying it runs any later pair of iterations.
-template <typename T>
-int capture_pair(mtomg_ctx* ctx, Design& d, CaseBufs& c, double tol2) {
-    if (c.pair_exec) {
-        HIPCHK(ctx, hipGraphExecDestroy(c.pair_exec));
-        c.pair_exec = nullptr;
-    }
-    hipStream_t cs = ctx->cap_stream;
-    HIPCHK(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    CycleCtx<T> cx{&d, &c, cs, c.state, nullptr};
-    for (int k = 1; k <= 2; ++k) {
-        cg_step<T>(d, c, cs, k, 0, nullptr);
-        fine_cycle<T>(cx, k, tol2);
-    }
-    hipGraph_t g = nullptr;
-    HIPCHK(ctx, hipStreamEndCapture(cs, &g));
-    const hipError_t e = hipGraphInstantiate(&c.pair_exec, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
-    if (e != hipSuccess) {
-        c.pair_exec = nullptr;
-        return fail(ctx, MTOMG_HIP_ERROR, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-    }
-    c.pair_tol2 = tol2;
-    return MTOMG_OK;
-}
-
-template <typename T>
-int solve_case(mtomg_ctx* ctx, Design& d, CaseBufs& c, double rel_tol, int max_iter, int warm, mtomg_stats* out) {
-    hipStream_t st = ctx->stream;
-    const LevelBufs& L = d.lev[d.fine()];
-    const LevelOp<double> op64 = level_op<double>(d, d.fine());
-    const Mat<double> mat64 = make_mat<double>(d, d.omega);
-    const double tol2 = rel_tol * rel_tol;
-    const bool graphs = ctx->use_graphs && ctx->prof.kernel == MTOMG_KERNEL_NONE;
-    HIPCHK(ctx, hipEventRecord(d.ev[0], st));
-    launch_fill<int>(st, c.state, 4, 0);
-    launch_residual(st, op64, mat64, L.sw_apply, c.F, c.U, warm ? 1 : 0, c.r[0], c.rr[0], c.ff);
-    CycleCtx<T> cx{&d, &c, st, c.state, &ctx->prof};
-    fine_cycle<T>(cx, -1, tol2);
-    LAUNCHCHK(ctx);
-    // iterations [from, from + count): pairs starting at an odd index replay the graph
-    auto launch_iters = [&](int from, int count) -> int {
-        int k = from;
-        const int end = from + count;
-        while (k < end) {
-            if (graphs && (k & 1) && end - k >= 2) {
-                if (!c.pair_exec || c.pair_tol2 != tol2) {
-                    const int rc = capture_pair<T>(ctx, d, c, tol2);
-                    if (rc) return rc;
-                }
-                HIPCHK(ctx, hipGraphLaunch(c.pair_exec, st));
-                k += 2;
-            } else {
-                cg_step<T>(d, c, st, k, k == 0 ? 1 : 0, &ctx->prof);
-                fine_cycle<T>(cx, k, tol2);
-                ++k;
-            }
-        }
-        LAUNCHCHK(ctx);
-        return MTOMG_OK;
-    };
-    int it = 0;
-    int done = 0;
-    // first batch: the previous solve's count (a design loop changes slowly), then small steps
-    int batch = c.last_iters > 0 ? c.last_iters + 1 : std::max(2, ctx->batch);
-    while (it < max_iter) {
-        const int nb = std::min(batch, max_iter - it);
-        const int rc = launch_iters(it, nb);
-        if (rc) return rc;
-        it += nb;
-        HIPCHK(ctx, hipMemcpyAsync(ctx->host_state, c.state, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
-        HIPCHK(ctx, hipStreamSynchronize(st));
-        done = ctx->host_state[0];
-        if (done != 0) break;
-        batch = std::max(2, std::min(it / 2, 16));
-    }
-    if (done == 0 && max_iter > 0) {
-        // pending x update of the last iteration
-        cg_step<T>(d, c, st, it, 2);
-    } else if (done == 1 && it > 0) {
-        // converged in the last launched iteration: the pending update
-        cg_step<T>(d, c, st, it, 0);
-    }
-    launch_residual(st, op64, mat64, L.sw_apply, c.F, c.U, 1, nullptr, c.trr, nullptr);
-    HIPCHK(ctx, hipMemcpyAsync(ctx->host_state, c.state, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(ctx, hipStreamSynchronize(st));
-    const int iters = ctx->host_state[1];
-    SumJob job{};
-    job.p[0] = c.ff; job.n[0] = L.sw_apply.n_tiles;
-    job.p[1] = c.rr[iters & 1]; job.n[1] = iters == 0 ? L.sw_apply.n_tiles : L.sw_pre.n_tiles;
-    job.p[2] = c.trr; job.n[2] = L.sw_apply.n_tiles;
-    job.count = 3;
-    launch_sums(st, job, c.sums);
-    LAUNCHCHK(ctx);
-    HIPCHK(ctx, hipEventRecord(d.ev[1], st));
-    HIPCHK(ctx, hipMemcpyAsync(ctx->host_sums, c.sums, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(ctx, hipMemcpyAsync(ctx->host_state, c.state, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(ctx, hipStreamSynchronize(st));
-    float ms = 0.f;
-    HIPCHK(ctx, hipEventElapsedTime(&ms, d.ev[0], d.ev[1]));
-    const double ff = ctx->host_sums[0];
-    const int cv = ctx->host_state[0];
-    out->status = (cv == 1 || cv == 2) ? MTOMG_OK : cv == 3 ? MTOMG_BREAKDOWN : cv == 4 ? MTOMG_NAN : MTOMG_NOT_CONVERGED;
-    out->iters = ctx->host_state[1];
-    out->vcycles = out->iters + 1;
-    c.last_iters = out->iters;
-    out->n_dof = (int)(2 * L.nodes());
-    out->relres_rec = ff > 0 ? std::sqrt(ctx->host_sums[1] / ff) : 0.0;
-    out->relres_true = ff > 0 ? std::sqrt(ctx->host_sums[2] / ff) : 0.0;
-    out->t_setup_ms = d.t_setup_ms;
-    out->t_solve_ms = ms;
-    // algorithmic bytes of one iteration (each array touched once per kernel)
+// algorithmic bytes of one PCG iteration of one system (each array touched once per kernel)
+double model_bytes(const Design& d) {
     double bytes = 0.0;
-    const double t = sizeof(T);
+    const double t = d.mixed() ? 4.0 : 8.0;
     for (int l = 0; l < d.levels; ++l) {
         const double n = (double)d.lev[l].nodes(), ne = (double)d.lev[l].nx * d.lev[l].ny;
         if (l == d.fine()) {
@@ -597,8 +618,254 @@ int solve_case(mtomg_ctx* ctx, Design& d, CaseBufs& c, double rel_tol, int max_i
             bytes += 8.0 * d.n0 * d.n0 + n * 2 * t * 2;
         }
     }
-    out->model_bytes = bytes;
-    return out->status;
+    return bytes;
+}
+
+// Coarsest factorisation (Algorithm 3 and the explicit inverse) of every
+// design whose densities changed since its last factorisation: one launch
+// sequence per group, designs not flagged skip it.  Synchronises to read
+// the positive-definiteness flags and the setup times.
+int factor_pending(mtomg_ctx* c) {
+    hipStream_t st = c->stream;
+    std::vector<char> ran(c->groups.size(), 0);
+    int sys0 = 0;
+    for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+        Group& g = c->groups[gi];
+        for (int di : g.designs) ran[gi] |= c->d[di].has_dens && c->d[di].needs_factor;
+        if (ran[gi]) {
+            Design& d0 = c->d[g.designs[0]];
+            const int nd = (int)g.designs.size();
+            HIPCHK(c, hipEventRecord(d0.fev[0], st));
+            launch_coarse_factor(st, d0.A0, d0.n0, d0.np0, d0.Dinv, d0.W0, d0.Ainv, d0.chol_status, d0.Lbuf,
+                                 d0.Sacc, nd, g.ds);
+            launch_fill_strided(st, d0.chol_status + 1, g.ds, nd, 0);
+            HIPCHK(c, hipEventRecord(d0.fev[1], st));
+            LAUNCHCHK(c);
+            HIPCHK(c, hipMemcpy2DAsync(c->host_state + 4 * sys0, 4 * sizeof(int), d0.chol_status, (size_t)g.ds,
+                                       4 * sizeof(int), nd, hipMemcpyDeviceToHost, st));
+        }
+        sys0 += g.n_sys;
+    }
+    if (std::none_of(ran.begin(), ran.end(), [](char v) { return v != 0; })) return MTOMG_OK;
+    HIPCHK(c, hipStreamSynchronize(st));
+    sys0 = 0;
+    for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+        Group& g = c->groups[gi];
+        if (ran[gi]) {
+            float fac_ms = 0.f;
+            Design& d0 = c->d[g.designs[0]];
+            HIPCHK(c, hipEventElapsedTime(&fac_ms, d0.fev[0], d0.fev[1]));
+            for (size_t k = 0; k < g.designs.size(); ++k) {
+                Design& d = c->d[g.designs[k]];
+                if (!(d.has_dens && d.needs_factor)) continue;
+                float ms = 0.f;
+                HIPCHK(c, hipEventElapsedTime(&ms, d.ev[0], d.ev[1]));
+                d.t_setup_ms = ms + fac_ms;
+                d.fac_failed = c->host_state[4 * (sys0 + k)] != 0;
+                d.needs_factor = false;
+            }
+        }
+        sys0 += g.n_sys;
+    }
+    return MTOMG_OK;
+}
+
+template <typename T>
+CycleCtx<T> group_cycle(mtomg_ctx* c, Group& g, hipStream_t st, Prof* prof) {
+    Design& d0 = c->d[g.designs[0]];
+    CycleCtx<T> cx{&d0, &d0.cases[0], st, d0.cases[0].state, prof};
+    cx.bt = g.batch();
+    return cx;
+}
+
+// PCG iteration `it` of every group in `act` (mode as k_cg_apply)
+void run_iteration(mtomg_ctx* c, const std::vector<int>& act, hipStream_t st, int it, int mode, double tol2,
+                   Prof* prof) {
+    for (int gi : act) {
+        Group& g = c->groups[gi];
+        if (c->d[g.designs[0]].mixed()) {
+            CycleCtx<float> cx = group_cycle<float>(c, g, st, prof);
+            cg_step<float>(cx, it, mode);
+            if (mode < 2) fine_cycle<float>(cx, it, tol2);
+        } else {
+            CycleCtx<double> cx = group_cycle<double>(c, g, st, prof);
+            cg_step<double>(cx, it, mode);
+            if (mode < 2) fine_cycle<double>(cx, it, tol2);
+        }
+    }
+}
+
+// Capture iterations 1 and 2 (parities 1, 0) of every group in `act` into
+// one graph; replaying it runs any later pair of iterations.
+int capture_pair(mtomg_ctx* c, const std::vector<int>& act, double tol2) {
+    drop_graphs(c);
+    hipStream_t cs = c->cap_stream;
+    HIPCHK(c, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    for (int k = 1; k <= 2; ++k) run_iteration(c, act, cs, k, 0, tol2, nullptr);
+    hipGraph_t g = nullptr;
+    HIPCHK(c, hipStreamEndCapture(cs, &g));
+    const hipError_t e = hipGraphInstantiate(&c->pair_exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        c->pair_exec = nullptr;
+        return fail(c, MTOMG_HIP_ERROR, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    c->pair_tol2 = tol2;
+    c->pair_groups = act;
+    return MTOMG_OK;
+}
+
+// r_0 = f - K u_0 and the first preconditioner application, every system of a group
+template <typename T>
+void start_group(mtomg_ctx* c, Group& g, hipStream_t st, int warm, double tol2) {
+    CycleCtx<T> cx = group_cycle<T>(c, g, st, &c->prof);
+    Design& d = *cx.d;
+    CaseBufs& cb = *cx.c;
+    const LevelBufs& L = d.lev[d.fine()];
+    launch_residual(st, level_op<double>(d, d.fine()), make_mat<double>(d, d.omega), L.sw_apply, nullptr, nullptr,
+                    warm ? 1 : 0, cb.r[0], cb.rr[0], cb.ff, cb.state, cx.bt);
+    fine_cycle<T>(cx, -1, tol2);
+}
+
+// Every system of every design with densities, in lockstep (see the file comment).
+int solve_all(mtomg_ctx* c, double rel_tol, int max_iter, int warm, mtomg_stats* stats) {
+    int rc = factor_pending(c);
+    if (rc) return rc;
+    hipStream_t st = c->stream;
+    const double tol2 = rel_tol * rel_tol;
+    const bool graphs = c->use_graphs && c->prof.kernel == MTOMG_KERNEL_NONE;
+    std::vector<int> act, gsys0(c->groups.size(), 0);
+    int sys0 = 0;
+    for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+        Group& g = c->groups[gi];
+        gsys0[gi] = sys0;
+        bool any = false;
+        for (size_t k = 0; k < g.designs.size(); ++k) {
+            const Design& d = c->d[g.designs[k]];
+            const int v = (d.has_dens && !d.fac_failed) ? 0 : ST_INACTIVE;
+            any = any || v == 0;
+            for (int q = 0; q < g.cpd; ++q) {
+                int* h = c->host_state + 4 * (sys0 + (int)k * g.cpd + q);
+                h[0] = v;
+                h[1] = h[2] = h[3] = 0;
+            }
+        }
+        if (any) {
+            act.push_back((int)gi);
+            HIPCHK(c, hipMemcpy2DAsync(c->d[g.designs[0]].cases[0].state, (size_t)g.cs, c->host_state + 4 * sys0,
+                                       4 * sizeof(int), 4 * sizeof(int), g.n_sys, hipMemcpyHostToDevice, st));
+        }
+        sys0 += g.n_sys;
+    }
+    HIPCHK(c, hipEventRecord(c->ev_solve[0], st));
+    auto read_states = [&]() -> int {
+        for (int gi : act) {
+            Group& g = c->groups[gi];
+            HIPCHK(c, hipMemcpy2DAsync(c->host_state + 4 * gsys0[gi], 4 * sizeof(int),
+                                       c->d[g.designs[0]].cases[0].state, (size_t)g.cs, 4 * sizeof(int), g.n_sys,
+                                       hipMemcpyDeviceToHost, st));
+        }
+        HIPCHK(c, hipStreamSynchronize(st));
+        return MTOMG_OK;
+    };
+    int it = 0;
+    if (!act.empty()) {
+        for (int gi : act) {
+            if (c->d[c->groups[gi].designs[0]].mixed()) start_group<float>(c, c->groups[gi], st, warm, tol2);
+            else start_group<double>(c, c->groups[gi], st, warm, tol2);
+        }
+        LAUNCHCHK(c);
+        // iterations [from, from + count): pairs starting at an odd index replay the graph
+        auto launch_iters = [&](int from, int count) -> int {
+            int k = from;
+            const int end = from + count;
+            while (k < end) {
+                if (graphs && (k & 1) && end - k >= 2) {
+                    if (!c->pair_exec || c->pair_tol2 != tol2 || c->pair_groups != act) {
+                        const int r2 = capture_pair(c, act, tol2);
+                        if (r2) return r2;
+                    }
+                    HIPCHK(c, hipGraphLaunch(c->pair_exec, st));
+                    k += 2;
+                } else {
+                    run_iteration(c, act, st, k, k == 0 ? 1 : 0, tol2, &c->prof);
+                    ++k;
+                }
+            }
+            LAUNCHCHK(c);
+            return MTOMG_OK;
+        };
+        // first batch: the previous solve's count (a design loop changes slowly), then small steps
+        int batch = c->last_iters > 0 ? c->last_iters + 1 : std::max(2, c->batch);
+        while (it < max_iter) {
+            const int nb = std::min(batch, max_iter - it);
+            rc = launch_iters(it, nb);
+            if (rc) return rc;
+            it += nb;
+            rc = read_states();
+            if (rc) return rc;
+            bool running = false;
+            for (int gi : act)
+                for (int q = 0; q < c->groups[gi].n_sys; ++q) running = running || c->host_state[4 * (gsys0[gi] + q)] == 0;
+            if (!running) break;
+            batch = std::max(2, std::min(it / 2, 16));
+        }
+        // the pending x update of systems that converged in the last iteration or hit max_iter
+        if (it > 0) run_iteration(c, act, st, it, 3, tol2, &c->prof);
+        for (int gi : act) {
+            Group& g = c->groups[gi];
+            Design& d = c->d[g.designs[0]];
+            CaseBufs& cb = d.cases[0];
+            const LevelBufs& L = d.lev[d.fine()];
+            const Batch bt = g.batch();
+            launch_residual(st, level_op<double>(d, d.fine()), make_mat<double>(d, d.omega), L.sw_apply, nullptr,
+                            nullptr, 1, nullptr, cb.trr, nullptr, cb.state, bt);
+            launch_solve_sums(st, cb.ff, L.sw_apply.n_tiles, cb.rr[0], cb.rr[1], L.sw_apply.n_tiles,
+                              L.sw_pre.n_tiles, cb.trr, cb.state, cb.sums, bt);
+        }
+        LAUNCHCHK(c);
+    }
+    HIPCHK(c, hipEventRecord(c->ev_solve[1], st));
+    for (int gi : act) {
+        Group& g = c->groups[gi];
+        HIPCHK(c, hipMemcpy2DAsync(c->host_sums + 4 * gsys0[gi], 4 * sizeof(double), c->d[g.designs[0]].cases[0].sums,
+                                   (size_t)g.cs, 3 * sizeof(double), g.n_sys, hipMemcpyDeviceToHost, st));
+    }
+    rc = read_states();
+    if (rc) return rc;
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev_solve[0], c->ev_solve[1]));
+    int k = 0, worst = MTOMG_OK, most = 0;
+    for (Design& d : c->d) {
+        if (!d.has_grid || !d.has_dens) continue;
+        const Group& g = c->groups[d.group];
+        const int s0 = gsys0[d.group] + d.gidx * g.cpd;
+        for (int q = 0; q < d.n_cases; ++q) {
+            mtomg_stats& o = stats[k++];
+            std::memset(&o, 0, sizeof(o));
+            o.n_dof = (int)(2 * d.lev[d.fine()].nodes());
+            o.t_setup_ms = d.t_setup_ms;
+            o.model_bytes = model_bytes(d);
+            if (d.fac_failed) {
+                o.status = MTOMG_BREAKDOWN;
+            } else {
+                const int* h = c->host_state + 4 * (s0 + q);
+                const double* sm = c->host_sums + 4 * (s0 + q);
+                const int cv = h[0];
+                o.status = (cv == 1 || cv == 2) ? MTOMG_OK : cv == 3 ? MTOMG_BREAKDOWN : cv == 4 ? MTOMG_NAN
+                                                                                             : MTOMG_NOT_CONVERGED;
+                o.iters = h[1];
+                o.vcycles = o.iters + 1;
+                o.relres_rec = sm[0] > 0 ? std::sqrt(sm[1] / sm[0]) : 0.0;
+                o.relres_true = sm[0] > 0 ? std::sqrt(sm[2] / sm[0]) : 0.0;
+                o.t_solve_ms = ms;
+                most = std::max(most, o.iters);
+            }
+            if (o.status < worst) worst = o.status;
+        }
+    }
+    c->last_iters = most;
+    return worst;
 }
 
 }  // namespace
@@ -620,9 +887,8 @@ int mtomg_create(mtomg_ctx** ctx, int max_designs, void* hip_stream) {
         delete c;
         return MTOMG_HIP_ERROR;
     }
-    if (hipHostMalloc((void**)&c->host_state, 16 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&c->host_sums, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
-        delete c;
+    if (hipEventCreate(&c->ev_solve[0]) != hipSuccess || hipEventCreate(&c->ev_solve[1]) != hipSuccess) {
+        mtomg_destroy(c);
         return MTOMG_HIP_ERROR;
     }
     *ctx = c;
@@ -634,9 +900,14 @@ int mtomg_destroy(mtomg_ctx* c) {
     hipStreamSynchronize(c->stream);
     drop_graphs(c);
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
-    for (Design& d : c->d)
+    for (Design& d : c->d) {
         for (hipEvent_t& e : d.ev)
             if (e) hipEventDestroy(e);
+        for (hipEvent_t& e : d.fev)
+            if (e) hipEventDestroy(e);
+    }
+    for (hipEvent_t& e : c->ev_solve)
+        if (e) hipEventDestroy(e);
     if (c->ws_owned && c->ws) hipFree(c->ws);
     if (c->host_state) hipHostFree(c->host_state);
     if (c->host_sums) hipHostFree(c->host_sums);
@@ -674,6 +945,8 @@ int mtomg_set_grid(mtomg_ctx* c, int design, int nelx, int nely, double nu, int 
     drop_graphs(c);
     for (hipEvent_t& e : d.ev)
         if (e) hipEventDestroy(e);
+    for (hipEvent_t& e : d.fev)
+        if (e) hipEventDestroy(e);
     d = Design();
     d.nelx = nelx; d.nely = nely; d.nu = nu; d.m = m; d.E_min = E_min; d.penal = penal; d.levels = levels;
     d.n_pre = n_pre; d.n_post = n_post; d.omega = omega; d.precision = precision; d.n_cases = n_cases;
@@ -689,8 +962,7 @@ int mtomg_set_grid(mtomg_ctx* c, int design, int nelx, int nely, double nu, int 
     d.n0 = 2 * (d.lev[0].nx + 1) * d.lev[0].ny;
     d.np0 = (d.n0 + COARSE_NB - 1) / COARSE_NB * COARSE_NB;
     d.cases.assign(n_cases, CaseBufs());
-    HIPCHK(c, hipEventCreate(&d.ev[0]));
-    HIPCHK(c, hipEventCreate(&d.ev[1]));
+    for (hipEvent_t* e : {&d.ev[0], &d.ev[1], &d.fev[0], &d.fev[1]}) HIPCHK(c, hipEventCreate(e));
     d.has_grid = true;
     // the layout changes: drop an owned workspace, forget a borrowed one
     if (c->ws_owned && c->ws) {
@@ -707,13 +979,13 @@ int mtomg_set_grid(mtomg_ctx* c, int design, int nelx, int nely, double nu, int 
 
 size_t mtomg_workspace_bytes(const mtomg_ctx* c) {
     if (!c) return 0;
-    return layout_all(const_cast<mtomg_ctx*>(c), nullptr);
+    return measure_workspace(c);
 }
 
 int mtomg_set_workspace(mtomg_ctx* c, void* dev, size_t bytes) {
     if (!c) return MTOMG_BAD_INPUT;
     if (!dev || (reinterpret_cast<uintptr_t>(dev) & 255)) return fail(c, MTOMG_BAD_INPUT, "workspace must be a 256-byte aligned device pointer");
-    const size_t need = layout_all(c, nullptr);
+    const size_t need = measure_workspace(c);
     if (bytes < need) return fail(c, MTOMG_WORKSPACE, "workspace smaller than mtomg_workspace_bytes()");
     hipStreamSynchronize(c->stream);
     drop_graphs(c);
@@ -746,42 +1018,27 @@ int mtomg_set_densities(mtomg_ctx* c, int design, const double* x) {
     }
     launch_fill<double>(st, d.A0, (size_t)d.np0 * d.np0, 0.0);
     launch_fill<int>(st, d.chol_status, 4, 0);
+    launch_fill<int>(st, d.chol_status + 1, 1, 1);   // factor at the next solve
     launch_assemble_dense(st, false, level_op<double>(d, 0), make_mat<double>(d, d.omega), d.A0, d.np0);
-    launch_coarse_factor(st, d.A0, d.n0, d.np0, d.Dinv, d.W0, d.Ainv, d.chol_status, d.Lbuf, d.Sacc);
     LAUNCHCHK(c);
     HIPCHK(c, hipEventRecord(d.ev[1], st));
-    HIPCHK(c, hipMemcpyAsync(c->host_state + 8, d.chol_status, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(c, hipStreamSynchronize(st));
-    HIPCHK(c, hipEventElapsedTime(&d.t_setup_ms, d.ev[0], d.ev[1]));
-    if (c->host_state[8] != 0) {
-        d.has_dens = false;
-        return fail(c, MTOMG_BREAKDOWN, "coarsest matrix is not positive definite");
-    }
     d.x_dev = x;
     d.has_dens = true;
+    d.needs_factor = true;
+    d.fac_failed = false;
     return MTOMG_OK;
 }
 
 int mtomg_solve(mtomg_ctx* c, double rel_tol, int max_iter, int warm_start, mtomg_stats* stats) {
     if (!c || !stats) return MTOMG_BAD_INPUT;
     if (!(rel_tol >= 0.0) || max_iter < 0) return fail(c, MTOMG_BAD_INPUT, "rel_tol must be >= 0 and max_iter >= 0");
-    int worst = MTOMG_OK, k = 0, any = 0;
-    for (Design& d : c->d) {
-        if (!d.has_grid) continue;
-        if (!d.has_dens) continue;
-        any = 1;
-        for (CaseBufs& cb : d.cases) {
-            mtomg_stats& s = stats[k++];
-            std::memset(&s, 0, sizeof(s));
-            int rc = d.mixed() ? solve_case<float>(c, d, cb, rel_tol, max_iter, warm_start, &s)
-                               : solve_case<double>(c, d, cb, rel_tol, max_iter, warm_start, &s);
-            if (rc == MTOMG_HIP_ERROR) return rc;
-            if (rc < worst) worst = rc;
-        }
-    }
+    bool any = false;
+    for (const Design& d : c->d) any = any || (d.has_grid && d.has_dens);
     if (!any) return fail(c, MTOMG_STATE, "no design has densities");
-    if (worst != MTOMG_OK) c->err = mtomg_status_string(worst);
-    return worst;
+    const int rc = solve_all(c, rel_tol, max_iter, warm_start, stats);
+    if (rc == MTOMG_HIP_ERROR) return rc;
+    if (rc != MTOMG_OK) c->err = mtomg_status_string(rc);
+    return rc;
 }
 
 int mtomg_compliance_and_grad(mtomg_ctx* c, int design, double* cout, double* dcdx) {
@@ -844,8 +1101,7 @@ int mtomg_set_option(mtomg_ctx* c, int option, int value) {
         case MTOMG_OPT_BATCH:
             if (value < 1 || value > 1000) return fail(c, MTOMG_BAD_INPUT, "batch must be in [1, 1000]");
             c->batch = value;
-            for (Design& d : c->d)
-                for (CaseBufs& cb : d.cases) cb.last_iters = 0;
+            c->last_iters = 0;
             return MTOMG_OK;
         default:
             return fail(c, MTOMG_BAD_INPUT, "unknown option");
@@ -881,7 +1137,10 @@ int mtomg_profile_read(mtomg_ctx* c, double* ms_out, int cap, int* launches) {
 int mtomg_debug_apply(mtomg_ctx* c, int design, int level, int op, const void* in, void* out) {
     int rc = check_design(c, design, true);
     if (rc) return rc;
+    rc = factor_pending(c);
+    if (rc) return rc;
     Design& d = c->d[design];
+    if (d.fac_failed) return fail(c, MTOMG_BREAKDOWN, "coarsest matrix is not positive definite");
     if (level < 0 || level >= d.levels) return fail(c, MTOMG_BAD_INPUT, "level out of range");
     if (!out) return fail(c, MTOMG_BAD_INPUT, "out must be a device pointer");
     hipStream_t st = c->stream;

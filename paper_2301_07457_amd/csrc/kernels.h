@@ -7,6 +7,31 @@
 
 namespace mtomg {
 
+// The independent systems of one launch, system s = blockIdx.y.  Buffers
+// owned by a load case lie `cs` bytes apart, buffers owned by a design `ds`
+// bytes apart, and design g owns systems g * cpd .. g * cpd + cpd - 1.  The
+// caller's loads F and displacements U are looked up per system when the
+// tables are given.  The default describes one system.
+struct Batch {
+    long long cs = 0, ds = 0;
+    int cpd = 1, n = 1;
+    const double* const* F = nullptr;
+    double* const* U = nullptr;
+};
+
+struct SysOff {
+    long long c, d;
+    int s;
+};
+__device__ __forceinline__ SysOff sys_off(const Batch& b) {
+    const int s = blockIdx.y;
+    return SysOff{(long long)s * b.cs, (long long)(s / b.cpd) * b.ds, s};
+}
+// p shifted by `off` bytes (a null pointer stays null)
+template <typename P> __device__ __forceinline__ P* at(P* p, long long off) {
+    return p ? reinterpret_cast<P*>(reinterpret_cast<char*>(const_cast<void*>(static_cast<const void*>(p))) + off) : p;
+}
+
 // Launch geometry of a marching sweep: tiles are (strip, block of
 // WAVES_PER_WG row chunks); `rows` node rows (coarse rows for restriction)
 // per wave.
@@ -44,25 +69,28 @@ template <typename TZ>
 void launch_cg_apply(hipStream_t st, LevelOp<double> op, Mat<double> mat, Sweep sw, const TZ* z,
                      const double* p_old, double* p_new, double* x, double* q, const double* zr_cur,
                      const double* zr_prev, int n_zr, const double* pq_prev, int n_pq,
-                     double* pq_out, const int* conv, int mode);
+                     double* pq_out, const int* conv, int mode, const Batch& bt = Batch{});
 void launch_residual(hipStream_t st, LevelOp<double> op, Mat<double> mat, Sweep sw, const double* f,
-                     double* x, int use_x, double* r, double* rr_out, double* ff_out);
+                     double* x, int use_x, double* r, double* rr_out, double* ff_out, const int* conv = nullptr,
+                     const Batch& bt = Batch{});
 template <typename T>
 void launch_presmooth(hipStream_t st, bool fine, bool cgmode, LevelOp<T> op, Mat<T> mat, Sweep sw,
-                      const T* b, T* u_out, int sweeps, const CgRhs& cg, const int* conv);
+                      const T* b, T* u_out, int sweeps, const CgRhs& cg, const int* conv,
+                      const Batch& bt = Batch{});
 template <typename T>
 void launch_restrict(hipStream_t st, bool fine, bool check, LevelOp<T> op, Mat<T> mat, Sweep sw,
-                     const T* b, const T* u, T* rc, const ConvCheck& chk, const int* conv);
+                     const T* b, const T* u, T* rc, const ConvCheck& chk, const int* conv,
+                     const Batch& bt = Batch{});
 template <typename T>
 void launch_post(hipStream_t st, bool fine, bool prolong, bool dot, LevelOp<T> op, Mat<T> mat, Sweep sw,
                  const T* u_in, const T* ec, const T* b, T* u_out, const double* r64, double* zr_out,
-                 const int* conv);
+                 const int* conv, const Batch& bt = Batch{});
 template <typename T>
 void launch_apply(hipStream_t st, bool fine, bool diag, LevelOp<T> op, Mat<T> mat, Sweep sw, const T* u,
                   T* q);
 template <typename T>
 void launch_coarse_solve(hipStream_t st, const double* Ainv, int n0, int ld, int nx0, const T* b, T* e,
-                         const int* conv);
+                         const int* conv, const Batch& bt = Batch{});
 
 // setup
 struct Phases {
@@ -79,8 +107,13 @@ constexpr int COARSE_NB = 32;   // block size of the coarse factorisation
 void launch_assemble_dense(hipStream_t st, bool fine, LevelOp<double> op, Mat<double> mat, double* A, int ld);
 // A (np x np, n0 used, identity padding written here; overwritten) ->
 // Dinv = inverses of the diagonal blocks of L, W = L^{-1}, Ainv = A^{-1}.
+// status[0]: 0 or 1 (not positive definite); status[1]: factor this design
+// (the launch skips designs with 0).  `n_designs` designs, `ds` bytes apart.
 void launch_coarse_factor(hipStream_t st, double* A, int n0, int np, double* Dinv, double* W, double* Ainv,
-                          int* status, double* Lbuf /* np x np */, double* Sacc /* np x np */);
+                          int* status, double* Lbuf /* np x np */, double* Sacc /* np x np */,
+                          int n_designs = 1, long long ds = 0);
+// p[k * stride_bytes] = v for k < n
+void launch_fill_strided(hipStream_t st, int* p, long long stride_bytes, int n, int v);
 template <typename T>
 void launch_fill(hipStream_t st, T* p, size_t n, T v);
 void launch_cast_f32(hipStream_t st, const double* a, float* b, size_t n);
@@ -98,5 +131,9 @@ struct SumJob {
     int count;
 };
 void launch_sums(hipStream_t st, SumJob job, double* out);
+// Per system after a solve: out[0] = ||f||^2, out[1] = recursive ||r||^2
+// (from rr[iters & 1], iters = state[1]), out[2] = true ||r||^2.
+void launch_solve_sums(hipStream_t st, const double* ff, int n_ff, const double* rr0, const double* rr1,
+                       int n_rr0, int n_rr, const double* trr, const int* state, double* out, const Batch& bt);
 
 }  // namespace mtomg

@@ -231,8 +231,18 @@ __device__ __forceinline__ void blk_gemm_nt(double (*C)[NB + 1], double (*X)[NB 
 // Every block a launch reads was written by an earlier launch.
 __global__ __launch_bounds__(256) void k_factor_step(double* __restrict__ A, int np, int k, double* __restrict__ Dinv,
                                                      double* __restrict__ Lbuf, double* __restrict__ W,
-                                                     double* __restrict__ Sacc, int* __restrict__ status) {
+                                                     double* __restrict__ Sacc, int* __restrict__ status,
+                                                     long long ds) {
     __shared__ double B0[NB][NB + 1], B1[NB][NB + 1], B2[NB][NB + 1], B3[NB][NB + 1], B4[NB][NB + 1];
+    // design blockIdx.y; skipped unless flagged for factorisation and still positive definite
+    const long long off = (long long)blockIdx.y * ds;
+    status = at(status, off);
+    if (status[1] == 0 || status[0] != 0) return;
+    A = at(A, off);
+    Dinv = at(Dinv, off);
+    Lbuf = at(Lbuf, off);
+    W = at(W, off);
+    Sacc = at(Sacc, off);
     const int nblk = np / NB;
     int r, c4;
     blk_coords(r, c4);
@@ -333,8 +343,14 @@ __global__ __launch_bounds__(256) void k_factor_step(double* __restrict__ A, int
 
 // K_0^{-1} = W^T W: one workgroup per lower block (ib >= jb), mirrored to
 // the upper block so the inverse is exactly symmetric.
-__global__ __launch_bounds__(256) void k_gram_blk(const double* __restrict__ W, double* __restrict__ Ainv, int np) {
+__global__ __launch_bounds__(256) void k_gram_blk(const double* __restrict__ W, double* __restrict__ Ainv, int np,
+                                                  const int* __restrict__ status, long long ds) {
     __shared__ double Wi[NB][NB + 1], Wj[NB][NB + 1];
+    const long long off = (long long)blockIdx.y * ds;
+    status = at(status, off);
+    if (status[1] == 0 || status[0] != 0) return;
+    W = at(W, off);
+    Ainv = at(Ainv, off);
     const int nblk = np / NB;
     int ib = 0, rem = blockIdx.x;
     while (rem > ib) { rem -= ib + 1; ++ib; }
@@ -361,7 +377,11 @@ __global__ __launch_bounds__(256) void k_gram_blk(const double* __restrict__ W, 
     }
 }
 
-__global__ void k_pad_identity(double* __restrict__ A, int n0, int np) {
+__global__ void k_pad_identity(double* __restrict__ A, int n0, int np, const int* __restrict__ status,
+                               long long ds) {
+    const long long off = (long long)blockIdx.y * ds;
+    if (at(status, off)[1] == 0) return;
+    A = at(A, off);
     const int k = n0 + blockIdx.x * blockDim.x + threadIdx.x;
     if (k < np) A[(size_t)k * np + k] = 1.0;
 }
@@ -405,6 +425,33 @@ __global__ __launch_bounds__(WG_THREADS) void k_dot_partials(const double* __res
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
+__global__ void k_fill_strided(int* __restrict__ p, long long stride, int n, int v) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) *at(p, (long long)k * stride) = v;
+}
+
+// solve statistics of system blockIdx.y (see launch_solve_sums)
+__global__ __launch_bounds__(WG_THREADS) void k_solve_sums(const double* __restrict__ ff, int n_ff,
+                                                           const double* __restrict__ rr0,
+                                                           const double* __restrict__ rr1, int n_rr0, int n_rr,
+                                                           const double* __restrict__ trr,
+                                                           const int* __restrict__ state, double* __restrict__ out,
+                                                           Batch bt) {
+    const SysOff so = sys_off(bt);
+    state = at(state, so.c);
+    const int iters = state[1];
+    const double* rr = at(iters & 1 ? rr1 : rr0, so.c);
+    const double a = sum_partials(at(ff, so.c), n_ff);
+    const double b = sum_partials(rr, iters == 0 ? n_rr0 : n_rr);
+    const double c = sum_partials(at(trr, so.c), n_ff);
+    if (threadIdx.x == 0) {
+        double* o = at(out, so.c);
+        o[0] = a;
+        o[1] = b;
+        o[2] = c;
+    }
+}
+
 __global__ __launch_bounds__(WG_THREADS) void k_sums(SumJob job, double* __restrict__ out) {
     for (int k = 0; k < job.count; ++k) {
         const double s = sum_partials(job.p[k], job.n[k]);
@@ -432,9 +479,10 @@ void launch_assemble_dense(hipStream_t st, bool fine, LevelOp<double> op, Mat<do
     else hipLaunchKernelGGL(k_assemble_dense<false>, dim3(blocks_for(n, 256)), dim3(256), 0, st, op, mat, A, ld);
 }
 void launch_coarse_factor(hipStream_t st, double* A, int n0, int np, double* Dinv, double* W, double* Ainv,
-                          int* status, double* Lbuf, double* Sacc) {
+                          int* status, double* Lbuf, double* Sacc, int n_designs, long long ds) {
     if (np > n0)
-        hipLaunchKernelGGL(k_pad_identity, dim3(blocks_for(np - n0, 256)), dim3(256), 0, st, A, n0, np);
+        hipLaunchKernelGGL(k_pad_identity, dim3(blocks_for(np - n0, 256), n_designs), dim3(256), 0, st, A, n0, np,
+                           status, ds);
     const int nblk = np / NB;
     for (int k = 0; k <= nblk; ++k) {
         const int m = nblk - k;
@@ -442,10 +490,22 @@ void launch_coarse_factor(hipStream_t st, double* A, int n0, int np, double* Din
         const int t = k - 2;
         const int n_inv = (t >= 0 && t <= nblk - 2) ? (nblk - 1 - t) * (t + 1) : 0;
         if (n_chol + n_inv == 0) continue;
-        hipLaunchKernelGGL(k_factor_step, dim3(n_chol + n_inv), dim3(256), 0, st, A, np, k, Dinv, Lbuf, W, Sacc,
-                           status);
+        hipLaunchKernelGGL(k_factor_step, dim3(n_chol + n_inv, n_designs), dim3(256), 0, st, A, np, k, Dinv, Lbuf,
+                           W, Sacc, status, ds);
     }
-    hipLaunchKernelGGL(k_gram_blk, dim3(nblk * (nblk + 1) / 2), dim3(256), 0, st, W, Ainv, np);
+    hipLaunchKernelGGL(k_gram_blk, dim3(nblk * (nblk + 1) / 2, n_designs), dim3(256), 0, st, W, Ainv, np, status,
+                       ds);
+}
+
+void launch_fill_strided(hipStream_t st, int* p, long long stride_bytes, int n, int v) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_fill_strided, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, stride_bytes, n, v);
+}
+
+void launch_solve_sums(hipStream_t st, const double* ff, int n_ff, const double* rr0, const double* rr1,
+                       int n_rr0, int n_rr, const double* trr, const int* state, double* out, const Batch& bt) {
+    hipLaunchKernelGGL(k_solve_sums, dim3(1, bt.n), dim3(WG_THREADS), 0, st, ff, n_ff, rr0, rr1, n_rr0, n_rr, trr,
+                       state, out, bt);
 }
 template <typename T>
 void launch_fill(hipStream_t st, T* p, size_t n, T v) {

@@ -40,7 +40,9 @@ __device__ __forceinline__ TileInfo tile_info(const Sweep& s, int n_rows) {
 // ===========================================================================
 // Outer CG: p = z + beta p_old, x += alpha_prev p_old, q = K p, partial p.q
 // mode 0: iteration i >= 1; mode 1: first iteration (beta = 0, no x update);
-// mode 2: only the pending x update (after the last iteration).
+// mode 2: only the pending x update (after the last iteration); mode 3: the
+// same for the systems whose state is 0 (iteration limit) or 1 (converged,
+// update pending), nothing for the others.
 // Geometry: H_L = 1, H_R = 1, 62 output columns per strip.
 // Every kernel first issues all loads of its rows (masked, branch-free),
 // then marches through the rows from registers.
@@ -51,11 +53,23 @@ __global__ __launch_bounds__(WG_THREADS) void k_cg_apply(
     const double* __restrict__ p_old, double* __restrict__ p_new, double* __restrict__ x,
     double* __restrict__ q, const double* __restrict__ zr_cur, const double* __restrict__ zr_prev,
     int n_zr, const double* __restrict__ pq_prev, int n_pq, double* __restrict__ pq_out,
-    const int* conv, int mode) {
+    const int* conv, int mode, Batch bt) {
+    const SysOff so = sys_off(bt);
+    conv = at(conv, so.c);
+    op.data = at(op.data, so.d);
+    z = at(z, so.c);
+    p_old = at(p_old, so.c);
+    p_new = at(p_new, so.c);
+    x = bt.U ? bt.U[so.s] : x;
+    q = at(q, so.c);
+    zr_cur = at(zr_cur, so.c);
+    zr_prev = at(zr_prev, so.c);
+    pq_prev = at(pq_prev, so.c);
+    pq_out = at(pq_out, so.c);
     const int cst = *conv;
-    const bool final_only = (mode == 2) || (mode == 0 && cst == 1);
+    const bool final_only = (mode == 2) || (mode == 3) || (mode == 0 && cst == 1);
     if (mode == 1 && cst != 0) return;
-    if (mode == 0 && cst != 0 && cst != 1) return;
+    if ((mode == 0 || mode == 3) && cst != 0 && cst != 1) return;
     const int nx = op.nx, ny = op.ny;
     const TileInfo t = tile_info<R>(sw, ny + 1);
     if (!t.block_ok) return;
@@ -150,13 +164,23 @@ __global__ __launch_bounds__(WG_THREADS) void k_cg_apply(
 // Residual r = f - K x (FP64) at the start of a solve; x = 0 unless warm.
 // Writes r (clamped row zeroed) and x (clamped row zeroed), partial sums of
 // ||r||^2 and ||f||^2 over free DOFs.  Also used for the true residual
-// (then r may be null).  Geometry as k_cg_apply.
+// (then r may be null).  Systems whose state is 5 (not part of this solve)
+// are left alone.  Geometry as k_cg_apply.
 // ===========================================================================
 template <int R>
 __global__ __launch_bounds__(WG_THREADS) void k_residual(
     LevelOp<double> op, Mat<double> mat, Sweep sw, const double* __restrict__ f,
     double* __restrict__ x, int use_x, double* __restrict__ r, double* __restrict__ rr_out,
-    double* __restrict__ ff_out) {
+    double* __restrict__ ff_out, const int* conv, Batch bt) {
+    const SysOff so = sys_off(bt);
+    conv = at(conv, so.c);
+    if (conv && *conv == 5) return;
+    op.data = at(op.data, so.d);
+    f = bt.F ? bt.F[so.s] : f;
+    x = bt.U ? bt.U[so.s] : x;
+    r = at(r, so.c);
+    rr_out = at(rr_out, so.c);
+    ff_out = at(ff_out, so.c);
     const int nx = op.nx, ny = op.ny;
     const TileInfo t = tile_info<R>(sw, ny + 1);
     if (!t.block_ok) return;
@@ -225,7 +249,23 @@ __global__ __launch_bounds__(WG_THREADS) void k_residual(
 template <typename T, bool FINE, bool CG, int R>
 __global__ __launch_bounds__(WG_THREADS) void k_presmooth(
     LevelOp<T> op, Mat<T> mat, Sweep sw, const T* __restrict__ b, T* __restrict__ u_out,
-    int sweeps, CgRhs cg, const int* conv) {
+    int sweeps, CgRhs cg, const int* conv, Batch bt) {
+    const SysOff so = sys_off(bt);
+    conv = at(conv, so.c);
+    op.data = at(op.data, so.d);
+    b = at(b, so.c);
+    u_out = at(u_out, so.c);
+    if constexpr (CG) {
+        cg.r_old = at(cg.r_old, so.c);
+        cg.q = at(cg.q, so.c);
+        cg.r_new = at(cg.r_new, so.c);
+        cg.r32 = at(cg.r32, so.c);
+        cg.zr = at(cg.zr, so.c);
+        cg.pq = at(cg.pq, so.c);
+        cg.rr_out = at(cg.rr_out, so.c);
+        cg.conv_rw = at(cg.conv_rw, so.c);
+        cg.iters = at(cg.iters, so.c);
+    }
     int cst = 0;
     if (conv) cst = *conv;
     if constexpr (CG) {
@@ -356,7 +396,18 @@ __global__ __launch_bounds__(WG_THREADS) void k_presmooth(
 template <typename T, bool FINE, bool CHECK, int R>
 __global__ __launch_bounds__(WG_THREADS) void k_restrict(
     LevelOp<T> op, Mat<T> mat, Sweep sw, const T* __restrict__ b, const T* __restrict__ u,
-    T* __restrict__ rc, ConvCheck chk, const int* conv) {
+    T* __restrict__ rc, ConvCheck chk, const int* conv, Batch bt) {
+    const SysOff so = sys_off(bt);
+    conv = at(conv, so.c);
+    op.data = at(op.data, so.d);
+    b = at(b, so.c);
+    u = at(u, so.c);
+    rc = at(rc, so.c);
+    if constexpr (CHECK) {
+        chk.rr = at(chk.rr, so.c);
+        chk.ff = at(chk.ff, so.c);
+        chk.conv_rw = at(chk.conv_rw, so.c);
+    }
     int cst = 0;
     if (conv) cst = *conv;
     if (cst != 0) return;
@@ -468,7 +519,16 @@ template <typename T, bool FINE, bool PROLONG, bool DOT, int R>
 __global__ __launch_bounds__(WG_THREADS) void k_post(
     LevelOp<T> op, Mat<T> mat, Sweep sw, const T* __restrict__ u_in, const T* __restrict__ ec,
     const T* __restrict__ b, T* __restrict__ u_out, const double* __restrict__ r64,
-    double* __restrict__ zr_out, const int* conv) {
+    double* __restrict__ zr_out, const int* conv, Batch bt) {
+    const SysOff so = sys_off(bt);
+    conv = at(conv, so.c);
+    op.data = at(op.data, so.d);
+    u_in = at(u_in, so.c);
+    ec = at(ec, so.c);
+    b = at(b, so.c);
+    u_out = at(u_out, so.c);
+    r64 = at(r64, so.c);
+    zr_out = at(zr_out, so.c);
     int cst = 0;
     if (conv) cst = *conv;
     if (cst != 0) return;
@@ -596,8 +656,13 @@ __global__ __launch_bounds__(WG_THREADS) void k_apply(LevelOp<T> op, Mat<T> mat,
 template <typename T>
 __global__ __launch_bounds__(WG_THREADS) void k_coarse_solve(const double* __restrict__ Ainv, int n0,
                                                              int ld, int nx0, const T* __restrict__ b,
-                                                             T* __restrict__ e, const int* conv) {
+                                                             T* __restrict__ e, const int* conv, Batch bt) {
+    const SysOff so = sys_off(bt);
+    conv = at(conv, so.c);
     if (conv && *conv != 0) return;
+    Ainv = at(Ainv, so.d);
+    b = at(b, so.c);
+    e = at(e, so.c);
     extern __shared__ double sb[];
     const int off = 2 * (nx0 + 1);
     for (int k = threadIdx.x; k < n0; k += WG_THREADS) sb[k] = (double)b[off + k];
@@ -618,7 +683,10 @@ __global__ __launch_bounds__(WG_THREADS) void k_coarse_solve(const double* __res
 // launchers: the rows per wave (a compile-time loop length, so all loads of
 // a wave can be issued together) is chosen per level on the host.
 // ===========================================================================
-static inline dim3 grid_of(const Sweep& s) { return dim3(8 * ((s.n_tiles + 7) / 8)); }
+// x: tiles (a multiple of 8, for the XCD-aware tile order), y: systems
+static inline dim3 grid_of(const Sweep& s, const Batch& bt = Batch{}) {
+    return dim3(8 * ((s.n_tiles + 7) / 8), bt.n);
+}
 
 #define MTOMG_ROWS_SWITCH(R_, CALL)               \
     switch (R_) {                                 \
@@ -632,30 +700,33 @@ template <typename TZ>
 void launch_cg_apply(hipStream_t st, LevelOp<double> op, Mat<double> mat, Sweep sw, const TZ* z,
                      const double* p_old, double* p_new, double* x, double* q, const double* zr_cur,
                      const double* zr_prev, int n_zr, const double* pq_prev, int n_pq,
-                     double* pq_out, const int* conv, int mode) {
-    MTOMG_ROWS_SWITCH(sw.rows, hipLaunchKernelGGL((k_cg_apply<TZ, RR>), grid_of(sw), dim3(WG_THREADS), 0, st, op,
-                                                   mat, sw, z, p_old, p_new, x, q, zr_cur, zr_prev, n_zr, pq_prev,
-                                                   n_pq, pq_out, conv, mode))
+                     double* pq_out, const int* conv, int mode, const Batch& bt) {
+    MTOMG_ROWS_SWITCH(sw.rows, hipLaunchKernelGGL((k_cg_apply<TZ, RR>), grid_of(sw, bt), dim3(WG_THREADS), 0, st,
+                                                   op, mat, sw, z, p_old, p_new, x, q, zr_cur, zr_prev, n_zr,
+                                                   pq_prev, n_pq, pq_out, conv, mode, bt))
 }
 template void launch_cg_apply<float>(hipStream_t, LevelOp<double>, Mat<double>, Sweep, const float*,
                                      const double*, double*, double*, double*, const double*,
-                                     const double*, int, const double*, int, double*, const int*, int);
+                                     const double*, int, const double*, int, double*, const int*, int,
+                                     const Batch&);
 template void launch_cg_apply<double>(hipStream_t, LevelOp<double>, Mat<double>, Sweep, const double*,
                                       const double*, double*, double*, double*, const double*,
-                                      const double*, int, const double*, int, double*, const int*, int);
+                                      const double*, int, const double*, int, double*, const int*, int,
+                                      const Batch&);
 
 void launch_residual(hipStream_t st, LevelOp<double> op, Mat<double> mat, Sweep sw, const double* f,
-                     double* x, int use_x, double* r, double* rr_out, double* ff_out) {
-    MTOMG_ROWS_SWITCH(sw.rows, hipLaunchKernelGGL((k_residual<RR>), grid_of(sw), dim3(WG_THREADS), 0, st, op, mat,
-                                                   sw, f, x, use_x, r, rr_out, ff_out))
+                     double* x, int use_x, double* r, double* rr_out, double* ff_out, const int* conv,
+                     const Batch& bt) {
+    MTOMG_ROWS_SWITCH(sw.rows, hipLaunchKernelGGL((k_residual<RR>), grid_of(sw, bt), dim3(WG_THREADS), 0, st, op,
+                                                   mat, sw, f, x, use_x, r, rr_out, ff_out, conv, bt))
 }
 
 template <typename T>
 void launch_presmooth(hipStream_t st, bool fine, bool cgmode, LevelOp<T> op, Mat<T> mat, Sweep sw,
-                      const T* b, T* u_out, int sweeps, const CgRhs& cg, const int* conv) {
+                      const T* b, T* u_out, int sweeps, const CgRhs& cg, const int* conv, const Batch& bt) {
 #define MTOMG_PRE(F, C)                                                                              \
-    MTOMG_ROWS_SWITCH(sw.rows, hipLaunchKernelGGL((k_presmooth<T, F, C, RR>), grid_of(sw), dim3(WG_THREADS), 0, \
-                                                   st, op, mat, sw, b, u_out, sweeps, cg, conv))
+    MTOMG_ROWS_SWITCH(sw.rows, hipLaunchKernelGGL((k_presmooth<T, F, C, RR>), grid_of(sw, bt), dim3(WG_THREADS), \
+                                                   0, st, op, mat, sw, b, u_out, sweeps, cg, conv, bt))
     if (cgmode) MTOMG_PRE(true, true)
     else if (fine) MTOMG_PRE(true, false)
     else MTOMG_PRE(false, false)
@@ -664,10 +735,10 @@ void launch_presmooth(hipStream_t st, bool fine, bool cgmode, LevelOp<T> op, Mat
 
 template <typename T>
 void launch_restrict(hipStream_t st, bool fine, bool check, LevelOp<T> op, Mat<T> mat, Sweep sw,
-                     const T* b, const T* u, T* rc, const ConvCheck& chk, const int* conv) {
+                     const T* b, const T* u, T* rc, const ConvCheck& chk, const int* conv, const Batch& bt) {
 #define MTOMG_RES(F, C)                                                                              \
-    MTOMG_ROWS_SWITCH(sw.rows, hipLaunchKernelGGL((k_restrict<T, F, C, RR>), grid_of(sw), dim3(WG_THREADS), 0, \
-                                                   st, op, mat, sw, b, u, rc, chk, conv))
+    MTOMG_ROWS_SWITCH(sw.rows, hipLaunchKernelGGL((k_restrict<T, F, C, RR>), grid_of(sw, bt), dim3(WG_THREADS), \
+                                                   0, st, op, mat, sw, b, u, rc, chk, conv, bt))
     if (check) MTOMG_RES(true, true)
     else if (fine) MTOMG_RES(true, false)
     else MTOMG_RES(false, false)
@@ -677,10 +748,10 @@ void launch_restrict(hipStream_t st, bool fine, bool check, LevelOp<T> op, Mat<T
 template <typename T>
 void launch_post(hipStream_t st, bool fine, bool prolong, bool dot, LevelOp<T> op, Mat<T> mat, Sweep sw,
                  const T* u_in, const T* ec, const T* b, T* u_out, const double* r64, double* zr_out,
-                 const int* conv) {
+                 const int* conv, const Batch& bt) {
 #define MTOMG_POST(F, P, D)                                                                          \
-    MTOMG_ROWS_SWITCH(sw.rows, hipLaunchKernelGGL((k_post<T, F, P, D, RR>), grid_of(sw), dim3(WG_THREADS), 0, \
-                                                   st, op, mat, sw, u_in, ec, b, u_out, r64, zr_out, conv))
+    MTOMG_ROWS_SWITCH(sw.rows, hipLaunchKernelGGL((k_post<T, F, P, D, RR>), grid_of(sw, bt), dim3(WG_THREADS), \
+                                                   0, st, op, mat, sw, u_in, ec, b, u_out, r64, zr_out, conv, bt))
     if (fine) {
         if (prolong) { if (dot) MTOMG_POST(true, true, true) else MTOMG_POST(true, true, false) }
         else { if (dot) MTOMG_POST(true, false, true) else MTOMG_POST(true, false, false) }
@@ -704,21 +775,23 @@ void launch_apply(hipStream_t st, bool fine, bool diag, LevelOp<T> op, Mat<T> ma
 
 template <typename T>
 void launch_coarse_solve(hipStream_t st, const double* Ainv, int n0, int ld, int nx0, const T* b, T* e,
-                         const int* conv) {
+                         const int* conv, const Batch& bt) {
     const int nblk = (n0 + WAVES_PER_WG - 1) / WAVES_PER_WG;
-    hipLaunchKernelGGL((k_coarse_solve<T>), dim3(nblk), dim3(WG_THREADS), n0 * sizeof(double), st, Ainv,
-                       n0, ld, nx0, b, e, conv);
+    hipLaunchKernelGGL((k_coarse_solve<T>), dim3(nblk, bt.n), dim3(WG_THREADS), n0 * sizeof(double), st, Ainv,
+                       n0, ld, nx0, b, e, conv, bt);
 }
 
 #define MTOMG_INST(T)                                                                              \
     template void launch_presmooth<T>(hipStream_t, bool, bool, LevelOp<T>, Mat<T>, Sweep, const T*, T*, \
-                                      int, const CgRhs&, const int*);                              \
+                                      int, const CgRhs&, const int*, const Batch&);                \
     template void launch_restrict<T>(hipStream_t, bool, bool, LevelOp<T>, Mat<T>, Sweep, const T*,    \
-                                     const T*, T*, const ConvCheck&, const int*);                  \
+                                     const T*, T*, const ConvCheck&, const int*, const Batch&);    \
     template void launch_post<T>(hipStream_t, bool, bool, bool, LevelOp<T>, Mat<T>, Sweep, const T*,  \
-                                 const T*, const T*, T*, const double*, double*, const int*);      \
+                                 const T*, const T*, T*, const double*, double*, const int*,       \
+                                 const Batch&);                                                    \
     template void launch_apply<T>(hipStream_t, bool, bool, LevelOp<T>, Mat<T>, Sweep, const T*, T*);  \
-    template void launch_coarse_solve<T>(hipStream_t, const double*, int, int, int, const T*, T*, const int*);
+    template void launch_coarse_solve<T>(hipStream_t, const double*, int, int, int, const T*, T*, const int*, \
+                                         const Batch&);
 MTOMG_INST(float)
 MTOMG_INST(double)
 #undef MTOMG_INST
