@@ -42,7 +42,8 @@ enum {
     MTOMG_OK = 0,
     MTOMG_BAD_INPUT = -1,     /* invalid argument or size                        */
     MTOMG_NOT_CONVERGED = -2, /* max_iter reached; U holds the last iterate      */
-    MTOMG_BREAKDOWN = -3,     /* p^T K p <= 0 or z^T r <= 0 inside PCG           */
+    MTOMG_BREAKDOWN = -3,     /* p^T K p <= 0 or z^T r <= 0 inside PCG, or the   */
+                              /* coarsest matrix is not positive definite        */
     MTOMG_NAN = -4,           /* non-finite residual                             */
     MTOMG_WORKSPACE = -5,     /* workspace missing or too small                  */
     MTOMG_HIP_ERROR = -6,     /* a HIP runtime call failed                       */
@@ -62,8 +63,9 @@ typedef struct {
     int32_t n_dof;       /* 2 (nelx+1)(nely+1), clamped DOFs included          */
     double relres_rec;   /* recursive ||r|| / ||f|| at exit                    */
     double relres_true;  /* ||f - K u|| / ||f|| recomputed in FP64 at exit     */
-    double t_setup_ms;   /* device time of the last set_densities             */
-    double t_solve_ms;   /* device time of the solve of this design            */
+    double t_setup_ms;   /* device time of the last set_densities plus the     */
+                         /* coarsest factorisation (shared by its group)       */
+    double t_solve_ms;   /* device time of the whole solve call (all systems)  */
     double model_bytes;  /* algorithmic HBM bytes of one PCG iteration         */
 } mtomg_stats;
 
@@ -112,18 +114,28 @@ size_t mtomg_workspace_bytes(const mtomg_ctx *ctx);
 int mtomg_set_workspace(mtomg_ctx *ctx, void *dev, size_t bytes);
 
 /* Load phase densities for a design and build its preconditioner:
- * element moduli by Eq. (5), Galerkin coarse operators for every level,
- * and the coarsest Cholesky factor (Algorithm 3) turned into an explicit
- * inverse.  x: device [nely][nelx][m] FP64 in [0, 1], read during the call
- * (stream-ordered).  Returns BREAKDOWN (from the next solve) if the
- * coarsest matrix is not positive definite. */
+ * element moduli by Eq. (5), Galerkin coarse operators for every level and
+ * the assembled coarsest matrix.  Its Cholesky factor (Algorithm 3), turned
+ * into an explicit inverse, is computed at the start of the next solve,
+ * together with those of the other designs of the same shape whose
+ * densities changed (one launch sequence for all of them).
+ * x: device [nely][nelx][m] FP64 in [0, 1], read in stream order (keep it
+ * alive until the work is done).  Asynchronous; a coarsest matrix that is
+ * not positive definite is reported by the next solve (status BREAKDOWN
+ * for every load case of the design). */
 int mtomg_set_densities(mtomg_ctx *ctx, int design, const double *x);
 
 /* Solve every load case of every design that has densities: PCG
  * (Algorithm 2) from u = 0 (or from U when warm_start != 0), stopping when
  * ||r||_2 <= rel_tol ||f||_2 over the free DOFs, or after max_iter
- * iterations.  stats: host array of sum(n_cases) entries, filled in design
- * then case order.  Blocks until done.  Returns the worst status. */
+ * iterations.  Designs that share nelx, nely, levels, precision, n_pre,
+ * n_post, nu, omega and n_cases form a group: each kernel launch serves
+ * every (design, load case) system of a group, all groups iterate together
+ * and two iterations of all of them replay as one HIP graph; a system that
+ * has converged skips the remaining launches.  Designs without densities
+ * are left untouched.  stats: host array with one entry per load case of
+ * every design that has densities, in design then case order.  Blocks
+ * until done.  Returns the worst status. */
 int mtomg_solve(mtomg_ctx *ctx, double rel_tol, int max_iter, int warm_start,
                 mtomg_stats *stats);
 
@@ -156,10 +168,11 @@ const char *mtomg_last_error(const mtomg_ctx *ctx);
 enum { MTOMG_OPT_GRAPHS = 0, MTOMG_OPT_BATCH = 1, MTOMG_OPT_ROWS_FINE = 2, MTOMG_OPT_ROWS_COARSE = 3 };
 int mtomg_set_option(mtomg_ctx *ctx, int option, int value);
 
-/* Profiling: bracket every launch of one solver kernel with HIP events on
- * the solve stream during the following solves, so its device time can be
- * read back (two event records per launch; kernel = MTOMG_KERNEL_NONE
- * switches it off).  At most 4096 launches are timed between reads.
+/* Profiling: time every launch of one solver kernel during the following
+ * solves with a pair of HIP events stamped by that launch's own dispatch
+ * (hipExtLaunchKernel), so a duration is the kernel's execution alone;
+ * graphs are not replayed meanwhile (kernel = MTOMG_KERNEL_NONE switches
+ * it off).  At most 4096 launches are timed between reads.
  * mtomg_profile_read synchronises the stream, writes the duration in ms of
  * each timed launch since the last read, in launch order, to ms[0..cap-1]
  * (host) and their count to *launches (host), then starts a new record.

@@ -46,6 +46,8 @@ struct LevelBufs {
     double* op64 = nullptr;   // E (finest) or 6 moment planes
     float* op32 = nullptr;    // FP32 copy for the FP32 cycle
     Sweep sw_apply{}, sw_pre{}, sw_res{}, sw_post{};
+    Sweep sw_cg{};      // outer-CG apply (finest level)
+    Sweep sw_post2{};   // two fused post-smoothing sweeps
     size_t nodes() const { return (size_t)(nx + 1) * (ny + 1); }
 };
 
@@ -82,6 +84,12 @@ struct Design {
     hipEvent_t fev[2] = {nullptr, nullptr};  // around the last factorisation of its group (group lead)
     int fine() const { return levels - 1; }
     bool mixed() const { return precision == MTOMG_FP32MG; }
+    // partial sums of z.r come from the last post-smoothing launch: a fused
+    // pair when n_post is even and positive, a single sweep otherwise
+    int zr_tiles() const {
+        const LevelBufs& L = lev[fine()];
+        return (n_post >= 2 && n_post % 2 == 0) ? L.sw_post2.n_tiles : L.sw_post.n_tiles;
+    }
 };
 
 // Designs solved together (same shape); see the file comment.
@@ -108,13 +116,14 @@ struct Prof {
     int kernel = 0;
     std::vector<hipEvent_t> ev;
     int used = 0;
-    void begin(int id, hipStream_t st) {
+    // exactly one kernel launch happens between begin and end; it stamps
+    // the two events from its own dispatch
+    void begin(int id, hipStream_t) {
         if (id != kernel || used + 2 > (int)ev.size()) return;
-        hipEventRecord(ev[used], st);
+        time_next_launch(ev[used], ev[used + 1]);
     }
-    void end(int id, hipStream_t st) {
+    void end(int id, hipStream_t) {
         if (id != kernel || used + 2 > (int)ev.size()) return;
-        hipEventRecord(ev[used + 1], st);
         used += 2;
     }
 };
@@ -198,8 +207,14 @@ Sweep make_sweep(int cols, int wout, int rows_total, int R = 0) {
 }
 
 void plan_level(LevelBufs& L, int R = 0) {
+    // The outer-CG apply streams the most bytes per node; 8 rows per wave
+    // keep more loads in flight, as long as that still leaves >= 2048 waves.
+    const int strips = (L.nx + 1 + 61) / 62;
+    const int Rcg = R > 0 ? R : ((long)strips * ((L.ny + 1 + 7) / 8) >= 2048 ? 8 : 0);
+    L.sw_cg = make_sweep(L.nx + 1, 62, L.ny + 1, Rcg);
     L.sw_apply = make_sweep(L.nx + 1, 62, L.ny + 1, R);
     L.sw_post = L.sw_apply;
+    L.sw_post2 = make_sweep(L.nx + 1, 60, L.ny + 1, R);
     L.sw_pre = make_sweep(L.nx + 1, 61, L.ny + 1, R);
     if (L.nx % 2 == 0 && L.ny % 2 == 0)
         L.sw_res = make_sweep(L.nx / 2 + 1, 30, L.ny / 2 + 1, R);
@@ -246,7 +261,8 @@ void layout_case_slab(const Design& d, CaseBufs& c, Bump& B) {
     const size_t tsz = mx ? sizeof(float) : sizeof(double);
     const LevelBufs& Lf = d.lev[d.fine()];
     const size_t nf = Lf.nodes() * 2;
-    const int np = std::max({Lf.sw_apply.n_tiles, Lf.sw_pre.n_tiles, Lf.sw_post.n_tiles, 1});
+    const int np = std::max({Lf.sw_apply.n_tiles, Lf.sw_cg.n_tiles, Lf.sw_pre.n_tiles, Lf.sw_post.n_tiles,
+                             Lf.sw_post2.n_tiles, 1});
     for (int k = 0; k < 2; ++k) {
         c.r[k] = B.take<double>(nf);
         c.p[k] = B.take<double>(nf);
@@ -438,15 +454,23 @@ void post_chain(CycleCtx<T>& cx, int l, const T* u_cur, const T* ec, const T* b,
                        cx.bt);
         return;
     }
+    // pairs of sweeps in one launch, a single sweep for an odd remainder
     const T* in = u_cur;
-    for (int k = 1; k <= n; ++k) {
-        T* dst = (k == n) ? out : ((in == t0) ? t1 : t0);
-        const int pid = !fine ? 0 : (k == n ? MTOMG_KERNEL_FINE_POST_DOT : MTOMG_KERNEL_FINE_POST);
+    for (int k = 0; k < n;) {
+        const int step = (n - k >= 2) ? 2 : 1;
+        const bool first = k == 0, last = k + step == n;
+        T* dst = last ? out : ((in == t0) ? t1 : t0);
+        const int pid = !fine ? 0 : (last ? MTOMG_KERNEL_FINE_POST_DOT : MTOMG_KERNEL_FINE_POST);
         cx.begin(pid);
-        launch_post<T>(cx.st, fine, k == 1, dot && k == n, op, make_mat<T>(d, d.omega), L.sw_post, in,
-                       k == 1 ? ec : nullptr, b, dst, r64, zr_out, cx.conv, cx.bt);
+        if (step == 2)
+            launch_post2<T>(cx.st, fine, first, dot && last, op, make_mat<T>(d, d.omega), L.sw_post2, in,
+                            first ? ec : nullptr, b, dst, r64, zr_out, cx.conv, cx.bt);
+        else
+            launch_post<T>(cx.st, fine, first, dot && last, op, make_mat<T>(d, d.omega), L.sw_post, in,
+                           first ? ec : nullptr, b, dst, r64, zr_out, cx.conv, cx.bt);
         cx.end(pid);
         in = dst;
+        k += step;
     }
 }
 
@@ -516,9 +540,9 @@ void fine_cycle(CycleCtx<T>& cx, int it, double tol2) {
     cg.r_new = c.r[nxt];
     cg.r32 = c.r32;
     cg.zr = c.zr[par];
-    cg.n_zr = L.sw_post.n_tiles;
+    cg.n_zr = d.zr_tiles();
     cg.pq = c.pq[par];
-    cg.n_pq = L.sw_apply.n_tiles;
+    cg.n_pq = L.sw_cg.n_tiles;
     cg.rr_out = c.rr[nxt];
     cg.update = it >= 0;
     cg.conv_rw = c.state;
@@ -554,9 +578,9 @@ void cg_step(CycleCtx<T>& cx, int it, int mode) {
     const LevelBufs& L = d.lev[d.fine()];
     const int par = it & 1, prv = 1 - par;
     cx.begin(MTOMG_KERNEL_CG_APPLY);
-    launch_cg_apply<T>(cx.st, level_op<double>(d, d.fine()), make_mat<double>(d, d.omega), L.sw_apply,
-                       (const T*)c.z, c.p[prv], c.p[par], c.U, c.q, c.zr[par], c.zr[prv], L.sw_post.n_tiles,
-                       c.pq[prv], L.sw_apply.n_tiles, c.pq[par], c.state, mode, cx.bt);
+    launch_cg_apply<T>(cx.st, level_op<double>(d, d.fine()), make_mat<double>(d, d.omega), L.sw_cg,
+                       (const T*)c.z, c.p[prv], c.p[par], c.U, c.q, c.zr[par], c.zr[prv], d.zr_tiles(),
+                       c.pq[prv], L.sw_cg.n_tiles, c.pq[par], c.state, mode, cx.bt);
     cx.end(MTOMG_KERNEL_CG_APPLY);
 }
 

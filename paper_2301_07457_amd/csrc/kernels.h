@@ -65,6 +65,10 @@ struct ConvCheck {
     int* conv_rw;
 };
 
+// The next sweep or coarse-solve launch records `start` and `stop` from its
+// own dispatch (profiling); both events must exist.
+void time_next_launch(hipEvent_t start, hipEvent_t stop);
+
 template <typename TZ>
 void launch_cg_apply(hipStream_t st, LevelOp<double> op, Mat<double> mat, Sweep sw, const TZ* z,
                      const double* p_old, double* p_new, double* x, double* q, const double* zr_cur,
@@ -85,6 +89,11 @@ template <typename T>
 void launch_post(hipStream_t st, bool fine, bool prolong, bool dot, LevelOp<T> op, Mat<T> mat, Sweep sw,
                  const T* u_in, const T* ec, const T* b, T* u_out, const double* r64, double* zr_out,
                  const int* conv, const Batch& bt = Batch{});
+// two post-smoothing sweeps in one launch (geometry: 60 output columns per strip)
+template <typename T>
+void launch_post2(hipStream_t st, bool fine, bool prolong, bool dot, LevelOp<T> op, Mat<T> mat, Sweep sw,
+                  const T* u_in, const T* ec, const T* b, T* u_out, const double* r64, double* zr_out,
+                  const int* conv, const Batch& bt = Batch{});
 template <typename T>
 void launch_apply(hipStream_t st, bool fine, bool diag, LevelOp<T> op, Mat<T> mat, Sweep sw, const T* u,
                   T* q);

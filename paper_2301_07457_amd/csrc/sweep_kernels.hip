@@ -15,6 +15,8 @@
 // row.  Lanes at the strip edges only feed their neighbours; strips overlap
 // by H_L + H_R columns and chunks re-read one or two halo rows.
 // Four waves form a workgroup (four stacked chunks of one strip).
+#include <hip/hip_ext.h>
+
 #include "device_common.h"
 #include "kernels.h"
 
@@ -607,6 +609,122 @@ __global__ __launch_bounds__(WG_THREADS) void k_post(
 }
 
 // ===========================================================================
+// Two post-smoothing sweeps in one pass: u1 = v + w D^-1 (b - K v) and
+// u_out = u1 + w D^-1 (b - K u1), with v = u_in + P e_c when PROLONG.
+// The second stage marches one element row behind the first, so u1 never
+// leaves registers.  With DOT, partial sums of u_out . r over the free DOFs.
+// Geometry: H_L = 2, H_R = 2, 60 output columns per strip.
+// ===========================================================================
+template <typename T, bool FINE, bool PROLONG, bool DOT, int R>
+__global__ __launch_bounds__(WG_THREADS) void k_post2(
+    LevelOp<T> op, Mat<T> mat, Sweep sw, const T* __restrict__ u_in, const T* __restrict__ ec,
+    const T* __restrict__ b, T* __restrict__ u_out, const double* __restrict__ r64,
+    double* __restrict__ zr_out, const int* conv, Batch bt) {
+    const SysOff so = sys_off(bt);
+    conv = at(conv, so.c);
+    op.data = at(op.data, so.d);
+    u_in = at(u_in, so.c);
+    ec = at(ec, so.c);
+    b = at(b, so.c);
+    u_out = at(u_out, so.c);
+    r64 = at(r64, so.c);
+    zr_out = at(zr_out, so.c);
+    int cst = 0;
+    if (conv) cst = *conv;
+    if (cst != 0) return;
+    const int nx = op.nx, ny = op.ny;
+    const int ncx = nx / 2, ncy = ny / 2;
+    const TileInfo t = tile_info<R>(sw, ny + 1);
+    if (!t.block_ok) return;
+    constexpr int HL = 2, WOUT = 60;
+    const int lane = lane_id();
+    const int i = t.strip * WOUT - HL + lane;
+    const bool out_lane = lane >= HL && lane < HL + WOUT && i <= nx;
+    const bool node_col = i >= 0 && i <= nx;
+    const int I0 = i >> 1, I1 = (i + 1) >> 1;
+    double dot = 0.0;
+    if (t.j0 < t.j1) {
+        // v rows j0-2 .. j0+R+1, element rows j0-2 .. j0+R, b rows j0-1 .. j0+R
+        V2<T> vr[R + 4], br[R + 2];
+        Mom<T> me[R + 3];
+        V2<double> rr64[DOT ? R : 1];
+        if (u_in) {
+#pragma unroll
+            for (int s = 0; s < R + 4; ++s) vr[s] = load_node(u_in, nx, ny, i, t.j0 - 2 + s);
+        } else {
+#pragma unroll
+            for (int s = 0; s < R + 4; ++s) vr[s] = V2<T>{T(0), T(0)};
+        }
+        if constexpr (PROLONG) {
+            // fine rows j0-2 .. j0+R+1 = rows (j0-1)-1 .. (j0-1)+(R+2)
+            if (t.j0 & 1) add_prolongation<T, R + 2, 0>(vr, ec, ncx, ncy, I0, I1, t.j0 - 1, node_col, ny);
+            else add_prolongation<T, R + 2, 1>(vr, ec, ncx, ncy, I0, I1, t.j0 - 1, node_col, ny);
+        }
+#pragma unroll
+        for (int s = 0; s < R + 2; ++s) br[s] = load_node(b, nx, ny, i, t.j0 - 1 + s);
+        if constexpr (DOT) {
+#pragma unroll
+            for (int s = 0; s < R; ++s) rr64[s] = load_node(r64, nx, ny, i, t.j0 + s);
+        }
+#pragma unroll
+        for (int s = 0; s < R + 3; ++s) me[s] = load_elem<T, FINE>(op, i, t.j0 - 2 + s);
+
+        V2<T> f0, f1, f2, f3, d0, d1, d2, d3;
+        V2<T> vlo = from_right(vr[0]), vhi = from_right(vr[1]);
+        elem_force(me[0], mat, vr[0], vlo, vhi, vr[1], f0, f1, f2, f3);
+        elem_diag(me[0], mat, d0, d1, d2, d3);
+        V2<T> fc1 = f3 + from_left(f2), dc1 = d3 + from_left(d2);
+        V2<T> fc2{T(0), T(0)};
+        V2<T> u1_prev{T(0), T(0)}, u1r_prev{T(0), T(0)}, D_prev{T(1), T(1)};
+#pragma unroll
+        for (int s = 1; s < R + 3; ++s) {
+            // stage 1: element row j0-2+s completes node row k = j0-2+s
+            const int k = t.j0 - 2 + s;
+            vlo = vhi;
+            vhi = from_right(vr[s + 1]);
+            elem_force(me[s], mat, vr[s], vlo, vhi, vr[s + 1], f0, f1, f2, f3);
+            elem_diag(me[s], mat, d0, d1, d2, d3);
+            const V2<T> F = fc1 + f0 + from_left(f1);
+            const V2<T> D = dc1 + d0 + from_left(d1);
+            fc1 = f3 + from_left(f2);
+            dc1 = d3 + from_left(d2);
+            const bool kok = node_col && k >= 1 && k <= ny;
+            const V2<T> bk = br[s - 1];
+            const V2<T> u1{kok ? vr[s].x + mat.omega * (bk.x - F.x) / D.x : T(0),
+                           kok ? vr[s].y + mat.omega * (bk.y - F.y) / D.y : T(0)};
+            const V2<T> u1r = from_right(u1);
+            if (s >= 2) {
+                // stage 2: element row k-1 from u1 rows k-1, k completes node row k-1
+                V2<T> g0, g1, g2, g3;
+                elem_force(me[s - 1], mat, u1_prev, u1r_prev, u1r, u1, g0, g1, g2, g3);
+                const V2<T> G = fc2 + g0 + from_left(g1);
+                fc2 = g3 + from_left(g2);
+                const int jr = k - 1;
+                if (s >= 3 && out_lane && jr < t.j1) {
+                    if (jr >= 1) {
+                        const V2<T> bj = br[s - 2];
+                        V2<T> uo;
+                        uo.x = u1_prev.x + mat.omega * (bj.x - G.x) / D_prev.x;
+                        uo.y = u1_prev.y + mat.omega * (bj.y - G.y) / D_prev.y;
+                        store_node(u_out, nx, i, jr, uo);
+                        if constexpr (DOT) dot += (double)uo.x * rr64[s - 3].x + (double)uo.y * rr64[s - 3].y;
+                    } else {
+                        store_node(u_out, nx, i, jr, V2<T>{T(0), T(0)});
+                    }
+                }
+            }
+            u1_prev = u1;
+            u1r_prev = u1r;
+            D_prev = D;
+        }
+    }
+    if constexpr (DOT) {
+        const double s = block_sum(dot);
+        if (threadIdx.x == 0) zr_out[t.tile] = s;
+    }
+}
+
+// ===========================================================================
 // Plain stiffness apply q = K_l u (or its diagonal) in the level precision
 // (test hook and building block).  Geometry as k_cg_apply.
 // ===========================================================================
@@ -683,6 +801,24 @@ __global__ __launch_bounds__(WG_THREADS) void k_coarse_solve(const double* __res
 // launchers: the rows per wave (a compile-time loop length, so all loads of
 // a wave can be issued together) is chosen per level on the host.
 // ===========================================================================
+// Profiling: a start/stop event pair for the next launch, stamped by the
+// kernel's own dispatch (hipExtLaunchKernel), so the interval is the
+// kernel's execution without the launch gaps around it.
+static hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
+void time_next_launch(hipEvent_t start, hipEvent_t stop) {
+    g_ev_start = start;
+    g_ev_stop = stop;
+}
+#define MTOMG_LAUNCH(K, GRID, BLOCK, SHM, ST, ...)                                                   \
+    do {                                                                                         \
+        if (g_ev_start) {                                                                        \
+            hipExtLaunchKernelGGL(K, GRID, BLOCK, SHM, ST, g_ev_start, g_ev_stop, 0, __VA_ARGS__); \
+            g_ev_start = g_ev_stop = nullptr;                                                    \
+        } else {                                                                                 \
+            hipLaunchKernelGGL(K, GRID, BLOCK, SHM, ST, __VA_ARGS__);                            \
+        }                                                                                        \
+    } while (0)
+
 // x: tiles (a multiple of 8, for the XCD-aware tile order), y: systems
 static inline dim3 grid_of(const Sweep& s, const Batch& bt = Batch{}) {
     return dim3(8 * ((s.n_tiles + 7) / 8), bt.n);
@@ -701,7 +837,7 @@ void launch_cg_apply(hipStream_t st, LevelOp<double> op, Mat<double> mat, Sweep 
                      const double* p_old, double* p_new, double* x, double* q, const double* zr_cur,
                      const double* zr_prev, int n_zr, const double* pq_prev, int n_pq,
                      double* pq_out, const int* conv, int mode, const Batch& bt) {
-    MTOMG_ROWS_SWITCH(sw.rows, hipLaunchKernelGGL((k_cg_apply<TZ, RR>), grid_of(sw, bt), dim3(WG_THREADS), 0, st,
+    MTOMG_ROWS_SWITCH(sw.rows, MTOMG_LAUNCH((k_cg_apply<TZ, RR>), grid_of(sw, bt), dim3(WG_THREADS), 0, st,
                                                    op, mat, sw, z, p_old, p_new, x, q, zr_cur, zr_prev, n_zr,
                                                    pq_prev, n_pq, pq_out, conv, mode, bt))
 }
@@ -717,7 +853,7 @@ template void launch_cg_apply<double>(hipStream_t, LevelOp<double>, Mat<double>,
 void launch_residual(hipStream_t st, LevelOp<double> op, Mat<double> mat, Sweep sw, const double* f,
                      double* x, int use_x, double* r, double* rr_out, double* ff_out, const int* conv,
                      const Batch& bt) {
-    MTOMG_ROWS_SWITCH(sw.rows, hipLaunchKernelGGL((k_residual<RR>), grid_of(sw, bt), dim3(WG_THREADS), 0, st, op,
+    MTOMG_ROWS_SWITCH(sw.rows, MTOMG_LAUNCH((k_residual<RR>), grid_of(sw, bt), dim3(WG_THREADS), 0, st, op,
                                                    mat, sw, f, x, use_x, r, rr_out, ff_out, conv, bt))
 }
 
@@ -725,7 +861,7 @@ template <typename T>
 void launch_presmooth(hipStream_t st, bool fine, bool cgmode, LevelOp<T> op, Mat<T> mat, Sweep sw,
                       const T* b, T* u_out, int sweeps, const CgRhs& cg, const int* conv, const Batch& bt) {
 #define MTOMG_PRE(F, C)                                                                              \
-    MTOMG_ROWS_SWITCH(sw.rows, hipLaunchKernelGGL((k_presmooth<T, F, C, RR>), grid_of(sw, bt), dim3(WG_THREADS), \
+    MTOMG_ROWS_SWITCH(sw.rows, MTOMG_LAUNCH((k_presmooth<T, F, C, RR>), grid_of(sw, bt), dim3(WG_THREADS), \
                                                    0, st, op, mat, sw, b, u_out, sweeps, cg, conv, bt))
     if (cgmode) MTOMG_PRE(true, true)
     else if (fine) MTOMG_PRE(true, false)
@@ -737,7 +873,7 @@ template <typename T>
 void launch_restrict(hipStream_t st, bool fine, bool check, LevelOp<T> op, Mat<T> mat, Sweep sw,
                      const T* b, const T* u, T* rc, const ConvCheck& chk, const int* conv, const Batch& bt) {
 #define MTOMG_RES(F, C)                                                                              \
-    MTOMG_ROWS_SWITCH(sw.rows, hipLaunchKernelGGL((k_restrict<T, F, C, RR>), grid_of(sw, bt), dim3(WG_THREADS), \
+    MTOMG_ROWS_SWITCH(sw.rows, MTOMG_LAUNCH((k_restrict<T, F, C, RR>), grid_of(sw, bt), dim3(WG_THREADS), \
                                                    0, st, op, mat, sw, b, u, rc, chk, conv, bt))
     if (check) MTOMG_RES(true, true)
     else if (fine) MTOMG_RES(true, false)
@@ -750,7 +886,7 @@ void launch_post(hipStream_t st, bool fine, bool prolong, bool dot, LevelOp<T> o
                  const T* u_in, const T* ec, const T* b, T* u_out, const double* r64, double* zr_out,
                  const int* conv, const Batch& bt) {
 #define MTOMG_POST(F, P, D)                                                                          \
-    MTOMG_ROWS_SWITCH(sw.rows, hipLaunchKernelGGL((k_post<T, F, P, D, RR>), grid_of(sw, bt), dim3(WG_THREADS), \
+    MTOMG_ROWS_SWITCH(sw.rows, MTOMG_LAUNCH((k_post<T, F, P, D, RR>), grid_of(sw, bt), dim3(WG_THREADS), \
                                                    0, st, op, mat, sw, u_in, ec, b, u_out, r64, zr_out, conv, bt))
     if (fine) {
         if (prolong) { if (dot) MTOMG_POST(true, true, true) else MTOMG_POST(true, true, false) }
@@ -763,10 +899,27 @@ void launch_post(hipStream_t st, bool fine, bool prolong, bool dot, LevelOp<T> o
 }
 
 template <typename T>
+void launch_post2(hipStream_t st, bool fine, bool prolong, bool dot, LevelOp<T> op, Mat<T> mat, Sweep sw,
+                  const T* u_in, const T* ec, const T* b, T* u_out, const double* r64, double* zr_out,
+                  const int* conv, const Batch& bt) {
+#define MTOMG_POST2(F, P, D)                                                                         \
+    MTOMG_ROWS_SWITCH(sw.rows, MTOMG_LAUNCH((k_post2<T, F, P, D, RR>), grid_of(sw, bt), dim3(WG_THREADS), \
+                                                   0, st, op, mat, sw, u_in, ec, b, u_out, r64, zr_out, conv, bt))
+    if (fine) {
+        if (prolong) { if (dot) MTOMG_POST2(true, true, true) else MTOMG_POST2(true, true, false) }
+        else { if (dot) MTOMG_POST2(true, false, true) else MTOMG_POST2(true, false, false) }
+    } else {
+        if (prolong) MTOMG_POST2(false, true, false)
+        else MTOMG_POST2(false, false, false)
+    }
+#undef MTOMG_POST2
+}
+
+template <typename T>
 void launch_apply(hipStream_t st, bool fine, bool diag, LevelOp<T> op, Mat<T> mat, Sweep sw, const T* u,
                   T* q) {
 #define MTOMG_APP(F, D)                                                                              \
-    MTOMG_ROWS_SWITCH(sw.rows, hipLaunchKernelGGL((k_apply<T, F, D, RR>), grid_of(sw), dim3(WG_THREADS), 0, st, \
+    MTOMG_ROWS_SWITCH(sw.rows, MTOMG_LAUNCH((k_apply<T, F, D, RR>), grid_of(sw), dim3(WG_THREADS), 0, st, \
                                                    op, mat, sw, u, q))
     if (fine) { if (diag) MTOMG_APP(true, true) else MTOMG_APP(true, false) }
     else { if (diag) MTOMG_APP(false, true) else MTOMG_APP(false, false) }
@@ -777,7 +930,7 @@ template <typename T>
 void launch_coarse_solve(hipStream_t st, const double* Ainv, int n0, int ld, int nx0, const T* b, T* e,
                          const int* conv, const Batch& bt) {
     const int nblk = (n0 + WAVES_PER_WG - 1) / WAVES_PER_WG;
-    hipLaunchKernelGGL((k_coarse_solve<T>), dim3(nblk, bt.n), dim3(WG_THREADS), n0 * sizeof(double), st, Ainv,
+    MTOMG_LAUNCH((k_coarse_solve<T>), dim3(nblk, bt.n), dim3(WG_THREADS), n0 * sizeof(double), st, Ainv,
                        n0, ld, nx0, b, e, conv, bt);
 }
 
@@ -789,6 +942,9 @@ void launch_coarse_solve(hipStream_t st, const double* Ainv, int n0, int ld, int
     template void launch_post<T>(hipStream_t, bool, bool, bool, LevelOp<T>, Mat<T>, Sweep, const T*,  \
                                  const T*, const T*, T*, const double*, double*, const int*,       \
                                  const Batch&);                                                    \
+    template void launch_post2<T>(hipStream_t, bool, bool, bool, LevelOp<T>, Mat<T>, Sweep, const T*, \
+                                  const T*, const T*, T*, const double*, double*, const int*,      \
+                                  const Batch&);                                                   \
     template void launch_apply<T>(hipStream_t, bool, bool, LevelOp<T>, Mat<T>, Sweep, const T*, T*);  \
     template void launch_coarse_solve<T>(hipStream_t, const double*, int, int, int, const T*, T*, const int*, \
                                          const Batch&);

@@ -144,3 +144,27 @@ def test_coarse_solve_and_vcycle(setup):
         want = multigrid.cycle(o.H, l, free_of(b, nx), None, prob.omega, prob.n_pre, prob.n_post)
         got = run(s, prec, l, "VCYCLE", [b], (ny + 1, nx + 1, 2))
         assert rel(free_of(got, nx), want) < tol(prec, 2e-11), f"vcycle level {l}"
+
+
+@pytest.mark.parametrize("n_post", [1, 3, 4])
+def test_post_chain_sweep_counts(n_post):
+    """u + P e_c followed by n_post sweeps (one fused pair per two sweeps,
+    a single sweep for an odd remainder) against the oracle, every level."""
+    from tests.gpu_util import gpu_solver
+    prob = make_prob(124, 60, 3, 77)
+    o = OracleLevels(124, 60, prob.x, prob.E_phase, prob.E_min, prob.penal, prob.nu, 3)
+    rng = np.random.default_rng(n_post)
+    for prec in ("fp64", "fp32mg"):
+        s = gpu_solver(prob, prec, n_pre=n_post, n_post=n_post)
+        for l in range(1, o.levels):
+            nx, ny = o.dims(l)
+            cx, cy = o.dims(l - 1)
+            lev = o.H.levels[l]
+            b, u, ec = rnd_nodal(rng, nx, ny), rnd_nodal(rng, nx, ny), rnd_nodal(rng, cx, cy)
+            v = free_of(u, nx) + lev.P @ free_of(ec, cx)
+            want = linalg.damped_jacobi(lev.K, free_of(b, nx), v, prob.omega, n_post)
+            got = run(s, prec, l, "PROLONG_POSTSMOOTH", [b, u, ec], (ny + 1, nx + 1, 2))
+            assert rel(free_of(got, nx), want) < tol(prec), (prec, l)
+            want = multigrid.cycle(o.H, l, free_of(b, nx), None, prob.omega, n_post, n_post)
+            got = run(s, prec, l, "VCYCLE", [b], (ny + 1, nx + 1, 2))
+            assert rel(free_of(got, nx), want) < tol(prec, 2e-11), (prec, l)
