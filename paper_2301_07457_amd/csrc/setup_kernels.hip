@@ -130,77 +130,89 @@ __device__ __forceinline__ void blk_load(double (*S)[NB + 1], const double* __re
     }
 }
 
-// Lower-triangle elements of a 32x32 block owned by thread t: indices
-// t, t+256, t+512 (< 528) of the row-major lower triangle.
-struct TriOwn {
-    int n, r[3], c[3];
-};
-__device__ __forceinline__ TriOwn tri_own() {
-    TriOwn o;
-    o.n = 0;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        const int idx = threadIdx.x + 256 * q;
-        const int ic = min(idx, NB * (NB + 1) / 2 - 1);
-        int r = (int)((sqrtf(8.0f * ic + 1.0f) - 1.0f) * 0.5f);
-        while (r * (r + 1) / 2 > ic) --r;
-        while ((r + 1) * (r + 2) / 2 <= ic) ++r;
-        o.r[q] = r;
-        o.c[q] = ic - r * (r + 1) / 2;
-        if (idx < NB * (NB + 1) / 2) o.n = q + 1;
-    }
-    return o;
+// ---------------------------------------------------------------------------
+// Factor and inverse of one SPD 32x32 block by a single wave, in registers.
+// Lane l holds row r = l & 31 at the columns c = 2j + h, h = l >> 5.  Step
+// k of the right-looking factorisation scales column k into L and, as the
+// same elementary row operation applied to X (initially I), row k of X;
+// then every row below eliminates: S[r][c] -= L[r][k] L[c][k] and
+// X[r][:] -= L[r][k] X[k][:].  After 32 steps X = L^{-1} (Gauss-Jordan on
+// the factor).  Column k of L and row k of X reach the other lanes through
+// LDS; the lanes of one wave access LDS in order, so only the compiler is
+// fenced between the writes and the reads.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Cholesky factor L of the SPD block S (LDS, lower triangle; S is used as
-// work space) and Li = L^{-1}, by all 256 threads with one barrier per step.
-// Right-looking: step k scales column k into L and updates the trailing
-// part of S; no element is read and written in the same step.  The inverse
-// is formed row by row, each thread finishing its own entries of row r and
-// adding row r-1's contribution to the rows below.  Acc is scratch.
-// Returns false (uniformly) if a pivot is not positive.
-__device__ bool block_potrf_inv(double (*S)[NB + 1], double (*L)[NB + 1], double (*Li)[NB + 1],
-                                double (*Acc)[NB + 1]) {
-    const TriOwn o = tri_own();
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// 1/sqrt(d): hardware estimate, then two Newton steps y <- y (3 - d y^2) / 2
+__device__ __forceinline__ double rsqrt_nr(double d) {
+    double y = __builtin_amdgcn_rsq(d);
+    const double hd = 0.5 * d;
+    y = y * fma(-hd, y * y, 1.5);
+    y = y * fma(-hd, y * y, 1.5);
+    return y;
+}
+
+// S: input block (LDS, lower triangle read); Li: receives L^{-1} (full
+// block, zero above the diagonal); buf: 128 doubles of LDS.  Call from one
+// whole wave.  Returns false (uniformly) if a pivot is not positive.
+__device__ bool wave_potrf_inv(const double (*S)[NB + 1], double (*Li)[NB + 1], double* buf) {
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 31, h = lane >> 5;
+    double a[16], x[16];
 #pragma unroll
-    for (int q = 0; q < 3; ++q)
-        if (q < o.n) Acc[o.r[q]][o.c[q]] = 0.0;
-    for (int k = 0; k < NB; ++k) {
-        __syncthreads();
-        const double d = S[k][k];
-        if (!(d > 0.0)) return false;
-        const double sq = sqrt(d), inv = 1.0 / sq;
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            if (q >= o.n) continue;
-            const int r = o.r[q], c = o.c[q];
-            if (c == k) L[r][k] = (r == k) ? sq : S[r][k] * inv;
-            else if (c > k) S[r][c] -= (S[r][k] * inv) * (S[c][k] * inv);
-        }
+    for (int j = 0; j < 16; ++j) {
+        a[j] = S[r][2 * j + h];
+        x[j] = (2 * j + h == r) ? 1.0 : 0.0;
     }
-    __syncthreads();
-    for (int r = 0; r < NB; ++r) {
+    double* colb = buf;            // L[c][k] at (c & 1) * 16 + (c >> 1)
+    double* rowb = buf + 2 * NB;   // X[k][c] at (c & 1) * 16 + (c >> 1)
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            if (q >= o.n) continue;
-            const int i = o.r[q], c = o.c[q];
-            if (i == r) {
-                double s = (c == r) ? 1.0 : 0.0;
-                s -= Acc[r][c];
-                if (r >= 1 && c <= r - 1) s -= L[r][r - 1] * Li[r - 1][c];
-                Li[r][c] = s / L[r][r];
-            } else if (i > r && r >= 1 && c <= r - 1) {
-                Acc[i][c] += L[i][r - 1] * Li[r - 1][c];
+    for (int k = 0; k < NB; ++k) {
+        const int jk = k >> 1, hk = k & 1;
+        const double d = readlane_d(a[jk], k + 32 * hk);
+        if (!(d > 0.0)) return false;
+        const double inv = rsqrt_nr(d);
+        if (h == hk) {
+            const double v = (r > k) ? a[jk] * inv : (r == k ? d * inv : 0.0);
+            a[jk] = v;
+            colb[(r & 1) * 16 + (r >> 1)] = v;
+        }
+        if (r == k) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                x[j] *= inv;
+                rowb[h * 16 + j] = x[j];
             }
         }
-        __syncthreads();
+        wave_fence();
+        const double lrk = colb[(r & 1) * 16 + (r >> 1)];
+        double lc[16], xk[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            lc[j] = colb[h * 16 + j];
+            xk[j] = rowb[h * 16 + j];
+        }
+        if (r > k) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                if (2 * j + h > k) a[j] -= lrk * lc[j];
+                x[j] -= lrk * xk[j];
+            }
+        }
+        wave_fence();
     }
-    // zero the strict upper part of Li (it is read as a full block)
-    for (int x = threadIdx.x; x < NB * NB; x += 256) {
-        const int r = x / NB, c = x % NB;
-        if (c > r) Li[r][c] = 0.0;
-    }
-    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 16; ++j) Li[r][2 * j + h] = x[j];
     return true;
 }
 
@@ -228,11 +240,17 @@ __device__ __forceinline__ void blk_gemm_nt(double (*C)[NB + 1], double (*X)[NB 
 //  * W = L^{-1} part, step t = k - 2 (0 <= t <= nblk-2): workgroup (i, j),
 //    i > t >= j: S[i,j] (+)= L[i,t] W[t,j] (W[t,t] = Dinv[t]); for i == t+1
 //    the sum is complete and W[t+1,j] = -Dinv[t+1] S[t+1,j].
-// Every block a launch reads was written by an earlier launch.
+//  * K_0^{-1} = W^T W part, block row t = k - 2 of W (complete since the
+//    previous launch), 0 <= t <= nblk-1: workgroup (i, j), t >= i >= j:
+//    Ainv[i,j] (+)= W[t,i]^T W[t,j], summed over t in increasing order; the
+//    last row (t = nblk-1) also writes the mirrored block Ainv[j,i], so the
+//    inverse is exactly symmetric.
+// Every block a launch reads was written by an earlier launch; launches
+// run for k = 0 .. nblk+1.
 __global__ __launch_bounds__(256) void k_factor_step(double* __restrict__ A, int np, int k, double* __restrict__ Dinv,
                                                      double* __restrict__ Lbuf, double* __restrict__ W,
-                                                     double* __restrict__ Sacc, int* __restrict__ status,
-                                                     long long ds) {
+                                                     double* __restrict__ Sacc, double* __restrict__ Ainv,
+                                                     int* __restrict__ status, long long ds) {
     __shared__ double B0[NB][NB + 1], B1[NB][NB + 1], B2[NB][NB + 1], B3[NB][NB + 1], B4[NB][NB + 1];
     // design blockIdx.y; skipped unless flagged for factorisation and still positive definite
     const long long off = (long long)blockIdx.y * ds;
@@ -243,10 +261,38 @@ __global__ __launch_bounds__(256) void k_factor_step(double* __restrict__ A, int
     Lbuf = at(Lbuf, off);
     W = at(W, off);
     Sacc = at(Sacc, off);
+    Ainv = at(Ainv, off);
     const int nblk = np / NB;
     int r, c4;
     blk_coords(r, c4);
     const int n_chol = (k >= nblk) ? 0 : (k == 0 ? 1 : (nblk - k) * (nblk - k + 1) / 2);
+    const int t_inv = k - 2;
+    const int n_inv = (t_inv >= 0 && t_inv <= nblk - 2) ? (nblk - 1 - t_inv) * (t_inv + 1) : 0;
+    if ((int)blockIdx.x >= n_chol + n_inv) {
+        // ---- Ainv = W^T W, block row t of W
+        const int t = k - 2;
+        int i = 0, j = blockIdx.x - n_chol - n_inv;
+        while (j > i) { j -= i + 1; ++i; }
+        blk_load(B0, W, np, t, i);
+        blk_load(B1, W, np, t, j);
+        __syncthreads();
+        double* blk = Ainv + (size_t)(i * NB + r) * np + j * NB + c4;
+        double acc[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = (t == i) ? 0.0 : blk[q];
+        for (int s = 0; s < NB; ++s) {
+            const double wr = B0[s][r];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] += wr * B1[s][c4 + q];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) blk[q] = acc[q];
+        if (t == nblk - 1 && i != j) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Ainv[(size_t)(j * NB + c4 + q) * np + i * NB + r] = acc[q];
+        }
+        return;
+    }
     if ((int)blockIdx.x >= n_chol) {
         // ---- W = L^{-1}, step t
         const int t = k - 2;
@@ -287,9 +333,16 @@ __global__ __launch_bounds__(256) void k_factor_step(double* __restrict__ A, int
         return;
     }
     // ---- Cholesky
+    __shared__ int not_spd;
     auto finish_diag = [&](int kk) {
-        // B0 holds the finished diagonal block kk
-        if (!block_potrf_inv(B0, B1, B2, B3)) {
+        // B0 holds the finished diagonal block kk; wave 0 factors it into B2 = L_kk^{-1}
+        __syncthreads();
+        if (threadIdx.x < WAVE) {
+            const bool ok = wave_potrf_inv(B0, B2, &B3[0][0]);
+            if (threadIdx.x == 0) not_spd = ok ? 0 : 1;
+        }
+        __syncthreads();
+        if (not_spd) {
             if (threadIdx.x == 0) *status = 1;
             return;
         }
@@ -338,42 +391,6 @@ __global__ __launch_bounds__(256) void k_factor_step(double* __restrict__ A, int
 #pragma unroll
         for (int q = 0; q < 4; ++q) B0[r][c4 + q] = nv[q];
         finish_diag(k);
-    }
-}
-
-// K_0^{-1} = W^T W: one workgroup per lower block (ib >= jb), mirrored to
-// the upper block so the inverse is exactly symmetric.
-__global__ __launch_bounds__(256) void k_gram_blk(const double* __restrict__ W, double* __restrict__ Ainv, int np,
-                                                  const int* __restrict__ status, long long ds) {
-    __shared__ double Wi[NB][NB + 1], Wj[NB][NB + 1];
-    const long long off = (long long)blockIdx.y * ds;
-    status = at(status, off);
-    if (status[1] == 0 || status[0] != 0) return;
-    W = at(W, off);
-    Ainv = at(Ainv, off);
-    const int nblk = np / NB;
-    int ib = 0, rem = blockIdx.x;
-    while (rem > ib) { rem -= ib + 1; ++ib; }
-    const int jb = rem;   // 0 <= jb <= ib
-    int r, c4;
-    blk_coords(r, c4);
-    double acc[4] = {0, 0, 0, 0};
-    for (int t = ib; t < nblk; ++t) {
-        blk_load(Wi, W, np, t, ib);
-        blk_load(Wj, W, np, t, jb);
-        __syncthreads();
-        for (int s = 0; s < NB; ++s) {
-            const double wr = Wi[s][r];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc[q] += wr * Wj[s][c4 + q];
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int c = c4 + q;
-        Ainv[(size_t)(ib * NB + r) * np + jb * NB + c] = acc[q];
-        Ainv[(size_t)(jb * NB + c) * np + ib * NB + r] = acc[q];
     }
 }
 
@@ -484,17 +501,16 @@ void launch_coarse_factor(hipStream_t st, double* A, int n0, int np, double* Din
         hipLaunchKernelGGL(k_pad_identity, dim3(blocks_for(np - n0, 256), n_designs), dim3(256), 0, st, A, n0, np,
                            status, ds);
     const int nblk = np / NB;
-    for (int k = 0; k <= nblk; ++k) {
+    for (int k = 0; k <= nblk + 1; ++k) {
         const int m = nblk - k;
         const int n_chol = (k >= nblk) ? 0 : (k == 0 ? 1 : m * (m + 1) / 2);
         const int t = k - 2;
         const int n_inv = (t >= 0 && t <= nblk - 2) ? (nblk - 1 - t) * (t + 1) : 0;
-        if (n_chol + n_inv == 0) continue;
-        hipLaunchKernelGGL(k_factor_step, dim3(n_chol + n_inv, n_designs), dim3(256), 0, st, A, np, k, Dinv, Lbuf,
-                           W, Sacc, status, ds);
+        const int n_gram = (t >= 0 && t <= nblk - 1) ? (t + 1) * (t + 2) / 2 : 0;
+        if (n_chol + n_inv + n_gram == 0) continue;
+        hipLaunchKernelGGL(k_factor_step, dim3(n_chol + n_inv + n_gram, n_designs), dim3(256), 0, st, A, np, k,
+                           Dinv, Lbuf, W, Sacc, Ainv, status, ds);
     }
-    hipLaunchKernelGGL(k_gram_blk, dim3(nblk * (nblk + 1) / 2, n_designs), dim3(256), 0, st, W, Ainv, np, status,
-                       ds);
 }
 
 void launch_fill_strided(hipStream_t st, int* p, long long stride_bytes, int n, int v) {

@@ -3,7 +3,8 @@
 * 256 x 256, binary 1e9 contrast (5 levels, FP64): against the oracle's
   direct solve element by element, and the adjoint gradient against central
   finite differences on 64 solid (element, phase) pairs plus 8 pairs whose
-  gradient is ~0.  At this contrast the residual 1e-8 leaves an error of
+  gradient is ~0 (relative 1e-5 for gradients of at least 1e-4 max|g|,
+  absolute 1e-9 max|g| below).  At this contrast the residual 1e-8 leaves an error of
   ~6e-6 in u (condition number ~1e9), so the u comparison solves to 1e-10.
 * 1024 x 1024 smooth field (7 levels, FP32 cycle) and 2048 x 2048
   near-binary 4-phase field (8 levels, FP32 cycle): against oracle samples
@@ -92,7 +93,11 @@ def test_wall256_gradient_central_differences(wall256, chunk):
         # c+ - c- = -(E+ - E-) u-_e^T K0 u+_e  (no cancellation)
         fd = -(Ep - Em) * (um @ KE @ up) / (2 * h)
         naive = (cp - cm) / (2 * h)
-        tol = 1e-5 * max(abs(g[e, ph]), 1e-6 * gmax)
+        # relative 1e-5 where the gradient is at least 1e-4 of the largest;
+        # below that an absolute 1e-9 max|g|: solid islands floating in the
+        # 1e-9 void carry almost no strain energy, and their u_e at a 1e-10
+        # residual is set by solver noise (condition number ~1e9)
+        tol = 1e-5 * max(abs(g[e, ph]), 1e-4 * gmax)
         assert abs(fd - g[e, ph]) <= tol, (e, ph, fd, g[e, ph], naive)
         print(f"[fd] e={e} ph={ph} grad={g[e, ph]:.6e} fd={fd:.6e} naive={naive:.6e}")
 

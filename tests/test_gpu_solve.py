@@ -164,3 +164,19 @@ def test_other_sweep_counts(sweeps, prec):
     assert st["status"] == 0 and st["relres_true"] <= 1.05e-8, st
     assert abs(st["iters"] - o.iters[0]) <= 1, (st["iters"], o.iters)
     assert rel(s.U(0).cpu().numpy(), ref.U) <= 1e-6
+
+
+@pytest.mark.parametrize("nx,ny,L", [(2, 2, 2), (4, 4, 2), (8, 6, 2), (8, 8, 3), (6, 20, 2)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32mg"])
+def test_tiny_grids(nx, ny, L, prec):
+    """Degenerate sizes: a single coarsest element, one- and two-block coarse
+    factorisations, one strip narrower than a wave."""
+    p = rand_prob(nx, ny, L, 40 + nx + ny)
+    ref = oracle_direct(p)
+    s = gpu_solver(p, prec)
+    st = s.solve(1e-8, 1000)[0]
+    assert st["status"] == 0 and st["relres_true"] <= 1.05e-8, st
+    assert rel(s.U(0).cpu().numpy(), ref.U) <= 1e-6
+    c, dc = s.compliance_and_grad(0)
+    np.testing.assert_allclose(c.cpu().numpy(), ref.c, rtol=1e-7)
+    assert rel(dc.cpu().numpy(), ref.dcdx) <= 1e-5
