@@ -48,6 +48,7 @@ struct LevelBufs {
     Sweep sw_apply{}, sw_pre{}, sw_res{}, sw_post{};
     Sweep sw_cg{};      // outer-CG apply (finest level)
     Sweep sw_post2{};   // two fused post-smoothing sweeps
+    Sweep sw_rp{};      // restriction fused with the next level's pre-smoothing (coarse geometry)
     size_t nodes() const { return (size_t)(nx + 1) * (ny + 1); }
 };
 
@@ -216,8 +217,10 @@ void plan_level(LevelBufs& L, int R = 0) {
     L.sw_post = L.sw_apply;
     L.sw_post2 = make_sweep(L.nx + 1, 60, L.ny + 1, R);
     L.sw_pre = make_sweep(L.nx + 1, 61, L.ny + 1, R);
-    if (L.nx % 2 == 0 && L.ny % 2 == 0)
+    if (L.nx % 2 == 0 && L.ny % 2 == 0) {
         L.sw_res = make_sweep(L.nx / 2 + 1, 30, L.ny / 2 + 1, R);
+        L.sw_rp = make_sweep(L.nx / 2 + 1, 28, L.ny / 2 + 1, R);
+    }
 }
 
 
@@ -488,29 +491,55 @@ T* pre_chain_extra(CycleCtx<T>& cx, int l, T* cur, const T* b, T* t0, T* t1) {
     return cur;
 }
 
-// Levels l-1 .. 0 of Algorithm 1 given the restricted right-hand side in
-// c.b[top]; leaves the coarse correction in c.e[top].  The pre-smoothed
+// Residual restriction from level l to l-1.  When level l-1 has a smoother
+// (l - 1 >= 1) and is small, the same launch also runs its first
+// pre-smoothing sweeps from zero into u2[l-1]; returns whether it did.
+// The fused kernel re-forms two halo rows of the restriction per wave, so
+// it only pays where launches, not bytes, dominate: up to 32768 coarse
+// nodes summed over the systems of the launch.
+constexpr long FUSE_MAX_COARSE_NODES = 32768;
+template <typename T>
+bool restrict_down(CycleCtx<T>& cx, int l, const T* b, const T* u, bool check, const ConvCheck& chk) {
+    Design& d = *cx.d;
+    CaseBufs& c = *cx.c;
+    const bool fine = l == d.fine();
+    const bool fuse = l - 1 >= 1 && d.n_pre > 0 &&
+                      (long)d.lev[l - 1].nodes() * cx.bt.n <= FUSE_MAX_COARSE_NODES;
+    if (fuse)
+        launch_restrict_pre<T>(cx.st, fine, check, level_op<T>(d, l), level_op<T>(d, l - 1), make_mat<T>(d, d.omega),
+                               d.lev[l].sw_rp, b, u, (T*)c.b[l - 1], (T*)c.u2[l - 1], std::min(d.n_pre, 2), chk,
+                               cx.conv, cx.bt);
+    else
+        launch_restrict<T>(cx.st, fine, check, level_op<T>(d, l), make_mat<T>(d, d.omega), d.lev[l].sw_res, b, u,
+                           (T*)c.b[l - 1], chk, cx.conv, cx.bt);
+    return fuse;
+}
+
+// Levels top .. 0 of Algorithm 1 given the restricted right-hand side in
+// c.b[top] (and, when top_pre, its first pre-smoothing sweeps already in
+// u2[top]); leaves the coarse correction in c.e[top].  The pre-smoothed
 // iterate of each level stays in u2 or u4 (which one depends on the number
 // of sweeps only), so a captured launch sequence is the same every time.
 template <typename T>
-void coarse_cycle(CycleCtx<T>& cx, int top) {
+void coarse_cycle(CycleCtx<T>& cx, int top, bool top_pre) {
     Design& d = *cx.d;
     CaseBufs& c = *cx.c;
     ConvCheck nochk{};
     CgRhs nocg{};
     T* pre[16] = {};
+    bool pre_done = top_pre;
     for (int l = top; l >= 1; --l) {
         T* b = (T*)c.b[l];
         T* t0 = (T*)c.u2[l];
         T* t1 = (T*)c.u4[l];
         T* cur = t0;
         if (d.n_pre > 0) {
-            launch_presmooth<T>(cx.st, false, false, level_op<T>(d, l), make_mat<T>(d, d.omega), d.lev[l].sw_pre,
-                                b, t0, std::min(d.n_pre, 2), nocg, cx.conv, cx.bt);
+            if (!pre_done)
+                launch_presmooth<T>(cx.st, false, false, level_op<T>(d, l), make_mat<T>(d, d.omega), d.lev[l].sw_pre,
+                                    b, t0, std::min(d.n_pre, 2), nocg, cx.conv, cx.bt);
             cur = pre_chain_extra<T>(cx, l, cur, b, t0, t1);
         }
-        launch_restrict<T>(cx.st, false, false, level_op<T>(d, l), make_mat<T>(d, d.omega), d.lev[l].sw_res, b,
-                           d.n_pre > 0 ? cur : nullptr, (T*)c.b[l - 1], nochk, cx.conv, cx.bt);
+        pre_done = restrict_down<T>(cx, l, b, d.n_pre > 0 ? cur : nullptr, false, nochk);
         pre[l] = cur;
     }
     cx.begin(MTOMG_KERNEL_COARSE_SOLVE);
@@ -563,10 +592,9 @@ void fine_cycle(CycleCtx<T>& cx, int it, double tol2) {
     chk.tol2 = tol2;
     chk.conv_rw = c.state;
     cx.begin(MTOMG_KERNEL_FINE_RESTRICT);
-    launch_restrict<T>(cx.st, true, true, level_op<T>(d, f), make_mat<T>(d, d.omega), L.sw_res, bfine,
-                       d.n_pre > 0 ? cur : nullptr, (T*)c.b[f - 1], chk, cx.conv, cx.bt);
+    const bool pre_done = restrict_down<T>(cx, f, bfine, d.n_pre > 0 ? cur : nullptr, true, chk);
     cx.end(MTOMG_KERNEL_FINE_RESTRICT);
-    coarse_cycle<T>(cx, f - 1);
+    coarse_cycle<T>(cx, f - 1, pre_done);
     post_chain<T>(cx, f, d.n_pre > 0 ? cur : nullptr, (const T*)c.e[f - 1], bfine, (T*)c.z, cur == t0 ? t1 : t0,
                   cur, true, c.r[nxt], c.zr[it < 0 ? 0 : nxt]);
 }
@@ -610,9 +638,8 @@ int debug_vcycle(mtomg_ctx* ctx, Design& d, CaseBufs& cb, hipStream_t st, int le
         launch_presmooth<T>(st, fine, false, opT, mat, d.lev[level].sw_pre, bl, t0, std::min(d.n_pre, 2), nocg, nullptr);
         cur = pre_chain_extra<T>(cx, level, cur, bl, t0, t1);
     }
-    launch_restrict<T>(st, fine, false, opT, mat, d.lev[level].sw_res, bl, d.n_pre > 0 ? cur : nullptr,
-                       (T*)cb.b[level - 1], nochk, nullptr);
-    coarse_cycle<T>(cx, level - 1);
+    const bool pre_done = restrict_down<T>(cx, level, bl, d.n_pre > 0 ? cur : nullptr, false, nochk);
+    coarse_cycle<T>(cx, level - 1, pre_done);
     post_chain<T>(cx, level, d.n_pre > 0 ? cur : nullptr, (const T*)cb.e[level - 1], bl, vout, cur == t0 ? t1 : t0,
                   cur, false, nullptr, nullptr);
     return MTOMG_OK;

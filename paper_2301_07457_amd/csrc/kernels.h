@@ -85,6 +85,12 @@ template <typename T>
 void launch_restrict(hipStream_t st, bool fine, bool check, LevelOp<T> op, Mat<T> mat, Sweep sw,
                      const T* b, const T* u, T* rc, const ConvCheck& chk, const int* conv,
                      const Batch& bt = Batch{});
+// restriction to level l-1 fused with its first (up to two) pre-smoothing
+// sweeps; op / opc: levels l and l-1; geometry: 28 coarse columns per strip
+template <typename T>
+void launch_restrict_pre(hipStream_t st, bool fine, bool check, LevelOp<T> op, LevelOp<T> opc, Mat<T> mat,
+                         Sweep sw, const T* b, const T* u, T* rc, T* uc, int sweeps, const ConvCheck& chk,
+                         const int* conv, const Batch& bt = Batch{});
 template <typename T>
 void launch_post(hipStream_t st, bool fine, bool prolong, bool dot, LevelOp<T> op, Mat<T> mat, Sweep sw,
                  const T* u_in, const T* ec, const T* b, T* u_out, const double* r64, double* zr_out,

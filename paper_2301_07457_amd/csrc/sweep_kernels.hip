@@ -482,6 +482,167 @@ __global__ __launch_bounds__(WG_THREADS) void k_restrict(
     }
 }
 
+// ===========================================================================
+// Restriction to level l-1 fused with the pre-smoothing there.  Phase A
+// (lanes = fine columns) forms rc = P^T (b - K u) for the chunk's coarse
+// rows J0-1 .. J0+R, exactly as k_restrict; phase B (lanes 0..31 = coarse
+// columns) takes them through LDS and runs the first `sweeps` (1 or 2)
+// damped-Jacobi sweeps from zero on level l-1, as k_presmooth.  rc is
+// stored as well (the post-smoother of level l-1 reads it).  With CHECK the
+// convergence test of k_restrict comes first.
+// Geometry: a wave covers 64 fine = 32 coarse columns; phase A's rc is
+// valid on coarse lanes 1..30, so the smoothed values are valid and owned
+// on coarse lanes 2..29 (28 coarse columns per strip).
+// ===========================================================================
+template <typename T, bool FINE, bool CHECK, int R>
+__global__ __launch_bounds__(WG_THREADS) void k_restrict_pre(
+    LevelOp<T> op, LevelOp<T> opc, Mat<T> mat, Sweep sw, const T* __restrict__ b, const T* __restrict__ u,
+    T* __restrict__ rc, T* __restrict__ uc, int sweeps, ConvCheck chk, const int* conv, Batch bt) {
+    constexpr int RA = R + 2;                  // coarse rows formed in phase A
+    __shared__ V2<T> cbuf[WAVES_PER_WG][RA][32];
+    const SysOff so = sys_off(bt);
+    conv = at(conv, so.c);
+    op.data = at(op.data, so.d);
+    opc.data = at(opc.data, so.d);
+    b = at(b, so.c);
+    u = at(u, so.c);
+    rc = at(rc, so.c);
+    uc = at(uc, so.c);
+    if constexpr (CHECK) {
+        chk.rr = at(chk.rr, so.c);
+        chk.ff = at(chk.ff, so.c);
+        chk.conv_rw = at(chk.conv_rw, so.c);
+    }
+    int cst = 0;
+    if (conv) cst = *conv;
+    if (cst != 0) return;
+    const int nx = op.nx, ny = op.ny;
+    const int ncx = opc.nx, ncy = opc.ny;
+    const TileInfo t = tile_info<R>(sw, ncy + 1);
+    if (!t.block_ok) return;
+    if constexpr (CHECK) {
+        const double rr = sum_partials(chk.rr, chk.n_rr);
+        const double ff = sum_partials(chk.ff, chk.n_ff);
+        const bool done = rr <= chk.tol2 * ff;
+        if (!(rr == rr)) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) *chk.conv_rw = 4;
+            return;
+        }
+        if (done) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) *chk.conv_rw = 1;
+            return;
+        }
+    }
+    if (t.j0 >= t.j1) return;
+    constexpr int CHL = 2, CWOUT = 28;
+    const int lane = lane_id();
+    const int Ib = t.strip * CWOUT - CHL;      // coarse column of coarse lane 0
+    V2<T>(*cb)[32] = cbuf[wave_id()];
+
+    // ---- phase A: fine lane l <-> fine column 2 Ib + l
+    {
+        const int i = 2 * Ib + lane;
+        const bool node_col = i >= 0 && i <= nx;
+        constexpr int NF = 2 * RA + 1;         // fine rows jf0 .. jf0 + 2 RA
+        const int jf0 = 2 * (t.j0 - 1) - 1;
+        V2<T> ur[NF + 2], br[NF];
+        Mom<T> me[NF + 1];
+        if (u) {
+#pragma unroll
+            for (int s = 0; s < NF + 2; ++s) ur[s] = load_node(u, nx, ny, i, jf0 - 1 + s);
+        } else {
+#pragma unroll
+            for (int s = 0; s < NF + 2; ++s) ur[s] = V2<T>{T(0), T(0)};
+        }
+#pragma unroll
+        for (int s = 0; s < NF; ++s) br[s] = load_node(b, nx, ny, i, jf0 + s);
+#pragma unroll
+        for (int s = 0; s < NF + 1; ++s) me[s] = load_elem<T, FINE>(op, i, jf0 - 1 + s);
+        V2<T> f0, f1, f2, f3;
+        V2<T> ur_lo = from_right(ur[0]), ur_hi = from_right(ur[1]);
+        elem_force(me[0], mat, ur[0], ur_lo, ur_hi, ur[1], f0, f1, f2, f3);
+        V2<T> carry = f3 + from_left(f2);
+        V2<T> h_m2{T(0), T(0)}, h_m1{T(0), T(0)};
+#pragma unroll
+        for (int s = 0; s < NF; ++s) {
+            const int j = jf0 + s;
+            ur_lo = ur_hi;
+            ur_hi = from_right(ur[s + 2]);
+            elem_force(me[s + 1], mat, ur[s + 1], ur_lo, ur_hi, ur[s + 2], f0, f1, f2, f3);
+            const V2<T> ku = carry + f0 + from_left(f1);
+            carry = f3 + from_left(f2);
+            const bool jok = node_col && j >= 1 && j <= ny;
+            const V2<T> rr{jok ? br[s].x - ku.x : T(0), jok ? br[s].y - ku.y : T(0)};
+            const V2<T> rl = from_left(rr), rrt = from_right(rr);
+            const V2<T> h{rr.x + T(0.5) * (rl.x + rrt.x), rr.y + T(0.5) * (rl.y + rrt.y)};
+            if ((s & 1) == 0 && s >= 2) {
+                // coarse row J = J0 - 1 + (s - 2) / 2
+                const int J = (j - 1) >> 1;
+                V2<T> v{h_m1.x + T(0.5) * (h_m2.x + h.x), h_m1.y + T(0.5) * (h_m2.y + h.y)};
+                if (J <= 0) v = V2<T>{T(0), T(0)};
+                if (!(lane & 1)) cb[(s - 2) >> 1][lane >> 1] = v;
+            }
+            h_m2 = h_m1;
+            h_m1 = h;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    // ---- phase B: lane c < 32 <-> coarse column Ib + c (lanes 32..63 mirror them, unused)
+    const int cl = lane & 31;
+    const int i = Ib + cl;
+    const bool node_col = lane < 32 && i >= 0 && i <= ncx;
+    const bool out_lane = lane >= CHL && lane < CHL + CWOUT && i <= ncx;
+    V2<T> br[R + 2];
+    Mom<T> me[R + 3];
+#pragma unroll
+    for (int s = 0; s < R + 2; ++s) br[s] = cb[s][cl];   // coarse rows j0-1 .. j0+R
+#pragma unroll
+    for (int s = 0; s < R + 3; ++s) me[s] = load_elem<T, false>(opc, i, t.j0 - 2 + s);
+#pragma unroll
+    for (int s = 1; s <= R; ++s) {
+        const int jj = t.j0 - 1 + s;
+        if (out_lane && jj < t.j1) store_node(rc, ncx, i, jj, br[s]);
+    }
+    if (t.j0 == 0 && out_lane) store_node(uc, ncx, i, 0, V2<T>{T(0), T(0)});
+    V2<T> d0, d1, d2, d3;
+    elem_diag(me[0], mat, d0, d1, d2, d3);
+    V2<T> dcarry = d3 + from_left(d2);
+    V2<T> fcarry{T(0), T(0)};
+    V2<T> u1_prev{T(0), T(0)}, u1r_prev{T(0), T(0)}, b_prev{T(0), T(0)}, D_prev{T(1), T(1)};
+#pragma unroll
+    for (int s = 0; s < R + 2; ++s) {
+        const int k = t.j0 - 1 + s;   // coarse node row completed by the diagonal stage
+        elem_diag(me[s + 1], mat, d0, d1, d2, d3);
+        const V2<T> D = dcarry + d0 + from_left(d1);
+        dcarry = d3 + from_left(d2);
+        const V2<T> bk = br[s];
+        const bool kok = node_col && k >= 1 && k <= ncy;
+        const V2<T> u1{kok ? mat.omega * bk.x / D.x : T(0), kok ? mat.omega * bk.y / D.y : T(0)};
+        const V2<T> u1r = from_right(u1);
+        if (s >= 1) {
+            V2<T> f0, f1, f2, f3;
+            elem_force(me[s], mat, u1_prev, u1r_prev, u1r, u1, f0, f1, f2, f3);
+            const V2<T> fs = fcarry + f0 + from_left(f1);
+            fcarry = f3 + from_left(f2);
+            const int jr = k - 1;
+            if (jr >= t.j0 && jr < t.j1 && jr >= 1 && out_lane) {
+                V2<T> uo = u1_prev;
+                if (sweeps >= 2) {
+                    uo.x = u1_prev.x + mat.omega * (b_prev.x - fs.x) / D_prev.x;
+                    uo.y = u1_prev.y + mat.omega * (b_prev.y - fs.y) / D_prev.y;
+                }
+                store_node(uc, ncx, i, jr, uo);
+            }
+        }
+        u1_prev = u1;
+        u1r_prev = u1r;
+        b_prev = bk;
+        D_prev = D;
+    }
+}
+
 // v(i, jj) += (P e_c)(i, jj) for the fine rows jj = j0-1 .. j0+R of one
 // lane (bilinear weights; nodes off the grid or on the clamped row get 0).
 // With j0 = 2h + PAR, the coarse rows needed are h-1 .. h-1+NC-1 and the
@@ -882,6 +1043,19 @@ void launch_restrict(hipStream_t st, bool fine, bool check, LevelOp<T> op, Mat<T
 }
 
 template <typename T>
+void launch_restrict_pre(hipStream_t st, bool fine, bool check, LevelOp<T> op, LevelOp<T> opc, Mat<T> mat,
+                         Sweep sw, const T* b, const T* u, T* rc, T* uc, int sweeps, const ConvCheck& chk,
+                         const int* conv, const Batch& bt) {
+#define MTOMG_RP(F, C)                                                                               \
+    MTOMG_ROWS_SWITCH(sw.rows, MTOMG_LAUNCH((k_restrict_pre<T, F, C, RR>), grid_of(sw, bt), dim3(WG_THREADS), \
+                                             0, st, op, opc, mat, sw, b, u, rc, uc, sweeps, chk, conv, bt))
+    if (check) MTOMG_RP(true, true)
+    else if (fine) MTOMG_RP(true, false)
+    else MTOMG_RP(false, false)
+#undef MTOMG_RP
+}
+
+template <typename T>
 void launch_post(hipStream_t st, bool fine, bool prolong, bool dot, LevelOp<T> op, Mat<T> mat, Sweep sw,
                  const T* u_in, const T* ec, const T* b, T* u_out, const double* r64, double* zr_out,
                  const int* conv, const Batch& bt) {
@@ -939,6 +1113,9 @@ void launch_coarse_solve(hipStream_t st, const double* Ainv, int n0, int ld, int
                                       int, const CgRhs&, const int*, const Batch&);                \
     template void launch_restrict<T>(hipStream_t, bool, bool, LevelOp<T>, Mat<T>, Sweep, const T*,    \
                                      const T*, T*, const ConvCheck&, const int*, const Batch&);    \
+    template void launch_restrict_pre<T>(hipStream_t, bool, bool, LevelOp<T>, LevelOp<T>, Mat<T>, Sweep,  \
+                                         const T*, const T*, T*, T*, int, const ConvCheck&, const int*, \
+                                         const Batch&);                                            \
     template void launch_post<T>(hipStream_t, bool, bool, bool, LevelOp<T>, Mat<T>, Sweep, const T*,  \
                                  const T*, const T*, T*, const double*, double*, const int*,       \
                                  const Batch&);                                                    \
