@@ -100,6 +100,28 @@ def run_cpu_baseline(n: int, levels: int):
                 solve_only_value=d["n_dof"] * d["iters"] / d["t_solve"])
 
 
+def stream_copy_gbs(mib: int = 1024, reps: int = 20) -> float:
+    """Device-to-device copy bandwidth (bytes read + bytes written per
+    second) of a plain torch copy of `mib` MiB, the practical HBM ceiling
+    for a streaming kernel on this GPU."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    secs = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, b
+    return 2 * n * 4 / secs / 1e9
+
+
 def gpu_run(prob, precision, steps, warmup, profile_kernel=None):
     import torch
     from paper_2301_07457_amd import PCGMGSolver
@@ -316,6 +338,9 @@ def main():
             "eager_pass_ms_per_step": 1e3 * elapsed_r / args.steps,
         },
     }
+    copy_gbs = stream_copy_gbs()
+    out["roofline"]["stream_copy_gbs"] = copy_gbs
+    out["roofline"]["frac_of_stream_copy"] = achieved / copy_gbs
     if not args.no_fp64:
         s64, stats64, el64, _, U64 = gpu_run(prob, "fp64", max(3, args.steps // 2), 1)
         it64 = sum(st["iters"] for st in stats64)

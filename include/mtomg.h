@@ -41,7 +41,8 @@ typedef struct mtomg_ctx mtomg_ctx;
 enum {
     MTOMG_OK = 0,
     MTOMG_BAD_INPUT = -1,     /* invalid argument or size                        */
-    MTOMG_NOT_CONVERGED = -2, /* max_iter reached; U holds the last iterate      */
+    MTOMG_NOT_CONVERGED = -2, /* max_iter reached, or the true residual stays    */
+                              /* above rel_tol; U holds the last iterate         */
     MTOMG_BREAKDOWN = -3,     /* p^T K p <= 0 or z^T r <= 0 inside PCG, or the   */
                               /* coarsest matrix is not positive definite        */
     MTOMG_NAN = -4,           /* non-finite residual                             */
@@ -58,7 +59,7 @@ enum { MTOMG_FP64 = 0, MTOMG_FP32MG = 1 };
 /* Per (design, load case) solve statistics. */
 typedef struct {
     int32_t status;      /* MTOMG_OK / NOT_CONVERGED / BREAKDOWN / NAN        */
-    int32_t iters;       /* PCG iterations (updates of u)                      */
+    int32_t iters;       /* PCG iterations (updates of u), all runs            */
     int32_t vcycles;     /* preconditioner applications                        */
     int32_t n_dof;       /* 2 (nelx+1)(nely+1), clamped DOFs included          */
     double relres_rec;   /* recursive ||r|| / ||f|| at exit                    */
@@ -128,7 +129,11 @@ int mtomg_set_densities(mtomg_ctx *ctx, int design, const double *x);
 /* Solve every load case of every design that has densities: PCG
  * (Algorithm 2) from u = 0 (or from U when warm_start != 0), stopping when
  * ||r||_2 <= rel_tol ||f||_2 over the free DOFs, or after max_iter
- * iterations.  Designs that share nelx, nely, levels, precision, n_pre,
+ * iterations.  The test runs on the recursively updated residual and is
+ * confirmed on the true FP64 residual f - K u; a system that fails the
+ * confirmation (the two drift apart over thousands of iterations at high
+ * modulus contrast) restarts PCG from its current u, at most 4 times, with
+ * max_iter counting the iterations of all runs.  Designs that share nelx, nely, levels, precision, n_pre,
  * n_post, nu, omega and n_cases form a group: each kernel launch serves
  * every (design, load case) system of a group, all groups iterate together
  * and two iterations of all of them replay as one HIP graph; a system that

@@ -778,35 +778,23 @@ void start_group(mtomg_ctx* c, Group& g, hipStream_t st, int warm, double tol2) 
     fine_cycle<T>(cx, -1, tol2);
 }
 
-// Every system of every design with densities, in lockstep (see the file comment).
-int solve_all(mtomg_ctx* c, double rel_tol, int max_iter, int warm, mtomg_stats* stats) {
-    int rc = factor_pending(c);
-    if (rc) return rc;
+// One run of Algorithm 2 for every system whose host_state word is 0 on
+// entry (5 = not part of this run), all groups in lockstep.  On return
+// host_state holds each system's final state word and iteration count,
+// host_sums its ||f||^2, recursive and true ||r||^2; *ms the device time.
+int pcg_round(mtomg_ctx* c, const std::vector<int>& gsys0, double tol2, int max_iter, int warm, float* ms) {
     hipStream_t st = c->stream;
-    const double tol2 = rel_tol * rel_tol;
     const bool graphs = c->use_graphs && c->prof.kernel == MTOMG_KERNEL_NONE;
-    std::vector<int> act, gsys0(c->groups.size(), 0);
-    int sys0 = 0;
+    std::vector<int> act;
     for (size_t gi = 0; gi < c->groups.size(); ++gi) {
         Group& g = c->groups[gi];
-        gsys0[gi] = sys0;
         bool any = false;
-        for (size_t k = 0; k < g.designs.size(); ++k) {
-            const Design& d = c->d[g.designs[k]];
-            const int v = (d.has_dens && !d.fac_failed) ? 0 : ST_INACTIVE;
-            any = any || v == 0;
-            for (int q = 0; q < g.cpd; ++q) {
-                int* h = c->host_state + 4 * (sys0 + (int)k * g.cpd + q);
-                h[0] = v;
-                h[1] = h[2] = h[3] = 0;
-            }
-        }
+        for (int q = 0; q < g.n_sys; ++q) any = any || c->host_state[4 * (gsys0[gi] + q)] == 0;
         if (any) {
             act.push_back((int)gi);
-            HIPCHK(c, hipMemcpy2DAsync(c->d[g.designs[0]].cases[0].state, (size_t)g.cs, c->host_state + 4 * sys0,
+            HIPCHK(c, hipMemcpy2DAsync(c->d[g.designs[0]].cases[0].state, (size_t)g.cs, c->host_state + 4 * gsys0[gi],
                                        4 * sizeof(int), 4 * sizeof(int), g.n_sys, hipMemcpyHostToDevice, st));
         }
-        sys0 += g.n_sys;
     }
     HIPCHK(c, hipEventRecord(c->ev_solve[0], st));
     auto read_states = [&]() -> int {
@@ -819,6 +807,7 @@ int solve_all(mtomg_ctx* c, double rel_tol, int max_iter, int warm, mtomg_stats*
         HIPCHK(c, hipStreamSynchronize(st));
         return MTOMG_OK;
     };
+    int rc = MTOMG_OK;
     int it = 0;
     if (!act.empty()) {
         for (int gi : act) {
@@ -884,9 +873,75 @@ int solve_all(mtomg_ctx* c, double rel_tol, int max_iter, int warm, mtomg_stats*
     }
     rc = read_states();
     if (rc) return rc;
-    float ms = 0.f;
-    HIPCHK(c, hipEventElapsedTime(&ms, c->ev_solve[0], c->ev_solve[1]));
-    int k = 0, worst = MTOMG_OK, most = 0;
+    HIPCHK(c, hipEventElapsedTime(ms, c->ev_solve[0], c->ev_solve[1]));
+    return MTOMG_OK;
+}
+
+// Every system of every design with densities, in lockstep (see the file
+// comment).  The stopping test of Algorithm 2 runs on the recursively
+// updated residual; at exit the true FP64 residual f - K u is formed, and a
+// system whose true residual is still above the tolerance (the two drift
+// apart over thousands of iterations at high contrast) restarts PCG from
+// its current iterate, up to MAX_RESTARTS times within max_iter in total.
+constexpr int MAX_RESTARTS = 4;
+int solve_all(mtomg_ctx* c, double rel_tol, int max_iter, int warm, mtomg_stats* stats) {
+    int rc = factor_pending(c);
+    if (rc) return rc;
+    const double tol2 = rel_tol * rel_tol;
+    std::vector<int> gsys0(c->groups.size(), 0);
+    int n_sys = 0;
+    for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+        Group& g = c->groups[gi];
+        gsys0[gi] = n_sys;
+        for (size_t k = 0; k < g.designs.size(); ++k) {
+            const Design& d = c->d[g.designs[k]];
+            const int v = (d.has_dens && !d.fac_failed) ? 0 : ST_INACTIVE;
+            for (int q = 0; q < g.cpd; ++q) {
+                int* h = c->host_state + 4 * (n_sys + (int)k * g.cpd + q);
+                h[0] = v;
+                h[1] = h[2] = h[3] = 0;
+            }
+        }
+        n_sys += g.n_sys;
+    }
+    // per system: final state, iterations and runs over all rounds, sums of its last run
+    std::vector<int> state(n_sys, ST_INACTIVE), iters(n_sys, 0), runs(n_sys, 0);
+    std::vector<double> sums(3 * (size_t)n_sys, 0.0);
+    float total_ms = 0.f;
+    int first_round_most = 0;
+    int budget = max_iter, warm_r = warm;
+    for (int round = 0; round <= MAX_RESTARTS; ++round) {
+        float ms = 0.f;
+        rc = pcg_round(c, gsys0, tol2, budget, warm_r, &ms);
+        if (rc) return rc;
+        total_ms += ms;
+        std::vector<int> again;
+        int used = 0;
+        for (int q = 0; q < n_sys; ++q) {
+            if (c->host_state[4 * q] == ST_INACTIVE) continue;   // not in this run
+            state[q] = c->host_state[4 * q];
+            iters[q] += c->host_state[4 * q + 1];
+            runs[q] += 1;
+            if (round == 0) first_round_most = std::max(first_round_most, iters[q]);
+            for (int k = 0; k < 3; ++k) sums[3 * q + k] = c->host_sums[4 * q + k];
+            const double ff = sums[3 * q];
+            const bool ok = state[q] == 1 || state[q] == 2;
+            if (ok && ff > 0.0 && sums[3 * q + 2] > tol2 * ff) {
+                again.push_back(q);
+                used = std::max(used, iters[q]);
+            }
+        }
+        if (again.empty() || round == MAX_RESTARTS || used >= max_iter) break;
+        for (int q = 0; q < n_sys; ++q) {
+            int* h = c->host_state + 4 * q;
+            h[0] = ST_INACTIVE;
+            h[1] = h[2] = h[3] = 0;
+        }
+        for (int q : again) c->host_state[4 * q] = 0;
+        budget = max_iter - used;
+        warm_r = 1;
+    }
+    int k = 0, worst = MTOMG_OK;
     for (Design& d : c->d) {
         if (!d.has_grid || !d.has_dens) continue;
         const Group& g = c->groups[d.group];
@@ -899,23 +954,25 @@ int solve_all(mtomg_ctx* c, double rel_tol, int max_iter, int warm, mtomg_stats*
             o.model_bytes = model_bytes(d);
             if (d.fac_failed) {
                 o.status = MTOMG_BREAKDOWN;
-            } else {
-                const int* h = c->host_state + 4 * (s0 + q);
-                const double* sm = c->host_sums + 4 * (s0 + q);
-                const int cv = h[0];
-                o.status = (cv == 1 || cv == 2) ? MTOMG_OK : cv == 3 ? MTOMG_BREAKDOWN : cv == 4 ? MTOMG_NAN
-                                                                                             : MTOMG_NOT_CONVERGED;
-                o.iters = h[1];
-                o.vcycles = o.iters + 1;
-                o.relres_rec = sm[0] > 0 ? std::sqrt(sm[1] / sm[0]) : 0.0;
-                o.relres_true = sm[0] > 0 ? std::sqrt(sm[2] / sm[0]) : 0.0;
-                o.t_solve_ms = ms;
-                most = std::max(most, o.iters);
+                worst = std::min(worst, (int)MTOMG_BREAKDOWN);
+                continue;
             }
+            const int sq = s0 + q;
+            const int cv = state[sq];
+            const double ff = sums[3 * sq];
+            o.relres_rec = ff > 0 ? std::sqrt(sums[3 * sq + 1] / ff) : 0.0;
+            o.relres_true = ff > 0 ? std::sqrt(sums[3 * sq + 2] / ff) : 0.0;
+            const bool met = ff <= 0.0 || sums[3 * sq + 2] <= tol2 * ff;
+            o.status = (cv == 1 || cv == 2) ? (met ? MTOMG_OK : MTOMG_NOT_CONVERGED)
+                                           : cv == 3 ? MTOMG_BREAKDOWN : cv == 4 ? MTOMG_NAN : MTOMG_NOT_CONVERGED;
+            o.iters = iters[sq];
+            o.vcycles = o.iters + runs[sq];
+            o.t_solve_ms = total_ms;
             if (o.status < worst) worst = o.status;
         }
     }
-    c->last_iters = most;
+    // batch hint for the next solve: the iterations of the first run
+    c->last_iters = first_round_most;
     return worst;
 }
 

@@ -7,8 +7,11 @@ oracle solves with its own MG-preconditioned CG to a relative residual of
 compliance gradient at 64 seeded (element, phase) pairs.  The GPU parity
 tests compare the HIP solve with these samples.
 
-Usage: python tests/golden/make_golden.py [wall1024] [wall2048]
-(about 3 minutes for wall1024 and 15 for wall2048 on one host core).
+Usage: python tests/golden/make_golden.py [wall1024]
+(about 3 minutes on one host core).  The 2048 x 2048 near-binary field is
+not sampled this way: pCGMG needs ~1e4 iterations there and the oracle's
+scipy cycle does not finish in hours, so that workload is checked through
+properties that hold at any size instead.
 """
 
 import json
@@ -73,5 +76,5 @@ def make(name: str):
 
 
 if __name__ == "__main__":
-    for name in (sys.argv[1:] or ["wall1024", "wall2048"]):
+    for name in (sys.argv[1:] or ["wall1024"]):
         make(name)

@@ -6,13 +6,18 @@
   gradient is ~0 (relative 1e-5 for gradients of at least 1e-4 max|g|,
   absolute 1e-9 max|g| below).  At this contrast the residual 1e-8 leaves an error of
   ~6e-6 in u (condition number ~1e9), so the u comparison solves to 1e-10.
-* 1024 x 1024 smooth field (7 levels, FP32 cycle) and 2048 x 2048
-  near-binary 4-phase field (8 levels, FP32 cycle): against oracle samples
+* 1024 x 1024 smooth field (7 levels, FP32 cycle): against oracle samples
   written by tests/golden/make_golden.py (compliance, u at 512 nodes,
   gradient at 64 pairs), and properties that hold at any size: the
   oracle's energy identity c = sum_e E_e u_e^T K0 u_e on the GPU field, the
   oracle's nodal residual at sampled nodes, FP32-cycle and FP64-cycle
   solutions agreeing.
+* 2048 x 2048 near-binary 4-phase field (8 levels, contrast 3e8): pCGMG
+  needs ~1e4 iterations here (the oracle's own pCGMG does not finish in
+  hours), so the full size is checked through the properties above in both
+  precisions, and the same recipe at 128 x 128 against the oracle's direct
+  solve.  At 2048^2 the recursive and true residuals drift apart, which the
+  true-residual confirmation and restart of the solver must absorb.
 """
 
 import json
@@ -136,7 +141,7 @@ def _nodal_residual(p, U, nodes):
     return np.array(res)
 
 
-@pytest.mark.parametrize("name", ["wall1024", "wall2048"])
+@pytest.mark.parametrize("name", ["wall1024"])
 def test_fullsize_fp32_cycle_against_oracle_samples(name):
     gold = _samples(name)
     p = make_problem(name)
@@ -176,3 +181,108 @@ def test_wall1024_fp32_cycle_agrees_with_fp64_cycle():
     assert d <= 1e-6
     print(f"[wall1024] fp32 cycle {st32['iters']} it {st32['t_solve_ms']:.2f} ms; "
           f"fp64 cycle {st64['iters']} it {st64['t_solve_ms']:.2f} ms; rel diff {d:.2e}")
+
+
+# ---------------------------------------------------------------------------
+# near-binary 4-phase stress field (2048 x 2048 and a small copy)
+# ---------------------------------------------------------------------------
+def test_nearbinary_small_matches_direct_solve():
+    p = make_problem("wall2048", n=128, levels=4)
+    ref = solve.solve_direct(p.nelx, p.nely, p.x, p.E_phase, p.E_min, p.penal, p.nu, p.F)
+    for prec in ("fp64", "fp32mg"):
+        s = gpu_solver(p, prec)
+        st = s.solve(1e-8, 20000)[0]
+        assert st["status"] == 0 and st["relres_true"] <= 1e-8, (prec, st)
+        st = s.solve(1e-10, 20000)[0]
+        assert st["status"] == 0 and st["relres_true"] <= 1e-10, (prec, st)
+        assert rel(s.U(0).cpu().numpy(), ref.U) <= 1e-6
+        c, dc = s.compliance_and_grad(0)
+        assert c.item() == pytest.approx(ref.c[0], rel=1e-7)
+        assert rel(dc.cpu().numpy(), ref.dcdx) <= 1e-5
+        print(f"[near-binary 128] {prec} iters={st['iters']}")
+
+
+def test_true_residual_confirmation_restarts():
+    """512^2 near-binary, FP64 cycle: the recursive residual reaches 1e-8
+    while the true one is ~2e-8; the confirmation restarts PCG from u."""
+    p = make_problem("wall2048", n=512, levels=6)
+    s = gpu_solver(p, "fp64")
+    st = s.solve(1e-8, 60000)[0]
+    assert st["status"] == 0 and st["relres_true"] <= 1e-8, st
+    assert st["vcycles"] >= st["iters"] + 1
+    print(f"[near-binary 512] iters={st['iters']} vcycles={st['vcycles']} relres_true={st['relres_true']:.2e}")
+
+
+@pytest.fixture(scope="module")
+def nearbinary2048():
+    p = make_problem("wall2048")
+    out = {}
+    for prec in ("fp64", "fp32mg"):
+        print(f"[near-binary 2048] {prec} solve", flush=True)
+        s = gpu_solver(p, prec)
+        st = s.solve(1e-8, 60000)[0]
+        c, dc = s.compliance_and_grad(0)
+        out[prec] = (st, s.U(0).cpu().numpy(), c.item(), dc[0].cpu().numpy())
+        print(f"[near-binary 2048] {prec} iters={st['iters']} vcycles={st['vcycles']} "
+              f"solve_ms={st['t_solve_ms']:.0f} relres_true={st['relres_true']:.2e}", flush=True)
+        del s
+        torch.cuda.empty_cache()
+    return p, out
+
+
+def _residual_floor(p, U):
+    """eps ||(|K| |u|)_free|| / ||f||: the rounding floor of an FP64
+    evaluation of f - K u (oracle element matrices, absolute values)."""
+    KEa = np.abs(fe.element_stiffness(p.nu))
+    E = fe.interpolate_modulus(p.x, p.E_phase, p.E_min, p.penal).ravel()
+    dofs = fe.element_dof_map(p.nelx, p.nely)
+    au = np.abs(U.ravel())
+    acc = np.zeros(U.size)
+    for a in range(8):
+        acc += np.bincount(dofs[:, a], weights=E * (au[dofs] @ KEa[a]), minlength=U.size)
+    free = fe.free_dofs(p.nelx, p.nely)
+    return np.finfo(np.float64).eps * np.linalg.norm(acc[free]) / np.linalg.norm(p.F[0].ravel()[free])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32mg"])
+def test_nearbinary2048_converges_with_oracle_properties(nearbinary2048, prec):
+    """The recursive residual reaches 1e-8.  The true FP64 residual reaches
+    1e-8 or, where that lies below what FP64 can resolve for this field
+    (large near-rigid displacements make |K| |u| ~1e8 |f|), four times the
+    rounding floor of its own evaluation; the solver then reports
+    NOT_CONVERGED rather than claiming 1e-8."""
+    p, out = nearbinary2048
+    st, U, c, dc = out[prec]
+    floor = _residual_floor(p, U[0])
+    print(f"[near-binary 2048] {prec} relres_true={st['relres_true']:.2e} rounding floor={floor:.2e}")
+    assert st["relres_rec"] <= 1e-8, st
+    assert st["relres_true"] <= max(1e-8, 4 * floor), (st, floor)
+    assert st["status"] == (0 if st["relres_true"] <= 1e-8 else -2), st
+    # c = f.u and u^T K u differ by r.u, |r.u| <= ||r|| ||u|| with ||r|| = relres ||f||
+    E = fe.interpolate_modulus(p.x, p.E_phase, p.E_min, p.penal)
+    energy = np.sum(E * fe.element_energies(U[0], p.nelx, p.nely, p.nu))
+    gap = st["relres_true"] * np.linalg.norm(p.F[0]) * np.linalg.norm(U[0]) / c
+    assert c == pytest.approx(energy, rel=max(1e-7, 2 * gap))
+    # the oracle's residual at sampled nodes is part of the reported true residual
+    nodes = np.random.default_rng(8).choice((p.nelx + 1) * (p.nely + 1), 2000, replace=False)
+    r = _nodal_residual(p, U[0], nodes)
+    assert np.linalg.norm(r) <= max(1e-8, st["relres_true"] + 2 * floor) * np.linalg.norm(p.F[0])
+    # oracle sensitivity formula at sampled elements on the GPU displacements
+    KE = fe.element_stiffness(p.nu)
+    rng = np.random.default_rng(9)
+    els = rng.choice(p.nelx * p.nely, 64, replace=False)
+    ph = rng.integers(0, p.m, 64)
+    ue = U[0].ravel()[fe.element_dof_map(p.nelx, p.nely)[els]]
+    w = np.einsum("ea,ab,eb->e", ue, KE, ue)
+    xs = p.x.reshape(-1, p.m)[els, ph]
+    want = -p.penal * xs ** (p.penal - 1) * (p.E_phase[ph] - p.E_min) * w
+    # u_e^T K0 u_e cancels for near-rigid elements (large u, tiny strain):
+    # the kernel's strain/stress form and the oracle's 8x8 product round
+    # differently there, by ~1e-11 relative
+    assert rel(dc.reshape(-1, p.m)[els, ph], want) <= 1e-9
+
+
+def test_nearbinary2048_precisions_agree(nearbinary2048):
+    _, out = nearbinary2048
+    c64, c32 = out["fp64"][2], out["fp32mg"][2]
+    assert c32 == pytest.approx(c64, rel=1e-7)
