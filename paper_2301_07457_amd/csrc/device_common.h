@@ -142,11 +142,65 @@ __device__ __forceinline__ double block_sum(double v) {
     return s;
 }
 
-// Sum of n partials in a fixed order; identical in every block that calls it.
+// Sums of K partial arrays (p[q] holds n[q] >= 1 entries, n[q] used) in a
+// fixed order, identical in every block that calls it: thread t adds
+// entries t, t + WG_THREADS, ... in increasing order, then the wave and
+// workgroup trees of block_sum.  Loads are issued eight per thread and
+// array at a time, all before the first add (out-of-range slots load a
+// valid entry and are not added), and the K reductions share one barrier
+// pair.  Requires all threads of the block to call.
+template <int K>
+__device__ __forceinline__ void sum_partials_k(const double* const (&p)[K], const int (&n)[K], double (&out)[K]) {
+    constexpr int U = 8;
+    double s[K];
+    int nmax = 0;
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        s[q] = 0.0;
+        nmax = max(nmax, n[q]);
+    }
+    for (int base = 0; base < nmax; base += U * WG_THREADS) {
+        double v[K][U];
+#pragma unroll
+        for (int q = 0; q < K; ++q)
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = base + threadIdx.x + u * WG_THREADS;
+                v[q][u] = p[q][max(min(k, n[q] - 1), 0)];
+            }
+#pragma unroll
+        for (int q = 0; q < K; ++q)
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = base + threadIdx.x + u * WG_THREADS;
+                s[q] = (k < n[q]) ? s[q] + v[q][u] : s[q];
+            }
+    }
+    __shared__ double red[K][WAVES_PER_WG];
+#pragma unroll
+    for (int q = 0; q < K; ++q) s[q] = wave_sum(s[q]);
+    __syncthreads();
+    if (lane_id() == 0) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) red[q][wave_id()] = s[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < WAVES_PER_WG; ++w) t += red[q][w];
+        out[q] = t;
+    }
+}
+
+// Sum of n >= 1 partials in a fixed order; identical in every block that calls it.
 __device__ __forceinline__ double sum_partials(const double* __restrict__ p, int n) {
-    double s = 0.0;
-    for (int k = threadIdx.x; k < n; k += WG_THREADS) s += p[k];
-    return block_sum(s);
+    const double* ps[1] = {p};
+    const int ns[1] = {n};
+    double out[1];
+    sum_partials_k<1>(ps, ns, out);
+    return out[0];
 }
 
 // ---------------------------------------------------------------------------

@@ -458,9 +458,11 @@ __global__ __launch_bounds__(WG_THREADS) void k_solve_sums(const double* __restr
     state = at(state, so.c);
     const int iters = state[1];
     const double* rr = at(iters & 1 ? rr1 : rr0, so.c);
-    const double a = sum_partials(at(ff, so.c), n_ff);
-    const double b = sum_partials(rr, iters == 0 ? n_rr0 : n_rr);
-    const double c = sum_partials(at(trr, so.c), n_ff);
+    const double* ps[3] = {at(ff, so.c), rr, at(trr, so.c)};
+    const int ns[3] = {n_ff, iters == 0 ? n_rr0 : n_rr, n_ff};
+    double sv[3];
+    sum_partials_k<3>(ps, ns, sv);
+    const double a = sv[0], b = sv[1], c = sv[2];
     if (threadIdx.x == 0) {
         double* o = at(out, so.c);
         o[0] = a;

@@ -80,10 +80,17 @@ __global__ __launch_bounds__(WG_THREADS) void k_cg_apply(
     const int i = t.strip * WOUT - HL + lane;
     const bool out_lane = lane >= HL && lane < HL + WOUT && i <= nx;
 
-    double alpha_prev = 0.0, beta = 0.0, rho_prev = 1.0;
+    double alpha_prev = 0.0, beta = 0.0, rho_prev = 1.0, rho_cur = 0.0;
     if (mode != 1) {
-        rho_prev = sum_partials(zr_prev, n_zr);
-        alpha_prev = rho_prev / sum_partials(pq_prev, n_pq);
+        // rho_{i-1}, p_{i-1}.q_{i-1} and rho_i in one pass (rho_i is unused
+        // by the final-only modes; its partials are valid memory there)
+        const double* ps[3] = {zr_prev, pq_prev, zr_cur};
+        const int ns[3] = {n_zr, n_pq, n_zr};
+        double sv[3];
+        sum_partials_k<3>(ps, ns, sv);
+        rho_prev = sv[0];
+        alpha_prev = rho_prev / sv[1];
+        rho_cur = sv[2];
     }
     if (final_only) {
         if (out_lane) {
@@ -97,7 +104,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_cg_apply(
         }
         return;
     }
-    if (mode == 0) beta = sum_partials(zr_cur, n_zr) / rho_prev;
+    if (mode == 0) beta = rho_cur / rho_prev;
 
     double dot = 0.0;
     if (t.j0 < t.j1) {
@@ -286,8 +293,11 @@ __global__ __launch_bounds__(WG_THREADS) void k_presmooth(
     double alpha = 0.0;
     if constexpr (CG) {
         if (cg.update) {
-            const double rho = sum_partials(cg.zr, cg.n_zr);
-            const double pq = sum_partials(cg.pq, cg.n_pq);
+            const double* ps[2] = {cg.zr, cg.pq};
+            const int ns[2] = {cg.n_zr, cg.n_pq};
+            double sv[2];
+            sum_partials_k<2>(ps, ns, sv);
+            const double rho = sv[0], pq = sv[1];
             alpha = rho / pq;
             if (!(pq > 0.0) || !(rho > 0.0) || !isfinite(alpha)) {
                 if (blockIdx.x == 0 && threadIdx.x == 0) *cg.conv_rw = isfinite(alpha) ? 3 : 4;
@@ -418,8 +428,11 @@ __global__ __launch_bounds__(WG_THREADS) void k_restrict(
     const TileInfo t = tile_info<R>(sw, ncy + 1);
     if (!t.block_ok) return;
     if constexpr (CHECK) {
-        const double rr = sum_partials(chk.rr, chk.n_rr);
-        const double ff = sum_partials(chk.ff, chk.n_ff);
+        const double* ps[2] = {chk.rr, chk.ff};
+        const int ns[2] = {chk.n_rr, chk.n_ff};
+        double sv[2];
+        sum_partials_k<2>(ps, ns, sv);
+        const double rr = sv[0], ff = sv[1];
         const bool done = rr <= chk.tol2 * ff;
         if (!(rr == rr)) {
             if (blockIdx.x == 0 && threadIdx.x == 0) *chk.conv_rw = 4;
@@ -521,8 +534,11 @@ __global__ __launch_bounds__(WG_THREADS) void k_restrict_pre(
     const TileInfo t = tile_info<R>(sw, ncy + 1);
     if (!t.block_ok) return;
     if constexpr (CHECK) {
-        const double rr = sum_partials(chk.rr, chk.n_rr);
-        const double ff = sum_partials(chk.ff, chk.n_ff);
+        const double* ps[2] = {chk.rr, chk.ff};
+        const int ns[2] = {chk.n_rr, chk.n_ff};
+        double sv[2];
+        sum_partials_k<2>(ps, ns, sv);
+        const double rr = sv[0], ff = sv[1];
         const bool done = rr <= chk.tol2 * ff;
         if (!(rr == rr)) {
             if (blockIdx.x == 0 && threadIdx.x == 0) *chk.conv_rw = 4;
