@@ -105,10 +105,25 @@ __device__ __forceinline__ void mom_accumulate_child(Mom<T>& P, const Mom<T>& c,
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
 __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 
-// value of lane l-1 (lane 0 gets its own value)
-template <typename T> __device__ __forceinline__ T from_left(T v) { return __shfl_up(v, 1, WAVE); }
-// value of lane l+1 (lane 63 gets its own value)
-template <typename T> __device__ __forceinline__ T from_right(T v) { return __shfl_down(v, 1, WAVE); }
+// Neighbour lanes by whole-wave DPP shifts (a VALU operand modifier, no
+// LDS round trip): from_left gives lane l the value of lane l-1 (lane 0
+// gets 0), from_right the value of lane l+1 (lane 63 gets 0).  Edge lanes
+// are halo lanes in every kernel, so their values are never used.
+constexpr int DPP_WAVE_SHR1 = 0x138, DPP_WAVE_SHL1 = 0x130;
+template <int CTRL> __device__ __forceinline__ int dpp_shift(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL> __device__ __forceinline__ float dpp_shift(float v) {
+    return __int_as_float(dpp_shift<CTRL>(__float_as_int(v)));
+}
+template <int CTRL> __device__ __forceinline__ double dpp_shift(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_shift<CTRL>((int)(b & 0xffffffff));
+    const int hi = dpp_shift<CTRL>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <typename T> __device__ __forceinline__ T from_left(T v) { return dpp_shift<DPP_WAVE_SHR1>(v); }
+template <typename T> __device__ __forceinline__ T from_right(T v) { return dpp_shift<DPP_WAVE_SHL1>(v); }
 
 template <typename T> __device__ __forceinline__ V2<T> from_left(V2<T> v) {
     return V2<T>{from_left(v.x), from_left(v.y)};
