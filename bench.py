@@ -122,7 +122,10 @@ def stream_copy_gbs(mib: int = 1024, reps: int = 20) -> float:
     return 2 * n * 4 / secs / 1e9
 
 
-def gpu_run(prob, precision, steps, warmup, profile_kernel=None):
+def gpu_run(prob, precision, steps, warmup, profile_kernel=None, tiles=None):
+    """Time `steps` steps; the tiles (rows per wave on the finest / coarse
+    grids) are autotuned first unless given.  Returns the solver, per-step
+    stats, elapsed seconds, profiled durations, U and (tiles, timings)."""
     import torch
     from paper_2301_07457_amd import PCGMGSolver
     from paper_2301_07457_amd import _lib
@@ -131,6 +134,13 @@ def gpu_run(prob, precision, steps, warmup, profile_kernel=None):
                  prob.penal, prob.nu, prob.levels, prob.n_pre, prob.n_post, prob.omega, precision)
     x = torch.from_numpy(prob.x).cuda()
     s.set_densities(0, x)
+    tune = None
+    if tiles is None:
+        tiles, t = s.autotune(1e-8, 1000)
+        tune = {f"{a},{b}": round(v, 4) for (a, b), v in t.items()}
+    else:
+        s.set_option("ROWS_FINE", tiles[0])
+        s.set_option("ROWS_COARSE", tiles[1])
 
     def step():
         s.set_densities(0, x)
@@ -161,7 +171,7 @@ def gpu_run(prob, precision, steps, warmup, profile_kernel=None):
     if profile_kernel:
         _lib.mtomg_profile_kernel(s.ctx, "NONE")
     U = s.U(0).clone()
-    return s, stats, t1 - t0, durs, U
+    return s, stats, t1 - t0, durs, U, (tiles, tune)
 
 
 def batched_run(steps, warmup, per_size=16):
@@ -180,6 +190,9 @@ def batched_run(steps, warmup, per_size=16):
         s.add_design(k, p.nelx, p.nely, torch.from_numpy(p.F), list(p.E_phase), p.E_min, p.penal, p.nu,
                      p.levels, p.n_pre, p.n_post, p.omega, "fp32mg")
     xs = [torch.from_numpy(p.x).cuda() for p in probs]
+    for k, x in enumerate(xs):
+        s.set_densities(k, x)
+    tiles, tune = s.autotune(1e-8, 1000, repeats=1)
 
     def step():
         for k, x in enumerate(xs):
@@ -213,6 +226,8 @@ def batched_run(steps, warmup, per_size=16):
         "iters_min": min(st["iters"] for st in last),
         "relres_true_max": max(st["relres_true"] for st in last),
         "all_ok": all(st["status"] == 0 for st in last),
+        "tiles": {"rows_fine": tiles[0], "rows_coarse": tiles[1],
+                  "autotune_solve_ms": {f"{a},{b}": round(v, 3) for (a, b), v in tune.items()}},
     }
 
 
@@ -278,7 +293,7 @@ def main():
     n_elem = prob.nelx * prob.nely
 
     # timed pass: graph-replayed iterations, nothing instrumented
-    s, stats, elapsed, _, U32 = gpu_run(prob, "fp32mg", args.steps, args.warmup)
+    s, stats, elapsed, _, U32, (tiles, tune) = gpu_run(prob, "fp32mg", args.steps, args.warmup)
     iters_total = sum(st["iters"] for st in stats)
     value = n_dof * iters_total / elapsed
     solve_ms = float(np.mean([st["t_solve_ms"] for st in stats]))
@@ -287,7 +302,7 @@ def main():
     del s
     # roofline pass: same steps, kernels launched one by one so every launch of
     # the stiffness apply is bracketed by HIP events on the solve stream
-    s, stats_r, elapsed_r, durs, _ = gpu_run(prob, "fp32mg", args.steps, 1, "CG_APPLY")
+    s, stats_r, elapsed_r, durs, _, _ = gpu_run(prob, "fp32mg", args.steps, 1, "CG_APPLY", tiles=tiles)
     del s
 
     # roofline of the FP64 stiffness apply of the outer CG: algorithmic bytes per launch
@@ -321,6 +336,7 @@ def main():
             "solve_ms": solve_ms,
             "setup_ms": setup_ms,
             "relres_true": stats[-1]["relres_true"],
+            "tiles": {"rows_fine": tiles[0], "rows_coarse": tiles[1], "autotune_solve_ms": tune},
         },
         "roofline": {
             "kernel": "k_cg_apply (FP64 p-update + stiffness apply + p.q)",
@@ -342,7 +358,7 @@ def main():
     out["roofline"]["stream_copy_gbs"] = copy_gbs
     out["roofline"]["frac_of_stream_copy"] = achieved / copy_gbs
     if not args.no_fp64:
-        s64, stats64, el64, _, U64 = gpu_run(prob, "fp64", max(3, args.steps // 2), 1)
+        s64, stats64, el64, _, U64, (tiles64, _) = gpu_run(prob, "fp64", max(3, args.steps // 2), 1)
         it64 = sum(st["iters"] for st in stats64)
         out["fp64_cycle"] = {
             "value": n_dof * it64 / el64,
@@ -350,6 +366,7 @@ def main():
             "solve_ms": float(np.mean([st["t_solve_ms"] for st in stats64])),
             "iters": stats64[-1]["iters"],
             "relres_true": stats64[-1]["relres_true"],
+            "tiles": {"rows_fine": tiles64[0], "rows_coarse": tiles64[1]},
         }
         out["fp32mg_vs_fp64_solve_speedup"] = out["fp64_cycle"]["solve_ms"] / solve_ms
         out["fp32mg_vs_fp64_rel_diff_u"] = float(torch.linalg.norm(U32 - U64) / torch.linalg.norm(U64))

@@ -355,7 +355,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_presmooth(
         elem_diag(me[0], mat, d0, d1, d2, d3);
         V2<T> dcarry = d3 + from_left(d2);
         V2<T> fcarry{T(0), T(0)};
-        V2<T> u1_prev{T(0), T(0)}, u1r_prev{T(0), T(0)}, b_prev{T(0), T(0)}, D_prev{T(1), T(1)};
+        V2<T> u1_prev{T(0), T(0)}, u1r_prev{T(0), T(0)}, b_prev{T(0), T(0)}, wD_prev{T(0), T(0)};
 #pragma unroll
         for (int s = 0; s < R + 2; ++s) {
             const int k = t.j0 - 1 + s;   // node row completed by the diagonal stage
@@ -364,7 +364,8 @@ __global__ __launch_bounds__(WG_THREADS) void k_presmooth(
             dcarry = d3 + from_left(d2);
             const V2<T> bk = br[s];
             const bool kok = node_col && k >= 1 && k <= ny;
-            const V2<T> u1{kok ? mat.omega * bk.x / D.x : T(0), kok ? mat.omega * bk.y / D.y : T(0)};
+            const V2<T> wD{mat.omega / D.x, mat.omega / D.y};   // w D^-1, reused by the second sweep
+            const V2<T> u1{kok ? bk.x * wD.x : T(0), kok ? bk.y * wD.y : T(0)};
             const V2<T> u1r = from_right(u1);
             if (s >= 1) {
                 // force stage for element row k-1 -> node row k-1 complete
@@ -376,8 +377,8 @@ __global__ __launch_bounds__(WG_THREADS) void k_presmooth(
                 if (jr >= t.j0 && jr < t.j1 && jr >= 1 && out_lane) {
                     V2<T> uo = sweeps == 0 ? V2<T>{T(0), T(0)} : u1_prev;
                     if (sweeps >= 2) {
-                        uo.x = u1_prev.x + mat.omega * (b_prev.x - fs.x) / D_prev.x;
-                        uo.y = u1_prev.y + mat.omega * (b_prev.y - fs.y) / D_prev.y;
+                        uo.x = u1_prev.x + (b_prev.x - fs.x) * wD_prev.x;
+                        uo.y = u1_prev.y + (b_prev.y - fs.y) * wD_prev.y;
                     }
                     store_node(u_out, nx, i, jr, uo);
                 }
@@ -385,7 +386,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_presmooth(
             u1_prev = u1;
             u1r_prev = u1r;
             b_prev = bk;
-            D_prev = D;
+            wD_prev = wD;
         }
     }
     if constexpr (CG) {
@@ -626,7 +627,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_restrict_pre(
     elem_diag(me[0], mat, d0, d1, d2, d3);
     V2<T> dcarry = d3 + from_left(d2);
     V2<T> fcarry{T(0), T(0)};
-    V2<T> u1_prev{T(0), T(0)}, u1r_prev{T(0), T(0)}, b_prev{T(0), T(0)}, D_prev{T(1), T(1)};
+    V2<T> u1_prev{T(0), T(0)}, u1r_prev{T(0), T(0)}, b_prev{T(0), T(0)}, wD_prev{T(0), T(0)};
 #pragma unroll
     for (int s = 0; s < R + 2; ++s) {
         const int k = t.j0 - 1 + s;   // coarse node row completed by the diagonal stage
@@ -635,7 +636,8 @@ __global__ __launch_bounds__(WG_THREADS) void k_restrict_pre(
         dcarry = d3 + from_left(d2);
         const V2<T> bk = br[s];
         const bool kok = node_col && k >= 1 && k <= ncy;
-        const V2<T> u1{kok ? mat.omega * bk.x / D.x : T(0), kok ? mat.omega * bk.y / D.y : T(0)};
+        const V2<T> wD{mat.omega / D.x, mat.omega / D.y};   // w D^-1, reused by the second sweep
+        const V2<T> u1{kok ? bk.x * wD.x : T(0), kok ? bk.y * wD.y : T(0)};
         const V2<T> u1r = from_right(u1);
         if (s >= 1) {
             V2<T> f0, f1, f2, f3;
@@ -646,8 +648,8 @@ __global__ __launch_bounds__(WG_THREADS) void k_restrict_pre(
             if (jr >= t.j0 && jr < t.j1 && jr >= 1 && out_lane) {
                 V2<T> uo = u1_prev;
                 if (sweeps >= 2) {
-                    uo.x = u1_prev.x + mat.omega * (b_prev.x - fs.x) / D_prev.x;
-                    uo.y = u1_prev.y + mat.omega * (b_prev.y - fs.y) / D_prev.y;
+                    uo.x = u1_prev.x + (b_prev.x - fs.x) * wD_prev.x;
+                    uo.y = u1_prev.y + (b_prev.y - fs.y) * wD_prev.y;
                 }
                 store_node(uc, ncx, i, jr, uo);
             }
@@ -655,7 +657,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_restrict_pre(
         u1_prev = u1;
         u1r_prev = u1r;
         b_prev = bk;
-        D_prev = D;
+        wD_prev = wD;
     }
 }
 
@@ -852,7 +854,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_post2(
         elem_diag(me[0], mat, d0, d1, d2, d3);
         V2<T> fc1 = f3 + from_left(f2), dc1 = d3 + from_left(d2);
         V2<T> fc2{T(0), T(0)};
-        V2<T> u1_prev{T(0), T(0)}, u1r_prev{T(0), T(0)}, D_prev{T(1), T(1)};
+        V2<T> u1_prev{T(0), T(0)}, u1r_prev{T(0), T(0)}, wD_prev{T(0), T(0)};
 #pragma unroll
         for (int s = 1; s < R + 3; ++s) {
             // stage 1: element row j0-2+s completes node row k = j0-2+s
@@ -867,8 +869,9 @@ __global__ __launch_bounds__(WG_THREADS) void k_post2(
             dc1 = d3 + from_left(d2);
             const bool kok = node_col && k >= 1 && k <= ny;
             const V2<T> bk = br[s - 1];
-            const V2<T> u1{kok ? vr[s].x + mat.omega * (bk.x - F.x) / D.x : T(0),
-                           kok ? vr[s].y + mat.omega * (bk.y - F.y) / D.y : T(0)};
+            const V2<T> wD{mat.omega / D.x, mat.omega / D.y};   // w D^-1, reused by the second stage
+            const V2<T> u1{kok ? vr[s].x + (bk.x - F.x) * wD.x : T(0),
+                           kok ? vr[s].y + (bk.y - F.y) * wD.y : T(0)};
             const V2<T> u1r = from_right(u1);
             if (s >= 2) {
                 // stage 2: element row k-1 from u1 rows k-1, k completes node row k-1
@@ -881,8 +884,8 @@ __global__ __launch_bounds__(WG_THREADS) void k_post2(
                     if (jr >= 1) {
                         const V2<T> bj = br[s - 2];
                         V2<T> uo;
-                        uo.x = u1_prev.x + mat.omega * (bj.x - G.x) / D_prev.x;
-                        uo.y = u1_prev.y + mat.omega * (bj.y - G.y) / D_prev.y;
+                        uo.x = u1_prev.x + (bj.x - G.x) * wD_prev.x;
+                        uo.y = u1_prev.y + (bj.y - G.y) * wD_prev.y;
                         store_node(u_out, nx, i, jr, uo);
                         if constexpr (DOT) dot += (double)uo.x * rr64[s - 3].x + (double)uo.y * rr64[s - 3].y;
                     } else {
@@ -892,7 +895,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_post2(
             }
             u1_prev = u1;
             u1r_prev = u1r;
-            D_prev = D;
+            wD_prev = wD;
         }
     }
     if constexpr (DOT) {

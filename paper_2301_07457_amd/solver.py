@@ -83,6 +83,30 @@ class PCGMGSolver:
                 if info["x"] is not None:
                     _lib.mtomg_set_densities(self.ctx, d, info["x"].data_ptr())
 
+    AUTOTUNE_CANDIDATES = ((0, 0), (2, 1), (4, 1), (4, 2), (8, 1), (8, 2))
+
+    def autotune(self, rel_tol: float = 1e-8, max_iter: int = 1000, candidates=None, repeats: int = 2):
+        """Tile autotuner: time the solve of the designs as they are now for
+        each (ROWS_FINE, ROWS_COARSE) pair of rows per wave (0 = the
+        library's own choice), keep the fastest and return
+        (best pair, {pair: ms}).  Densities must be set; the densities are
+        reloaded for every candidate (the launch geometry changes the
+        workspace), and each candidate's time is its best of `repeats`
+        solves after one warm-up solve."""
+        if any(info["x"] is None for info in self.designs.values()):
+            raise ValueError("autotune needs densities for every design")
+        timings = {}
+        for rf, rc in (candidates or self.AUTOTUNE_CANDIDATES):
+            self.set_option("ROWS_FINE", rf)
+            self.set_option("ROWS_COARSE", rc)
+            self.solve(rel_tol, max_iter)
+            ms = min(self.solve(rel_tol, max_iter)[0]["t_solve_ms"] for _ in range(repeats))
+            timings[(rf, rc)] = ms
+        best = min(timings, key=timings.get)
+        self.set_option("ROWS_FINE", best[0])
+        self.set_option("ROWS_COARSE", best[1])
+        return best, timings
+
     def set_densities(self, design: int, x: torch.Tensor):
         info = self.designs[design]
         x = x.to(self.device, torch.float64).contiguous()

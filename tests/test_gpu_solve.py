@@ -180,3 +180,16 @@ def test_tiny_grids(nx, ny, L, prec):
     c, dc = s.compliance_and_grad(0)
     np.testing.assert_allclose(c.cpu().numpy(), ref.c, rtol=1e-7)
     assert rel(dc.cpu().numpy(), ref.dcdx) <= 1e-5
+
+
+def test_autotune_picks_a_candidate_and_keeps_parity():
+    p = rand_prob(124, 60, 3, 50)
+    ref = oracle_direct(p)
+    s = gpu_solver(p, "fp32mg")
+    cands = ((0, 0), (1, 1), (2, 2), (4, 1))
+    best, timings = s.autotune(1e-8, 1000, candidates=cands, repeats=1)
+    assert best in cands and set(timings) == set(cands)
+    assert all(t > 0 for t in timings.values())
+    st = s.solve(1e-8, 1000)[0]
+    assert st["status"] == 0 and st["relres_true"] <= 1e-8
+    assert rel(s.U(0).cpu().numpy(), ref.U) <= 1e-6
