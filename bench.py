@@ -264,6 +264,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--breakdown", action="store_true", help="add per-kernel average times")
     ap.add_argument("--no-batched", action="store_true", help="skip the 48-design batched workload")
+    ap.add_argument("--tiles", default=None, metavar="RF,RC",
+                    help="rows per wave on the finest / coarse grids instead of autotuning (0 = library choice)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (counter calibration)")
     ap.add_argument("--cpu-baseline-worker", action="store_true", help=argparse.SUPPRESS)
@@ -293,7 +295,8 @@ def main():
     n_elem = prob.nelx * prob.nely
 
     # timed pass: graph-replayed iterations, nothing instrumented
-    s, stats, elapsed, _, U32, (tiles, tune) = gpu_run(prob, "fp32mg", args.steps, args.warmup)
+    fixed = tuple(int(v) for v in args.tiles.split(",")) if args.tiles else None
+    s, stats, elapsed, _, U32, (tiles, tune) = gpu_run(prob, "fp32mg", args.steps, args.warmup, tiles=fixed)
     iters_total = sum(st["iters"] for st in stats)
     value = n_dof * iters_total / elapsed
     solve_ms = float(np.mean([st["t_solve_ms"] for st in stats]))

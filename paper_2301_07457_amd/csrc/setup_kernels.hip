@@ -436,8 +436,26 @@ __global__ __launch_bounds__(WG_THREADS) void k_dot_partials(const double* __res
                                                              size_t n, double* __restrict__ partials) {
     const size_t per = (n + gridDim.x - 1) / gridDim.x;
     const size_t s0 = blockIdx.x * per, s1 = min(n, s0 + per);
+    // thread t adds a[k] b[k] for k = s0 + t, s0 + t + 256, ... in order;
+    // the loads of U consecutive terms are issued before any is added
+    constexpr int U = 8;
     double s = 0.0;
-    for (size_t k = s0 + threadIdx.x; k < s1; k += WG_THREADS) s += a[k] * b[k];
+    if (s1 > s0) {
+        for (size_t base = s0; base < s1; base += (size_t)U * WG_THREADS) {
+            double va[U], vb[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const size_t k = min(base + threadIdx.x + (size_t)u * WG_THREADS, s1 - 1);
+                va[u] = a[k];
+                vb[u] = b[k];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const size_t k = base + threadIdx.x + (size_t)u * WG_THREADS;
+                s = (k < s1) ? s + va[u] * vb[u] : s;
+            }
+        }
+    }
     s = block_sum(s);
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }

@@ -963,7 +963,19 @@ __global__ __launch_bounds__(WG_THREADS) void k_coarse_solve(const double* __res
     e = at(e, so.c);
     extern __shared__ double sb[];
     const int off = 2 * (nx0 + 1);
-    for (int k = threadIdx.x; k < n0; k += WG_THREADS) sb[k] = (double)b[off + k];
+    // loads are issued in batches of U per thread before they are used, so a
+    // wave waits for one memory round trip per batch, not one per element
+    constexpr int U = 16;
+    for (int base = 0; base < n0; base += U * WG_THREADS) {
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = b[off + min(base + (int)threadIdx.x + u * WG_THREADS, n0 - 1)];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = base + threadIdx.x + u * WG_THREADS;
+            if (k < n0) sb[k] = (double)v[u];
+        }
+    }
     if (blockIdx.x == 0) {
         for (int k = threadIdx.x; k < off; k += WG_THREADS) e[k] = T(0);
     }
@@ -971,8 +983,18 @@ __global__ __launch_bounds__(WG_THREADS) void k_coarse_solve(const double* __res
     const int row = blockIdx.x * WAVES_PER_WG + wave_id();
     if (row >= n0) return;
     const double* a = Ainv + (size_t)row * ld;
+    // s = sum over k = lane, lane + 64, ... of a[k] b[k], in that order
     double s = 0.0;
-    for (int k = lane_id(); k < n0; k += WAVE) s += a[k] * sb[k];
+    for (int base = 0; base < n0; base += U * WAVE) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = a[min(base + lane_id() + u * WAVE, n0 - 1)];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = base + lane_id() + u * WAVE;
+            s = (k < n0) ? s + v[u] * sb[min(k, n0 - 1)] : s;
+        }
+    }
     s = wave_sum(s);
     if (lane_id() == 0) e[off + row] = (T)s;
 }
