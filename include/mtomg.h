@@ -66,7 +66,9 @@ typedef struct {
     double relres_true;  /* ||f - K u|| / ||f|| recomputed in FP64 at exit     */
     double t_setup_ms;   /* device time of the last set_densities plus the     */
                          /* coarsest factorisation (shared by its group)       */
-    double t_solve_ms;   /* device time of the whole solve call (all systems)  */
+    double t_solve_ms;   /* device time of the whole solve call (all systems), */
+                         /* including waits for coarsest factorisations that   */
+                         /* run beside its first V-cycle                       */
     double model_bytes;  /* algorithmic HBM bytes of one PCG iteration         */
 } mtomg_stats;
 
@@ -117,9 +119,10 @@ int mtomg_set_workspace(mtomg_ctx *ctx, void *dev, size_t bytes);
 /* Load phase densities for a design and build its preconditioner:
  * element moduli by Eq. (5), Galerkin coarse operators for every level and
  * the assembled coarsest matrix.  Its Cholesky factor (Algorithm 3), turned
- * into an explicit inverse, is computed at the start of the next solve,
- * together with those of the other designs of the same shape whose
- * densities changed (one launch sequence for all of them).
+ * into an explicit inverse, is computed by the next solve, together with
+ * those of the other designs of the same shape whose densities changed (one
+ * launch sequence for all of them), on a private stream beside the first
+ * V-cycle, whose coarse solve waits for it.
  * x: device [nely][nelx][m] FP64 in [0, 1], read in stream order (keep it
  * alive until the work is done).  Asynchronous; a coarsest matrix that is
  * not positive definite is reported by the next solve (status BREAKDOWN

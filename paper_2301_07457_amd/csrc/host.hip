@@ -150,6 +150,9 @@ struct mtomg_ctx {
     bool use_graphs = true;
     int rows_fine = 0, rows_coarse = 0;   // rows per wave overrides (0 = automatic)
     hipStream_t cap_stream = nullptr;     // capture stream (default priority)
+    hipStream_t side_stream = nullptr;    // coarsest factorisations during a solve (default priority)
+    hipEvent_t ev_fac[2] = {nullptr, nullptr};   // [0] main -> side, [1] side -> main
+    int* host_chol = nullptr;             // pinned [cap][4]: coarsest-factor flags
     hipGraphExec_t pair_exec = nullptr;   // two PCG iterations (parities 1, 0) of the groups below
     double pair_tol2 = -1.0;
     std::vector<int> pair_groups;
@@ -398,11 +401,14 @@ int ensure_workspace(mtomg_ctx* c) {
     if (total > c->host_cap) {
         if (c->host_state) hipHostFree(c->host_state);
         if (c->host_sums) hipHostFree(c->host_sums);
+        if (c->host_chol) hipHostFree(c->host_chol);
         c->host_state = nullptr;
         c->host_sums = nullptr;
+        c->host_chol = nullptr;
         c->host_cap = 0;
         HIPCHK(c, hipHostMalloc((void**)&c->host_state, (size_t)total * 4 * sizeof(int), hipHostMallocDefault));
         HIPCHK(c, hipHostMalloc((void**)&c->host_sums, (size_t)total * 4 * sizeof(double), hipHostMallocDefault));
+        HIPCHK(c, hipHostMalloc((void**)&c->host_chol, (size_t)total * 4 * sizeof(int), hipHostMallocDefault));
         c->host_cap = total;
     }
     c->laid_out = true;
@@ -439,6 +445,7 @@ template <typename T> struct CycleCtx {
     const int* conv;   // nullable (debug use)
     Prof* prof = nullptr;
     Batch bt{};        // systems of every launch (pointers above are system 0's)
+    hipEvent_t wait_coarse = nullptr;   // the coarse solve waits for it (coarsest factors ready)
     void begin(int id) { if (prof) prof->begin(id, st); }
     void end(int id) { if (prof) prof->end(id, st); }
 };
@@ -542,6 +549,7 @@ void coarse_cycle(CycleCtx<T>& cx, int top, bool top_pre) {
         pre_done = restrict_down<T>(cx, l, b, d.n_pre > 0 ? cur : nullptr, false, nochk);
         pre[l] = cur;
     }
+    if (cx.wait_coarse) hipStreamWaitEvent(cx.st, cx.wait_coarse, 0);
     cx.begin(MTOMG_KERNEL_COARSE_SOLVE);
     launch_coarse_solve<T>(cx.st, d.Ainv, d.n0, d.np0, d.lev[0].nx, (const T*)c.b[0], (T*)c.e[0], cx.conv, cx.bt);
     cx.end(MTOMG_KERNEL_COARSE_SOLVE);
@@ -673,17 +681,20 @@ double model_bytes(const Design& d) {
 }
 
 // Coarsest factorisation (Algorithm 3 and the explicit inverse) of every
-// design whose densities changed since its last factorisation: one launch
-// sequence per group, designs not flagged skip it.  Synchronises to read
-// the positive-definiteness flags and the setup times.
-int factor_pending(mtomg_ctx* c) {
-    hipStream_t st = c->stream;
-    std::vector<char> ran(c->groups.size(), 0);
+// design whose densities changed since its last factorisation, on stream
+// st: one launch sequence per group, designs not flagged skip it.  The
+// positive-definiteness flags are copied to host_chol (row = design slot of
+// the group's systems) and read by factor_finalize after a synchronisation.
+// Returns whether anything was launched in *ran_any.
+int factor_launch(mtomg_ctx* c, hipStream_t st, bool* ran_any) {
+    *ran_any = false;
     int sys0 = 0;
     for (size_t gi = 0; gi < c->groups.size(); ++gi) {
         Group& g = c->groups[gi];
-        for (int di : g.designs) ran[gi] |= c->d[di].has_dens && c->d[di].needs_factor;
-        if (ran[gi]) {
+        bool ran = false;
+        for (int di : g.designs) ran = ran || (c->d[di].has_dens && c->d[di].needs_factor);
+        if (ran) {
+            *ran_any = true;
             Design& d0 = c->d[g.designs[0]];
             const int nd = (int)g.designs.size();
             HIPCHK(c, hipEventRecord(d0.fev[0], st));
@@ -692,17 +703,22 @@ int factor_pending(mtomg_ctx* c) {
             launch_fill_strided(st, d0.chol_status + 1, g.ds, nd, 0);
             HIPCHK(c, hipEventRecord(d0.fev[1], st));
             LAUNCHCHK(c);
-            HIPCHK(c, hipMemcpy2DAsync(c->host_state + 4 * sys0, 4 * sizeof(int), d0.chol_status, (size_t)g.ds,
+            HIPCHK(c, hipMemcpy2DAsync(c->host_chol + 4 * sys0, 4 * sizeof(int), d0.chol_status, (size_t)g.ds,
                                        4 * sizeof(int), nd, hipMemcpyDeviceToHost, st));
         }
         sys0 += g.n_sys;
     }
-    if (std::none_of(ran.begin(), ran.end(), [](char v) { return v != 0; })) return MTOMG_OK;
-    HIPCHK(c, hipStreamSynchronize(st));
-    sys0 = 0;
+    return MTOMG_OK;
+}
+
+// After the factorisation has completed: flags and setup times per design.
+int factor_finalize(mtomg_ctx* c) {
+    int sys0 = 0;
     for (size_t gi = 0; gi < c->groups.size(); ++gi) {
         Group& g = c->groups[gi];
-        if (ran[gi]) {
+        bool ran = false;
+        for (int di : g.designs) ran = ran || (c->d[di].has_dens && c->d[di].needs_factor);
+        if (ran) {
             float fac_ms = 0.f;
             Design& d0 = c->d[g.designs[0]];
             HIPCHK(c, hipEventElapsedTime(&fac_ms, d0.fev[0], d0.fev[1]));
@@ -712,13 +728,23 @@ int factor_pending(mtomg_ctx* c) {
                 float ms = 0.f;
                 HIPCHK(c, hipEventElapsedTime(&ms, d.ev[0], d.ev[1]));
                 d.t_setup_ms = ms + fac_ms;
-                d.fac_failed = c->host_state[4 * (sys0 + k)] != 0;
+                d.fac_failed = c->host_chol[4 * (sys0 + k)] != 0;
                 d.needs_factor = false;
             }
         }
         sys0 += g.n_sys;
     }
     return MTOMG_OK;
+}
+
+// Factorise now and wait (used outside the solve, e.g. by the test hook).
+int factor_pending(mtomg_ctx* c) {
+    bool ran = false;
+    int rc = factor_launch(c, c->stream, &ran);
+    if (rc) return rc;
+    if (!ran) return MTOMG_OK;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return factor_finalize(c);
 }
 
 template <typename T>
@@ -768,8 +794,9 @@ int capture_pair(mtomg_ctx* c, const std::vector<int>& act, double tol2) {
 
 // r_0 = f - K u_0 and the first preconditioner application, every system of a group
 template <typename T>
-void start_group(mtomg_ctx* c, Group& g, hipStream_t st, int warm, double tol2) {
+void start_group(mtomg_ctx* c, Group& g, hipStream_t st, int warm, double tol2, hipEvent_t wait_fac) {
     CycleCtx<T> cx = group_cycle<T>(c, g, st, &c->prof);
+    cx.wait_coarse = wait_fac;
     Design& d = *cx.d;
     CaseBufs& cb = *cx.c;
     const LevelBufs& L = d.lev[d.fine()];
@@ -782,7 +809,8 @@ void start_group(mtomg_ctx* c, Group& g, hipStream_t st, int warm, double tol2) 
 // entry (5 = not part of this run), all groups in lockstep.  On return
 // host_state holds each system's final state word and iteration count,
 // host_sums its ||f||^2, recursive and true ||r||^2; *ms the device time.
-int pcg_round(mtomg_ctx* c, const std::vector<int>& gsys0, double tol2, int max_iter, int warm, float* ms) {
+int pcg_round(mtomg_ctx* c, const std::vector<int>& gsys0, double tol2, int max_iter, int warm, float* ms,
+              hipEvent_t wait_fac) {
     hipStream_t st = c->stream;
     const bool graphs = c->use_graphs && c->prof.kernel == MTOMG_KERNEL_NONE;
     std::vector<int> act;
@@ -811,8 +839,8 @@ int pcg_round(mtomg_ctx* c, const std::vector<int>& gsys0, double tol2, int max_
     int it = 0;
     if (!act.empty()) {
         for (int gi : act) {
-            if (c->d[c->groups[gi].designs[0]].mixed()) start_group<float>(c, c->groups[gi], st, warm, tol2);
-            else start_group<double>(c, c->groups[gi], st, warm, tol2);
+            if (c->d[c->groups[gi].designs[0]].mixed()) start_group<float>(c, c->groups[gi], st, warm, tol2, wait_fac);
+            else start_group<double>(c, c->groups[gi], st, warm, tol2, wait_fac);
         }
         LAUNCHCHK(c);
         // iterations [from, from + count): pairs starting at an odd index replay the graph
@@ -885,10 +913,21 @@ int pcg_round(mtomg_ctx* c, const std::vector<int>& gsys0, double tol2, int max_
 // its current iterate, up to MAX_RESTARTS times within max_iter in total.
 constexpr int MAX_RESTARTS = 4;
 int solve_all(mtomg_ctx* c, double rel_tol, int max_iter, int warm, mtomg_stats* stats) {
-    int rc = factor_pending(c);
+    // Coarsest factorisations of designs with new densities run on the side
+    // stream, overlapped with the start of the first run (initial residual
+    // and the descent of the first V-cycle); only its coarse solve waits.
+    bool fac_ran = false;
+    hipEvent_t wait_fac = nullptr;
+    HIPCHK(c, hipEventRecord(c->ev_fac[0], c->stream));
+    HIPCHK(c, hipStreamWaitEvent(c->side_stream, c->ev_fac[0], 0));
+    int rc = factor_launch(c, c->side_stream, &fac_ran);
     if (rc) return rc;
+    if (fac_ran) {
+        HIPCHK(c, hipEventRecord(c->ev_fac[1], c->side_stream));
+        wait_fac = c->ev_fac[1];
+    }
     const double tol2 = rel_tol * rel_tol;
-    std::vector<int> gsys0(c->groups.size(), 0);
+    std::vector<int> gsys0(c->groups.size(), 0), sys_design;
     int n_sys = 0;
     for (size_t gi = 0; gi < c->groups.size(); ++gi) {
         Group& g = c->groups[gi];
@@ -900,6 +939,7 @@ int solve_all(mtomg_ctx* c, double rel_tol, int max_iter, int warm, mtomg_stats*
                 int* h = c->host_state + 4 * (n_sys + (int)k * g.cpd + q);
                 h[0] = v;
                 h[1] = h[2] = h[3] = 0;
+                sys_design.push_back(g.designs[k]);
             }
         }
         n_sys += g.n_sys;
@@ -912,9 +952,14 @@ int solve_all(mtomg_ctx* c, double rel_tol, int max_iter, int warm, mtomg_stats*
     int budget = max_iter, warm_r = warm;
     for (int round = 0; round <= MAX_RESTARTS; ++round) {
         float ms = 0.f;
-        rc = pcg_round(c, gsys0, tol2, budget, warm_r, &ms);
+        rc = pcg_round(c, gsys0, tol2, budget, warm_r, &ms, round == 0 ? wait_fac : nullptr);
         if (rc) return rc;
         total_ms += ms;
+        if (round == 0 && fac_ran) {
+            HIPCHK(c, hipStreamSynchronize(c->side_stream));
+            rc = factor_finalize(c);
+            if (rc) return rc;
+        }
         std::vector<int> again;
         int used = 0;
         for (int q = 0; q < n_sys; ++q) {
@@ -925,7 +970,7 @@ int solve_all(mtomg_ctx* c, double rel_tol, int max_iter, int warm, mtomg_stats*
             if (round == 0) first_round_most = std::max(first_round_most, iters[q]);
             for (int k = 0; k < 3; ++k) sums[3 * q + k] = c->host_sums[4 * q + k];
             const double ff = sums[3 * q];
-            const bool ok = state[q] == 1 || state[q] == 2;
+            const bool ok = (state[q] == 1 || state[q] == 2) && !c->d[sys_design[q]].fac_failed;
             if (ok && ff > 0.0 && sums[3 * q + 2] > tol2 * ff) {
                 again.push_back(q);
                 used = std::max(used, iters[q]);
@@ -995,7 +1040,10 @@ int mtomg_create(mtomg_ctx** ctx, int max_designs, void* hip_stream) {
         delete c;
         return MTOMG_HIP_ERROR;
     }
-    if (hipEventCreate(&c->ev_solve[0]) != hipSuccess || hipEventCreate(&c->ev_solve[1]) != hipSuccess) {
+    if (hipEventCreate(&c->ev_solve[0]) != hipSuccess || hipEventCreate(&c->ev_solve[1]) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fac[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fac[1], hipEventDisableTiming) != hipSuccess) {
         mtomg_destroy(c);
         return MTOMG_HIP_ERROR;
     }
@@ -1006,8 +1054,13 @@ int mtomg_create(mtomg_ctx** ctx, int max_designs, void* hip_stream) {
 int mtomg_destroy(mtomg_ctx* c) {
     if (!c) return MTOMG_OK;
     hipStreamSynchronize(c->stream);
+    hipStreamSynchronize(c->side_stream);
     drop_graphs(c);
+    if (c->side_stream) hipStreamSynchronize(c->side_stream);
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+    if (c->side_stream) hipStreamDestroy(c->side_stream);
+    for (hipEvent_t& e : c->ev_fac)
+        if (e) hipEventDestroy(e);
     for (Design& d : c->d) {
         for (hipEvent_t& e : d.ev)
             if (e) hipEventDestroy(e);
@@ -1019,6 +1072,7 @@ int mtomg_destroy(mtomg_ctx* c) {
     if (c->ws_owned && c->ws) hipFree(c->ws);
     if (c->host_state) hipHostFree(c->host_state);
     if (c->host_sums) hipHostFree(c->host_sums);
+    if (c->host_chol) hipHostFree(c->host_chol);
     for (hipEvent_t& e : c->prof.ev)
         if (e) hipEventDestroy(e);
     delete c;
@@ -1050,6 +1104,7 @@ int mtomg_set_grid(mtomg_ctx* c, int design, int nelx, int nely, double nu, int 
     if (!F || !U) return fail(c, MTOMG_BAD_INPUT, "F and U must be device pointers");
     Design& d = c->d[design];
     hipStreamSynchronize(c->stream);
+    hipStreamSynchronize(c->side_stream);
     drop_graphs(c);
     for (hipEvent_t& e : d.ev)
         if (e) hipEventDestroy(e);
@@ -1096,6 +1151,7 @@ int mtomg_set_workspace(mtomg_ctx* c, void* dev, size_t bytes) {
     const size_t need = measure_workspace(c);
     if (bytes < need) return fail(c, MTOMG_WORKSPACE, "workspace smaller than mtomg_workspace_bytes()");
     hipStreamSynchronize(c->stream);
+    hipStreamSynchronize(c->side_stream);
     drop_graphs(c);
     if (c->ws_owned && c->ws) hipFree(c->ws);
     c->ws = dev;
@@ -1197,6 +1253,7 @@ int mtomg_set_option(mtomg_ctx* c, int option, int value) {
                 return fail(c, MTOMG_BAD_INPUT, "rows per wave must be 0 (automatic), 1, 2, 4 or 8");
             (option == MTOMG_OPT_ROWS_FINE ? c->rows_fine : c->rows_coarse) = value;
             hipStreamSynchronize(c->stream);
+            hipStreamSynchronize(c->side_stream);
             drop_graphs(c);
             for (Design& d : c->d)
                 for (int l = 0; l < d.levels; ++l) plan_level(d.lev[l], l == d.levels - 1 ? c->rows_fine : c->rows_coarse);

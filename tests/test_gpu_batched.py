@@ -139,3 +139,25 @@ def test_config4_shapes_small_slice():
         assert rel(s.U(k).cpu().numpy(), ref.U) <= 1e-6
     print(f"[config4 slice] solve {stats[0]['t_solve_ms']:.2f} ms, iters "
           f"{sorted(set(st['iters'] for st in stats))}")
+
+
+def test_non_spd_design_reports_breakdown_and_spares_the_group():
+    """x = -1 gives negative moduli: the coarsest matrix is not positive
+    definite, which the deferred factorisation reports as BREAKDOWN for each
+    load case of that design, while a valid design of the same group solves."""
+    from paper_2301_07457_amd import PCGMGSolver
+    a = make(64, 64, 3, 2201)
+    s = PCGMGSolver(max_designs=2)
+    add(s, 0, a, "fp32mg")
+    add(s, 1, a, "fp32mg")
+    s.set_densities(0, torch.from_numpy(-np.ones_like(a.x)))
+    s.set_densities(1, torch.from_numpy(a.x))
+    stats = s.solve(1e-8, 200)
+    assert [st["status"] for st in stats[:4]] == [-3] * 4
+    assert all(st["status"] == 0 and st["relres_true"] <= 1e-8 for st in stats[4:])
+    ref = solve.solve_direct(a.nelx, a.nely, a.x, a.E_phase, a.E_min, a.penal, a.nu, a.F)
+    assert rel(s.U(1).cpu().numpy(), ref.U) <= 1e-6
+    # new valid densities clear the failure
+    s.set_densities(0, torch.from_numpy(a.x))
+    stats = s.solve(1e-8, 1000)
+    assert all(st["status"] == 0 for st in stats)
