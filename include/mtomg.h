@@ -172,8 +172,15 @@ const char *mtomg_last_error(const mtomg_ctx *ctx);
  *     1, 2, 4 or 8): node rows each wave marches through in the sweeps of
  *     the finest grid / of the coarse grids (a tuning knob).  Changing it
  *     re-plans every design: a workspace given with set_workspace must be
- *     given again (the size may change) and densities set again. */
-enum { MTOMG_OPT_GRAPHS = 0, MTOMG_OPT_BATCH = 1, MTOMG_OPT_ROWS_FINE = 2, MTOMG_OPT_ROWS_COARSE = 3 };
+ *     given again (the size may change) and densities set again.
+ *   MTOMG_OPT_DENSE_FACTOR (default 0): 1 factors the coarsest matrix by the
+ *     dense 32 x 32 block sequence (one launch per block step, vector FP64
+ *     products) instead of the banded kernels (one workgroup per design for
+ *     the Cholesky chain, products on the FP64 matrix cores); both give
+ *     K_0^{-1} to rounding (a test and comparison knob).  Applies to
+ *     factorisations run after the call. */
+enum { MTOMG_OPT_GRAPHS = 0, MTOMG_OPT_BATCH = 1, MTOMG_OPT_ROWS_FINE = 2, MTOMG_OPT_ROWS_COARSE = 3,
+       MTOMG_OPT_DENSE_FACTOR = 4 };
 int mtomg_set_option(mtomg_ctx *ctx, int option, int value);
 
 /* Profiling: time every launch of one solver kernel during the following

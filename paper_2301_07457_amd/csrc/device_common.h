@@ -229,12 +229,20 @@ __device__ __forceinline__ int xcd_tile(int n_tiles) {
     return (b & 7) * per + (b >> 3);
 }
 
+// State word of a system (0 = running; a null pointer reads 0).  The load is
+// unconditional, so a latency-bound kernel can issue it together with its
+// data loads and test it once they are in flight.
+static __device__ int g_state_running = 0;   // never written
+__device__ __forceinline__ int load_state(const int* w) { return *(w ? w : &g_state_running); }
+
 // Nodal vector access with the clamped row (j = 0) and out-of-grid nodes read
 // as 0.  The index is clamped into the grid and the load is always issued,
 // then masked: no branch, so the loads of consecutive rows can be batched.
+// use = false reads 0 (v must still point at a nodal vector of the level).
 template <typename T>
-__device__ __forceinline__ V2<T> load_node(const T* __restrict__ v, int nx, int ny, int i, int j) {
-    const bool ok = (i >= 0) & (i <= nx) & (j >= 1) & (j <= ny);
+__device__ __forceinline__ V2<T> load_node(const T* __restrict__ v, int nx, int ny, int i, int j,
+                                           bool use = true) {
+    const bool ok = use & (i >= 0) & (i <= nx) & (j >= 1) & (j <= ny);
     const int ic = min(max(i, 0), nx), jc = min(max(j, 1), ny);
     const size_t n = (size_t)jc * (nx + 1) + ic;
     // the clamped address always holds finite data, so multiplying by the

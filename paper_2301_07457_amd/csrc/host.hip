@@ -148,6 +148,7 @@ struct mtomg_ctx {
     int batch = 8;                // iterations between host checks (first solve)
     int last_iters = 0;           // most iterations of the previous solve (batch hint)
     bool use_graphs = true;
+    bool dense_factor = false;   // coarsest factorisation by the dense block sequence
     int rows_fine = 0, rows_coarse = 0;   // rows per wave overrides (0 = automatic)
     hipStream_t cap_stream = nullptr;     // capture stream (default priority)
     hipStream_t side_stream = nullptr;    // coarsest factorisations during a solve (default priority)
@@ -698,8 +699,10 @@ int factor_launch(mtomg_ctx* c, hipStream_t st, bool* ran_any) {
             Design& d0 = c->d[g.designs[0]];
             const int nd = (int)g.designs.size();
             HIPCHK(c, hipEventRecord(d0.fev[0], st));
+            // DOFs 2 ((j-1)(nx+1) + i) + c: neighbouring nodes lie at most 2 nx + 5 apart
+            const int half_bw = c->dense_factor ? 0 : 2 * d0.lev[0].nx + 5;
             launch_coarse_factor(st, d0.A0, d0.n0, d0.np0, d0.Dinv, d0.W0, d0.Ainv, d0.chol_status, d0.Lbuf,
-                                 d0.Sacc, nd, g.ds);
+                                 d0.Sacc, nd, g.ds, half_bw);
             launch_fill_strided(st, d0.chol_status + 1, g.ds, nd, 0);
             HIPCHK(c, hipEventRecord(d0.fev[1], st));
             LAUNCHCHK(c);
@@ -1263,6 +1266,9 @@ int mtomg_set_option(mtomg_ctx* c, int option, int value) {
             if (c->ws_owned && c->ws) { hipFree(c->ws); c->ws = nullptr; c->ws_owned = false; c->ws_bytes = 0; }
             return MTOMG_OK;
         }
+        case MTOMG_OPT_DENSE_FACTOR:
+            c->dense_factor = value != 0;
+            return MTOMG_OK;
         case MTOMG_OPT_BATCH:
             if (value < 1 || value > 1000) return fail(c, MTOMG_BAD_INPUT, "batch must be in [1, 1000]");
             c->batch = value;

@@ -124,9 +124,13 @@ void launch_assemble_dense(hipStream_t st, bool fine, LevelOp<double> op, Mat<do
 // Dinv = inverses of the diagonal blocks of L, W = L^{-1}, Ainv = A^{-1}.
 // status[0]: 0 or 1 (not positive definite); status[1]: factor this design
 // (the launch skips designs with 0).  `n_designs` designs, `ds` bytes apart.
+// half_bw > 0: A[i][j] = 0 for |i - j| > half_bw; up to 64 this selects the
+// banded kernels (one workgroup per design for the Cholesky chain, block
+// products on the FP64 matrix cores); half_bw <= 0 (or wider bands) runs
+// the dense block sequence.  Both give the same factors to rounding.
 void launch_coarse_factor(hipStream_t st, double* A, int n0, int np, double* Dinv, double* W, double* Ainv,
                           int* status, double* Lbuf /* np x np */, double* Sacc /* np x np */,
-                          int n_designs = 1, long long ds = 0);
+                          int n_designs = 1, long long ds = 0, int half_bw = 0);
 // p[k * stride_bytes] = v for k < n
 void launch_fill_strided(hipStream_t st, int* p, long long stride_bytes, int n, int v);
 template <typename T>

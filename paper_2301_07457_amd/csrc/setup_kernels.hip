@@ -132,14 +132,16 @@ __device__ __forceinline__ void blk_load(double (*S)[NB + 1], const double* __re
 
 // ---------------------------------------------------------------------------
 // Factor and inverse of one SPD 32x32 block by a single wave, in registers.
-// Lane l holds row r = l & 31 at the columns c = 2j + h, h = l >> 5.  Step
-// k of the right-looking factorisation scales column k into L and, as the
-// same elementary row operation applied to X (initially I), row k of X;
-// then every row below eliminates: S[r][c] -= L[r][k] L[c][k] and
+// Lanes 0..31 hold the rows r of the block, lanes 32..63 the columns c of
+// X (initially I).  Step k of the right-looking factorisation scales column
+// k into L and, as the same elementary row operation applied to X, row k of
+// X; then every row below eliminates: S[r][c] -= L[r][k] L[c][k] and
 // X[r][:] -= L[r][k] X[k][:].  After 32 steps X = L^{-1} (Gauss-Jordan on
-// the factor).  Column k of L and row k of X reach the other lanes through
-// LDS; the lanes of one wave access LDS in order, so only the compiler is
-// fenced between the writes and the reads.
+// the factor).  With X held by columns, both updates read as
+// v[j] -= own * L[j][k] for j > k (own = L[r][k] on a row lane, X[k][c] on
+// a column lane), so one instruction stream serves both halves and only
+// column k of L travels, through LDS; the lanes of one wave access LDS in
+// order, so only the compiler is fenced between the write and the reads.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void wave_fence() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -163,57 +165,48 @@ __device__ __forceinline__ double rsqrt_nr(double d) {
 }
 
 // S: input block (LDS, lower triangle read); Li: receives L^{-1} (full
-// block, zero above the diagonal); buf: 128 doubles of LDS.  Call from one
-// whole wave.  Returns false (uniformly) if a pivot is not positive.
-__device__ bool wave_potrf_inv(const double (*S)[NB + 1], double (*Li)[NB + 1], double* buf) {
+// block, zero above the diagonal); buf: 32 doubles of LDS.  Call from one
+// whole wave.  Returns false (uniformly) if a pivot is not positive; Li is
+// then not meaningful.
+template <int LD>
+__device__ __forceinline__ bool wave_potrf_inv(const double (*S)[LD], double (*Li)[LD], double* buf) {
     const int lane = threadIdx.x & 63;
-    const int r = lane & 31, h = lane >> 5;
-    double a[16], x[16];
+    const bool xl = lane >= 32;   // column lane of X
+    const int q = lane & 31;      // row of S / column of X
+    double v[NB];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        a[j] = S[r][2 * j + h];
-        x[j] = (2 * j + h == r) ? 1.0 : 0.0;
+    for (int j = 0; j < NB; ++j) {
+        const double sv = S[q][j];
+        v[j] = xl ? (j == q ? 1.0 : 0.0) : sv;
     }
-    double* colb = buf;            // L[c][k] at (c & 1) * 16 + (c >> 1)
-    double* rowb = buf + 2 * NB;   // X[k][c] at (c & 1) * 16 + (c >> 1)
+    bool ok = true;
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
-        const int jk = k >> 1, hk = k & 1;
-        const double d = readlane_d(a[jk], k + 32 * hk);
-        if (!(d > 0.0)) return false;
+        const double d = readlane_d(v[k], k);
+        ok = ok && (d > 0.0);
         const double inv = rsqrt_nr(d);
-        if (h == hk) {
-            const double v = (r > k) ? a[jk] * inv : (r == k ? d * inv : 0.0);
-            a[jk] = v;
-            colb[(r & 1) * 16 + (r >> 1)] = v;
-        }
-        if (r == k) {
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                x[j] *= inv;
-                rowb[h * 16 + j] = x[j];
-            }
-        }
+        const double lk = (q > k) ? v[k] * inv : (q == k ? d * inv : 0.0);
+        v[k] = xl ? v[k] * inv : lk;
+        const double own = v[k];
+        if (!xl) buf[q] = lk;
         wave_fence();
-        const double lrk = colb[(r & 1) * 16 + (r >> 1)];
-        double lc[16], xk[16];
+        double bk[NB];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            lc[j] = colb[h * 16 + j];
-            xk[j] = rowb[h * 16 + j];
-        }
-        if (r > k) {
+        for (int j = k + 1; j < NB; ++j) bk[j] = buf[j];
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                if (2 * j + h > k) a[j] -= lrk * lc[j];
-                x[j] -= lrk * xk[j];
-            }
+        for (int j = k + 1; j < NB; ++j) {
+            v[j] -= own * bk[j];
+            // materialise the update in this step (deferring it would keep
+            // every step's column live and spill)
+            asm volatile("" : "+v"(v[j]));
         }
         wave_fence();
     }
+    if (xl) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) Li[r][2 * j + h] = x[j];
-    return true;
+        for (int r = 0; r < NB; ++r) Li[r][q] = v[r];
+    }
+    return ok;
 }
 
 // C (LDS) = X Y^T for 32x32 blocks in LDS; thread (r, c4..c4+3).
@@ -338,7 +331,7 @@ __global__ __launch_bounds__(256) void k_factor_step(double* __restrict__ A, int
         // B0 holds the finished diagonal block kk; wave 0 factors it into B2 = L_kk^{-1}
         __syncthreads();
         if (threadIdx.x < WAVE) {
-            const bool ok = wave_potrf_inv(B0, B2, &B3[0][0]);
+            const bool ok = wave_potrf_inv<NB + 1>(B0, B2, &B3[0][0]);
             if (threadIdx.x == 0) not_spd = ok ? 0 : 1;
         }
         __syncthreads();
@@ -391,6 +384,291 @@ __global__ __launch_bounds__(256) void k_factor_step(double* __restrict__ A, int
 #pragma unroll
         for (int q = 0; q < 4; ++q) B0[r][c4 + q] = nv[q];
         finish_diag(k);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Banded form of the same factorisation.  The coarsest matrix couples DOFs
+// at most 2 nx0 + 5 apart (neighbouring nodes, two DOFs each, rows of
+// nx0 + 1 nodes), so with 32 x 32 blocks only the NBW = ceil(bw / 32)
+// blocks below the diagonal are nonzero, and Cholesky creates no fill
+// outside that band.  Every operation of the dense launch sequence that
+// involves a block outside the band adds exact zeros; the kernels below
+// skip those, so they compute the same L^{-1} blocks, W and K_0^{-1} (up to
+// the rounding order of the matrix-core products).
+// ---------------------------------------------------------------------------
+
+// Blocks of the banded kernels sit in LDS with a row stride of BL doubles.
+// Their 32 x 32 x 32 block products run on the FP64 matrix cores
+// (v_mfma_f64_16x16x4: A[i][k] from lane i + 16 k, B[k][j] from lane
+// j + 16 k, result element (4 v + lane / 16, lane % 16) in register v);
+// wave w of a 256-thread workgroup owns the 16 x 16 quadrant
+// (w >> 1, w & 1) of every block product.
+constexpr int BL = NB + 2;
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+struct Quad {
+    int i0, j0, li, lk;
+};
+__device__ __forceinline__ Quad quad_of_wave() {
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    return Quad{16 * (w >> 1), 16 * (w & 1), l & 15, l >> 4};
+}
+
+// acc += X[i0.., :] Y[j0.., :]^T  (sum over s of X[i][s] Y[j][s])
+__device__ __forceinline__ dbl4 mfma_nt(const double (*X)[BL], const double (*Y)[BL], const Quad& q, dbl4 acc) {
+#pragma unroll
+    for (int kk = 0; kk < NB; kk += 4) {
+        const double a = X[q.i0 + q.li][kk + q.lk];
+        const double b = Y[q.j0 + q.li][kk + q.lk];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    return acc;
+}
+// acc += X[i0.., :] Y[:, j0..]  (sum over s of X[i][s] Y[s][j])
+__device__ __forceinline__ dbl4 mfma_nn(const double (*X)[BL], const double (*Y)[BL], const Quad& q, dbl4 acc) {
+#pragma unroll
+    for (int kk = 0; kk < NB; kk += 4) {
+        const double a = X[q.i0 + q.li][kk + q.lk];
+        const double b = Y[kk + q.lk][q.j0 + q.li];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    return acc;
+}
+// acc += X[:, i0..]^T Y[:, j0..]  (sum over s of X[s][i] Y[s][j])
+__device__ __forceinline__ dbl4 mfma_tn(const double (*X)[BL], const double (*Y)[BL], const Quad& q, dbl4 acc) {
+#pragma unroll
+    for (int kk = 0; kk < NB; kk += 4) {
+        const double a = X[kk + q.lk][q.i0 + q.li];
+        const double b = Y[kk + q.lk][q.j0 + q.li];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    return acc;
+}
+// the quadrant's elements: (i0 + 4 v + lk, j0 + li), v = 0..3
+__device__ __forceinline__ void quad_store(double (*C)[BL], const Quad& q, dbl4 d) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) C[q.i0 + 4 * v + q.lk][q.j0 + q.li] = d[v];
+}
+__device__ __forceinline__ void quad_store_g(double* __restrict__ G, size_t ld, const Quad& q, dbl4 d) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) G[(size_t)(q.i0 + 4 * v + q.lk) * ld + q.j0 + q.li] = d[v];
+}
+__device__ __forceinline__ dbl4 quad_load(const double (*C)[BL], const Quad& q) {
+    dbl4 d;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) d[v] = C[q.i0 + 4 * v + q.lk][q.j0 + q.li];
+    return d;
+}
+
+__device__ __forceinline__ void ld4(double* v, const double* __restrict__ p) {
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    const double2 b = *reinterpret_cast<const double2*>(p + 2);
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = b.x;
+    v[3] = b.y;
+}
+__device__ __forceinline__ void st4(double* p, const double* v) {
+    *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+    *reinterpret_cast<double2*>(p + 2) = make_double2(v[2], v[3]);
+}
+
+// Cholesky of the band by one workgroup per design: block step k factors
+// the diagonal block (Dinv_k = L_kk^{-1}, also W's diagonal block), forms
+// the panel L[k+d][k] = A[k+d][k] Dinv_k^T (d = 1..NBW; stored to Lbuf) and
+// updates the trailing blocks A[i][j] -= L[i][k] L[j][k]^T, k < j <= i <=
+// k + NBW.  The active block rows live in LDS (block (i, i-d) in slot
+// [i % (NBW+2)][d]); block row k+NBW+1 is fetched from A by waves 1..3
+// while wave 0 factors the diagonal block of step k.
+template <int NBW>
+__global__ __launch_bounds__(256) void k_band_chol(const double* __restrict__ A, int np, double* __restrict__ Dinv,
+                                                   double* __restrict__ Lbuf, double* __restrict__ W,
+                                                   int* __restrict__ status, long long ds) {
+    constexpr int NR = NBW + 2;
+    __shared__ __align__(16) double win[NR][NBW + 1][NB][BL];
+    __shared__ __align__(16) double Dk[NB][BL];
+    __shared__ __align__(16) double gbuf[NB];
+    __shared__ int not_spd;
+    const long long off = (long long)blockIdx.y * ds;
+    status = at(status, off);
+    if (status[1] == 0 || status[0] != 0) return;
+    A = at(A, off);
+    Dinv = at(Dinv, off);
+    Lbuf = at(Lbuf, off);
+    W = at(W, off);
+    const int nblk = np / NB;
+    int r, c4;
+    blk_coords(r, c4);
+    const Quad qd = quad_of_wave();
+    auto gblk = [&](int bi, int bj) { return (size_t)(bi * NB + r) * np + bj * NB + c4; };
+    auto gbase = [&](int bi, int bj) { return (size_t)(bi * NB) * np + bj * NB; };
+    for (int i = 0; i <= NBW && i < nblk; ++i)
+        for (int d = 0; d <= NBW && d <= i; ++d) ld4(&win[i % NR][d][r][c4], A + gblk(i, i - d));
+    for (int k = 0; k < nblk; ++k) {
+        const int rn = k + NBW + 1;
+        __syncthreads();
+        if (threadIdx.x < WAVE) {
+            const bool ok = wave_potrf_inv<BL>(win[k % NR][0], Dk, gbuf);
+            if (threadIdx.x == 0) not_spd = ok ? 0 : 1;
+        } else if (rn < nblk) {
+            // meanwhile waves 1..3 bring block row k + NBW + 1 into its slot
+            // (which held row k - 1, finished)
+            constexpr int TOT = (NBW + 1) * NB * NB / 2;   // double2 elements
+            constexpr int NT = 256 - WAVE;
+            constexpr int PER = (TOT + NT - 1) / NT;
+            const int t0 = threadIdx.x - WAVE;
+            double2 v[PER];
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int e = min(t0 + u * NT, TOT - 1);
+                const int d = e / (NB * NB / 2), rem = e % (NB * NB / 2);
+                v[u] = *reinterpret_cast<const double2*>(A + (size_t)(rn * NB + rem / (NB / 2)) * np + (rn - d) * NB +
+                                                         (rem % (NB / 2)) * 2);
+            }
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int e = t0 + u * NT;
+                if (e < TOT) {
+                    const int d = e / (NB * NB / 2), rem = e % (NB * NB / 2);
+                    *reinterpret_cast<double2*>(&win[rn % NR][d][rem / (NB / 2)][(rem % (NB / 2)) * 2]) = v[u];
+                }
+            }
+        }
+        __syncthreads();
+        if (not_spd) {
+            if (threadIdx.x == 0) *status = 1;
+            return;
+        }
+        st4(Dinv + (size_t)k * NB * NB + r * NB + c4, &Dk[r][c4]);
+        st4(W + gblk(k, k), &Dk[r][c4]);
+        // panel (this wave's quadrant of each block)
+        dbl4 Lp[NBW];
+#pragma unroll
+        for (int d = 1; d <= NBW; ++d) {
+            if (k + d >= nblk) break;
+            Lp[d - 1] = mfma_nt(win[(k + d) % NR][d], Dk, qd, dbl4{0, 0, 0, 0});
+        }
+        __syncthreads();
+#pragma unroll
+        for (int d = 1; d <= NBW; ++d) {
+            if (k + d >= nblk) break;
+            quad_store(win[(k + d) % NR][d], qd, Lp[d - 1]);
+            quad_store_g(Lbuf + gbase(k + d, k), np, qd, Lp[d - 1]);
+        }
+        __syncthreads();
+        // trailing update; the blocks written and the panel blocks read are disjoint
+#pragma unroll
+        for (int di = 1; di <= NBW; ++di) {
+            if (k + di >= nblk) break;
+#pragma unroll
+            for (int dj = 1; dj <= di; ++dj) {
+                const dbl4 upd = mfma_nt(win[(k + di) % NR][di], win[(k + dj) % NR][dj], qd, dbl4{0, 0, 0, 0});
+                double(*B)[BL] = win[(k + di) % NR][di - dj];
+                quad_store(B, qd, quad_load(B, qd) - upd);
+            }
+        }
+    }
+}
+
+// W = L^{-1}, block column j per workgroup: W[j][j] = Dinv_j and, for
+// i > j, W[i][j] = -Dinv_i S with S = sum over t = max(j, i-NBW) .. i-1 of
+// L[i][t] W[t][j].  The L blocks and Dinv_i of the next block row are
+// fetched while the current one is formed.
+template <int NBW>
+__global__ __launch_bounds__(256) void k_band_winv(const double* __restrict__ Dinv, const double* __restrict__ Lbuf,
+                                                   double* __restrict__ W, int np, const int* __restrict__ status,
+                                                   long long ds) {
+    constexpr int NQ = NBW + 1;
+    __shared__ __align__(16) double Wq[NQ][NB][BL];   // W[t][j] at slot t % NQ
+    __shared__ __align__(16) double Lq[NBW][NB][BL];  // L[i][i-d] at slot d-1
+    __shared__ __align__(16) double Dq[NB][BL];       // Dinv_i
+    __shared__ __align__(16) double Sq[NB][BL];
+    const long long off = (long long)blockIdx.y * ds;
+    status = at(status, off);
+    if (status[1] == 0 || status[0] != 0) return;
+    Dinv = at(Dinv, off);
+    Lbuf = at(Lbuf, off);
+    W = at(W, off);
+    const int nblk = np / NB;
+    const int j = blockIdx.x;
+    int r, c4;
+    blk_coords(r, c4);
+    const Quad qd = quad_of_wave();
+    auto gblk = [&](int bi, int bj) { return (size_t)(bi * NB + r) * np + bj * NB + c4; };
+    double pl[NBW][4], pd[4];
+    auto fetch = [&](int i) {
+#pragma unroll
+        for (int d = 1; d <= NBW; ++d)
+            if (d <= i - j) ld4(pl[d - 1], Lbuf + gblk(i, i - d));
+        ld4(pd, Dinv + (size_t)i * NB * NB + r * NB + c4);
+    };
+    {
+        double w0[4];
+        ld4(w0, Dinv + (size_t)j * NB * NB + r * NB + c4);
+        st4(&Wq[j % NQ][r][c4], w0);
+    }
+    if (j + 1 < nblk) fetch(j + 1);
+    for (int i = j + 1; i < nblk; ++i) {
+        const int dmax = min(NBW, i - j);
+#pragma unroll
+        for (int d = 1; d <= NBW; ++d)
+            if (d <= dmax) st4(&Lq[d - 1][r][c4], pl[d - 1]);
+        st4(&Dq[r][c4], pd);
+        if (i + 1 < nblk) fetch(i + 1);
+        __syncthreads();
+        dbl4 acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int d = NBW; d >= 1; --d)
+            if (d <= dmax) acc = mfma_nn(Lq[d - 1], Wq[(i - d) % NQ], qd, acc);
+        quad_store(Sq, qd, acc);
+        __syncthreads();
+        const dbl4 w = -mfma_nn(Dq, Sq, qd, dbl4{0, 0, 0, 0});
+        quad_store(Wq[i % NQ], qd, w);
+        quad_store_g(W + (size_t)(i * NB) * np + j * NB, np, qd, w);
+        __syncthreads();
+    }
+}
+
+// K_0^{-1} = W^T W: workgroup (i, j), i >= j, sums W[t][i]^T W[t][j] over
+// t = i .. nblk-1 and writes block (i, j) and its mirror (j, i).  The blocks
+// of the next t are fetched during the product.
+__global__ __launch_bounds__(256) void k_band_gram(const double* __restrict__ W, double* __restrict__ Ainv, int np,
+                                                   const int* __restrict__ status, long long ds) {
+    __shared__ __align__(16) double B[2][2][NB][BL];
+    const long long off = (long long)blockIdx.y * ds;
+    status = at(status, off);
+    if (status[1] == 0 || status[0] != 0) return;
+    W = at(W, off);
+    Ainv = at(Ainv, off);
+    const int nblk = np / NB;
+    int i = 0, j = blockIdx.x;
+    while (j > i) { j -= i + 1; ++i; }
+    int r, c4;
+    blk_coords(r, c4);
+    const Quad qd = quad_of_wave();
+    auto gblk = [&](int bi, int bj) { return (size_t)(bi * NB + r) * np + bj * NB + c4; };
+    double pa[4], pb[4];
+    ld4(pa, W + gblk(i, i));
+    ld4(pb, W + gblk(i, j));
+    dbl4 acc = {0, 0, 0, 0};
+    for (int t = i; t < nblk; ++t) {
+        const int cur = (t - i) & 1;
+        st4(&B[cur][0][r][c4], pa);
+        st4(&B[cur][1][r][c4], pb);
+        if (t + 1 < nblk) {
+            ld4(pa, W + gblk(t + 1, i));
+            ld4(pb, W + gblk(t + 1, j));
+        }
+        __syncthreads();
+        acc = mfma_tn(B[cur][0], B[cur][1], qd, acc);
+    }
+    quad_store_g(Ainv + (size_t)(i * NB) * np + j * NB, np, qd, acc);
+    if (i != j) {
+        // mirror: element (a, b) of block (i, j) goes to (b, a) of block (j, i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            Ainv[(size_t)(j * NB + qd.j0 + qd.li) * np + i * NB + qd.i0 + 4 * v + qd.lk] = acc[v];
     }
 }
 
@@ -516,11 +794,24 @@ void launch_assemble_dense(hipStream_t st, bool fine, LevelOp<double> op, Mat<do
     else hipLaunchKernelGGL(k_assemble_dense<false>, dim3(blocks_for(n, 256)), dim3(256), 0, st, op, mat, A, ld);
 }
 void launch_coarse_factor(hipStream_t st, double* A, int n0, int np, double* Dinv, double* W, double* Ainv,
-                          int* status, double* Lbuf, double* Sacc, int n_designs, long long ds) {
+                          int* status, double* Lbuf, double* Sacc, int n_designs, long long ds, int half_bw) {
     if (np > n0)
         hipLaunchKernelGGL(k_pad_identity, dim3(blocks_for(np - n0, 256), n_designs), dim3(256), 0, st, A, n0, np,
                            status, ds);
     const int nblk = np / NB;
+    const int nbw = half_bw > 0 ? (half_bw + NB - 1) / NB : nblk;
+    if (nbw <= 2) {
+        if (nbw <= 1) {
+            hipLaunchKernelGGL(k_band_chol<1>, dim3(1, n_designs), dim3(256), 0, st, A, np, Dinv, Lbuf, W, status, ds);
+            hipLaunchKernelGGL(k_band_winv<1>, dim3(nblk, n_designs), dim3(256), 0, st, Dinv, Lbuf, W, np, status, ds);
+        } else {
+            hipLaunchKernelGGL(k_band_chol<2>, dim3(1, n_designs), dim3(256), 0, st, A, np, Dinv, Lbuf, W, status, ds);
+            hipLaunchKernelGGL(k_band_winv<2>, dim3(nblk, n_designs), dim3(256), 0, st, Dinv, Lbuf, W, np, status, ds);
+        }
+        hipLaunchKernelGGL(k_band_gram, dim3(nblk * (nblk + 1) / 2, n_designs), dim3(256), 0, st, W, Ainv, np, status,
+                           ds);
+        return;
+    }
     for (int k = 0; k <= nblk + 1; ++k) {
         const int m = nblk - k;
         const int n_chol = (k >= nblk) ? 0 : (k == 0 ? 1 : m * (m + 1) / 2);

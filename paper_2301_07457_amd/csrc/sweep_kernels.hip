@@ -275,12 +275,15 @@ __global__ __launch_bounds__(WG_THREADS) void k_presmooth(
         cg.conv_rw = at(cg.conv_rw, so.c);
         cg.iters = at(cg.iters, so.c);
     }
-    int cst = 0;
-    if (conv) cst = *conv;
+    // a running system has state 0; latency-bound coarse sweeps test it
+    // after issuing their loads
+    const int cst = load_state(conv);
     if constexpr (CG) {
         if (cst == 1 && blockIdx.x == 0 && threadIdx.x == 0) *cg.conv_rw = 2;
     }
-    if (cst != 0) return;
+    if constexpr (FINE || CG) {
+        if (cst != 0) return;
+    }
     const int nx = op.nx, ny = op.ny;
     const TileInfo t = tile_info<R>(sw, ny + 1);
     if (!t.block_ok) return;
@@ -348,6 +351,10 @@ __global__ __launch_bounds__(WG_THREADS) void k_presmooth(
             for (int s = 0; s < R + 2; ++s) br[s] = load_node(b, nx, ny, i, t.j0 - 1 + s);
 #pragma unroll
             for (int s = 0; s < R + 3; ++s) me[s] = load_elem<T, FINE>(op, i, t.j0 - 2 + s);
+            if constexpr (!FINE) {
+                __builtin_amdgcn_sched_barrier(0);
+                if (cst != 0) return;
+            }
         }
         if (t.j0 == 0 && out_lane) store_node(u_out, nx, i, 0, V2<T>{T(0), T(0)});
 
@@ -421,9 +428,10 @@ __global__ __launch_bounds__(WG_THREADS) void k_restrict(
         chk.ff = at(chk.ff, so.c);
         chk.conv_rw = at(chk.conv_rw, so.c);
     }
-    int cst = 0;
-    if (conv) cst = *conv;
-    if (cst != 0) return;
+    const int cst = load_state(conv);   // coarse levels test it after issuing their loads
+    if constexpr (FINE || CHECK) {
+        if (cst != 0) return;
+    }
     const int nx = op.nx, ny = op.ny;
     const int ncx = nx / 2, ncy = ny / 2;
     const TileInfo t = tile_info<R>(sw, ncy + 1);
@@ -455,17 +463,19 @@ __global__ __launch_bounds__(WG_THREADS) void k_restrict(
     const int jf0 = 2 * t.j0 - 1;
     V2<T> ur[NF + 2], br[NF];
     Mom<T> me[NF + 1];
-    if (u) {
+    const T* uu = u ? u : b;   // u == null reads zeros, without a branch
 #pragma unroll
-        for (int s = 0; s < NF + 2; ++s) ur[s] = load_node(u, nx, ny, i, jf0 - 1 + s);
-    } else {
-#pragma unroll
-        for (int s = 0; s < NF + 2; ++s) ur[s] = V2<T>{T(0), T(0)};
-    }
+    for (int s = 0; s < NF + 2; ++s) ur[s] = load_node(uu, nx, ny, i, jf0 - 1 + s, u != nullptr);
 #pragma unroll
     for (int s = 0; s < NF; ++s) br[s] = load_node(b, nx, ny, i, jf0 + s);
 #pragma unroll
     for (int s = 0; s < NF + 1; ++s) me[s] = load_elem<T, FINE>(op, i, jf0 - 1 + s);
+    if constexpr (!FINE) {
+        __builtin_amdgcn_sched_barrier(0);   // latency-bound: one batch of loads
+        if constexpr (!CHECK) {
+            if (cst != 0) return;
+        }
+    }
     V2<T> f0, f1, f2, f3;
     V2<T> ur_lo = from_right(ur[0]), ur_hi = from_right(ur[1]);
     elem_force(me[0], mat, ur[0], ur_lo, ur_hi, ur[1], f0, f1, f2, f3);
@@ -527,9 +537,10 @@ __global__ __launch_bounds__(WG_THREADS) void k_restrict_pre(
         chk.ff = at(chk.ff, so.c);
         chk.conv_rw = at(chk.conv_rw, so.c);
     }
-    int cst = 0;
-    if (conv) cst = *conv;
-    if (cst != 0) return;
+    const int cst = load_state(conv);   // coarse levels test it after issuing their loads
+    if constexpr (FINE || CHECK) {
+        if (cst != 0) return;
+    }
     const int nx = op.nx, ny = op.ny;
     const int ncx = opc.nx, ncy = opc.ny;
     const TileInfo t = tile_info<R>(sw, ncy + 1);
@@ -555,6 +566,11 @@ __global__ __launch_bounds__(WG_THREADS) void k_restrict_pre(
     const int lane = lane_id();
     const int Ib = t.strip * CWOUT - CHL;      // coarse column of coarse lane 0
     V2<T>(*cb)[32] = cbuf[wave_id()];
+    // coarse lane c = lane & 31 <-> coarse column Ib + c (phase B)
+    const int cl = lane & 31;
+    const int ic = Ib + cl;
+    // phase B's coarse element rows j0-2 .. j0+R, loaded with phase A's data
+    Mom<T> mc[R + 3];
 
     // ---- phase A: fine lane l <-> fine column 2 Ib + l
     {
@@ -564,17 +580,21 @@ __global__ __launch_bounds__(WG_THREADS) void k_restrict_pre(
         const int jf0 = 2 * (t.j0 - 1) - 1;
         V2<T> ur[NF + 2], br[NF];
         Mom<T> me[NF + 1];
-        if (u) {
+        const T* uu = u ? u : b;   // u == null reads zeros, without a branch
 #pragma unroll
-            for (int s = 0; s < NF + 2; ++s) ur[s] = load_node(u, nx, ny, i, jf0 - 1 + s);
-        } else {
-#pragma unroll
-            for (int s = 0; s < NF + 2; ++s) ur[s] = V2<T>{T(0), T(0)};
-        }
+        for (int s = 0; s < NF + 2; ++s) ur[s] = load_node(uu, nx, ny, i, jf0 - 1 + s, u != nullptr);
 #pragma unroll
         for (int s = 0; s < NF; ++s) br[s] = load_node(b, nx, ny, i, jf0 + s);
 #pragma unroll
         for (int s = 0; s < NF + 1; ++s) me[s] = load_elem<T, FINE>(op, i, jf0 - 1 + s);
+#pragma unroll
+        for (int s = 0; s < R + 3; ++s) mc[s] = load_elem<T, false>(opc, ic, t.j0 - 2 + s);
+        if constexpr (!FINE) {
+            __builtin_amdgcn_sched_barrier(0);   // latency-bound: one batch of loads
+            if constexpr (!CHECK) {
+                if (cst != 0) return;
+            }
+        }
         V2<T> f0, f1, f2, f3;
         V2<T> ur_lo = from_right(ur[0]), ur_hi = from_right(ur[1]);
         elem_force(me[0], mat, ur[0], ur_lo, ur_hi, ur[1], f0, f1, f2, f3);
@@ -607,16 +627,13 @@ __global__ __launch_bounds__(WG_THREADS) void k_restrict_pre(
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
     // ---- phase B: lane c < 32 <-> coarse column Ib + c (lanes 32..63 mirror them, unused)
-    const int cl = lane & 31;
-    const int i = Ib + cl;
+    const int i = ic;
     const bool node_col = lane < 32 && i >= 0 && i <= ncx;
     const bool out_lane = lane >= CHL && lane < CHL + CWOUT && i <= ncx;
     V2<T> br[R + 2];
-    Mom<T> me[R + 3];
+    const Mom<T>* me = mc;
 #pragma unroll
     for (int s = 0; s < R + 2; ++s) br[s] = cb[s][cl];   // coarse rows j0-1 .. j0+R
-#pragma unroll
-    for (int s = 0; s < R + 3; ++s) me[s] = load_elem<T, false>(opc, i, t.j0 - 2 + s);
 #pragma unroll
     for (int s = 1; s <= R; ++s) {
         const int jj = t.j0 - 1 + s;
@@ -661,22 +678,29 @@ __global__ __launch_bounds__(WG_THREADS) void k_restrict_pre(
     }
 }
 
-// v(i, jj) += (P e_c)(i, jj) for the fine rows jj = j0-1 .. j0+R of one
-// lane (bilinear weights; nodes off the grid or on the clamped row get 0).
-// With j0 = 2h + PAR, the coarse rows needed are h-1 .. h-1+NC-1 and the
-// coarse row below/above fine row j0-1+s is at offset ((PAR-1+s)>>1)+1 /
-// ((PAR+s)>>1)+1, both compile-time constants.
-template <typename T, int R, int PAR>
-__device__ __forceinline__ void add_prolongation(V2<T>* vr, const T* __restrict__ ec, int ncx, int ncy, int I0,
-                                                 int I1, int j0, bool node_col, int ny) {
+// Coarse-correction rows for the prolongation onto fine rows j0-1 .. j0+R:
+// coarse rows (j0 >> 1) - 1 .. + NC - 1 at coarse columns I0 and I1 (the
+// same rows for either parity of j0).
+template <typename T, int R>
+__device__ __forceinline__ void load_prolongation(V2<T>* c0, V2<T>* c1, const T* __restrict__ ec, int ncx,
+                                                  int ncy, int I0, int I1, int j0) {
     constexpr int NC = R / 2 + 3;
-    const int Jb = ((j0 - PAR) >> 1) - 1;
-    V2<T> c0[NC], c1[NC];
+    const int Jb = (j0 >> 1) - 1;
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
         c0[k] = load_node(ec, ncx, ncy, I0, Jb + k);
         c1[k] = load_node(ec, ncx, ncy, I1, Jb + k);
     }
+}
+
+// v(i, jj) += (P e_c)(i, jj) for the fine rows jj = j0-1 .. j0+R of one
+// lane (bilinear weights; nodes off the grid or on the clamped row get 0),
+// from the coarse rows of load_prolongation.  With PAR = parity of j0 the
+// coarse row below/above fine row j0-1+s is at offset ((PAR-1+s)>>1)+1 /
+// ((PAR+s)>>1)+1, both compile-time constants.
+template <typename T, int R, int PAR>
+__device__ __forceinline__ void add_prolongation(V2<T>* vr, const V2<T>* c0, const V2<T>* c1, int j0,
+                                                 bool node_col, int ny) {
 #pragma unroll
     for (int s = 0; s < R + 2; ++s) {
         const int k0 = ((PAR - 1 + s) >> 1) + 1, k1 = ((PAR + s) >> 1) + 1;
@@ -710,9 +734,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_post(
     u_out = at(u_out, so.c);
     r64 = at(r64, so.c);
     zr_out = at(zr_out, so.c);
-    int cst = 0;
-    if (conv) cst = *conv;
-    if (cst != 0) return;
+    if (load_state(conv) != 0) return;
     const int nx = op.nx, ny = op.ny;
     const int ncx = nx / 2, ncy = ny / 2;
     const TileInfo t = tile_info<R>(sw, ny + 1);
@@ -729,19 +751,13 @@ __global__ __launch_bounds__(WG_THREADS) void k_post(
         V2<T> vr[R + 2], br[R];
         Mom<T> me[R + 1];
         V2<double> rr64[DOT ? R : 1];
-        if (u_in) {
+        constexpr int NC = PROLONG ? R / 2 + 3 : 1;
+        V2<T> c0[NC], c1[NC];
+        // all loads first, none inside a branch (u_in == null reads zeros)
+        const T* uin = u_in ? u_in : b;
 #pragma unroll
-            for (int s = 0; s < R + 2; ++s) vr[s] = load_node(u_in, nx, ny, i, t.j0 - 1 + s);
-        } else {
-#pragma unroll
-            for (int s = 0; s < R + 2; ++s) vr[s] = V2<T>{T(0), T(0)};
-        }
-        if constexpr (PROLONG) {
-            // the parity of j0 is uniform over the wave: one branch, then
-            // compile-time indices into the coarse rows held in registers
-            if (t.j0 & 1) add_prolongation<T, R, 1>(vr, ec, ncx, ncy, I0, I1, t.j0, node_col, ny);
-            else add_prolongation<T, R, 0>(vr, ec, ncx, ncy, I0, I1, t.j0, node_col, ny);
-        }
+        for (int s = 0; s < R + 2; ++s) vr[s] = load_node(uin, nx, ny, i, t.j0 - 1 + s, u_in != nullptr);
+        if constexpr (PROLONG) load_prolongation<T, R>(c0, c1, ec, ncx, ncy, I0, I1, t.j0);
 #pragma unroll
         for (int s = 0; s < R; ++s) br[s] = load_node(b, nx, ny, i, t.j0 + s);
         if constexpr (DOT) {
@@ -750,6 +766,13 @@ __global__ __launch_bounds__(WG_THREADS) void k_post(
         }
 #pragma unroll
         for (int s = 0; s < R + 1; ++s) me[s] = load_elem<T, FINE>(op, i, t.j0 - 1 + s);
+        if constexpr (!FINE) __builtin_amdgcn_sched_barrier(0);   // latency-bound: one batch of loads
+        if constexpr (PROLONG) {
+            // the parity of j0 is uniform over the wave: one branch, then
+            // compile-time indices into the coarse rows held in registers
+            if (t.j0 & 1) add_prolongation<T, R, 1>(vr, c0, c1, t.j0, node_col, ny);
+            else add_prolongation<T, R, 0>(vr, c0, c1, t.j0, node_col, ny);
+        }
 
         V2<T> f0, f1, f2, f3, d0, d1, d2, d3;
         V2<T> vr_lo = from_right(vr[0]), vr_hi = from_right(vr[1]);
@@ -808,9 +831,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_post2(
     u_out = at(u_out, so.c);
     r64 = at(r64, so.c);
     zr_out = at(zr_out, so.c);
-    int cst = 0;
-    if (conv) cst = *conv;
-    if (cst != 0) return;
+    if (load_state(conv) != 0) return;
     const int nx = op.nx, ny = op.ny;
     const int ncx = nx / 2, ncy = ny / 2;
     const TileInfo t = tile_info<R>(sw, ny + 1);
@@ -827,18 +848,14 @@ __global__ __launch_bounds__(WG_THREADS) void k_post2(
         V2<T> vr[R + 4], br[R + 2];
         Mom<T> me[R + 3];
         V2<double> rr64[DOT ? R : 1];
-        if (u_in) {
+        constexpr int NC = PROLONG ? (R + 2) / 2 + 3 : 1;
+        V2<T> c0[NC], c1[NC];
+        // all loads first, none inside a branch (u_in == null reads zeros)
+        const T* uin = u_in ? u_in : b;
 #pragma unroll
-            for (int s = 0; s < R + 4; ++s) vr[s] = load_node(u_in, nx, ny, i, t.j0 - 2 + s);
-        } else {
-#pragma unroll
-            for (int s = 0; s < R + 4; ++s) vr[s] = V2<T>{T(0), T(0)};
-        }
-        if constexpr (PROLONG) {
-            // fine rows j0-2 .. j0+R+1 = rows (j0-1)-1 .. (j0-1)+(R+2)
-            if (t.j0 & 1) add_prolongation<T, R + 2, 0>(vr, ec, ncx, ncy, I0, I1, t.j0 - 1, node_col, ny);
-            else add_prolongation<T, R + 2, 1>(vr, ec, ncx, ncy, I0, I1, t.j0 - 1, node_col, ny);
-        }
+        for (int s = 0; s < R + 4; ++s) vr[s] = load_node(uin, nx, ny, i, t.j0 - 2 + s, u_in != nullptr);
+        // fine rows j0-2 .. j0+R+1 = rows (j0-1)-1 .. (j0-1)+(R+2)
+        if constexpr (PROLONG) load_prolongation<T, R + 2>(c0, c1, ec, ncx, ncy, I0, I1, t.j0 - 1);
 #pragma unroll
         for (int s = 0; s < R + 2; ++s) br[s] = load_node(b, nx, ny, i, t.j0 - 1 + s);
         if constexpr (DOT) {
@@ -847,6 +864,11 @@ __global__ __launch_bounds__(WG_THREADS) void k_post2(
         }
 #pragma unroll
         for (int s = 0; s < R + 3; ++s) me[s] = load_elem<T, FINE>(op, i, t.j0 - 2 + s);
+        if constexpr (!FINE) __builtin_amdgcn_sched_barrier(0);   // latency-bound: one batch of loads
+        if constexpr (PROLONG) {
+            if (t.j0 & 1) add_prolongation<T, R + 2, 0>(vr, c0, c1, t.j0 - 1, node_col, ny);
+            else add_prolongation<T, R + 2, 1>(vr, c0, c1, t.j0 - 1, node_col, ny);
+        }
 
         V2<T> f0, f1, f2, f3, d0, d1, d2, d3;
         V2<T> vlo = from_right(vr[0]), vhi = from_right(vr[1]);
@@ -956,8 +978,9 @@ __global__ __launch_bounds__(WG_THREADS) void k_coarse_solve(const double* __res
                                                              int ld, int nx0, const T* __restrict__ b,
                                                              T* __restrict__ e, const int* conv, Batch bt) {
     const SysOff so = sys_off(bt);
-    conv = at(conv, so.c);
-    if (conv && *conv != 0) return;
+    // the state word, b and the first U * 64 entries of this wave's row of
+    // K0^-1 are all requested before the first wait
+    const int cst = load_state(at(conv, so.c));
     Ainv = at(Ainv, so.d);
     b = at(b, so.c);
     e = at(e, so.c);
@@ -966,10 +989,16 @@ __global__ __launch_bounds__(WG_THREADS) void k_coarse_solve(const double* __res
     // loads are issued in batches of U per thread before they are used, so a
     // wave waits for one memory round trip per batch, not one per element
     constexpr int U = 16;
+    const int row = blockIdx.x * WAVES_PER_WG + wave_id();
+    const double* a = Ainv + (size_t)min(row, n0 - 1) * ld;
+    double va[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) va[u] = a[min(lane_id() + u * WAVE, n0 - 1)];
     for (int base = 0; base < n0; base += U * WG_THREADS) {
         T v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) v[u] = b[off + min(base + (int)threadIdx.x + u * WG_THREADS, n0 - 1)];
+        if (base == 0 && cst != 0) return;   // uniform over the block (one system)
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int k = base + threadIdx.x + u * WG_THREADS;
@@ -980,15 +1009,18 @@ __global__ __launch_bounds__(WG_THREADS) void k_coarse_solve(const double* __res
         for (int k = threadIdx.x; k < off; k += WG_THREADS) e[k] = T(0);
     }
     __syncthreads();
-    const int row = blockIdx.x * WAVES_PER_WG + wave_id();
     if (row >= n0) return;
-    const double* a = Ainv + (size_t)row * ld;
     // s = sum over k = lane, lane + 64, ... of a[k] b[k], in that order
     double s = 0.0;
     for (int base = 0; base < n0; base += U * WAVE) {
         double v[U];
+        if (base == 0) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = a[min(base + lane_id() + u * WAVE, n0 - 1)];
+            for (int u = 0; u < U; ++u) v[u] = va[u];
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = a[min(base + lane_id() + u * WAVE, n0 - 1)];
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int k = base + lane_id() + u * WAVE;
