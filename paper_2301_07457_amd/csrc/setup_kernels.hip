@@ -474,20 +474,31 @@ __device__ __forceinline__ void st4(double* p, const double* v) {
     *reinterpret_cast<double2*>(p + 2) = make_double2(v[2], v[3]);
 }
 
-// Cholesky of the band by one workgroup per design: block step k factors
+// Cholesky of the band by one workgroup per design.  Block step k factors
 // the diagonal block (Dinv_k = L_kk^{-1}, also W's diagonal block), forms
 // the panel L[k+d][k] = A[k+d][k] Dinv_k^T (d = 1..NBW; stored to Lbuf) and
-// updates the trailing blocks A[i][j] -= L[i][k] L[j][k]^T, k < j <= i <=
-// k + NBW.  The active block rows live in LDS (block (i, i-d) in slot
-// [i % (NBW+2)][d]); block row k+NBW+1 is fetched from A by waves 1..3
-// while wave 0 factors the diagonal block of step k.
+// applies A[i][j] -= L[i][k] L[j][k]^T, k < j <= i <= k + NBW.  Only the
+// chain Dinv_k -> L[k+1][k] -> A[k+1][k+1] -> Dinv_{k+1} is serial; the
+// rest of step k (with NBW = 2: L[k+2][k] and the updates of A[k+2][k+1],
+// A[k+2][k+2]) runs on waves 1..3 during step k+1, while wave 0 factors
+// the next diagonal block.  Per step:
+//   A  wave 0: factor A[k][k]; waves 1..3: fetch block row k+2 from A and
+//      finish step k-1 (each forms L[k+1][k-1] whole in its own scratch
+//      block, then a share of the two updates of block row k+1);
+//   B  all waves: L[k+1][k] (one 16 x 16 quadrant each);
+//   C  all waves: A[k+1][k+1] -= L[k+1][k] L[k+1][k]^T.
+// Block rows k..k+2 live in LDS (block (i, i-d) in slot [i % 3][d]);
+// Dinv_k and L[k+1][k] alternate between two buffers by the parity of k.
 template <int NBW>
 __global__ __launch_bounds__(256) void k_band_chol(const double* __restrict__ A, int np, double* __restrict__ Dinv,
                                                    double* __restrict__ Lbuf, double* __restrict__ W,
                                                    int* __restrict__ status, long long ds) {
-    constexpr int NR = NBW + 2;
+    static_assert(NBW == 1 || NBW == 2, "band of one or two blocks");
+    constexpr int NR = 3;
     __shared__ __align__(16) double win[NR][NBW + 1][NB][BL];
-    __shared__ __align__(16) double Dk[NB][BL];
+    __shared__ __align__(16) double Dk[2][NB][BL];
+    __shared__ __align__(16) double Lc[2][NB][BL];
+    __shared__ __align__(16) double scr[NBW == 2 ? 3 : 1][NB][BL];
     __shared__ __align__(16) double gbuf[NB];
     __shared__ int not_spd;
     const long long off = (long long)blockIdx.y * ds;
@@ -501,37 +512,70 @@ __global__ __launch_bounds__(256) void k_band_chol(const double* __restrict__ A,
     int r, c4;
     blk_coords(r, c4);
     const Quad qd = quad_of_wave();
+    const int wave = threadIdx.x >> 6;
     auto gblk = [&](int bi, int bj) { return (size_t)(bi * NB + r) * np + bj * NB + c4; };
     auto gbase = [&](int bi, int bj) { return (size_t)(bi * NB) * np + bj * NB; };
-    for (int i = 0; i <= NBW && i < nblk; ++i)
+    for (int i = 0; i <= 1 && i < nblk; ++i)
         for (int d = 0; d <= NBW && d <= i; ++d) ld4(&win[i % NR][d][r][c4], A + gblk(i, i - d));
     for (int k = 0; k < nblk; ++k) {
-        const int rn = k + NBW + 1;
         __syncthreads();
-        if (threadIdx.x < WAVE) {
-            const bool ok = wave_potrf_inv<BL>(win[k % NR][0], Dk, gbuf);
+        // ---- A
+        if (wave == 0) {
+            const bool ok = wave_potrf_inv<BL>(win[k % NR][0], Dk[k & 1], gbuf);
             if (threadIdx.x == 0) not_spd = ok ? 0 : 1;
-        } else if (rn < nblk) {
-            // meanwhile waves 1..3 bring block row k + NBW + 1 into its slot
-            // (which held row k - 1, finished)
-            constexpr int TOT = (NBW + 1) * NB * NB / 2;   // double2 elements
-            constexpr int NT = 256 - WAVE;
-            constexpr int PER = (TOT + NT - 1) / NT;
-            const int t0 = threadIdx.x - WAVE;
-            double2 v[PER];
+        } else {
+            const int rn = k + 2;   // its slot held block row k - 1, finished
+            if (rn < nblk) {
+                constexpr int TOT = (NBW + 1) * NB * NB / 2;   // double2 elements
+                constexpr int NT = 256 - WAVE;
+                constexpr int PER = (TOT + NT - 1) / NT;
+                const int t0 = threadIdx.x - WAVE;
+                double2 v[PER];
 #pragma unroll
-            for (int u = 0; u < PER; ++u) {
-                const int e = min(t0 + u * NT, TOT - 1);
-                const int d = e / (NB * NB / 2), rem = e % (NB * NB / 2);
-                v[u] = *reinterpret_cast<const double2*>(A + (size_t)(rn * NB + rem / (NB / 2)) * np + (rn - d) * NB +
-                                                         (rem % (NB / 2)) * 2);
-            }
-#pragma unroll
-            for (int u = 0; u < PER; ++u) {
-                const int e = t0 + u * NT;
-                if (e < TOT) {
+                for (int u = 0; u < PER; ++u) {
+                    const int e = min(t0 + u * NT, TOT - 1);
                     const int d = e / (NB * NB / 2), rem = e % (NB * NB / 2);
-                    *reinterpret_cast<double2*>(&win[rn % NR][d][rem / (NB / 2)][(rem % (NB / 2)) * 2]) = v[u];
+                    v[u] = *reinterpret_cast<const double2*>(A + (size_t)(rn * NB + rem / (NB / 2)) * np +
+                                                             (rn - d) * NB + (rem % (NB / 2)) * 2);
+                }
+#pragma unroll
+                for (int u = 0; u < PER; ++u) {
+                    const int e = t0 + u * NT;
+                    if (e < TOT) {
+                        const int d = e / (NB * NB / 2), rem = e % (NB * NB / 2);
+                        *reinterpret_cast<double2*>(&win[rn % NR][d][rem / (NB / 2)][(rem % (NB / 2)) * 2]) = v[u];
+                    }
+                }
+            }
+            if constexpr (NBW == 2) {
+                if (k >= 1 && k + 1 < nblk) {
+                    // rest of step k-1: L[k+1][k-1] = A[k+1][k-1] Dinv_{k-1}^T (whole block per wave)
+                    double(*Lx)[BL] = scr[wave - 1];
+                    const double(*Ain)[BL] = win[(k + 1) % NR][2];
+                    const double(*Dp)[BL] = Dk[(k - 1) & 1];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const Quad qq{16 * (q >> 1), 16 * (q & 1), qd.li, qd.lk};
+                        const dbl4 lx = mfma_nt(Ain, Dp, qq, dbl4{0, 0, 0, 0});
+                        quad_store(Lx, qq, lx);
+                        if (wave == 1) quad_store_g(Lbuf + gbase(k + 1, k - 1), np, qq, lx);
+                    }
+                    wave_fence();
+                    // A[k+1][k] -= L[k+1][k-1] L[k][k-1]^T, A[k+1][k+1] -= L[k+1][k-1] L[k+1][k-1]^T:
+                    // eight quadrant products shared 3 / 3 / 2 by waves 1..3
+#pragma unroll
+                    for (int u = 0; u < 3; ++u) {
+                        const int job = (wave - 1) * 3 + u;
+                        if (job < 8) {
+                            const int q = job & 3;
+                            const Quad qq{16 * (q >> 1), 16 * (q & 1), qd.li, qd.lk};
+                            const bool diag = job >= 4;
+                            const double(*Lj)[BL] = diag ? Lx : Lc[(k - 1) & 1];
+                            double(*T)[BL] = win[(k + 1) % NR][diag ? 0 : 1];
+                            const dbl4 upd = mfma_nt(Lx, Lj, qq, dbl4{0, 0, 0, 0});
+                            quad_store(T, qq, quad_load(T, qq) - upd);
+                        }
+                    }
                 }
             }
         }
@@ -540,33 +584,21 @@ __global__ __launch_bounds__(256) void k_band_chol(const double* __restrict__ A,
             if (threadIdx.x == 0) *status = 1;
             return;
         }
-        st4(Dinv + (size_t)k * NB * NB + r * NB + c4, &Dk[r][c4]);
-        st4(W + gblk(k, k), &Dk[r][c4]);
-        // panel (this wave's quadrant of each block)
-        dbl4 Lp[NBW];
-#pragma unroll
-        for (int d = 1; d <= NBW; ++d) {
-            if (k + d >= nblk) break;
-            Lp[d - 1] = mfma_nt(win[(k + d) % NR][d], Dk, qd, dbl4{0, 0, 0, 0});
+        // ---- B
+        st4(Dinv + (size_t)k * NB * NB + r * NB + c4, &Dk[k & 1][r][c4]);
+        st4(W + gblk(k, k), &Dk[k & 1][r][c4]);
+        if (k + 1 >= nblk) break;
+        {
+            const dbl4 l1 = mfma_nt(win[(k + 1) % NR][1], Dk[k & 1], qd, dbl4{0, 0, 0, 0});
+            quad_store(Lc[k & 1], qd, l1);
+            quad_store_g(Lbuf + gbase(k + 1, k), np, qd, l1);
         }
         __syncthreads();
-#pragma unroll
-        for (int d = 1; d <= NBW; ++d) {
-            if (k + d >= nblk) break;
-            quad_store(win[(k + d) % NR][d], qd, Lp[d - 1]);
-            quad_store_g(Lbuf + gbase(k + d, k), np, qd, Lp[d - 1]);
-        }
-        __syncthreads();
-        // trailing update; the blocks written and the panel blocks read are disjoint
-#pragma unroll
-        for (int di = 1; di <= NBW; ++di) {
-            if (k + di >= nblk) break;
-#pragma unroll
-            for (int dj = 1; dj <= di; ++dj) {
-                const dbl4 upd = mfma_nt(win[(k + di) % NR][di], win[(k + dj) % NR][dj], qd, dbl4{0, 0, 0, 0});
-                double(*B)[BL] = win[(k + di) % NR][di - dj];
-                quad_store(B, qd, quad_load(B, qd) - upd);
-            }
+        // ---- C
+        {
+            double(*T)[BL] = win[(k + 1) % NR][0];
+            const dbl4 upd = mfma_nt(Lc[k & 1], Lc[k & 1], qd, dbl4{0, 0, 0, 0});
+            quad_store(T, qd, quad_load(T, qd) - upd);
         }
     }
 }

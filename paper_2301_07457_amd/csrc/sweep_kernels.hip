@@ -413,6 +413,67 @@ __global__ __launch_bounds__(WG_THREADS) void k_presmooth(
 // Geometry: H_L = 2, 60 fine columns (30 coarse) per strip; the chunk is in
 // coarse rows.
 // ===========================================================================
+// Residual restriction rc = P^T (b - K u) of one wave's tile: coarse rows
+// j0 .. j1-1 (j0 < j1) of strip `strip` (60 fine columns; even lanes own
+// the coarse columns).  store(I, J, v) receives every coarse node of the
+// tile (J = 0, the clamped row, with v = 0).  With `abort` the wave returns
+// once its loads are issued (a latency-bound caller overlaps the state
+// read with them).
+template <typename T, bool FINE, int R, typename Store>
+__device__ __forceinline__ void restrict_tile(const LevelOp<T>& op, const Mat<T>& mat, int strip, int j0, int j1,
+                                              const T* __restrict__ b, const T* __restrict__ u, bool abort,
+                                              Store store) {
+    const int nx = op.nx, ny = op.ny;
+    const int ncx = nx / 2;
+    constexpr int HL = 2, WOUT = 60;
+    const int lane = lane_id();
+    const int i = strip * WOUT - HL + lane;   // even lanes <-> even fine columns
+    const int I = i >> 1;
+    const bool out_lane = lane >= HL && lane < HL + WOUT && !(lane & 1) && I <= ncx;
+    const bool node_col = i >= 0 && i <= nx;
+    constexpr int NF = 2 * R + 1;              // fine rows jf0 .. jf0 + 2R
+    const int jf0 = 2 * j0 - 1;
+    V2<T> ur[NF + 2], br[NF];
+    Mom<T> me[NF + 1];
+    const T* uu = u ? u : b;   // u == null reads zeros, without a branch
+#pragma unroll
+    for (int s = 0; s < NF + 2; ++s) ur[s] = load_node(uu, nx, ny, i, jf0 - 1 + s, u != nullptr);
+#pragma unroll
+    for (int s = 0; s < NF; ++s) br[s] = load_node(b, nx, ny, i, jf0 + s);
+#pragma unroll
+    for (int s = 0; s < NF + 1; ++s) me[s] = load_elem<T, FINE>(op, i, jf0 - 1 + s);
+    if constexpr (!FINE) __builtin_amdgcn_sched_barrier(0);   // latency-bound: one batch of loads
+    if (abort) return;
+    V2<T> f0, f1, f2, f3;
+    V2<T> ur_lo = from_right(ur[0]), ur_hi = from_right(ur[1]);
+    elem_force(me[0], mat, ur[0], ur_lo, ur_hi, ur[1], f0, f1, f2, f3);
+    V2<T> carry = f3 + from_left(f2);
+    V2<T> h_m2{T(0), T(0)}, h_m1{T(0), T(0)};
+#pragma unroll
+    for (int s = 0; s < NF; ++s) {
+        const int j = jf0 + s;
+        ur_lo = ur_hi;
+        ur_hi = from_right(ur[s + 2]);
+        elem_force(me[s + 1], mat, ur[s + 1], ur_lo, ur_hi, ur[s + 2], f0, f1, f2, f3);
+        const V2<T> ku = carry + f0 + from_left(f1);
+        carry = f3 + from_left(f2);
+        const bool jok = node_col && j >= 1 && j <= ny;
+        const V2<T> rr{jok ? br[s].x - ku.x : T(0), jok ? br[s].y - ku.y : T(0)};
+        const V2<T> rl = from_left(rr), rrt = from_right(rr);
+        const V2<T> h{rr.x + T(0.5) * (rl.x + rrt.x), rr.y + T(0.5) * (rl.y + rrt.y)};
+        if ((s & 1) == 0 && s >= 2) {
+            const int J = (j - 1) >> 1;
+            if (out_lane && J < j1) {
+                V2<T> v{h_m1.x + T(0.5) * (h_m2.x + h.x), h_m1.y + T(0.5) * (h_m2.y + h.y)};
+                if (J == 0) v = V2<T>{T(0), T(0)};
+                store(I, J, v);
+            }
+        }
+        h_m2 = h_m1;
+        h_m1 = h;
+    }
+}
+
 template <typename T, bool FINE, bool CHECK, int R>
 __global__ __launch_bounds__(WG_THREADS) void k_restrict(
     LevelOp<T> op, Mat<T> mat, Sweep sw, const T* __restrict__ b, const T* __restrict__ u,
@@ -452,58 +513,9 @@ __global__ __launch_bounds__(WG_THREADS) void k_restrict(
             return;
         }
     }
-    constexpr int HL = 2, WOUT = 60;
-    const int lane = lane_id();
-    const int i = t.strip * WOUT - HL + lane;   // even lanes <-> even fine columns
-    const int I = i >> 1;
-    const bool out_lane = lane >= HL && lane < HL + WOUT && !(lane & 1) && I <= ncx;
-    const bool node_col = i >= 0 && i <= nx;
     if (t.j0 >= t.j1) return;
-    constexpr int NF = 2 * R + 1;              // fine rows jf0 .. jf0 + 2R
-    const int jf0 = 2 * t.j0 - 1;
-    V2<T> ur[NF + 2], br[NF];
-    Mom<T> me[NF + 1];
-    const T* uu = u ? u : b;   // u == null reads zeros, without a branch
-#pragma unroll
-    for (int s = 0; s < NF + 2; ++s) ur[s] = load_node(uu, nx, ny, i, jf0 - 1 + s, u != nullptr);
-#pragma unroll
-    for (int s = 0; s < NF; ++s) br[s] = load_node(b, nx, ny, i, jf0 + s);
-#pragma unroll
-    for (int s = 0; s < NF + 1; ++s) me[s] = load_elem<T, FINE>(op, i, jf0 - 1 + s);
-    if constexpr (!FINE) {
-        __builtin_amdgcn_sched_barrier(0);   // latency-bound: one batch of loads
-        if constexpr (!CHECK) {
-            if (cst != 0) return;
-        }
-    }
-    V2<T> f0, f1, f2, f3;
-    V2<T> ur_lo = from_right(ur[0]), ur_hi = from_right(ur[1]);
-    elem_force(me[0], mat, ur[0], ur_lo, ur_hi, ur[1], f0, f1, f2, f3);
-    V2<T> carry = f3 + from_left(f2);
-    V2<T> h_m2{T(0), T(0)}, h_m1{T(0), T(0)};
-#pragma unroll
-    for (int s = 0; s < NF; ++s) {
-        const int j = jf0 + s;
-        ur_lo = ur_hi;
-        ur_hi = from_right(ur[s + 2]);
-        elem_force(me[s + 1], mat, ur[s + 1], ur_lo, ur_hi, ur[s + 2], f0, f1, f2, f3);
-        const V2<T> ku = carry + f0 + from_left(f1);
-        carry = f3 + from_left(f2);
-        const bool jok = node_col && j >= 1 && j <= ny;
-        const V2<T> rr{jok ? br[s].x - ku.x : T(0), jok ? br[s].y - ku.y : T(0)};
-        const V2<T> rl = from_left(rr), rrt = from_right(rr);
-        const V2<T> h{rr.x + T(0.5) * (rl.x + rrt.x), rr.y + T(0.5) * (rl.y + rrt.y)};
-        if ((s & 1) == 0 && s >= 2) {
-            const int J = (j - 1) >> 1;
-            if (out_lane && J < t.j1) {
-                V2<T> v{h_m1.x + T(0.5) * (h_m2.x + h.x), h_m1.y + T(0.5) * (h_m2.y + h.y)};
-                if (J == 0) v = V2<T>{T(0), T(0)};
-                store_node(rc, ncx, I, J, v);
-            }
-        }
-        h_m2 = h_m1;
-        h_m1 = h;
-    }
+    restrict_tile<T, FINE, R>(op, mat, t.strip, t.j0, t.j1, b, u, !FINE && !CHECK && cst != 0,
+                              [&](int I, int J, const V2<T>& v) { store_node(rc, ncx, I, J, v); });
 }
 
 // ===========================================================================
