@@ -139,9 +139,13 @@ __device__ __forceinline__ void blk_load(double (*S)[NB + 1], const double* __re
 // X[r][:] -= L[r][k] X[k][:].  After 32 steps X = L^{-1} (Gauss-Jordan on
 // the factor).  With X held by columns, both updates read as
 // v[j] -= own * L[j][k] for j > k (own = L[r][k] on a row lane, X[k][c] on
-// a column lane), so one instruction stream serves both halves and only
-// column k of L travels, through LDS; the lanes of one wave access LDS in
-// order, so only the compiler is fenced between the write and the reads.
+// a column lane), so one instruction stream serves both halves.  Steps go
+// in pairs: every lane forms the 2 x 2 corner of steps k, k+1 from three
+// broadcast entries, applies both steps to its own columns k and k+1, and
+// the two new columns of L travel through LDS together; each element still
+// receives the updates of step k and then of step k+1, as a step at a time
+// would apply them.  The lanes of one wave access LDS in order, so only the
+// compiler is fenced between the write and the reads.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void wave_fence() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -165,11 +169,12 @@ __device__ __forceinline__ double rsqrt_nr(double d) {
 }
 
 // S: input block (LDS, lower triangle read); Li: receives L^{-1} (full
-// block, zero above the diagonal); buf: 32 doubles of LDS.  Call from one
-// whole wave.  Returns false (uniformly) if a pivot is not positive; Li is
-// then not meaningful.
+// block, zero above the diagonal); buf: 64 doubles of LDS, 16-byte
+// aligned.  Call from one whole wave.  Returns false (uniformly) if a pivot
+// is not positive; Li is then not meaningful.
 template <int LD>
 __device__ __forceinline__ bool wave_potrf_inv(const double (*S)[LD], double (*Li)[LD], double* buf) {
+    static_assert(NB % 2 == 0, "pivots go in pairs");
     const int lane = threadIdx.x & 63;
     const bool xl = lane >= 32;   // column lane of X
     const int q = lane & 31;      // row of S / column of X
@@ -181,23 +186,35 @@ __device__ __forceinline__ bool wave_potrf_inv(const double (*S)[LD], double (*L
     }
     bool ok = true;
 #pragma unroll
-    for (int k = 0; k < NB; ++k) {
-        const double d = readlane_d(v[k], k);
-        ok = ok && (d > 0.0);
-        const double inv = rsqrt_nr(d);
-        const double lk = (q > k) ? v[k] * inv : (q == k ? d * inv : 0.0);
-        v[k] = xl ? v[k] * inv : lk;
-        const double own = v[k];
-        if (!xl) buf[q] = lk;
+    for (int k = 0; k < NB; k += 2) {
+        const double d0 = readlane_d(v[k], k);
+        const double e = readlane_d(v[k], k + 1);
+        const double d1 = readlane_d(v[k + 1], k + 1);
+        const double inv0 = rsqrt_nr(d0);
+        const double l10 = e * inv0;                  // L[k+1][k]
+        const double d1p = fma(-l10, l10, d1);        // A[k+1][k+1] after step k
+        ok = ok && (d0 > 0.0) && (d1p > 0.0);
+        const double inv1 = rsqrt_nr(d1p);
+        // step k on this lane's columns k (scale) and k+1 (eliminate)
+        const double lq0 = (q > k) ? v[k] * inv0 : (q == k ? d0 * inv0 : 0.0);
+        const double own0 = xl ? v[k] * inv0 : lq0;
+        v[k] = own0;
+        v[k + 1] = fma(-own0, l10, v[k + 1]);
+        // step k + 1 on column k+1
+        const double lq1 = (q > k + 1) ? v[k + 1] * inv1 : (q == k + 1 ? d1p * inv1 : 0.0);
+        const double own1 = xl ? v[k + 1] * inv1 : lq1;
+        v[k + 1] = own1;
+        if (!xl) *reinterpret_cast<double2*>(&buf[2 * q]) = make_double2(lq0, lq1);
         wave_fence();
-        double bk[NB];
+        double2 bk[NB];
 #pragma unroll
-        for (int j = k + 1; j < NB; ++j) bk[j] = buf[j];
+        for (int j = k + 2; j < NB; ++j) bk[j] = *reinterpret_cast<const double2*>(&buf[2 * j]);
 #pragma unroll
-        for (int j = k + 1; j < NB; ++j) {
-            v[j] -= own * bk[j];
+        for (int j = k + 2; j < NB; ++j) {
+            v[j] = fma(-own0, bk[j].x, v[j]);
+            v[j] = fma(-own1, bk[j].y, v[j]);
             // materialise the update in this step (deferring it would keep
-            // every step's column live and spill)
+            // every step's columns live and spill)
             asm volatile("" : "+v"(v[j]));
         }
         wave_fence();
@@ -244,7 +261,8 @@ __global__ __launch_bounds__(256) void k_factor_step(double* __restrict__ A, int
                                                      double* __restrict__ Lbuf, double* __restrict__ W,
                                                      double* __restrict__ Sacc, double* __restrict__ Ainv,
                                                      int* __restrict__ status, long long ds) {
-    __shared__ double B0[NB][NB + 1], B1[NB][NB + 1], B2[NB][NB + 1], B3[NB][NB + 1], B4[NB][NB + 1];
+    __shared__ double B0[NB][NB + 1], B1[NB][NB + 1], B2[NB][NB + 1], B4[NB][NB + 1];
+    __shared__ __align__(16) double B3[NB][NB + 1];
     // design blockIdx.y; skipped unless flagged for factorisation and still positive definite
     const long long off = (long long)blockIdx.y * ds;
     status = at(status, off);
@@ -499,7 +517,7 @@ __global__ __launch_bounds__(256) void k_band_chol(const double* __restrict__ A,
     __shared__ __align__(16) double Dk[2][NB][BL];
     __shared__ __align__(16) double Lc[2][NB][BL];
     __shared__ __align__(16) double scr[NBW == 2 ? 3 : 1][NB][BL];
-    __shared__ __align__(16) double gbuf[NB];
+    __shared__ __align__(16) double gbuf[2 * NB];
     __shared__ int not_spd;
     const long long off = (long long)blockIdx.y * ds;
     status = at(status, off);
