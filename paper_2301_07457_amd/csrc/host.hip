@@ -866,8 +866,10 @@ int pcg_round(mtomg_ctx* c, const std::vector<int>& gsys0, double tol2, int max_
             LAUNCHCHK(c);
             return MTOMG_OK;
         };
-        // first batch: the previous solve's count (a design loop changes slowly), then small steps
-        int batch = c->last_iters > 0 ? c->last_iters + 1 : std::max(2, c->batch);
+        // first batch: the previous solve's count (a design loop changes slowly), then small steps.
+        // Iteration it forms r_{it+1} and tests it, so a solve of n iterations
+        // stops inside iteration n-1: a batch of exactly n launches nothing after it.
+        int batch = c->last_iters > 0 ? c->last_iters : std::max(2, c->batch);
         while (it < max_iter) {
             const int nb = std::min(batch, max_iter - it);
             rc = launch_iters(it, nb);
