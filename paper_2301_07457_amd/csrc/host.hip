@@ -506,6 +506,10 @@ T* pre_chain_extra(CycleCtx<T>& cx, int l, T* cur, const T* b, T* t0, T* t1) {
 // it only pays where launches, not bytes, dominate: up to 32768 coarse
 // nodes summed over the systems of the launch.
 constexpr long FUSE_MAX_COARSE_NODES = 32768;
+// Pairs of post-smoothers in one launch (k_post2_pair) re-form the rows of
+// level l that each wave's prolongation needs, so they pay up to a level
+// l+1 of this many nodes summed over the systems of the launch.
+constexpr long PAIR_MAX_NODES = 70000;
 template <typename T>
 bool restrict_down(CycleCtx<T>& cx, int l, const T* b, const T* u, bool check, const ConvCheck& chk) {
     Design& d = *cx.d;
@@ -554,10 +558,20 @@ void coarse_cycle(CycleCtx<T>& cx, int top, bool top_pre) {
     cx.begin(MTOMG_KERNEL_COARSE_SOLVE);
     launch_coarse_solve<T>(cx.st, d.Ainv, d.n0, d.np0, d.lev[0].nx, (const T*)c.b[0], (T*)c.e[0], cx.conv, cx.bt);
     cx.end(MTOMG_KERNEL_COARSE_SOLVE);
-    for (int l = 1; l <= top; ++l) {
+    for (int l = 1; l <= top;) {
+        // two sweeps per level and a small level l+1: one launch for levels l and l+1
+        if (d.n_post == 2 && l + 1 <= top && (long)d.lev[l + 1].nodes() * cx.bt.n <= PAIR_MAX_NODES) {
+            launch_post2_pair<T>(cx.st, level_op<T>(d, l), level_op<T>(d, l + 1), make_mat<T>(d, d.omega),
+                                 d.lev[l + 1].sw_post2, d.n_pre > 0 ? pre[l] : nullptr, (const T*)c.e[l - 1],
+                                 (const T*)c.b[l], d.n_pre > 0 ? pre[l + 1] : nullptr, (const T*)c.b[l + 1],
+                                 (T*)c.e[l + 1], cx.conv, cx.bt);
+            l += 2;
+            continue;
+        }
         T* other = pre[l] == (T*)c.u2[l] ? (T*)c.u4[l] : (T*)c.u2[l];
         post_chain<T>(cx, l, d.n_pre > 0 ? pre[l] : nullptr, (const T*)c.e[l - 1], (const T*)c.b[l], (T*)c.e[l],
                       other, pre[l], false, nullptr, nullptr);
+        ++l;
     }
 }
 

@@ -100,6 +100,14 @@ template <typename T>
 void launch_post2(hipStream_t st, bool fine, bool prolong, bool dot, LevelOp<T> op, Mat<T> mat, Sweep sw,
                   const T* u_in, const T* ec, const T* b, T* u_out, const double* r64, double* zr_out,
                   const int* conv, const Batch& bt = Batch{});
+// the paired post-smoother of coarse levels l (opc) and l+1 (opf) in one
+// launch: u_out = S^2(uf_in + P S^2(uc_in + P ee)) (S: one damped-Jacobi
+// sweep of the level; null iterates read zero); geometry: sw of k_post2 on
+// level l+1
+template <typename T>
+void launch_post2_pair(hipStream_t st, LevelOp<T> opc, LevelOp<T> opf, Mat<T> mat, Sweep sw, const T* uc_in,
+                       const T* ee, const T* bc, const T* uf_in, const T* bf, T* u_out, const int* conv,
+                       const Batch& bt = Batch{});
 template <typename T>
 void launch_apply(hipStream_t st, bool fine, bool diag, LevelOp<T> op, Mat<T> mat, Sweep sw, const T* u,
                   T* q);

@@ -822,6 +822,60 @@ __global__ __launch_bounds__(WG_THREADS) void k_post(
     }
 }
 
+// The two stages of the paired post-smoother on one wave's rows j0 ..
+// j0+RR-1 (lanes = node columns of the level): v rows j0-2 .. j0+RR+1 (the
+// prolonged iterate), b rows j0-1 .. j0+RR, element rows j0-2 .. j0+RR.
+// out(jr, u) receives row jr = j0 .. j0+RR-1 of u = S(S(v)) (S: one damped
+// Jacobi sweep); it is meaningful on lanes with both neighbours in the
+// wave, for grid nodes off the clamped row.
+template <typename T, int RR, typename Out>
+__device__ __forceinline__ void post2_stages(const Mat<T>& mat, const V2<T>* vr, const V2<T>* br, const Mom<T>* me,
+                                             int j0, bool node_col, int ny, Out out) {
+    V2<T> f0, f1, f2, f3, d0, d1, d2, d3;
+    V2<T> vlo = from_right(vr[0]), vhi = from_right(vr[1]);
+    elem_force(me[0], mat, vr[0], vlo, vhi, vr[1], f0, f1, f2, f3);
+    elem_diag(me[0], mat, d0, d1, d2, d3);
+    V2<T> fc1 = f3 + from_left(f2), dc1 = d3 + from_left(d2);
+    V2<T> fc2{T(0), T(0)};
+    V2<T> u1_prev{T(0), T(0)}, u1r_prev{T(0), T(0)}, wD_prev{T(0), T(0)};
+#pragma unroll
+    for (int s = 1; s < RR + 3; ++s) {
+        // stage 1: element row j0-2+s completes node row k = j0-2+s
+        const int k = j0 - 2 + s;
+        vlo = vhi;
+        vhi = from_right(vr[s + 1]);
+        elem_force(me[s], mat, vr[s], vlo, vhi, vr[s + 1], f0, f1, f2, f3);
+        elem_diag(me[s], mat, d0, d1, d2, d3);
+        const V2<T> F = fc1 + f0 + from_left(f1);
+        const V2<T> D = dc1 + d0 + from_left(d1);
+        fc1 = f3 + from_left(f2);
+        dc1 = d3 + from_left(d2);
+        const bool kok = node_col && k >= 1 && k <= ny;
+        const V2<T> bk = br[s - 1];
+        const V2<T> wD{mat.omega / D.x, mat.omega / D.y};   // w D^-1, reused by the second stage
+        const V2<T> u1{kok ? vr[s].x + (bk.x - F.x) * wD.x : T(0),
+                       kok ? vr[s].y + (bk.y - F.y) * wD.y : T(0)};
+        const V2<T> u1r = from_right(u1);
+        if (s >= 2) {
+            // stage 2: element row k-1 from u1 rows k-1, k completes node row k-1
+            V2<T> g0, g1, g2, g3;
+            elem_force(me[s - 1], mat, u1_prev, u1r_prev, u1r, u1, g0, g1, g2, g3);
+            const V2<T> G = fc2 + g0 + from_left(g1);
+            fc2 = g3 + from_left(g2);
+            if (s >= 3) {
+                const V2<T> bj = br[s - 2];
+                V2<T> uo;
+                uo.x = u1_prev.x + (bj.x - G.x) * wD_prev.x;
+                uo.y = u1_prev.y + (bj.y - G.y) * wD_prev.y;
+                out(k - 1, s - 3, uo);
+            }
+        }
+        u1_prev = u1;
+        u1r_prev = u1r;
+        wD_prev = wD;
+    }
+}
+
 // ===========================================================================
 // Two post-smoothing sweeps in one pass: u1 = v + w D^-1 (b - K v) and
 // u_out = u1 + w D^-1 (b - K u1), with v = u_in + P e_c when PROLONG.
@@ -882,60 +936,124 @@ __global__ __launch_bounds__(WG_THREADS) void k_post2(
             else add_prolongation<T, R + 2, 1>(vr, c0, c1, t.j0 - 1, node_col, ny);
         }
 
-        V2<T> f0, f1, f2, f3, d0, d1, d2, d3;
-        V2<T> vlo = from_right(vr[0]), vhi = from_right(vr[1]);
-        elem_force(me[0], mat, vr[0], vlo, vhi, vr[1], f0, f1, f2, f3);
-        elem_diag(me[0], mat, d0, d1, d2, d3);
-        V2<T> fc1 = f3 + from_left(f2), dc1 = d3 + from_left(d2);
-        V2<T> fc2{T(0), T(0)};
-        V2<T> u1_prev{T(0), T(0)}, u1r_prev{T(0), T(0)}, wD_prev{T(0), T(0)};
-#pragma unroll
-        for (int s = 1; s < R + 3; ++s) {
-            // stage 1: element row j0-2+s completes node row k = j0-2+s
-            const int k = t.j0 - 2 + s;
-            vlo = vhi;
-            vhi = from_right(vr[s + 1]);
-            elem_force(me[s], mat, vr[s], vlo, vhi, vr[s + 1], f0, f1, f2, f3);
-            elem_diag(me[s], mat, d0, d1, d2, d3);
-            const V2<T> F = fc1 + f0 + from_left(f1);
-            const V2<T> D = dc1 + d0 + from_left(d1);
-            fc1 = f3 + from_left(f2);
-            dc1 = d3 + from_left(d2);
-            const bool kok = node_col && k >= 1 && k <= ny;
-            const V2<T> bk = br[s - 1];
-            const V2<T> wD{mat.omega / D.x, mat.omega / D.y};   // w D^-1, reused by the second stage
-            const V2<T> u1{kok ? vr[s].x + (bk.x - F.x) * wD.x : T(0),
-                           kok ? vr[s].y + (bk.y - F.y) * wD.y : T(0)};
-            const V2<T> u1r = from_right(u1);
-            if (s >= 2) {
-                // stage 2: element row k-1 from u1 rows k-1, k completes node row k-1
-                V2<T> g0, g1, g2, g3;
-                elem_force(me[s - 1], mat, u1_prev, u1r_prev, u1r, u1, g0, g1, g2, g3);
-                const V2<T> G = fc2 + g0 + from_left(g1);
-                fc2 = g3 + from_left(g2);
-                const int jr = k - 1;
-                if (s >= 3 && out_lane && jr < t.j1) {
-                    if (jr >= 1) {
-                        const V2<T> bj = br[s - 2];
-                        V2<T> uo;
-                        uo.x = u1_prev.x + (bj.x - G.x) * wD_prev.x;
-                        uo.y = u1_prev.y + (bj.y - G.y) * wD_prev.y;
-                        store_node(u_out, nx, i, jr, uo);
-                        if constexpr (DOT) dot += (double)uo.x * rr64[s - 3].x + (double)uo.y * rr64[s - 3].y;
-                    } else {
-                        store_node(u_out, nx, i, jr, V2<T>{T(0), T(0)});
-                    }
+        post2_stages<T, R>(mat, vr, br, me, t.j0, node_col, ny, [&](int jr, int q, const V2<T>& uo) {
+            if (out_lane && jr < t.j1) {
+                if (jr >= 1) {
+                    store_node(u_out, nx, i, jr, uo);
+                    if constexpr (DOT) dot += (double)uo.x * rr64[q].x + (double)uo.y * rr64[q].y;
+                } else {
+                    store_node(u_out, nx, i, jr, V2<T>{T(0), T(0)});
                 }
             }
-            u1_prev = u1;
-            u1r_prev = u1r;
-            wD_prev = wD;
-        }
+        });
     }
     if constexpr (DOT) {
         const double s = block_sum(dot);
         if (threadIdx.x == 0) zr_out[t.tile] = s;
     }
+}
+
+// ===========================================================================
+// The paired post-smoother of two consecutive coarse levels in one launch:
+// level l gets u_l + P e_{l-1} followed by two sweeps (= e_l), and level
+// l+1 then u_{l+1} + P e_l followed by two sweeps, written to u_out.
+// Phase A (lanes = level-l columns): the four waves of a workgroup share
+// the NU level-l rows that the prolongation of their 4R level-(l+1) rows
+// reads, RA rows each; e_l passes through LDS and never reaches memory.
+// Phase B (lanes = level-(l+1) columns) is k_post2.  Both phases issue
+// their loads before the first wait.  A level-l node may be formed by
+// several workgroups, each in the operation order of k_post2, so the
+// result equals two k_post2 launches.
+// Geometry: that of k_post2 on level l+1 (60 output columns per strip).
+// ===========================================================================
+template <typename T, int R>
+__global__ __launch_bounds__(WG_THREADS) void k_post2_pair(
+    LevelOp<T> opc, LevelOp<T> opf, Mat<T> mat, Sweep sw, const T* __restrict__ uc_in, const T* __restrict__ ee,
+    const T* __restrict__ bc, const T* __restrict__ uf_in, const T* __restrict__ bf, T* __restrict__ u_out,
+    const int* conv, Batch bt) {
+    constexpr int NC = (R + 2) / 2 + 3;                     // level-l rows one wave's prolongation reads
+    constexpr int NU = ((3 * R - 1) >> 1) + NC + 1;         // their union over the workgroup
+    constexpr int RA = (NU + WAVES_PER_WG - 1) / WAVES_PER_WG;
+    __shared__ V2<T> ebuf[RA * WAVES_PER_WG][WAVE];
+    const SysOff so = sys_off(bt);
+    conv = at(conv, so.c);
+    opc.data = at(opc.data, so.d);
+    opf.data = at(opf.data, so.d);
+    uc_in = at(uc_in, so.c);
+    ee = at(ee, so.c);
+    bc = at(bc, so.c);
+    uf_in = at(uf_in, so.c);
+    bf = at(bf, so.c);
+    u_out = at(u_out, so.c);
+    if (load_state(conv) != 0) return;   // uniform over the workgroup (one system)
+    const int nxf = opf.nx, nyf = opf.ny, nxc = opc.nx, nyc = opc.ny;
+    const TileInfo t = tile_info<R>(sw, nyf + 1);
+    if (!t.block_ok) return;
+    constexpr int HL = 2, WOUT = 60;
+    const int lane = lane_id();
+    // phase B: level-(l+1) column i; phase A: level-l column ic (64 columns
+    // from the one left of this strip's, so phase B's I0, I1 = i >> 1,
+    // (i+1) >> 1 sit on lanes 2 .. 34 of phase A, all with both neighbours)
+    const int i = t.strip * WOUT - HL + lane;
+    const bool out_lane = lane >= HL && lane < HL + WOUT && i <= nxf;
+    const bool node_col = i >= 0 && i <= nxf;
+    const int icb = t.strip * (WOUT / 2) - 3;
+    const int ic = icb + lane;
+    const bool node_colc = ic >= 0 && ic <= nxc;
+    // the workgroup's first level-(l+1) row is even, so its level-l rows
+    // start at JU0 = j/2 - 2; this wave forms rows JA .. JA + RA - 1
+    const int jw0 = t.j0 - wave_id() * R;
+    const int JU0 = (jw0 >> 1) - 2;
+    const int JA = JU0 + wave_id() * RA;
+
+    // ---- all loads
+    V2<T> va[RA + 4], ba[RA + 2];
+    Mom<T> ma[RA + 3];
+    constexpr int NE = (RA + 2) / 2 + 3;
+    V2<T> e0[NE], e1[NE];
+    const T* ucin = uc_in ? uc_in : bc;
+#pragma unroll
+    for (int s = 0; s < RA + 4; ++s) va[s] = load_node(ucin, nxc, nyc, ic, JA - 2 + s, uc_in != nullptr);
+    load_prolongation<T, RA + 2>(e0, e1, ee, nxc / 2, nyc / 2, ic >> 1, (ic + 1) >> 1, JA - 1);
+#pragma unroll
+    for (int s = 0; s < RA + 2; ++s) ba[s] = load_node(bc, nxc, nyc, ic, JA - 1 + s);
+#pragma unroll
+    for (int s = 0; s < RA + 3; ++s) ma[s] = load_elem<T, false>(opc, ic, JA - 2 + s);
+    V2<T> vr[R + 4], br[R + 2];
+    Mom<T> me[R + 3];
+    const T* ufin = uf_in ? uf_in : bf;
+#pragma unroll
+    for (int s = 0; s < R + 4; ++s) vr[s] = load_node(ufin, nxf, nyf, i, t.j0 - 2 + s, uf_in != nullptr);
+#pragma unroll
+    for (int s = 0; s < R + 2; ++s) br[s] = load_node(bf, nxf, nyf, i, t.j0 - 1 + s);
+#pragma unroll
+    for (int s = 0; s < R + 3; ++s) me[s] = load_elem<T, false>(opf, i, t.j0 - 2 + s);
+    __builtin_amdgcn_sched_barrier(0);
+
+    // ---- phase A: e_l on rows JA .. JA + RA - 1, zero off the grid and on the clamped row
+    if ((JA - 1) & 1) add_prolongation<T, RA + 2, 1>(va, e0, e1, JA - 1, node_colc, nyc);
+    else add_prolongation<T, RA + 2, 0>(va, e0, e1, JA - 1, node_colc, nyc);
+    post2_stages<T, RA>(mat, va, ba, ma, JA, node_colc, nyc, [&](int jr, int q, const V2<T>& uo) {
+        const bool ok = node_colc && jr >= 1 && jr <= nyc;
+        ebuf[wave_id() * RA + q][lane] = ok ? uo : V2<T>{T(0), T(0)};
+    });
+    __syncthreads();
+    if (t.j0 >= t.j1) return;
+
+    // ---- phase B: k_post2 on level l+1 with e_l from LDS (rows Jb .. Jb + NC - 1)
+    const int Jb = ((t.j0 - 1) >> 1) - 1;
+    V2<T> c0[NC], c1[NC];
+    const int l0 = (i >> 1) - icb, l1 = ((i + 1) >> 1) - icb;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        c0[k] = ebuf[Jb - JU0 + k][l0];
+        c1[k] = ebuf[Jb - JU0 + k][l1];
+    }
+    if (t.j0 & 1) add_prolongation<T, R + 2, 0>(vr, c0, c1, t.j0 - 1, node_col, nyf);
+    else add_prolongation<T, R + 2, 1>(vr, c0, c1, t.j0 - 1, node_col, nyf);
+    post2_stages<T, R>(mat, vr, br, me, t.j0, node_col, nyf, [&](int jr, int q, const V2<T>& uo) {
+        if (out_lane && jr < t.j1) store_node(u_out, nxf, i, jr, jr >= 1 ? uo : V2<T>{T(0), T(0)});
+    });
 }
 
 // ===========================================================================
@@ -1175,6 +1293,14 @@ void launch_post2(hipStream_t st, bool fine, bool prolong, bool dot, LevelOp<T> 
 }
 
 template <typename T>
+void launch_post2_pair(hipStream_t st, LevelOp<T> opc, LevelOp<T> opf, Mat<T> mat, Sweep sw, const T* uc_in,
+                       const T* ee, const T* bc, const T* uf_in, const T* bf, T* u_out, const int* conv,
+                       const Batch& bt) {
+    MTOMG_ROWS_SWITCH(sw.rows, MTOMG_LAUNCH((k_post2_pair<T, RR>), grid_of(sw, bt), dim3(WG_THREADS), 0, st, opc, opf,
+                                            mat, sw, uc_in, ee, bc, uf_in, bf, u_out, conv, bt));
+}
+
+template <typename T>
 void launch_apply(hipStream_t st, bool fine, bool diag, LevelOp<T> op, Mat<T> mat, Sweep sw, const T* u,
                   T* q) {
 #define MTOMG_APP(F, D)                                                                              \
@@ -1209,7 +1335,9 @@ void launch_coarse_solve(hipStream_t st, const double* Ainv, int n0, int ld, int
                                   const Batch&);                                                   \
     template void launch_apply<T>(hipStream_t, bool, bool, LevelOp<T>, Mat<T>, Sweep, const T*, T*);  \
     template void launch_coarse_solve<T>(hipStream_t, const double*, int, int, int, const T*, T*, const int*, \
-                                         const Batch&);
+                                         const Batch&);                                            \
+    template void launch_post2_pair<T>(hipStream_t, LevelOp<T>, LevelOp<T>, Mat<T>, Sweep, const T*, const T*, \
+                                       const T*, const T*, const T*, T*, const int*, const Batch&);
 MTOMG_INST(float)
 MTOMG_INST(double)
 #undef MTOMG_INST
