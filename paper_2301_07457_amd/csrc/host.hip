@@ -67,6 +67,7 @@ struct CaseBufs {
 struct Design {
     bool has_grid = false, has_dens = false;
     bool needs_factor = false;   // densities set since the last factorisation
+    bool fac_launched = false;   // its factorisation is queued on the side stream, not yet finalised
     bool fac_failed = false;     // coarsest matrix not positive definite
     int nelx = 0, nely = 0, m = 0, levels = 0, n_pre = 2, n_post = 2, precision = 0, n_cases = 1;
     double nu = 0.3, E_min = 1e-9, penal = 3.0, omega = 0.6;
@@ -153,6 +154,7 @@ struct mtomg_ctx {
     hipStream_t cap_stream = nullptr;     // capture stream (default priority)
     hipStream_t side_stream = nullptr;    // coarsest factorisations during a solve (default priority)
     hipEvent_t ev_fac[2] = {nullptr, nullptr};   // [0] main -> side, [1] side -> main
+    bool fac_inflight = false;   // ev_fac[1] marks factorisations queued by set_densities
     int* host_chol = nullptr;             // pinned [cap][4]: coarsest-factor flags
     hipGraphExec_t pair_exec = nullptr;   // two PCG iterations (parities 1, 0) of the groups below
     double pair_tol2 = -1.0;
@@ -701,14 +703,21 @@ double model_bytes(const Design& d) {
 // positive-definiteness flags are copied to host_chol (row = design slot of
 // the group's systems) and read by factor_finalize after a synchronisation.
 // Returns whether anything was launched in *ran_any.
-int factor_launch(mtomg_ctx* c, hipStream_t st, bool* ran_any) {
+int factor_launch(mtomg_ctx* c, hipStream_t st, bool* ran_any, int only_group = -1) {
     *ran_any = false;
     int sys0 = 0;
     for (size_t gi = 0; gi < c->groups.size(); ++gi) {
         Group& g = c->groups[gi];
         bool ran = false;
-        for (int di : g.designs) ran = ran || (c->d[di].has_dens && c->d[di].needs_factor);
-        if (ran) {
+        for (int di : g.designs) {
+            const Design& d = c->d[di];
+            ran = ran || (d.has_dens && d.needs_factor && !d.fac_launched);
+        }
+        if (ran && (only_group < 0 || only_group == (int)gi)) {
+            for (int di : g.designs) {
+                Design& d = c->d[di];
+                if (d.has_dens && d.needs_factor) d.fac_launched = true;
+            }
             *ran_any = true;
             Design& d0 = c->d[g.designs[0]];
             const int nd = (int)g.designs.size();
@@ -734,19 +743,20 @@ int factor_finalize(mtomg_ctx* c) {
     for (size_t gi = 0; gi < c->groups.size(); ++gi) {
         Group& g = c->groups[gi];
         bool ran = false;
-        for (int di : g.designs) ran = ran || (c->d[di].has_dens && c->d[di].needs_factor);
+        for (int di : g.designs) ran = ran || (c->d[di].has_dens && c->d[di].needs_factor && c->d[di].fac_launched);
         if (ran) {
             float fac_ms = 0.f;
             Design& d0 = c->d[g.designs[0]];
             HIPCHK(c, hipEventElapsedTime(&fac_ms, d0.fev[0], d0.fev[1]));
             for (size_t k = 0; k < g.designs.size(); ++k) {
                 Design& d = c->d[g.designs[k]];
-                if (!(d.has_dens && d.needs_factor)) continue;
+                if (!(d.has_dens && d.needs_factor && d.fac_launched)) continue;
                 float ms = 0.f;
                 HIPCHK(c, hipEventElapsedTime(&ms, d.ev[0], d.ev[1]));
                 d.t_setup_ms = ms + fac_ms;
                 d.fac_failed = c->host_chol[4 * (sys0 + k)] != 0;
                 d.needs_factor = false;
+                d.fac_launched = false;
             }
         }
         sys0 += g.n_sys;
@@ -759,9 +769,17 @@ int factor_pending(mtomg_ctx* c) {
     bool ran = false;
     int rc = factor_launch(c, c->stream, &ran);
     if (rc) return rc;
-    if (!ran) return MTOMG_OK;
+    if (!ran && !c->fac_inflight) return MTOMG_OK;
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->side_stream));
+    c->fac_inflight = false;
     return factor_finalize(c);
+}
+
+// Queued factorisations are dropped (the layout or the densities change).
+void forget_factorisations(mtomg_ctx* c) {
+    c->fac_inflight = false;
+    for (Design& d : c->d) d.fac_launched = false;
 }
 
 template <typename T>
@@ -935,15 +953,18 @@ int solve_all(mtomg_ctx* c, double rel_tol, int max_iter, int warm, mtomg_stats*
     // Coarsest factorisations of designs with new densities run on the side
     // stream, overlapped with the start of the first run (initial residual
     // and the descent of the first V-cycle); only its coarse solve waits.
-    bool fac_ran = false;
-    hipEvent_t wait_fac = nullptr;
+    // (set_densities may have queued some already: then ev_fac[1] marks them)
+    bool fac_ran = c->fac_inflight;
+    hipEvent_t wait_fac = fac_ran ? c->ev_fac[1] : nullptr;
     HIPCHK(c, hipEventRecord(c->ev_fac[0], c->stream));
     HIPCHK(c, hipStreamWaitEvent(c->side_stream, c->ev_fac[0], 0));
-    int rc = factor_launch(c, c->side_stream, &fac_ran);
+    bool launched = false;
+    int rc = factor_launch(c, c->side_stream, &launched);
     if (rc) return rc;
-    if (fac_ran) {
+    if (launched) {
         HIPCHK(c, hipEventRecord(c->ev_fac[1], c->side_stream));
         wait_fac = c->ev_fac[1];
+        fac_ran = true;
     }
     const double tol2 = rel_tol * rel_tol;
     std::vector<int> gsys0(c->groups.size(), 0), sys_design;
@@ -976,6 +997,7 @@ int solve_all(mtomg_ctx* c, double rel_tol, int max_iter, int warm, mtomg_stats*
         total_ms += ms;
         if (round == 0 && fac_ran) {
             HIPCHK(c, hipStreamSynchronize(c->side_stream));
+            c->fac_inflight = false;
             rc = factor_finalize(c);
             if (rc) return rc;
         }
@@ -1156,6 +1178,7 @@ int mtomg_set_grid(mtomg_ctx* c, int design, int nelx, int nely, double nu, int 
     c->ws_owned = false;
     c->laid_out = false;
     for (Design& o : c->d) o.has_dens = false;
+    forget_factorisations(c);
     return MTOMG_OK;
 }
 
@@ -1178,6 +1201,7 @@ int mtomg_set_workspace(mtomg_ctx* c, void* dev, size_t bytes) {
     c->ws_owned = false;
     c->laid_out = false;
     for (Design& o : c->d) o.has_dens = false;
+    forget_factorisations(c);
     return ensure_workspace(c);
 }
 
@@ -1189,6 +1213,9 @@ int mtomg_set_densities(mtomg_ctx* c, int design, const double* x) {
     if (rc) return rc;
     Design& d = c->d[design];
     hipStream_t st = c->stream;
+    // a factorisation still queued on the side stream reads this design's matrix
+    if (c->fac_inflight) HIPCHK(c, hipStreamWaitEvent(st, c->ev_fac[1], 0));
+    d.fac_launched = false;   // new densities supersede a queued factorisation
     HIPCHK(c, hipEventRecord(d.ev[0], st));
     const int f = d.fine();
     LevelBufs& Lf = d.lev[f];
@@ -1209,6 +1236,21 @@ int mtomg_set_densities(mtomg_ctx* c, int design, const double* x) {
     d.has_dens = true;
     d.needs_factor = true;
     d.fac_failed = false;
+    // A design alone in its group starts its coarsest factorisation now, on
+    // the side stream: it then runs while the host returns and calls the
+    // solve.  Designs of larger groups wait for the solve, which factors a
+    // whole group per launch.
+    if (c->groups[d.group].designs.size() == 1) {
+        HIPCHK(c, hipEventRecord(c->ev_fac[0], st));
+        HIPCHK(c, hipStreamWaitEvent(c->side_stream, c->ev_fac[0], 0));
+        bool ran = false;
+        rc = factor_launch(c, c->side_stream, &ran, d.group);
+        if (rc) return rc;
+        if (ran) {
+            HIPCHK(c, hipEventRecord(c->ev_fac[1], c->side_stream));
+            c->fac_inflight = true;
+        }
+    }
     return MTOMG_OK;
 }
 
@@ -1279,12 +1321,24 @@ int mtomg_set_option(mtomg_ctx* c, int option, int value) {
             // partial-sum buffers are sized by the tile counts: re-lay out the workspace
             c->laid_out = false;
             for (Design& d : c->d) d.has_dens = false;
+            forget_factorisations(c);
             if (c->ws_owned && c->ws) { hipFree(c->ws); c->ws = nullptr; c->ws_owned = false; c->ws_bytes = 0; }
             return MTOMG_OK;
         }
-        case MTOMG_OPT_DENSE_FACTOR:
+        case MTOMG_OPT_DENSE_FACTOR: {
             c->dense_factor = value != 0;
+            // factorisations queued by set_densities run again with the new choice
+            HIPCHK(c, hipStreamSynchronize(c->side_stream));
+            c->fac_inflight = false;
+            for (Design& d : c->d) {
+                if (!(d.has_dens && d.needs_factor && d.fac_launched)) continue;
+                d.fac_launched = false;
+                launch_fill<int>(c->stream, d.chol_status, 1, 0);
+                launch_fill<int>(c->stream, d.chol_status + 1, 1, 1);
+            }
+            LAUNCHCHK(c);
             return MTOMG_OK;
+        }
         case MTOMG_OPT_BATCH:
             if (value < 1 || value > 1000) return fail(c, MTOMG_BAD_INPUT, "batch must be in [1, 1000]");
             c->batch = value;

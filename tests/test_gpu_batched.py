@@ -161,3 +161,37 @@ def test_non_spd_design_reports_breakdown_and_spares_the_group():
     s.set_densities(0, torch.from_numpy(a.x))
     stats = s.solve(1e-8, 1000)
     assert all(st["status"] == 0 for st in stats)
+
+
+def test_non_spd_single_design_reports_breakdown():
+    """A design alone in its group starts its factorisation inside
+    set_densities; a non-positive-definite coarsest matrix is still reported
+    as BREAKDOWN for each load case, and valid densities clear it."""
+    from paper_2301_07457_amd import PCGMGSolver
+    a = make(64, 64, 3, 2301)
+    s = PCGMGSolver(max_designs=1)
+    add(s, 0, a, "fp32mg")
+    s.set_densities(0, torch.from_numpy(-np.ones_like(a.x)))
+    stats = s.solve(1e-8, 200)
+    assert [st["status"] for st in stats] == [-3] * 4
+    s.set_densities(0, torch.from_numpy(a.x))
+    stats = s.solve(1e-8, 1000)
+    assert all(st["status"] == 0 and st["relres_true"] <= 1e-8 for st in stats)
+    ref = solve.solve_direct(a.nelx, a.nely, a.x, a.E_phase, a.E_min, a.penal, a.nu, a.F)
+    assert rel(s.U(0).cpu().numpy(), ref.U) <= 1e-6
+
+
+def test_densities_set_twice_before_a_solve():
+    """Densities replaced before the solve (the first factorisation may still
+    be queued): the solve uses the second set."""
+    from paper_2301_07457_amd import PCGMGSolver
+    a = make(64, 64, 3, 2401)
+    b = make(64, 64, 3, 2402)
+    s = PCGMGSolver(max_designs=1)
+    add(s, 0, a, "fp64")
+    s.set_densities(0, torch.from_numpy(a.x))
+    s.set_densities(0, torch.from_numpy(b.x))
+    stats = s.solve(1e-8, 1000)
+    assert all(st["status"] == 0 for st in stats)
+    ref = solve.solve_direct(b.nelx, b.nely, b.x, b.E_phase, b.E_min, b.penal, b.nu, b.F)
+    assert rel(s.U(0).cpu().numpy(), ref.U) <= 1e-6
