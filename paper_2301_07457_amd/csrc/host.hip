@@ -870,6 +870,32 @@ int pcg_round(mtomg_ctx* c, const std::vector<int>& gsys0, double tol2, int max_
         HIPCHK(c, hipStreamSynchronize(st));
         return MTOMG_OK;
     };
+    // after `it` iterations: the pending x update (mode 3 or 4 of k_cg_apply;
+    // none for mode < 0), the true residual f - K u and the per-system sums,
+    // then one synchronisation for the state words and sums
+    auto finish = [&](int it_done, int mode) -> int {
+        if (mode >= 0 && it_done > 0) run_iteration(c, act, st, it_done, mode, tol2, &c->prof);
+        for (int gi : act) {
+            Group& g = c->groups[gi];
+            Design& d = c->d[g.designs[0]];
+            CaseBufs& cb = d.cases[0];
+            const LevelBufs& L = d.lev[d.fine()];
+            const Batch bt = g.batch();
+            launch_residual(st, level_op<double>(d, d.fine()), make_mat<double>(d, d.omega), L.sw_apply, nullptr,
+                            nullptr, 1, nullptr, cb.trr, nullptr, cb.state, bt);
+            launch_solve_sums(st, cb.ff, L.sw_apply.n_tiles, cb.rr[0], cb.rr[1], L.sw_apply.n_tiles,
+                              L.sw_pre.n_tiles, cb.trr, cb.state, cb.sums, bt);
+        }
+        LAUNCHCHK(c);
+        HIPCHK(c, hipEventRecord(c->ev_solve[1], st));
+        for (int gi : act) {
+            Group& g = c->groups[gi];
+            HIPCHK(c, hipMemcpy2DAsync(c->host_sums + 4 * gsys0[gi], 4 * sizeof(double),
+                                       c->d[g.designs[0]].cases[0].sums, (size_t)g.cs, 3 * sizeof(double), g.n_sys,
+                                       hipMemcpyDeviceToHost, st));
+        }
+        return read_states();
+    };
     int rc = MTOMG_OK;
     int it = 0;
     if (!act.empty()) {
@@ -907,7 +933,11 @@ int pcg_round(mtomg_ctx* c, const std::vector<int>& gsys0, double tol2, int max_
             rc = launch_iters(it, nb);
             if (rc) return rc;
             it += nb;
-            rc = read_states();
+            // Finish every system that has converged (at the iteration limit
+            // every system) before the host looks: its pending x update, true
+            // residual and sums, and its state word 1 -> 2.  Systems still
+            // running are left alone and continue in the next batch.
+            rc = finish(it, it >= max_iter ? 3 : 4);
             if (rc) return rc;
             bool running = false;
             for (int gi : act)
@@ -915,29 +945,13 @@ int pcg_round(mtomg_ctx* c, const std::vector<int>& gsys0, double tol2, int max_
             if (!running) break;
             batch = std::max(2, std::min(it / 2, 16));
         }
-        // the pending x update of systems that converged in the last iteration or hit max_iter
-        if (it > 0) run_iteration(c, act, st, it, 3, tol2, &c->prof);
-        for (int gi : act) {
-            Group& g = c->groups[gi];
-            Design& d = c->d[g.designs[0]];
-            CaseBufs& cb = d.cases[0];
-            const LevelBufs& L = d.lev[d.fine()];
-            const Batch bt = g.batch();
-            launch_residual(st, level_op<double>(d, d.fine()), make_mat<double>(d, d.omega), L.sw_apply, nullptr,
-                            nullptr, 1, nullptr, cb.trr, nullptr, cb.state, bt);
-            launch_solve_sums(st, cb.ff, L.sw_apply.n_tiles, cb.rr[0], cb.rr[1], L.sw_apply.n_tiles,
-                              L.sw_pre.n_tiles, cb.trr, cb.state, cb.sums, bt);
-        }
         LAUNCHCHK(c);
     }
-    HIPCHK(c, hipEventRecord(c->ev_solve[1], st));
-    for (int gi : act) {
-        Group& g = c->groups[gi];
-        HIPCHK(c, hipMemcpy2DAsync(c->host_sums + 4 * gsys0[gi], 4 * sizeof(double), c->d[g.designs[0]].cases[0].sums,
-                                   (size_t)g.cs, 3 * sizeof(double), g.n_sys, hipMemcpyDeviceToHost, st));
+    if (it == 0) {
+        // no iteration ran (max_iter = 0 or no active system): sums of the start
+        rc = finish(0, -1);
+        if (rc) return rc;
     }
-    rc = read_states();
-    if (rc) return rc;
     HIPCHK(c, hipEventElapsedTime(ms, c->ev_solve[0], c->ev_solve[1]));
     return MTOMG_OK;
 }

@@ -159,8 +159,10 @@ struct SumJob {
 };
 void launch_sums(hipStream_t st, SumJob job, double* out);
 // Per system after a solve: out[0] = ||f||^2, out[1] = recursive ||r||^2
-// (from rr[iters & 1], iters = state[1]), out[2] = true ||r||^2.
+// (from rr[iters & 1], iters = state[1]), out[2] = true ||r||^2; a state
+// word 1 (converged, its final x update applied before this launch)
+// becomes 2 (done).
 void launch_solve_sums(hipStream_t st, const double* ff, int n_ff, const double* rr0, const double* rr1,
-                       int n_rr0, int n_rr, const double* trr, const int* state, double* out, const Batch& bt);
+                       int n_rr0, int n_rr, const double* trr, int* state, double* out, const Batch& bt);
 
 }  // namespace mtomg

@@ -798,10 +798,11 @@ __global__ __launch_bounds__(WG_THREADS) void k_solve_sums(const double* __restr
                                                            const double* __restrict__ rr0,
                                                            const double* __restrict__ rr1, int n_rr0, int n_rr,
                                                            const double* __restrict__ trr,
-                                                           const int* __restrict__ state, double* __restrict__ out,
+                                                           int* __restrict__ state, double* __restrict__ out,
                                                            Batch bt) {
     const SysOff so = sys_off(bt);
     state = at(state, so.c);
+    const int st0 = state[0];
     const int iters = state[1];
     const double* rr = at(iters & 1 ? rr1 : rr0, so.c);
     const double* ps[3] = {at(ff, so.c), rr, at(trr, so.c)};
@@ -814,6 +815,8 @@ __global__ __launch_bounds__(WG_THREADS) void k_solve_sums(const double* __restr
         o[0] = a;
         o[1] = b;
         o[2] = c;
+        // converged with its last x update applied (mode 4 or 3 ran before): done
+        if (st0 == 1) state[0] = 2;
     }
 }
 
@@ -880,7 +883,7 @@ void launch_fill_strided(hipStream_t st, int* p, long long stride_bytes, int n, 
 }
 
 void launch_solve_sums(hipStream_t st, const double* ff, int n_ff, const double* rr0, const double* rr1,
-                       int n_rr0, int n_rr, const double* trr, const int* state, double* out, const Batch& bt) {
+                       int n_rr0, int n_rr, const double* trr, int* state, double* out, const Batch& bt) {
     hipLaunchKernelGGL(k_solve_sums, dim3(1, bt.n), dim3(WG_THREADS), 0, st, ff, n_ff, rr0, rr1, n_rr0, n_rr, trr,
                        state, out, bt);
 }

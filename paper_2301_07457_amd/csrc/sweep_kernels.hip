@@ -44,7 +44,8 @@ __device__ __forceinline__ TileInfo tile_info(const Sweep& s, int n_rows) {
 // mode 0: iteration i >= 1; mode 1: first iteration (beta = 0, no x update);
 // mode 2: only the pending x update (after the last iteration); mode 3: the
 // same for the systems whose state is 0 (iteration limit) or 1 (converged,
-// update pending), nothing for the others.
+// update pending), nothing for the others; mode 4: the same for state 1
+// only (systems still running are left to continue).
 // Geometry: H_L = 1, H_R = 1, 62 output columns per strip.
 // Every kernel first issues all loads of its rows (masked, branch-free),
 // then marches through the rows from registers.
@@ -69,9 +70,10 @@ __global__ __launch_bounds__(WG_THREADS) void k_cg_apply(
     pq_prev = at(pq_prev, so.c);
     pq_out = at(pq_out, so.c);
     const int cst = *conv;
-    const bool final_only = (mode == 2) || (mode == 3) || (mode == 0 && cst == 1);
+    const bool final_only = (mode >= 2) || (mode == 0 && cst == 1);
     if (mode == 1 && cst != 0) return;
     if ((mode == 0 || mode == 3) && cst != 0 && cst != 1) return;
+    if (mode == 4 && cst != 1) return;
     const int nx = op.nx, ny = op.ny;
     const TileInfo t = tile_info<R>(sw, ny + 1);
     if (!t.block_ok) return;
