@@ -119,10 +119,12 @@ int mtomg_set_workspace(mtomg_ctx *ctx, void *dev, size_t bytes);
 /* Load phase densities for a design and build its preconditioner:
  * element moduli by Eq. (5), Galerkin coarse operators for every level and
  * the assembled coarsest matrix.  Its Cholesky factor (Algorithm 3), turned
- * into an explicit inverse, is computed by the next solve, together with
- * those of the other designs of the same shape whose densities changed (one
- * launch sequence for all of them), on a private stream beside the first
- * V-cycle, whose coarse solve waits for it.
+ * into an explicit inverse, is computed on a private stream of the context:
+ * for a design alone in its group (the designs sharing its shape, see
+ * mtomg_solve) it starts at once, after the assembly; otherwise the next
+ * solve starts it, together with those of the other designs of the group
+ * whose densities changed (one launch sequence for all of them).  Either way
+ * the first coarse solve of the next solve waits for it.
  * x: device [nely][nelx][m] FP64 in [0, 1], read in stream order (keep it
  * alive until the work is done).  Asynchronous; a coarsest matrix that is
  * not positive definite is reported by the next solve (status BREAKDOWN
