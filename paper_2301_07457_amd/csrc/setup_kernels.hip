@@ -195,16 +195,16 @@ __device__ __forceinline__ bool wave_potrf_inv(const double (*S)[LD], double (*L
         const double d1p = fma(-l10, l10, d1);        // A[k+1][k+1] after step k
         ok = ok && (d0 > 0.0) && (d1p > 0.0);
         const double inv1 = rsqrt_nr(d1p);
-        // step k on this lane's columns k (scale) and k+1 (eliminate)
-        const double lq0 = (q > k) ? v[k] * inv0 : (q == k ? d0 * inv0 : 0.0);
-        const double own0 = xl ? v[k] * inv0 : lq0;
+        // step k on this lane's columns k (scale) and k+1 (eliminate): L[q][k]
+        // on a row lane (zero above the diagonal; on lane k, v[k] is d0 itself,
+        // so the product is sqrt(d0)), X[k][c] on a column lane
+        const double own0 = (xl || q >= k) ? v[k] * inv0 : 0.0;
         v[k] = own0;
         v[k + 1] = fma(-own0, l10, v[k + 1]);
-        // step k + 1 on column k+1
-        const double lq1 = (q > k + 1) ? v[k + 1] * inv1 : (q == k + 1 ? d1p * inv1 : 0.0);
-        const double own1 = xl ? v[k + 1] * inv1 : lq1;
+        // step k + 1 on column k+1 (on lane k+1, v[k+1] is now d1p)
+        const double own1 = (xl || q >= k + 1) ? v[k + 1] * inv1 : 0.0;
         v[k + 1] = own1;
-        if (!xl) *reinterpret_cast<double2*>(&buf[2 * q]) = make_double2(lq0, lq1);
+        if (!xl) *reinterpret_cast<double2*>(&buf[2 * q]) = make_double2(own0, own1);
         wave_fence();
         double2 bk[NB];
 #pragma unroll
