@@ -1234,16 +1234,34 @@ int mtomg_set_densities(mtomg_ctx* c, int design, const double* x) {
     const int f = d.fine();
     LevelBufs& Lf = d.lev[f];
     launch_interp(st, x, phases_of(d), Lf.nx * Lf.ny, Lf.op64, d.mixed() ? Lf.op32 : nullptr);
-    for (int l = f - 1; l >= 0; --l) {
-        LevelBufs& L = d.lev[l];
+    // coarse moments, up to five levels per launch (tiles of 16 x 16 elements
+    // or the largest power of two dividing the level; 1 falls back to one
+    // launch per level)
+    for (int l = f - 1; l >= 0;) {
         LevelBufs& P = d.lev[l + 1];
-        if (l + 1 == f) launch_moments_from_fine(st, P.op64, P.nx, P.ny, L.op64, d.mixed() ? L.op32 : nullptr);
-        else launch_moments_coarsen(st, P.op64, P.nx, P.ny, L.op64, d.mixed() ? L.op32 : nullptr);
+        LevelBufs& L = d.lev[l];
+        int T = 16;
+        while (T > 1 && (L.nx % T || L.ny % T)) T >>= 1;
+        if (T == 1) {
+            if (l + 1 == f) launch_moments_from_fine(st, P.op64, P.nx, P.ny, L.op64, d.mixed() ? L.op32 : nullptr);
+            else launch_moments_coarsen(st, P.op64, P.nx, P.ny, L.op64, d.mixed() ? L.op32 : nullptr);
+            --l;
+            continue;
+        }
+        int n = 1;
+        while (n < 5 && l - n >= 0 && (T >> n) >= 1) ++n;
+        MomLevels out{};
+        for (int k = 0; k < n; ++k) {
+            out.m64[k] = d.lev[l - k].op64;
+            out.m32[k] = d.mixed() ? d.lev[l - k].op32 : nullptr;
+        }
+        launch_moments_tree(st, l + 1 == f, P.op64, P.nx, P.ny, T, n, out);
+        l -= n;
     }
     launch_fill<double>(st, d.A0, (size_t)d.np0 * d.np0, 0.0);
-    launch_fill<int>(st, d.chol_status, 4, 0);
-    launch_fill<int>(st, d.chol_status + 1, 1, 1);   // factor at the next solve
-    launch_assemble_dense(st, false, level_op<double>(d, 0), make_mat<double>(d, d.omega), d.A0, d.np0);
+    // also status = {0, 1, 0, 0}: positive definite so far, factor this design
+    launch_assemble_dense(st, false, level_op<double>(d, 0), make_mat<double>(d, d.omega), d.A0, d.np0,
+                          d.chol_status);
     LAUNCHCHK(c);
     HIPCHK(c, hipEventRecord(d.ev[1], st));
     d.x_dev = x;

@@ -126,8 +126,20 @@ void launch_moments_from_fine(hipStream_t st, const double* E64, int nxf, int ny
                               float* mom32);
 void launch_moments_coarsen(hipStream_t st, const double* momf, int nxf, int nyf, double* mom64,
                             float* mom32);
+// moments of nlev (<= 5) consecutive levels below src (moduli when from_e,
+// else moment planes) in one launch; T (<= 16, a power of two dividing both
+// dimensions of the first output level, T >> (nlev-1) >= 1) is the tile of
+// the first output level per workgroup; out.m32[l] may be null
+struct MomLevels {
+    double* m64[5];
+    float* m32[5];
+};
+void launch_moments_tree(hipStream_t st, bool from_e, const double* src, int nxs, int nys, int T, int nlev,
+                         const MomLevels& out);
 constexpr int COARSE_NB = 32;   // block size of the coarse factorisation
-void launch_assemble_dense(hipStream_t st, bool fine, LevelOp<double> op, Mat<double> mat, double* A, int ld);
+// also sets status = {0, 1, 0, 0} when given (factor this design)
+void launch_assemble_dense(hipStream_t st, bool fine, LevelOp<double> op, Mat<double> mat, double* A, int ld,
+                           int* status = nullptr);
 // A (np x np, n0 used, identity padding written here; overwritten) ->
 // Dinv = inverses of the diagonal blocks of L, W = L^{-1}, Ainv = A^{-1}.
 // status[0]: 0 or 1 (not positive definite); status[1]: factor this design

@@ -74,13 +74,78 @@ __global__ void k_moments_coarsen(const double* __restrict__ mf, int nxf, int ny
     }
 }
 
+// Galerkin moments of up to five consecutive coarse levels in one launch.
+// Each workgroup owns a T x T tile of the first output level (level of
+// src, halved) and coarsens it in LDS down to the last one (tile T >> (n-1)),
+// each parent from its four children in the order of k_moments_coarsen.
+// src: fine moduli (FROM_E) or the six moment planes of the level above.
+template <bool FROM_E>
+__global__ __launch_bounds__(256) void k_moments_tree(const double* __restrict__ src, int nxs, int nys, int T,
+                                                      int nlev, MomLevels out) {
+    __shared__ double buf[2][6][256];
+    const int nx0 = nxs / 2, ny0 = nys / 2;
+    const int t = threadIdx.x;
+    auto put = [&](int lv, int I, int J, const Mom<double>& P) {
+        const int nxl = nx0 >> lv, nyl = ny0 >> lv;
+        const size_t ps = (size_t)nxl * nyl, e = (size_t)J * nxl + I;
+        const double v[6] = {P.m00, P.m10, P.m01, P.m20, P.m11, P.m02};
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            out.m64[lv][k * ps + e] = v[k];
+            if (out.m32[lv]) out.m32[lv][k * ps + e] = (float)v[k];
+            buf[lv & 1][k][t] = v[k];
+        }
+    };
+    if (t < T * T) {
+        const int I = blockIdx.x * T + t % T, J = blockIdx.y * T + t / T;
+        Mom<double> P = mom_zero<double>();
+        const size_t pf = (size_t)nxs * nys;
+        for (int tt = 0; tt < 2; ++tt)
+            for (int ss = 0; ss < 2; ++ss) {
+                const size_t c = (size_t)(2 * J + tt) * nxs + 2 * I + ss;
+                if constexpr (FROM_E) {
+                    mom_accumulate_child(P, mom_const<double>(src[c]), ss, tt);
+                } else {
+                    const Mom<double> ch{src[c], src[pf + c], src[2 * pf + c], src[3 * pf + c], src[4 * pf + c],
+                                         src[5 * pf + c]};
+                    mom_accumulate_child(P, ch, ss, tt);
+                }
+            }
+        put(0, I, J, P);
+    }
+    for (int lv = 1; lv < nlev; ++lv) {
+        __syncthreads();
+        const int Tl = T >> lv, Tp = T >> (lv - 1);
+        if (t < Tl * Tl) {
+            const int il = t % Tl, jl = t / Tl;
+            Mom<double> P = mom_zero<double>();
+            for (int tt = 0; tt < 2; ++tt)
+                for (int ss = 0; ss < 2; ++ss) {
+                    const int c = (2 * jl + tt) * Tp + 2 * il + ss;
+                    const double(*b)[256] = buf[(lv - 1) & 1];
+                    const Mom<double> ch{b[0][c], b[1][c], b[2][c], b[3][c], b[4][c], b[5][c]};
+                    mom_accumulate_child(P, ch, ss, tt);
+                }
+            put(lv, blockIdx.x * Tl + il, blockIdx.y * Tl + jl, P);
+        }
+    }
+}
+
 // Dense free-DOF matrix of the coarsest grid: thread per (free node, one of
 // its 9 neighbours); each computes the 2x2 block as the sum over the shared
 // elements of element responses to unit displacements.
 template <bool FINE>
-__global__ void k_assemble_dense(LevelOp<double> op, Mat<double> mat, double* __restrict__ A, int ld) {
+__global__ void k_assemble_dense(LevelOp<double> op, Mat<double> mat, double* __restrict__ A, int ld,
+                                 int* __restrict__ status) {
     const int nx = op.nx, ny = op.ny;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (status && t == 0) {
+        // positive definite so far; factor this design at the next opportunity
+        status[0] = 0;
+        status[1] = 1;
+        status[2] = 0;
+        status[3] = 0;
+    }
     const int node = t / 9, o = t % 9;
     if (node >= (nx + 1) * ny) return;
     const int i = node % (nx + 1), j = node / (nx + 1) + 1;
@@ -841,10 +906,20 @@ void launch_moments_coarsen(hipStream_t st, const double* mf, int nxf, int nyf, 
     const int n = (nxf / 2) * (nyf / 2);
     hipLaunchKernelGGL(k_moments_coarsen, dim3(blocks_for(n, 256)), dim3(256), 0, st, mf, nxf, nyf, m64, m32);
 }
-void launch_assemble_dense(hipStream_t st, bool fine, LevelOp<double> op, Mat<double> mat, double* A, int ld) {
+void launch_assemble_dense(hipStream_t st, bool fine, LevelOp<double> op, Mat<double> mat, double* A, int ld,
+                           int* status) {
     const int n = 9 * (op.nx + 1) * op.ny;
-    if (fine) hipLaunchKernelGGL(k_assemble_dense<true>, dim3(blocks_for(n, 256)), dim3(256), 0, st, op, mat, A, ld);
-    else hipLaunchKernelGGL(k_assemble_dense<false>, dim3(blocks_for(n, 256)), dim3(256), 0, st, op, mat, A, ld);
+    if (fine)
+        hipLaunchKernelGGL(k_assemble_dense<true>, dim3(blocks_for(n, 256)), dim3(256), 0, st, op, mat, A, ld, status);
+    else
+        hipLaunchKernelGGL(k_assemble_dense<false>, dim3(blocks_for(n, 256)), dim3(256), 0, st, op, mat, A, ld,
+                           status);
+}
+void launch_moments_tree(hipStream_t st, bool from_e, const double* src, int nxs, int nys, int T, int nlev,
+                         const MomLevels& out) {
+    const dim3 grid((nxs / 2) / T, (nys / 2) / T);
+    if (from_e) hipLaunchKernelGGL(k_moments_tree<true>, grid, dim3(256), 0, st, src, nxs, nys, T, nlev, out);
+    else hipLaunchKernelGGL(k_moments_tree<false>, grid, dim3(256), 0, st, src, nxs, nys, T, nlev, out);
 }
 void launch_coarse_factor(hipStream_t st, double* A, int n0, int np, double* Dinv, double* W, double* Ainv,
                           int* status, double* Lbuf, double* Sacc, int n_designs, long long ds, int half_bw) {
