@@ -47,13 +47,34 @@ __device__ __forceinline__ Mom<T> mom_const(T E) {
 // The bilinear displacement has du_x/dxi = Ax + Bx eta, du_x/deta = Cx + Bx xi
 // (same for y); stresses sigma_xx, sigma_yy, tau are linear in (1, xi, eta)
 // and each nodal force integrates E * (linear shape derivative) * stress.
-template <typename T>
+// With UNIFORM (moments of a constant modulus E = m.m00, the finest grid)
+// E is folded into the material constants and the moments of the unit
+// modulus (1, 1/2, 1/2, 1/3, 1/4, 1/3) become literals.
+template <bool UNIFORM = false, typename T>
 __device__ __forceinline__ void elem_force(const Mom<T>& m, const Mat<T>& k,
                                            const V2<T>& u0, const V2<T>& u1,
                                            const V2<T>& u2, const V2<T>& u3,
                                            V2<T>& f0, V2<T>& f1, V2<T>& f2, V2<T>& f3) {
     const T Ax = u1.x - u0.x, Cx = u3.x - u0.x, Bx = (u0.x - u1.x) + (u2.x - u3.x);
     const T Ay = u1.y - u0.y, Cy = u3.y - u0.y, By = (u0.y - u1.y) + (u2.y - u3.y);
+    if constexpr (UNIFORM) {
+        const T h = T(0.5), q = T(0.25), r = T(1) / T(3);
+        const T cE = k.c * m.m00, nE = k.cnu * m.m00, gE = k.g * m.m00;
+        const T s0 = cE * Ax + nE * Cy, s1 = nE * By, s2 = cE * Bx;
+        const T w0 = nE * Ax + cE * Cy, w1 = cE * By, w2 = nE * Bx;
+        const T t0 = gE * (Cx + Ay), t1 = gE * Bx, t2 = gE * By;
+        const T Sxx = s0 + h * (s1 + s2);
+        const T Sxe = h * s0 + q * s1 + r * s2;
+        const T Syy = w0 + h * (w1 + w2);
+        const T Syx = h * w0 + r * w1 + q * w2;
+        const T Tt = t0 + h * (t1 + t2);
+        const T Ttx = h * t0 + r * t1 + q * t2;
+        const T Tte = h * t0 + q * t1 + r * t2;
+        const T a = Sxx - Sxe, b = Tt - Ttx, c = Syy - Syx, d = Tt - Tte;
+        f0.x = -a - b;   f1.x = a - Ttx;  f2.x = Sxe + Ttx; f3.x = b - Sxe;
+        f0.y = -c - d;   f1.y = d - Syx;  f2.y = Syx + Tte; f3.y = c - Tte;
+        return;
+    }
     // sigma_xx = s0 + s1 xi + s2 eta; sigma_yy = w0 + w1 xi + w2 eta; tau = t0 + t1 xi + t2 eta
     const T s0 = k.c * Ax + k.cnu * Cy, s1 = k.cnu * By, s2 = k.c * Bx;
     const T w0 = k.cnu * Ax + k.c * Cy, w1 = k.c * By, w2 = k.cnu * Bx;
@@ -72,9 +93,17 @@ __device__ __forceinline__ void elem_force(const Mom<T>& m, const Mat<T>& k,
 
 // Diagonal of K_e at the 8 local DOFs:
 // K[ax][ax] = int E (c (dN_a/dxi)^2 + g (dN_a/deta)^2), K[ay][ay] with c and g swapped.
-template <typename T>
+// With UNIFORM (moments of a constant modulus E = m.m00, the finest grid)
+// every integral of a squared shape derivative is E/3, so all eight
+// entries are E (c + g) / 3.
+template <bool UNIFORM = false, typename T>
 __device__ __forceinline__ void elem_diag(const Mom<T>& m, const Mat<T>& k,
                                           V2<T>& d0, V2<T>& d1, V2<T>& d2, V2<T>& d3) {
+    if constexpr (UNIFORM) {
+        const T v = m.m00 * ((k.c + k.g) * (T(1) / T(3)));
+        d0 = d1 = d2 = d3 = V2<T>{v, v};
+        return;
+    }
     const T P0 = m.m00 - T(2) * m.m01 + m.m02;  // int E (1-eta)^2
     const T P1 = m.m02;                          // int E eta^2
     const T Q0 = m.m00 - T(2) * m.m10 + m.m20;  // int E (1-xi)^2

@@ -147,14 +147,14 @@ __global__ __launch_bounds__(WG_THREADS) void k_cg_apply(
         }
         V2<double> f0, f1, f2, f3;
         V2<double> pr_lo = from_right(p[0]), pr_hi = from_right(p[1]);
-        elem_force(me[0], mat, p[0], pr_lo, pr_hi, p[1], f0, f1, f2, f3);
+        elem_force<true>(me[0], mat, p[0], pr_lo, pr_hi, p[1], f0, f1, f2, f3);
         V2<double> carry = f3 + from_left(f2);
 #pragma unroll
         for (int s = 0; s < R; ++s) {
             const int j = t.j0 + s;
             pr_lo = pr_hi;
             pr_hi = from_right(p[s + 2]);
-            elem_force(me[s + 1], mat, p[s + 1], pr_lo, pr_hi, p[s + 2], f0, f1, f2, f3);
+            elem_force<true>(me[s + 1], mat, p[s + 1], pr_lo, pr_hi, p[s + 2], f0, f1, f2, f3);
             const V2<double> qv = carry + f0 + from_left(f1);
             carry = f3 + from_left(f2);
             if (out_lane && j < t.j1) {
@@ -216,14 +216,14 @@ __global__ __launch_bounds__(WG_THREADS) void k_residual(
         for (int s = 0; s < R + 1; ++s) me[s] = load_elem<double, true>(op, i, t.j0 - 1 + s);
         V2<double> f0, f1, f2, f3;
         V2<double> xr_lo = from_right(xr[0]), xr_hi = from_right(xr[1]);
-        elem_force(me[0], mat, xr[0], xr_lo, xr_hi, xr[1], f0, f1, f2, f3);
+        elem_force<true>(me[0], mat, xr[0], xr_lo, xr_hi, xr[1], f0, f1, f2, f3);
         V2<double> carry = f3 + from_left(f2);
 #pragma unroll
         for (int s = 0; s < R; ++s) {
             const int j = t.j0 + s;
             xr_lo = xr_hi;
             xr_hi = from_right(xr[s + 2]);
-            elem_force(me[s + 1], mat, xr[s + 1], xr_lo, xr_hi, xr[s + 2], f0, f1, f2, f3);
+            elem_force<true>(me[s + 1], mat, xr[s + 1], xr_lo, xr_hi, xr[s + 2], f0, f1, f2, f3);
             const V2<double> kx = carry + f0 + from_left(f1);
             carry = f3 + from_left(f2);
             if (out_lane && j < t.j1) {
@@ -361,14 +361,14 @@ __global__ __launch_bounds__(WG_THREADS) void k_presmooth(
         if (t.j0 == 0 && out_lane) store_node(u_out, nx, i, 0, V2<T>{T(0), T(0)});
 
         V2<T> d0, d1, d2, d3;
-        elem_diag(me[0], mat, d0, d1, d2, d3);
+        elem_diag<FINE>(me[0], mat, d0, d1, d2, d3);
         V2<T> dcarry = d3 + from_left(d2);
         V2<T> fcarry{T(0), T(0)};
         V2<T> u1_prev{T(0), T(0)}, u1r_prev{T(0), T(0)}, b_prev{T(0), T(0)}, wD_prev{T(0), T(0)};
 #pragma unroll
         for (int s = 0; s < R + 2; ++s) {
             const int k = t.j0 - 1 + s;   // node row completed by the diagonal stage
-            elem_diag(me[s + 1], mat, d0, d1, d2, d3);
+            elem_diag<FINE>(me[s + 1], mat, d0, d1, d2, d3);
             const V2<T> D = dcarry + d0 + from_left(d1);
             dcarry = d3 + from_left(d2);
             const V2<T> bk = br[s];
@@ -379,7 +379,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_presmooth(
             if (s >= 1) {
                 // force stage for element row k-1 -> node row k-1 complete
                 V2<T> f0, f1, f2, f3;
-                elem_force(me[s], mat, u1_prev, u1r_prev, u1r, u1, f0, f1, f2, f3);
+                elem_force<FINE>(me[s], mat, u1_prev, u1r_prev, u1r, u1, f0, f1, f2, f3);
                 const V2<T> fs = fcarry + f0 + from_left(f1);
                 fcarry = f3 + from_left(f2);
                 const int jr = k - 1;
@@ -448,7 +448,7 @@ __device__ __forceinline__ void restrict_tile(const LevelOp<T>& op, const Mat<T>
     if (abort) return;
     V2<T> f0, f1, f2, f3;
     V2<T> ur_lo = from_right(ur[0]), ur_hi = from_right(ur[1]);
-    elem_force(me[0], mat, ur[0], ur_lo, ur_hi, ur[1], f0, f1, f2, f3);
+    elem_force<FINE>(me[0], mat, ur[0], ur_lo, ur_hi, ur[1], f0, f1, f2, f3);
     V2<T> carry = f3 + from_left(f2);
     V2<T> h_m2{T(0), T(0)}, h_m1{T(0), T(0)};
 #pragma unroll
@@ -456,7 +456,7 @@ __device__ __forceinline__ void restrict_tile(const LevelOp<T>& op, const Mat<T>
         const int j = jf0 + s;
         ur_lo = ur_hi;
         ur_hi = from_right(ur[s + 2]);
-        elem_force(me[s + 1], mat, ur[s + 1], ur_lo, ur_hi, ur[s + 2], f0, f1, f2, f3);
+        elem_force<FINE>(me[s + 1], mat, ur[s + 1], ur_lo, ur_hi, ur[s + 2], f0, f1, f2, f3);
         const V2<T> ku = carry + f0 + from_left(f1);
         carry = f3 + from_left(f2);
         const bool jok = node_col && j >= 1 && j <= ny;
@@ -611,7 +611,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_restrict_pre(
         }
         V2<T> f0, f1, f2, f3;
         V2<T> ur_lo = from_right(ur[0]), ur_hi = from_right(ur[1]);
-        elem_force(me[0], mat, ur[0], ur_lo, ur_hi, ur[1], f0, f1, f2, f3);
+        elem_force<FINE>(me[0], mat, ur[0], ur_lo, ur_hi, ur[1], f0, f1, f2, f3);
         V2<T> carry = f3 + from_left(f2);
         V2<T> h_m2{T(0), T(0)}, h_m1{T(0), T(0)};
 #pragma unroll
@@ -619,7 +619,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_restrict_pre(
             const int j = jf0 + s;
             ur_lo = ur_hi;
             ur_hi = from_right(ur[s + 2]);
-            elem_force(me[s + 1], mat, ur[s + 1], ur_lo, ur_hi, ur[s + 2], f0, f1, f2, f3);
+            elem_force<FINE>(me[s + 1], mat, ur[s + 1], ur_lo, ur_hi, ur[s + 2], f0, f1, f2, f3);
             const V2<T> ku = carry + f0 + from_left(f1);
             carry = f3 + from_left(f2);
             const bool jok = node_col && j >= 1 && j <= ny;
@@ -790,8 +790,8 @@ __global__ __launch_bounds__(WG_THREADS) void k_post(
 
         V2<T> f0, f1, f2, f3, d0, d1, d2, d3;
         V2<T> vr_lo = from_right(vr[0]), vr_hi = from_right(vr[1]);
-        elem_force(me[0], mat, vr[0], vr_lo, vr_hi, vr[1], f0, f1, f2, f3);
-        elem_diag(me[0], mat, d0, d1, d2, d3);
+        elem_force<FINE>(me[0], mat, vr[0], vr_lo, vr_hi, vr[1], f0, f1, f2, f3);
+        elem_diag<FINE>(me[0], mat, d0, d1, d2, d3);
         V2<T> fcarry = f3 + from_left(f2);
         V2<T> dcarry = d3 + from_left(d2);
 #pragma unroll
@@ -799,8 +799,8 @@ __global__ __launch_bounds__(WG_THREADS) void k_post(
             const int j = t.j0 + s;
             vr_lo = vr_hi;
             vr_hi = from_right(vr[s + 2]);
-            elem_force(me[s + 1], mat, vr[s + 1], vr_lo, vr_hi, vr[s + 2], f0, f1, f2, f3);
-            elem_diag(me[s + 1], mat, d0, d1, d2, d3);
+            elem_force<FINE>(me[s + 1], mat, vr[s + 1], vr_lo, vr_hi, vr[s + 2], f0, f1, f2, f3);
+            elem_diag<FINE>(me[s + 1], mat, d0, d1, d2, d3);
             const V2<T> fs = fcarry + f0 + from_left(f1);
             const V2<T> D = dcarry + d0 + from_left(d1);
             fcarry = f3 + from_left(f2);
@@ -830,13 +830,13 @@ __global__ __launch_bounds__(WG_THREADS) void k_post(
 // out(jr, u) receives row jr = j0 .. j0+RR-1 of u = S(S(v)) (S: one damped
 // Jacobi sweep); it is meaningful on lanes with both neighbours in the
 // wave, for grid nodes off the clamped row.
-template <typename T, int RR, typename Out>
+template <typename T, bool FINE, int RR, typename Out>
 __device__ __forceinline__ void post2_stages(const Mat<T>& mat, const V2<T>* vr, const V2<T>* br, const Mom<T>* me,
                                              int j0, bool node_col, int ny, Out out) {
     V2<T> f0, f1, f2, f3, d0, d1, d2, d3;
     V2<T> vlo = from_right(vr[0]), vhi = from_right(vr[1]);
-    elem_force(me[0], mat, vr[0], vlo, vhi, vr[1], f0, f1, f2, f3);
-    elem_diag(me[0], mat, d0, d1, d2, d3);
+    elem_force<FINE>(me[0], mat, vr[0], vlo, vhi, vr[1], f0, f1, f2, f3);
+    elem_diag<FINE>(me[0], mat, d0, d1, d2, d3);
     V2<T> fc1 = f3 + from_left(f2), dc1 = d3 + from_left(d2);
     V2<T> fc2{T(0), T(0)};
     V2<T> u1_prev{T(0), T(0)}, u1r_prev{T(0), T(0)}, wD_prev{T(0), T(0)};
@@ -846,8 +846,8 @@ __device__ __forceinline__ void post2_stages(const Mat<T>& mat, const V2<T>* vr,
         const int k = j0 - 2 + s;
         vlo = vhi;
         vhi = from_right(vr[s + 1]);
-        elem_force(me[s], mat, vr[s], vlo, vhi, vr[s + 1], f0, f1, f2, f3);
-        elem_diag(me[s], mat, d0, d1, d2, d3);
+        elem_force<FINE>(me[s], mat, vr[s], vlo, vhi, vr[s + 1], f0, f1, f2, f3);
+        elem_diag<FINE>(me[s], mat, d0, d1, d2, d3);
         const V2<T> F = fc1 + f0 + from_left(f1);
         const V2<T> D = dc1 + d0 + from_left(d1);
         fc1 = f3 + from_left(f2);
@@ -861,7 +861,7 @@ __device__ __forceinline__ void post2_stages(const Mat<T>& mat, const V2<T>* vr,
         if (s >= 2) {
             // stage 2: element row k-1 from u1 rows k-1, k completes node row k-1
             V2<T> g0, g1, g2, g3;
-            elem_force(me[s - 1], mat, u1_prev, u1r_prev, u1r, u1, g0, g1, g2, g3);
+            elem_force<FINE>(me[s - 1], mat, u1_prev, u1r_prev, u1r, u1, g0, g1, g2, g3);
             const V2<T> G = fc2 + g0 + from_left(g1);
             fc2 = g3 + from_left(g2);
             if (s >= 3) {
@@ -938,7 +938,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_post2(
             else add_prolongation<T, R + 2, 1>(vr, c0, c1, t.j0 - 1, node_col, ny);
         }
 
-        post2_stages<T, R>(mat, vr, br, me, t.j0, node_col, ny, [&](int jr, int q, const V2<T>& uo) {
+        post2_stages<T, FINE, R>(mat, vr, br, me, t.j0, node_col, ny, [&](int jr, int q, const V2<T>& uo) {
             if (out_lane && jr < t.j1) {
                 if (jr >= 1) {
                     store_node(u_out, nx, i, jr, uo);
@@ -1035,7 +1035,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_post2_pair(
     // ---- phase A: e_l on rows JA .. JA + RA - 1, zero off the grid and on the clamped row
     if ((JA - 1) & 1) add_prolongation<T, RA + 2, 1>(va, e0, e1, JA - 1, node_colc, nyc);
     else add_prolongation<T, RA + 2, 0>(va, e0, e1, JA - 1, node_colc, nyc);
-    post2_stages<T, RA>(mat, va, ba, ma, JA, node_colc, nyc, [&](int jr, int q, const V2<T>& uo) {
+    post2_stages<T, false, RA>(mat, va, ba, ma, JA, node_colc, nyc, [&](int jr, int q, const V2<T>& uo) {
         const bool ok = node_colc && jr >= 1 && jr <= nyc;
         ebuf[wave_id() * RA + q][lane] = ok ? uo : V2<T>{T(0), T(0)};
     });
@@ -1053,7 +1053,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_post2_pair(
     }
     if (t.j0 & 1) add_prolongation<T, R + 2, 0>(vr, c0, c1, t.j0 - 1, node_col, nyf);
     else add_prolongation<T, R + 2, 1>(vr, c0, c1, t.j0 - 1, node_col, nyf);
-    post2_stages<T, R>(mat, vr, br, me, t.j0, node_col, nyf, [&](int jr, int q, const V2<T>& uo) {
+    post2_stages<T, false, R>(mat, vr, br, me, t.j0, node_col, nyf, [&](int jr, int q, const V2<T>& uo) {
         if (out_lane && jr < t.j1) store_node(u_out, nxf, i, jr, jr >= 1 ? uo : V2<T>{T(0), T(0)});
     });
 }
@@ -1081,16 +1081,16 @@ __global__ __launch_bounds__(WG_THREADS) void k_apply(LevelOp<T> op, Mat<T> mat,
     for (int s = 0; s < R + 1; ++s) me[s] = load_elem<T, FINE>(op, i, t.j0 - 1 + s);
     V2<T> f0, f1, f2, f3;
     V2<T> ur_lo = from_right(ur[0]), ur_hi = from_right(ur[1]);
-    if (DIAG) elem_diag(me[0], mat, f0, f1, f2, f3);
-    else elem_force(me[0], mat, ur[0], ur_lo, ur_hi, ur[1], f0, f1, f2, f3);
+    if (DIAG) elem_diag<FINE>(me[0], mat, f0, f1, f2, f3);
+    else elem_force<FINE>(me[0], mat, ur[0], ur_lo, ur_hi, ur[1], f0, f1, f2, f3);
     V2<T> carry = f3 + from_left(f2);
 #pragma unroll
     for (int s = 0; s < R; ++s) {
         const int j = t.j0 + s;
         ur_lo = ur_hi;
         ur_hi = from_right(ur[s + 2]);
-        if (DIAG) elem_diag(me[s + 1], mat, f0, f1, f2, f3);
-        else elem_force(me[s + 1], mat, ur[s + 1], ur_lo, ur_hi, ur[s + 2], f0, f1, f2, f3);
+        if (DIAG) elem_diag<FINE>(me[s + 1], mat, f0, f1, f2, f3);
+        else elem_force<FINE>(me[s + 1], mat, ur[s + 1], ur_lo, ur_hi, ur[s + 2], f0, f1, f2, f3);
         V2<T> qv = carry + f0 + from_left(f1);
         carry = f3 + from_left(f2);
         if (out_lane && j < t.j1) {
