@@ -231,6 +231,50 @@ def batched_run(steps, warmup, per_size=16):
     }
 
 
+def cycle_sweep(n, precision, reps=3):
+    """Levels and cycle index at a fixed mesh (Section 2.1: the number of
+    levels and gamma of Algorithm 1): for every admissible L (coarsest grid
+    from 32^2 down to 1 element per side) and gamma in (1, 2), the smooth
+    3-phase wall at n^2 solved to 1e-8 from new densities.  Per setting:
+    iterations, set_densities time, solve time (device time of the solve
+    call, the overlapped coarsest factorisation included), time per
+    iteration; medians over `reps` steps after one warm-up step, library
+    tile choice."""
+    import numpy as np
+    import torch
+    from paper_2301_07457_amd import PCGMGSolver
+    from workloads import make_problem
+    rows = []
+    L_min = max(2, int(np.ceil(np.log2(n / 32))) + 1)
+    L_max = int(np.log2(n)) + 1
+    for L in range(L_min, L_max + 1):
+        prob = make_problem("wall1024", n=n, levels=L, mixed=precision == "fp32mg")
+        x = torch.from_numpy(prob.x).cuda()
+        for gamma in (1, 2):
+            s = PCGMGSolver(max_designs=1)
+            s.add_design(0, prob.nelx, prob.nely, torch.from_numpy(prob.F), list(prob.E_phase), prob.E_min,
+                         prob.penal, prob.nu, L, prob.n_pre, prob.n_post, prob.omega, precision)
+            s.set_option("GAMMA", gamma)
+            st_all = []
+            for k in range(reps + 1):
+                s.set_densities(0, x)
+                st = s.solve(1e-8, 1000)[0]
+                if k > 0:
+                    st_all.append(st)
+            torch.cuda.synchronize()
+            solve_ms = float(np.median([st["t_solve_ms"] for st in st_all]))
+            it = st_all[-1]["iters"]
+            rows.append({"levels": L, "coarsest": f"{n >> (L - 1)}^2", "gamma": gamma,
+                         "cycle": "V" if gamma == 1 else "W", "iters": it,
+                         "setup_ms": round(float(np.median([st["t_setup_ms"] for st in st_all])), 4),
+                         "solve_ms": round(solve_ms, 4),
+                         "ms_per_iter": round(solve_ms / max(1, it), 4),
+                         "status": st_all[-1]["status"], "relres_true": st_all[-1]["relres_true"]})
+            print(f"[cycle sweep] n={n} L={L} gamma={gamma}: {rows[-1]}", file=sys.stderr, flush=True)
+            del s
+    return rows
+
+
 def kernel_breakdown(prob, precision):
     """Average device ms per launch of each finest-grid kernel over one solve."""
     import torch
@@ -268,6 +312,11 @@ def main():
                     help="rows per wave on the finest / coarse grids instead of autotuning (0 = library choice)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (counter calibration)")
+    ap.add_argument("--cycle-sweep", action="store_true",
+                    help="instead of the benchmark: iterations and times for every number of levels "
+                         "and gamma in (1, 2) at --n (one JSON line)")
+    ap.add_argument("--precision", default="fp32mg", choices=("fp32mg", "fp64"),
+                    help="precision of the V-cycle for --cycle-sweep")
     ap.add_argument("--cpu-baseline-worker", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--cpu-n", type=int, default=256, help=argparse.SUPPRESS)
     ap.add_argument("--cpu-levels", type=int, default=5, help=argparse.SUPPRESS)
@@ -284,6 +333,14 @@ def main():
         print("bench.py: this solver runs on one GPU; multi-GPU runs are not supported "
               "(independent designs shard trivially, see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+
+    if args.cycle_sweep:
+        rows = cycle_sweep(args.n, args.precision)
+        print(json.dumps({"metric": "pCGMG iterations and solve time against levels and cycle index",
+                          "workload": (f"square wall {args.n}x{args.n} Q4, smooth 3-phase Gaussian-sum densities "
+                                       f"(seed 2), {args.precision}, 2+2 damped Jacobi omega 0.6, rel.res 1e-8"),
+                          "unit": "ms", "data": "synthetic", "rows": rows}))
+        return
 
     import numpy as np
     import torch

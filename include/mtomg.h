@@ -180,9 +180,19 @@ const char *mtomg_last_error(const mtomg_ctx *ctx);
  *     products) instead of the banded kernels (one workgroup per design for
  *     the Cholesky chain, products on the FP64 matrix cores); both give
  *     K_0^{-1} to rounding (a test and comparison knob).  Applies to
- *     factorisations run after the call. */
+ *     factorisations run after the call.
+ *   MTOMG_OPT_GAMMA (default 1; 1 or 2): the cycle index gamma of
+ *     Algorithm 1 (Section 2.1), used by every design of the context.
+ *     1 is the V-cycle; 2 the W-cycle, in which each level below the
+ *     finest is visited twice per visit of the level above, the second
+ *     visit starting from the first one's result.  The coarsest level is
+ *     the exact solve, so a repeated visit there gives the same result and
+ *     runs once.  A W-cycle visits level l 2^(L-1-l) times per
+ *     preconditioner application (L levels), so it pays only where the
+ *     V-cycle needs many more iterations.  Changing it drops the captured
+ *     graphs and the iteration-count history (MTOMG_OPT_BATCH). */
 enum { MTOMG_OPT_GRAPHS = 0, MTOMG_OPT_BATCH = 1, MTOMG_OPT_ROWS_FINE = 2, MTOMG_OPT_ROWS_COARSE = 3,
-       MTOMG_OPT_DENSE_FACTOR = 4 };
+       MTOMG_OPT_DENSE_FACTOR = 4, MTOMG_OPT_GAMMA = 5 };
 int mtomg_set_option(mtomg_ctx *ctx, int option, int value);
 
 /* Profiling: time every launch of one solver kernel during the following

@@ -33,7 +33,7 @@ EXPORTS = ["mtomg_create", "mtomg_destroy", "mtomg_set_grid", "mtomg_workspace_b
            "mtomg_debug_apply", "mtomg_profile_kernel", "mtomg_profile_read",
            "mtomg_set_option"]
 
-OPTIONS = dict(GRAPHS=0, BATCH=1, ROWS_FINE=2, ROWS_COARSE=3, DENSE_FACTOR=4)
+OPTIONS = dict(GRAPHS=0, BATCH=1, ROWS_FINE=2, ROWS_COARSE=3, DENSE_FACTOR=4, GAMMA=5)
 
 KERNELS = dict(NONE=0, CG_APPLY=1, FINE_PRESMOOTH=2, FINE_RESTRICT=3, FINE_POST=4, FINE_POST_DOT=5,
                COARSE_SOLVE=6)

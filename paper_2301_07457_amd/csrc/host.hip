@@ -151,6 +151,7 @@ struct mtomg_ctx {
     bool use_graphs = true;
     bool dense_factor = false;   // coarsest factorisation by the dense block sequence
     int rows_fine = 0, rows_coarse = 0;   // rows per wave overrides (0 = automatic)
+    int gamma = 1;                        // cycle index of Algorithm 1: 1 V-cycle, 2 W-cycle
     hipStream_t cap_stream = nullptr;     // capture stream (default priority)
     hipStream_t side_stream = nullptr;    // coarsest factorisations during a solve (default priority)
     hipEvent_t ev_fac[2] = {nullptr, nullptr};   // [0] main -> side, [1] side -> main
@@ -449,6 +450,7 @@ template <typename T> struct CycleCtx {
     Prof* prof = nullptr;
     Batch bt{};        // systems of every launch (pointers above are system 0's)
     hipEvent_t wait_coarse = nullptr;   // the coarse solve waits for it (coarsest factors ready)
+    int gamma = 1;                      // coarse-grid visits per level (Algorithm 1)
     void begin(int id) { if (prof) prof->begin(id, st); }
     void end(int id) { if (prof) prof->end(id, st); }
 };
@@ -577,6 +579,93 @@ void coarse_cycle(CycleCtx<T>& cx, int top, bool top_pre) {
     }
 }
 
+// n_pre damped Jacobi sweeps on level l from a nonzero iterate `in`
+// (never written), ping-ponging between t0 and t1; returns the buffer
+// holding the result.  With n_pre = 0 the iterate is copied into t0 (a
+// sweep with omega = 0), so the caller may overwrite `in`.
+template <typename T>
+T* smooth_from(CycleCtx<T>& cx, int l, const T* in, const T* b, T* t0, T* t1) {
+    Design& d = *cx.d;
+    const LevelBufs& L = d.lev[l];
+    const LevelOp<T> op = level_op<T>(d, l);
+    if (d.n_pre == 0) {
+        launch_post<T>(cx.st, false, false, false, op, make_mat<T>(d, 0.0), L.sw_post, in, nullptr, b, t0, nullptr,
+                       nullptr, cx.conv, cx.bt);
+        return t0;
+    }
+    const T* cur = in;
+    T* dst = t0;
+    for (int k = 0; k < d.n_pre;) {
+        const int step = (d.n_pre - k >= 2) ? 2 : 1;
+        if (step == 2)
+            launch_post2<T>(cx.st, false, false, false, op, make_mat<T>(d, d.omega), L.sw_post2, cur, nullptr, b, dst,
+                            nullptr, nullptr, cx.conv, cx.bt);
+        else
+            launch_post<T>(cx.st, false, false, false, op, make_mat<T>(d, d.omega), L.sw_post, cur, nullptr, b, dst,
+                           nullptr, nullptr, cx.conv, cx.bt);
+        cur = dst;
+        dst = dst == t0 ? t1 : t0;
+        k += step;
+    }
+    return const_cast<T*>(cur);
+}
+
+// One visit of coarse level l in a W-cycle (gamma = 2), Algorithm 1:
+// pre-smooth on c.b[l] from zero (from_e = false; pre_done: the fused
+// restriction above already did the first sweeps into u2[l]) or from the
+// previous visit's result in c.e[l] (from_e = true), restrict the residual,
+// visit level l-1 twice (its second visit starts from the first one's
+// result), prolongate, correct and post-smooth into c.e[l].  Level 0 is the
+// exact solve, which a second visit would repeat bit for bit, so it runs
+// once per visit of level 1.
+template <typename T>
+void w_visit(CycleCtx<T>& cx, int l, bool from_e, bool pre_done) {
+    Design& d = *cx.d;
+    CaseBufs& c = *cx.c;
+    if (l == 0) {
+        if (cx.wait_coarse) {
+            hipStreamWaitEvent(cx.st, cx.wait_coarse, 0);
+            cx.wait_coarse = nullptr;   // one wait covers every later coarse solve on the stream
+        }
+        cx.begin(MTOMG_KERNEL_COARSE_SOLVE);
+        launch_coarse_solve<T>(cx.st, d.Ainv, d.n0, d.np0, d.lev[0].nx, (const T*)c.b[0], (T*)c.e[0], cx.conv, cx.bt);
+        cx.end(MTOMG_KERNEL_COARSE_SOLVE);
+        return;
+    }
+    ConvCheck nochk{};
+    CgRhs nocg{};
+    T* b = (T*)c.b[l];
+    T* t0 = (T*)c.u2[l];
+    T* t1 = (T*)c.u4[l];
+    T* cur = nullptr;
+    if (from_e) {
+        cur = smooth_from<T>(cx, l, (const T*)c.e[l], b, t0, t1);
+    } else if (d.n_pre > 0) {
+        if (!pre_done)
+            launch_presmooth<T>(cx.st, false, false, level_op<T>(d, l), make_mat<T>(d, d.omega), d.lev[l].sw_pre, b,
+                                t0, std::min(d.n_pre, 2), nocg, cx.conv, cx.bt);
+        cur = pre_chain_extra<T>(cx, l, t0, b, t0, t1);
+    }
+    const bool sub_pre = restrict_down<T>(cx, l, b, cur, false, nochk);
+    w_visit<T>(cx, l - 1, false, sub_pre);
+    if (l - 1 >= 1) w_visit<T>(cx, l - 1, true, false);
+    T* other = cur == t0 ? t1 : t0;
+    post_chain<T>(cx, l, cur, (const T*)c.e[l - 1], b, (T*)c.e[l], other, cur ? cur : t1, false, nullptr, nullptr);
+}
+
+// Coarse-grid correction of the level above `top` into c.e[top]: levels
+// top .. 0 of Algorithm 1 with cycle index cx.gamma (the V-cycle visits
+// each level once, the W-cycle visits level top twice and recurses).
+template <typename T>
+void coarse_correction(CycleCtx<T>& cx, int top, bool top_pre) {
+    if (cx.gamma == 1) {
+        coarse_cycle<T>(cx, top, top_pre);
+        return;
+    }
+    w_visit<T>(cx, top, false, top_pre);
+    if (top >= 1) w_visit<T>(cx, top, true, false);
+}
+
 // One preconditioner application on the finest grid inside PCG.
 //   it < 0: initial cycle on r_0 (no residual update, writes rho_0)
 //   it >= 0: iteration it: r_{it+1} = r_it - alpha q, then z_{it+1} = M^-1 r_{it+1}
@@ -619,7 +708,7 @@ void fine_cycle(CycleCtx<T>& cx, int it, double tol2) {
     cx.begin(MTOMG_KERNEL_FINE_RESTRICT);
     const bool pre_done = restrict_down<T>(cx, f, bfine, d.n_pre > 0 ? cur : nullptr, true, chk);
     cx.end(MTOMG_KERNEL_FINE_RESTRICT);
-    coarse_cycle<T>(cx, f - 1, pre_done);
+    coarse_correction<T>(cx, f - 1, pre_done);
     post_chain<T>(cx, f, d.n_pre > 0 ? cur : nullptr, (const T*)c.e[f - 1], bfine, (T*)c.z, cur == t0 ? t1 : t0,
                   cur, true, c.r[nxt], c.zr[it < 0 ? 0 : nxt]);
 }
@@ -656,6 +745,7 @@ int debug_vcycle(mtomg_ctx* ctx, Design& d, CaseBufs& cb, hipStream_t st, int le
     CgRhs nocg{};
     ConvCheck nochk{};
     CycleCtx<T> cx{&d, &cb, st, nullptr};
+    cx.gamma = ctx->gamma;
     T* t0 = (T*)cb.u2[level];
     T* t1 = (T*)cb.u4[level];
     T* cur = t0;
@@ -664,7 +754,7 @@ int debug_vcycle(mtomg_ctx* ctx, Design& d, CaseBufs& cb, hipStream_t st, int le
         cur = pre_chain_extra<T>(cx, level, cur, bl, t0, t1);
     }
     const bool pre_done = restrict_down<T>(cx, level, bl, d.n_pre > 0 ? cur : nullptr, false, nochk);
-    coarse_cycle<T>(cx, level - 1, pre_done);
+    coarse_correction<T>(cx, level - 1, pre_done);
     post_chain<T>(cx, level, d.n_pre > 0 ? cur : nullptr, (const T*)cb.e[level - 1], bl, vout, cur == t0 ? t1 : t0,
                   cur, false, nullptr, nullptr);
     return MTOMG_OK;
@@ -787,6 +877,7 @@ CycleCtx<T> group_cycle(mtomg_ctx* c, Group& g, hipStream_t st, Prof* prof) {
     Design& d0 = c->d[g.designs[0]];
     CycleCtx<T> cx{&d0, &d0.cases[0], st, d0.cases[0].state, prof};
     cx.bt = g.batch();
+    cx.gamma = c->gamma;
     return cx;
 }
 
@@ -1371,6 +1462,15 @@ int mtomg_set_option(mtomg_ctx* c, int option, int value) {
             LAUNCHCHK(c);
             return MTOMG_OK;
         }
+        case MTOMG_OPT_GAMMA:
+            if (value != 1 && value != 2) return fail(c, MTOMG_BAD_INPUT, "cycle index must be 1 (V-cycle) or 2 (W-cycle)");
+            if (value != c->gamma) {
+                HIPCHK(c, hipStreamSynchronize(c->stream));
+                drop_graphs(c);
+                c->gamma = value;
+                c->last_iters = 0;
+            }
+            return MTOMG_OK;
         case MTOMG_OPT_BATCH:
             if (value < 1 || value > 1000) return fail(c, MTOMG_BAD_INPUT, "batch must be in [1, 1000]");
             c->batch = value;
