@@ -13,6 +13,8 @@ gradient multigrid method for multi-material topology optimization"):
 * ``multigrid`` — bilinear prolongation, restriction as its transpose,
                   Galerkin coarse operators and the gamma-cycle
                   (Algorithm 1) used as a PCG preconditioner (Section 2.2).
+* ``cone_filter`` — the cone density and sensitivity filters of the
+                  optimisation loop (Section 4, radius rf of Table 2).
 * ``solve``     — the plain definition u = K_ff^{-1} f_f by a direct solve,
                   and the oracle's own MG-preconditioned CG.
 
@@ -21,4 +23,4 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 and never imports it.
 """
 
-from . import fe, linalg, multigrid, solve  # noqa: F401
+from . import cone_filter, fe, linalg, multigrid, solve  # noqa: F401
