@@ -157,6 +157,30 @@ int mtomg_solve(mtomg_ctx *ctx, double rel_tol, int max_iter, int warm_start,
  * Uses the displacements of the last solve. */
 int mtomg_compliance_and_grad(mtomg_ctx *ctx, int design, double *c, double *dcdx);
 
+/* Cone filter of an element field, one pass per phase: the sensitivity
+ * filtering of the optimisation loop (Section 4) with the filter radius rf
+ * of Table 2.  The paper does not write the filter out; this is the usual
+ * cone filter on element centres,
+ *   H_ef = max(0, rf - |c_e - c_f|)   (distance in element widths),
+ *   S_e  = sum_f H_ef                 (over the elements of the grid),
+ * with, per phase,
+ *   MTOMG_FILTER_DENSITY:          out_e = sum_f H_ef in_f / S_e
+ *   MTOMG_FILTER_DENSITY_ADJOINT:  out_e = sum_f H_ef in_f / S_f, the chain
+ *                                  rule through the density filter (H is
+ *                                  symmetric): in = dJ/d(filtered x),
+ *                                  out = dJ/dx;
+ *   MTOMG_FILTER_SENSITIVITY:      out_e = sum_f H_ef x_f in_f
+ *                                          / (max(gmin, x_e) S_e).
+ * x, in, out: device [nely][nelx][m] FP64; x is read by the sensitivity
+ * filter only (densities of the same phases), gmin > 0 keeps void elements
+ * finite there (1e-3 is usual).  0 < rf <= 16; rf <= 1 leaves only the
+ * element itself.  out must not alias in or x.  Asynchronous on the
+ * context's stream; needs no design.  Returns BAD_INPUT for invalid
+ * arguments. */
+enum { MTOMG_FILTER_DENSITY = 0, MTOMG_FILTER_DENSITY_ADJOINT = 1, MTOMG_FILTER_SENSITIVITY = 2 };
+int mtomg_filter(mtomg_ctx *ctx, int nelx, int nely, int m, double rf, int mode, double gmin, const double *x,
+                 const double *in, double *out);
+
 /* Static description of a status code. */
 const char *mtomg_status_string(int status);
 

@@ -31,9 +31,11 @@ EXPORTS = ["mtomg_create", "mtomg_destroy", "mtomg_set_grid", "mtomg_workspace_b
            "mtomg_set_workspace", "mtomg_set_densities", "mtomg_solve",
            "mtomg_compliance_and_grad", "mtomg_status_string", "mtomg_last_error",
            "mtomg_debug_apply", "mtomg_profile_kernel", "mtomg_profile_read",
-           "mtomg_set_option"]
+           "mtomg_set_option", "mtomg_filter"]
 
 OPTIONS = dict(GRAPHS=0, BATCH=1, ROWS_FINE=2, ROWS_COARSE=3, DENSE_FACTOR=4, GAMMA=5)
+
+FILTERS = dict(DENSITY=0, DENSITY_ADJOINT=1, SENSITIVITY=2)
 
 KERNELS = dict(NONE=0, CG_APPLY=1, FINE_PRESMOOTH=2, FINE_RESTRICT=3, FINE_POST=4, FINE_POST_DOT=5,
                COARSE_SOLVE=6)
@@ -92,6 +94,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mtomg_debug_apply.argtypes = [vp, i, i, i, dp, dp]
     lib.mtomg_profile_kernel.argtypes = [vp, i]
     lib.mtomg_set_option.argtypes = [vp, i, i]
+    lib.mtomg_filter.argtypes = [vp, i, i, i, d, i, d, dp, dp, dp]
     lib.mtomg_profile_read.argtypes = [vp, ctypes.POINTER(d), i, ctypes.POINTER(i)]
     for name in EXPORTS:
         if name not in ("mtomg_workspace_bytes", "mtomg_status_string", "mtomg_last_error"):
@@ -183,3 +186,10 @@ def mtomg_profile_read(ctx, cap: int = 4096):
 
 def mtomg_set_option(ctx, option: str, value: int):
     return check(ctx, load().mtomg_set_option(ctx, OPTIONS[option], int(value)))
+
+
+def mtomg_filter(ctx, nelx: int, nely: int, m: int, rf: float, mode: str, gmin: float, x_ptr: int, in_ptr: int,
+                 out_ptr: int):
+    return check(ctx, load().mtomg_filter(ctx, nelx, nely, m, float(rf), FILTERS[mode], float(gmin),
+                                          ctypes.c_void_p(x_ptr or None), ctypes.c_void_p(in_ptr or None),
+                                          ctypes.c_void_p(out_ptr or None)))

@@ -1,0 +1,163 @@
+// Cone filter of element fields, per phase:
+//   H_ef = max(0, rf - |c_e - c_f|)  (centres e, f; distances in element widths),
+//   truncated at the grid edge, with S_e = sum_f H_ef:
+//   density           out_e = sum_f H_ef in_f / S_e
+//   density adjoint   out_e = sum_f H_ef (in_f / S_f)      (H is symmetric)
+//   sensitivity       out_e = sum_f H_ef x_f in_f / (max(gmin, x_e) S_e)
+//
+// A stencil gather that is bound by vector FP64 arithmetic and LDS reads,
+// not by HBM: each output reads (2R+1)^2 neighbours, R = ceil(rf) - 1.
+// A workgroup of four waves owns a 64 x 32 tile of one phase; the tile and
+// its R-wide halo are staged once in LDS (values outside the grid are 0),
+// with the (2R+1)^2 weights beside it.  Lane l of wave w forms the 8
+// outputs of column l, rows 8w .. 8w+7: for each column offset di it holds
+// the weight column w[.][di] in registers and walks the 8 + 2R tile rows
+// once, each value feeding up to 8 accumulators (R is a template
+// parameter, so these loops unroll).  S_e, the sum of the weights over the
+// part of the stencil inside the grid, is a rectangle sum of a 2-D prefix
+// table of the weights (four LDS reads).
+#include "filter_kernels.h"
+
+namespace mtomg {
+
+namespace {
+
+constexpr int FT_X = 64, FT_RY = 8, FT_WAVES = 4, FT_Y = FT_RY * FT_WAVES, FT_THREADS = 64 * FT_WAVES;
+
+// S_e of element (i, j) from the prefix table P[(2R+2)^2], where
+// P[a][b] sums the weights of stencil rows < a and columns < b.
+template <int R>
+__device__ __forceinline__ double weight_sum(const double* P, int i, int j, int nx, int ny) {
+    constexpr int W1 = 2 * R + 2;
+    const int a0 = R - min(j, R), a1 = R + 1 + min(ny - 1 - j, R);
+    const int b0 = R - min(i, R), b1 = R + 1 + min(nx - 1 - i, R);
+    return (P[a1 * W1 + b1] - P[a0 * W1 + b1]) - (P[a1 * W1 + b0] - P[a0 * W1 + b0]);
+}
+
+template <int R>
+__global__ __launch_bounds__(FT_THREADS) void k_cone_filter(int nx, int ny, int m, double rf, int mode,
+                                                            double gmin, const double* __restrict__ x,
+                                                            const double* __restrict__ in,
+                                                            double* __restrict__ out) {
+    constexpr int W = 2 * R + 1, W1 = W + 1;
+    constexpr int TW = FT_X + 2 * R, TH = FT_Y + 2 * R;
+    extern __shared__ double lds[];
+    double* wt = lds;                  // [W][W] weights, rows dj
+    double* P = wt + W * W;            // [W1][W1] prefix sums
+    double* tile = P + W1 * W1;        // [TH][TW]
+    const int k = blockIdx.z;
+    const int bx = blockIdx.x * FT_X, by = blockIdx.y * FT_Y;
+    for (int t = threadIdx.x; t < W * W; t += FT_THREADS) {
+        const int dj = t / W - R, di = t % W - R;
+        wt[t] = fmax(0.0, rf - sqrt((double)(di * di + dj * dj)));
+    }
+    __syncthreads();
+    // P[a][b]: running sums along each stencil row, then down the columns
+    if (threadIdx.x < W1) {
+        const int a = threadIdx.x;
+        double s = 0.0;
+        P[a * W1] = 0.0;
+        for (int b = 0; b < W; ++b) {
+            if (a > 0) s += wt[(a - 1) * W + b];
+            P[a * W1 + b + 1] = s;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < W1) {
+        const int b = threadIdx.x;
+        for (int a = 1; a < W1; ++a) P[a * W1 + b] += P[(a - 1) * W1 + b];
+    }
+    __syncthreads();
+    // every load of the tile is issued before the first is used (one
+    // memory round trip per workgroup, not one per element)
+    constexpr int NL = (TW * TH + FT_THREADS - 1) / FT_THREADS;
+    double v[NL], xv[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+        const int t = threadIdx.x + q * FT_THREADS;
+        const int gx = bx - R + t % TW, gy = by - R + t / TW;
+        const bool ok = t < TW * TH && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+        const size_t e = ok ? ((size_t)gy * nx + gx) * m + k : 0;
+        v[q] = ok ? in[e] : 0.0;
+        xv[q] = (ok && mode == FILTER_SENSITIVITY) ? x[e] : 1.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+        const int t = threadIdx.x + q * FT_THREADS;
+        if (t >= TW * TH) break;
+        double val = v[q] * xv[q];
+        if (mode == FILTER_DENSITY_ADJOINT && val != 0.0) {
+            const int gx = bx - R + t % TW, gy = by - R + t / TW;
+            val /= weight_sum<R>(P, gx, gy, nx, ny);
+        }
+        tile[t] = val;
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double acc[FT_RY];
+#pragma unroll
+    for (int r = 0; r < FT_RY; ++r) acc[r] = 0.0;
+    const double* trow = tile + wave * FT_RY * TW + lane;
+#pragma unroll 1
+    for (int di = 0; di < W; ++di) {
+        double wc[W];
+#pragma unroll
+        for (int dj = 0; dj < W; ++dj) wc[dj] = wt[dj * W + di];
+#pragma unroll
+        for (int jj = 0; jj < FT_RY + 2 * R; ++jj) {
+            const double v = trow[jj * TW + di];
+#pragma unroll
+            for (int r = 0; r < FT_RY; ++r) {
+                const int dj = jj - r;
+                if (dj >= 0 && dj < W) acc[r] = fma(wc[dj], v, acc[r]);
+            }
+        }
+    }
+
+    const int i = bx + lane;
+    if (i >= nx) return;
+    double xe[FT_RY];
+#pragma unroll
+    for (int r = 0; r < FT_RY; ++r) {
+        const int j = by + wave * FT_RY + r;
+        xe[r] = (mode == FILTER_SENSITIVITY && j < ny) ? x[((size_t)j * nx + i) * m + k] : 1.0;
+    }
+#pragma unroll
+    for (int r = 0; r < FT_RY; ++r) {
+        const int j = by + wave * FT_RY + r;
+        if (j >= ny) break;
+        double o = acc[r];
+        if (mode == FILTER_DENSITY) o /= weight_sum<R>(P, i, j, nx, ny);
+        else if (mode == FILTER_SENSITIVITY) o /= fmax(gmin, xe[r]) * weight_sum<R>(P, i, j, nx, ny);
+        out[((size_t)j * nx + i) * m + k] = o;
+    }
+}
+
+template <int R>
+void launch_r(hipStream_t st, int nx, int ny, int m, double rf, int mode, double gmin, const double* x,
+              const double* in, double* out) {
+    constexpr int W = 2 * R + 1;
+    const size_t lds = sizeof(double) * (W * W + (W + 1) * (W + 1) + (FT_X + 2 * R) * (FT_Y + 2 * R));
+    const dim3 grid((nx + FT_X - 1) / FT_X, (ny + FT_Y - 1) / FT_Y, m);
+    hipLaunchKernelGGL(k_cone_filter<R>, grid, dim3(FT_THREADS), lds, st, nx, ny, m, rf, mode, gmin, x, in, out);
+}
+
+}  // namespace
+
+void launch_cone_filter(hipStream_t st, int nx, int ny, int m, double rf, int mode, double gmin, const double* x,
+                        const double* in, double* out) {
+    const int R = rf <= 1.0 ? 0 : (int)ceil(rf) - 1;
+    switch (R) {
+#define MTOMG_FILTER_CASE(r) \
+    case r: launch_r<r>(st, nx, ny, m, rf, mode, gmin, x, in, out); break;
+        MTOMG_FILTER_CASE(0) MTOMG_FILTER_CASE(1) MTOMG_FILTER_CASE(2) MTOMG_FILTER_CASE(3)
+        MTOMG_FILTER_CASE(4) MTOMG_FILTER_CASE(5) MTOMG_FILTER_CASE(6) MTOMG_FILTER_CASE(7)
+        MTOMG_FILTER_CASE(8) MTOMG_FILTER_CASE(9) MTOMG_FILTER_CASE(10) MTOMG_FILTER_CASE(11)
+        MTOMG_FILTER_CASE(12) MTOMG_FILTER_CASE(13) MTOMG_FILTER_CASE(14) MTOMG_FILTER_CASE(15)
+#undef MTOMG_FILTER_CASE
+        default: break;
+    }
+}
+
+}  // namespace mtomg

@@ -32,6 +32,7 @@
 #include <vector>
 
 #include "../../include/mtomg.h"
+#include "filter_kernels.h"
 #include "kernels.h"
 
 using namespace mtomg;
@@ -1405,6 +1406,27 @@ int mtomg_compliance_and_grad(mtomg_ctx* c, int design, double* cout, double* dc
             launch_grad(st, cb.U, d.x_dev, phases_of(d), make_mat<double>(d, d.omega), L.nx, L.ny,
                         dcdx + (size_t)k * L.nx * L.ny * d.m);
     }
+    LAUNCHCHK(c);
+    return MTOMG_OK;
+}
+
+int mtomg_filter(mtomg_ctx* c, int nelx, int nely, int m, double rf, int mode, double gmin, const double* x,
+                 const double* in, double* out) {
+    if (!c) return MTOMG_BAD_INPUT;
+    if (nelx < 1 || nely < 1 || nely > (1 << 20) || (long)nelx * nely > (1L << 30))
+        return fail(c, MTOMG_BAD_INPUT, "filter grid must be 1 .. 2^20 element rows, at most 2^30 elements");
+    if (m < 1 || m > MAX_PHASES) return fail(c, MTOMG_BAD_INPUT, "m must be in [1, 8]");
+    if (!(rf > 0.0 && rf <= FILTER_MAX_RF)) return fail(c, MTOMG_BAD_INPUT, "rf must be in (0, 16]");
+    if (mode != MTOMG_FILTER_DENSITY && mode != MTOMG_FILTER_DENSITY_ADJOINT && mode != MTOMG_FILTER_SENSITIVITY)
+        return fail(c, MTOMG_BAD_INPUT, "unknown filter mode");
+    if (!in || !out) return fail(c, MTOMG_BAD_INPUT, "in and out must be device pointers");
+    if (in == out) return fail(c, MTOMG_BAD_INPUT, "out must not alias in");
+    if (mode == MTOMG_FILTER_SENSITIVITY) {
+        if (!x) return fail(c, MTOMG_BAD_INPUT, "the sensitivity filter needs the densities x");
+        if (x == out) return fail(c, MTOMG_BAD_INPUT, "out must not alias x");
+        if (!(gmin > 0.0 && std::isfinite(gmin))) return fail(c, MTOMG_BAD_INPUT, "gmin must be finite and > 0");
+    }
+    launch_cone_filter(c->stream, nelx, nely, m, rf, mode, gmin, x, in, out);
     LAUNCHCHK(c);
     return MTOMG_OK;
 }

@@ -131,6 +131,21 @@ class PCGMGSolver:
         _lib.mtomg_compliance_and_grad(self.ctx, design, c.data_ptr(), dc.data_ptr() if dc is not None else 0)
         return c, dc
 
+    def filter(self, field: torch.Tensor, rf: float, mode: str = "DENSITY", x: Optional[torch.Tensor] = None,
+               gmin: float = 1e-3) -> torch.Tensor:
+        """mtomg_filter: the cone filter of one element field [nely][nelx][m]
+        (or a stack [k][nely][nelx][m], filtered slice by slice) on the device.
+        mode: "DENSITY", "DENSITY_ADJOINT" or "SENSITIVITY" (needs x, the
+        densities [nely][nelx][m])."""
+        f = field.to(self.device, torch.float64).contiguous()
+        xs = x.to(self.device, torch.float64).contiguous() if x is not None else None
+        out = torch.empty_like(f)
+        ny, nx, m = f.shape[-3:]
+        for a, o in zip(f.reshape(-1, ny, nx, m), out.view(-1, ny, nx, m)):
+            _lib.mtomg_filter(self.ctx, nx, ny, m, rf, mode, gmin, xs.data_ptr() if xs is not None else 0,
+                              a.data_ptr(), o.data_ptr())
+        return out
+
     def U(self, design: int = 0) -> torch.Tensor:
         return self.designs[design]["U"]
 
