@@ -8,15 +8,21 @@
 // A stencil gather that is bound by vector FP64 arithmetic and LDS reads,
 // not by HBM: each output reads (2R+1)^2 neighbours, R = ceil(rf) - 1.
 // A workgroup of four waves owns a 64 x 32 tile of one phase; the tile and
-// its R-wide halo are staged once in LDS (values outside the grid are 0),
-// with the (2R+1)^2 weights beside it.  Lane l of wave w forms the 8
-// outputs of column l, rows 8w .. 8w+7: for each column offset di it holds
-// the weight column w[.][di] in registers and walks the 8 + 2R tile rows
-// once, each value feeding up to 8 accumulators (R is a template
-// parameter, so these loops unroll).  S_e, the sum of the weights over the
-// part of the stencil inside the grid, is a rectangle sum of a 2-D prefix
-// table of the weights (four LDS reads).
+// its R-wide halo are staged once in LDS (values outside the grid are 0).
+// Lane l of wave w forms the 8 outputs of column l, rows 8w .. 8w+7: for
+// each column offset di it takes the weight column w[.][di] from a small
+// table in device memory through scalar loads (the weights are the same
+// for every lane) and walks the 8 + 2R tile rows once, each value feeding
+// up to 8 accumulators (R is a template parameter, so these loops
+// unroll).  S_e, the sum of the weights over the part of the stencil
+// inside the grid, is a rectangle sum of a 2-D prefix table of the weights
+// stored after them (four reads).  The phases of a tile are consecutive
+// workgroups, so the interleaved phase values of a row are fetched from
+// HBM once.
 #include "filter_kernels.h"
+
+#include <algorithm>
+#include <cmath>
 
 namespace mtomg {
 
@@ -25,7 +31,8 @@ namespace {
 constexpr int FT_X = 64, FT_RY = 8, FT_WAVES = 4, FT_Y = FT_RY * FT_WAVES, FT_THREADS = 64 * FT_WAVES;
 
 // S_e of element (i, j) from the prefix table P[(2R+2)^2], where
-// P[a][b] sums the weights of stencil rows < a and columns < b.
+// P[a][b] sums the weights of stencil rows dj < a - R and columns
+// di < b - R.
 template <int R>
 __device__ __forceinline__ double weight_sum(const double* P, int i, int j, int nx, int ny) {
     constexpr int W1 = 2 * R + 2;
@@ -35,39 +42,21 @@ __device__ __forceinline__ double weight_sum(const double* P, int i, int j, int 
 }
 
 template <int R>
-__global__ __launch_bounds__(FT_THREADS) void k_cone_filter(int nx, int ny, int m, double rf, int mode,
-                                                            double gmin, const double* __restrict__ x,
+__global__ __launch_bounds__(FT_THREADS) void k_cone_filter(int nx, int ny, int m, int mode, double gmin,
+                                                            const double* __restrict__ tab,
+                                                            const double* __restrict__ x,
                                                             const double* __restrict__ in,
                                                             double* __restrict__ out) {
-    constexpr int W = 2 * R + 1, W1 = W + 1;
+    constexpr int W = 2 * R + 1;
     constexpr int TW = FT_X + 2 * R, TH = FT_Y + 2 * R;
-    extern __shared__ double lds[];
-    double* wt = lds;                  // [W][W] weights, rows dj
-    double* P = wt + W * W;            // [W1][W1] prefix sums
-    double* tile = P + W1 * W1;        // [TH][TW]
-    const int k = blockIdx.z;
-    const int bx = blockIdx.x * FT_X, by = blockIdx.y * FT_Y;
-    for (int t = threadIdx.x; t < W * W; t += FT_THREADS) {
-        const int dj = t / W - R, di = t % W - R;
-        wt[t] = fmax(0.0, rf - sqrt((double)(di * di + dj * dj)));
-    }
-    __syncthreads();
-    // P[a][b]: running sums along each stencil row, then down the columns
-    if (threadIdx.x < W1) {
-        const int a = threadIdx.x;
-        double s = 0.0;
-        P[a * W1] = 0.0;
-        for (int b = 0; b < W; ++b) {
-            if (a > 0) s += wt[(a - 1) * W + b];
-            P[a * W1 + b + 1] = s;
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x < W1) {
-        const int b = threadIdx.x;
-        for (int a = 1; a < W1; ++a) P[a * W1 + b] += P[(a - 1) * W1 + b];
-    }
-    __syncthreads();
+    extern __shared__ double tile[];   // [TH][TW]
+    // the weights are read through the constant address space, so the
+    // uniform loads of the main loop become scalar loads
+    typedef const __attribute__((address_space(4))) double cdouble;
+    cdouble* wcol = (cdouble*)tab;     // [W][W] weights, column di at wcol[di * W]
+    const double* P = tab + W * W;     // [W + 1][W + 1] prefix sums
+    const int k = blockIdx.x;
+    const int bx = blockIdx.y * FT_X, by = blockIdx.z * FT_Y;
     // every load of the tile is issued before the first is used (one
     // memory round trip per workgroup, not one per element)
     constexpr int NL = (TW * TH + FT_THREADS - 1) / FT_THREADS;
@@ -103,7 +92,7 @@ __global__ __launch_bounds__(FT_THREADS) void k_cone_filter(int nx, int ny, int 
     for (int di = 0; di < W; ++di) {
         double wc[W];
 #pragma unroll
-        for (int dj = 0; dj < W; ++dj) wc[dj] = wt[dj * W + di];
+        for (int dj = 0; dj < W; ++dj) wc[dj] = wcol[di * W + dj];
 #pragma unroll
         for (int jj = 0; jj < FT_RY + 2 * R; ++jj) {
             const double v = trow[jj * TW + di];
@@ -135,22 +124,42 @@ __global__ __launch_bounds__(FT_THREADS) void k_cone_filter(int nx, int ny, int 
 }
 
 template <int R>
-void launch_r(hipStream_t st, int nx, int ny, int m, double rf, int mode, double gmin, const double* x,
+void launch_r(hipStream_t st, int nx, int ny, int m, int mode, double gmin, const double* tab, const double* x,
               const double* in, double* out) {
-    constexpr int W = 2 * R + 1;
-    const size_t lds = sizeof(double) * (W * W + (W + 1) * (W + 1) + (FT_X + 2 * R) * (FT_Y + 2 * R));
-    const dim3 grid((nx + FT_X - 1) / FT_X, (ny + FT_Y - 1) / FT_Y, m);
-    hipLaunchKernelGGL(k_cone_filter<R>, grid, dim3(FT_THREADS), lds, st, nx, ny, m, rf, mode, gmin, x, in, out);
+    const size_t lds = sizeof(double) * (FT_X + 2 * R) * (FT_Y + 2 * R);
+    const dim3 grid(m, (nx + FT_X - 1) / FT_X, (ny + FT_Y - 1) / FT_Y);
+    hipLaunchKernelGGL(k_cone_filter<R>, grid, dim3(FT_THREADS), lds, st, nx, ny, m, mode, gmin, tab, x, in, out);
 }
 
 }  // namespace
 
-void launch_cone_filter(hipStream_t st, int nx, int ny, int m, double rf, int mode, double gmin, const double* x,
-                        const double* in, double* out) {
-    const int R = rf <= 1.0 ? 0 : (int)ceil(rf) - 1;
-    switch (R) {
+int filter_radius_cells(double rf) { return rf <= 1.0 ? 0 : (int)ceil(rf) - 1; }
+
+void filter_table(double rf, double* tab) {
+    const int R = filter_radius_cells(rf), W = 2 * R + 1, W1 = W + 1;
+    double* w = tab;
+    double* P = tab + W * W;
+    for (int di = -R; di <= R; ++di)
+        for (int dj = -R; dj <= R; ++dj)
+            w[(di + R) * W + dj + R] = std::max(0.0, rf - std::sqrt((double)(di * di + dj * dj)));
+    // running sums along each stencil row (dj), then down the columns
+    for (int a = 0; a < W1; ++a) {
+        double s = 0.0;
+        P[a * W1] = 0.0;
+        for (int b = 0; b < W; ++b) {
+            if (a > 0) s += w[b * W + (a - 1)];
+            P[a * W1 + b + 1] = s;
+        }
+    }
+    for (int a = 1; a < W1; ++a)
+        for (int b = 0; b < W1; ++b) P[a * W1 + b] += P[(a - 1) * W1 + b];
+}
+
+void launch_cone_filter(hipStream_t st, int nx, int ny, int m, double rf, int mode, double gmin, const double* tab,
+                        const double* x, const double* in, double* out) {
+    switch (filter_radius_cells(rf)) {
 #define MTOMG_FILTER_CASE(r) \
-    case r: launch_r<r>(st, nx, ny, m, rf, mode, gmin, x, in, out); break;
+    case r: launch_r<r>(st, nx, ny, m, mode, gmin, tab, x, in, out); break;
         MTOMG_FILTER_CASE(0) MTOMG_FILTER_CASE(1) MTOMG_FILTER_CASE(2) MTOMG_FILTER_CASE(3)
         MTOMG_FILTER_CASE(4) MTOMG_FILTER_CASE(5) MTOMG_FILTER_CASE(6) MTOMG_FILTER_CASE(7)
         MTOMG_FILTER_CASE(8) MTOMG_FILTER_CASE(9) MTOMG_FILTER_CASE(10) MTOMG_FILTER_CASE(11)

@@ -153,6 +153,9 @@ struct mtomg_ctx {
     bool dense_factor = false;   // coarsest factorisation by the dense block sequence
     int rows_fine = 0, rows_coarse = 0;   // rows per wave overrides (0 = automatic)
     int gamma = 1;                        // cycle index of Algorithm 1: 1 V-cycle, 2 W-cycle
+    double* filt_tab = nullptr;           // device weight table of mtomg_filter (FILTER_TAB_MAX doubles)
+    double* filt_host = nullptr;          // pinned staging copy of it
+    double filt_rf = -1.0;                // radius the table holds
     hipStream_t cap_stream = nullptr;     // capture stream (default priority)
     hipStream_t side_stream = nullptr;    // coarsest factorisations during a solve (default priority)
     hipEvent_t ev_fac[2] = {nullptr, nullptr};   // [0] main -> side, [1] side -> main
@@ -1220,6 +1223,8 @@ int mtomg_destroy(mtomg_ctx* c) {
     if (c->host_state) hipHostFree(c->host_state);
     if (c->host_sums) hipHostFree(c->host_sums);
     if (c->host_chol) hipHostFree(c->host_chol);
+    if (c->filt_tab) hipFree(c->filt_tab);
+    if (c->filt_host) hipHostFree(c->filt_host);
     for (hipEvent_t& e : c->prof.ev)
         if (e) hipEventDestroy(e);
     delete c;
@@ -1426,7 +1431,19 @@ int mtomg_filter(mtomg_ctx* c, int nelx, int nely, int m, double rf, int mode, d
         if (x == out) return fail(c, MTOMG_BAD_INPUT, "out must not alias x");
         if (!(gmin > 0.0 && std::isfinite(gmin))) return fail(c, MTOMG_BAD_INPUT, "gmin must be finite and > 0");
     }
-    launch_cone_filter(c->stream, nelx, nely, m, rf, mode, gmin, x, in, out);
+    if (!c->filt_tab) {
+        HIPCHK(c, hipMalloc(&c->filt_tab, FILTER_TAB_MAX * sizeof(double)));
+        HIPCHK(c, hipHostMalloc(&c->filt_host, FILTER_TAB_MAX * sizeof(double)));
+    }
+    if (rf != c->filt_rf) {
+        // the staging buffer may still feed an earlier copy: let it finish
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        filter_table(rf, c->filt_host);
+        HIPCHK(c, hipMemcpyAsync(c->filt_tab, c->filt_host, FILTER_TAB_MAX * sizeof(double), hipMemcpyHostToDevice,
+                                 c->stream));
+        c->filt_rf = rf;
+    }
+    launch_cone_filter(c->stream, nelx, nely, m, rf, mode, gmin, c->filt_tab, x, in, out);
     LAUNCHCHK(c);
     return MTOMG_OK;
 }
