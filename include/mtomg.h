@@ -6,9 +6,12 @@
  * nelx x nely square bilinear (Q4) elements, then returns the compliance
  * c = f^T u and its gradient with respect to the phase densities x.  The
  * method is the preconditioned conjugate gradient of Algorithm 2 with one
- * multigrid V-cycle (Algorithm 1, gamma = 1) as the preconditioner, damped
- * Jacobi smoothing (Section 2.3) and a direct Cholesky solve (Algorithm 3)
- * on the coarsest grid; the stiffness follows Eqs. (5)-(10).
+ * multigrid cycle (Algorithm 1: the V-cycle, gamma = 1, or the W-cycle,
+ * gamma = 2, see MTOMG_OPT_GAMMA) as the preconditioner, damped Jacobi
+ * smoothing (Section 2.3) and a direct Cholesky solve (Algorithm 3) on the
+ * coarsest grid; the stiffness follows Eqs. (5)-(10).  mtomg_filter adds
+ * the cone filter that an optimisation loop applies to the densities and
+ * sensitivities (Section 4).
  *
  * Conventions shared by every entry point:
  *   - Node (i, j), i = 0..nelx, j = 0..nely, stores its two displacement

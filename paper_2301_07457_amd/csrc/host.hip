@@ -9,9 +9,11 @@
 // size, so one launch serves every system of the group (blockIdx.y picks
 // the system and the kernels shift their pointers by whole slabs).  All
 // groups iterate in lockstep in one solve, and two PCG iterations of every
-// group are captured in one HIP graph.  The coarsest factorisation of the
-// designs whose densities changed runs at the start of the next solve, one
-// launch sequence per group.
+// group are captured in one HIP graph.  The coarsest factorisation of a
+// design whose densities changed runs on a side stream: started by
+// set_densities when the design is alone in its group, else at the start of
+// the next solve with the other changed designs of its group (one launch
+// sequence per group); the first coarse solve waits for it.
 //
 // Solve loop.  All PCG scalars stay on the device: every kernel that needs
 // alpha = rho / p^T q or beta = rho_i / rho_{i-1} re-sums the per-workgroup
