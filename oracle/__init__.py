@@ -15,6 +15,8 @@ gradient multigrid method for multi-material topology optimization"):
                   (Algorithm 1) used as a PCG preconditioner (Section 2.2).
 * ``cone_filter`` — the cone density and sensitivity filters of the
                   optimisation loop (Section 4, radius rf of Table 2).
+* ``poisson``   — the Poisson model problem of Section 5.1 (scalar Q4,
+                  zero boundary values) with its Galerkin hierarchy.
 * ``solve``     — the plain definition u = K_ff^{-1} f_f by a direct solve,
                   and the oracle's own MG-preconditioned CG.
 
@@ -23,4 +25,4 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 and never imports it.
 """
 
-from . import cone_filter, fe, linalg, multigrid, solve  # noqa: F401
+from . import cone_filter, fe, linalg, multigrid, poisson, solve  # noqa: F401
