@@ -184,6 +184,30 @@ enum { MTOMG_FILTER_DENSITY = 0, MTOMG_FILTER_DENSITY_ADJOINT = 1, MTOMG_FILTER_
 int mtomg_filter(mtomg_ctx *ctx, int nelx, int nely, int m, double rf, int mode, double gmin, const double *x,
                  const double *in, double *out);
 
+/* The Poisson model problem of Section 5.1: -Laplace(u) = f on the unit
+ * square with u = 0 on the whole boundary, bilinear (Q4) elements on an
+ * n x n grid of square elements, solved by PCG (Algorithm 2) with one
+ * multigrid V-cycle (Algorithm 1: n_pre + n_post damped Jacobi sweeps with
+ * weight omega, full-weighting restriction, bilinear prolongation) down to
+ * the 2 x 2 grid, where the one unknown is solved exactly, as in the
+ * paper's runs (16^2 .. 256^2 with 3 .. 7 levels).  All arithmetic is
+ * FP64; the operator on every grid is the Q4 Laplace stencil, which equals
+ * the Galerkin product of the finer one.
+ *   n:      power of two in [4, 8192]; levels = log2(n).
+ *   f:      device [n+1][n+1] FP64, the nodal load vector (the Q4 mass
+ *           matrix applied to the source); boundary entries are ignored.
+ *   u:      device [n+1][n+1] FP64 output (boundary entries 0); must not
+ *           alias f.
+ *   stats:  host, one entry (n_dof = (n-1)^2 interior unknowns,
+ *           t_solve_ms the device time of the call, t_setup_ms 0).
+ * Stops when ||f - K u|| <= rel_tol ||f|| on the recursive residual, or
+ * after max_iter iterations.  Uses the context's stream and a workspace the
+ * context allocates on first use (kept until mtomg_destroy); the host reads
+ * the residual once per iteration.  Blocks until done.  Returns the status
+ * (also in stats). */
+int mtomg_poisson_solve(mtomg_ctx *ctx, int n, int n_pre, int n_post, double omega, double rel_tol, int max_iter,
+                        const double *f, double *u, mtomg_stats *stats);
+
 /* Static description of a status code. */
 const char *mtomg_status_string(int status);
 

@@ -31,7 +31,7 @@ EXPORTS = ["mtomg_create", "mtomg_destroy", "mtomg_set_grid", "mtomg_workspace_b
            "mtomg_set_workspace", "mtomg_set_densities", "mtomg_solve",
            "mtomg_compliance_and_grad", "mtomg_status_string", "mtomg_last_error",
            "mtomg_debug_apply", "mtomg_profile_kernel", "mtomg_profile_read",
-           "mtomg_set_option", "mtomg_filter"]
+           "mtomg_set_option", "mtomg_filter", "mtomg_poisson_solve"]
 
 OPTIONS = dict(GRAPHS=0, BATCH=1, ROWS_FINE=2, ROWS_COARSE=3, DENSE_FACTOR=4, GAMMA=5)
 
@@ -95,6 +95,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mtomg_profile_kernel.argtypes = [vp, i]
     lib.mtomg_set_option.argtypes = [vp, i, i]
     lib.mtomg_filter.argtypes = [vp, i, i, i, d, i, d, dp, dp, dp]
+    lib.mtomg_poisson_solve.argtypes = [vp, i, i, i, d, d, i, dp, dp, ctypes.POINTER(mtomg_stats)]
     lib.mtomg_profile_read.argtypes = [vp, ctypes.POINTER(d), i, ctypes.POINTER(i)]
     for name in EXPORTS:
         if name not in ("mtomg_workspace_bytes", "mtomg_status_string", "mtomg_last_error"):
@@ -186,6 +187,17 @@ def mtomg_profile_read(ctx, cap: int = 4096):
 
 def mtomg_set_option(ctx, option: str, value: int):
     return check(ctx, load().mtomg_set_option(ctx, OPTIONS[option], int(value)))
+
+
+def mtomg_poisson_solve(ctx, n: int, n_pre: int, n_post: int, omega: float, rel_tol: float, max_iter: int,
+                        f_ptr: int, u_ptr: int):
+    """Returns (status, stats dict); NOT_CONVERGED, BREAKDOWN and NAN come back as a status."""
+    st = mtomg_stats()
+    status = load().mtomg_poisson_solve(ctx, n, n_pre, n_post, float(omega), float(rel_tol), max_iter,
+                                        ctypes.c_void_p(f_ptr or None), ctypes.c_void_p(u_ptr or None),
+                                        ctypes.byref(st))
+    check(ctx, status, allow=(MTOMG_NOT_CONVERGED, MTOMG_BREAKDOWN, MTOMG_NAN))
+    return status, st.as_dict()
 
 
 def mtomg_filter(ctx, nelx: int, nely: int, m: int, rf: float, mode: str, gmin: float, x_ptr: int, in_ptr: int,

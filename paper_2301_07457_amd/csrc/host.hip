@@ -36,6 +36,7 @@
 #include "../../include/mtomg.h"
 #include "filter_kernels.h"
 #include "kernels.h"
+#include "poisson_kernels.h"
 
 using namespace mtomg;
 
@@ -158,6 +159,9 @@ struct mtomg_ctx {
     double* filt_tab = nullptr;           // device weight table of mtomg_filter (FILTER_TAB_MAX doubles)
     double* filt_host = nullptr;          // pinned staging copy of it
     double filt_rf = -1.0;                // radius the table holds
+    double* pois_buf = nullptr;           // mtomg_poisson_solve workspace
+    size_t pois_bytes = 0;
+    double* pois_host = nullptr;          // pinned copies of its scalars
     hipStream_t cap_stream = nullptr;     // capture stream (default priority)
     hipStream_t side_stream = nullptr;    // coarsest factorisations during a solve (default priority)
     hipEvent_t ev_fac[2] = {nullptr, nullptr};   // [0] main -> side, [1] side -> main
@@ -1227,6 +1231,8 @@ int mtomg_destroy(mtomg_ctx* c) {
     if (c->host_chol) hipHostFree(c->host_chol);
     if (c->filt_tab) hipFree(c->filt_tab);
     if (c->filt_host) hipHostFree(c->filt_host);
+    if (c->pois_buf) hipFree(c->pois_buf);
+    if (c->pois_host) hipHostFree(c->pois_host);
     for (hipEvent_t& e : c->prof.ev)
         if (e) hipEventDestroy(e);
     delete c;
@@ -1448,6 +1454,188 @@ int mtomg_filter(mtomg_ctx* c, int nelx, int nely, int m, double rf, int mode, d
     launch_cone_filter(c->stream, nelx, nely, m, rf, mode, gmin, c->filt_tab, x, in, out);
     LAUNCHCHK(c);
     return MTOMG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Buffers of the Poisson solve: per grid level l (n_l = n >> (L-1-l)),
+// b (restricted right-hand side), e (correction), t0 / t1 (smoother
+// iterates) and res (residual); on the finest grid r, z, p, q.
+struct PoisBufs {
+    int L = 0;
+    int nl[16] = {};
+    double* b[16] = {};
+    double* e[16] = {};
+    double* t0[16] = {};
+    double* t1[16] = {};
+    double* res[16] = {};
+    double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+    double* part = nullptr;   // 64 dot-product partials
+    double* sc = nullptr;     // scalars: ff, rz[2], pq, rr
+};
+
+constexpr int POIS_PARTS = 64;
+
+size_t pois_layout(int n, int L, PoisBufs* pb, char* base) {
+    size_t off = 0;
+    auto take = [&](size_t count) -> double* {
+        double* ptr = base ? reinterpret_cast<double*>(base + off) : nullptr;
+        off += (count * sizeof(double) + 255) / 256 * 256;
+        return ptr;
+    };
+    if (pb) pb->L = L;
+    for (int l = 0; l < L; ++l) {
+        const int nl = n >> (L - 1 - l);
+        const size_t N = (size_t)(nl + 1) * (nl + 1);
+        double* b = take(N); double* e = take(N); double* t0 = take(N); double* t1 = take(N); double* res = take(N);
+        if (pb) { pb->nl[l] = nl; pb->b[l] = b; pb->e[l] = e; pb->t0[l] = t0; pb->t1[l] = t1; pb->res[l] = res; }
+    }
+    const size_t N = (size_t)(n + 1) * (n + 1);
+    double* r = take(N); double* z = take(N); double* p = take(N); double* q = take(N);
+    double* part = take(POIS_PARTS); double* sc = take(8);
+    if (pb) { pb->r = r; pb->z = z; pb->p = p; pb->q = q; pb->part = part; pb->sc = sc; }
+    return off;
+}
+
+// One cycle of Algorithm 1 (gamma = 1) on level l: out = M_l^{-1} b.
+void pois_cycle(hipStream_t st, const PoisBufs& pb, int l, const double* b, double* out, int n_pre, int n_post,
+                double omega) {
+    if (l == 0) {
+        launch_pois_coarse(st, b, out);
+        return;
+    }
+    const int nl = pb.nl[l], nc = pb.nl[l - 1];
+    double* cur = nullptr;
+    for (int k = 0; k < n_pre; ++k) {
+        double* dst = cur == pb.t0[l] ? pb.t1[l] : pb.t0[l];
+        launch_pois_jacobi(st, nl, omega, b, cur, dst);
+        cur = dst;
+    }
+    launch_pois_residual(st, nl, b, cur, pb.res[l]);
+    launch_pois_restrict(st, nc, pb.res[l], pb.b[l - 1]);
+    pois_cycle(st, pb, l - 1, pb.b[l - 1], pb.e[l - 1], n_pre, n_post, omega);
+    if (!cur) {
+        launch_fill<double>(st, pb.t0[l], (size_t)(nl + 1) * (nl + 1), 0.0);
+        cur = pb.t0[l];
+    }
+    launch_pois_prolong_add(st, nc, pb.e[l - 1], cur);
+    if (n_post == 0) {
+        launch_pois_jacobi(st, nl, 0.0, b, cur, out);   // omega = 0: a copy
+        return;
+    }
+    for (int k = 0; k < n_post; ++k) {
+        double* dst = k == n_post - 1 ? out : (cur == pb.t0[l] ? pb.t1[l] : pb.t0[l]);
+        launch_pois_jacobi(st, nl, omega, b, cur, dst);
+        cur = dst;
+    }
+}
+
+void pois_dot(hipStream_t st, const PoisBufs& pb, int n, const double* a, const double* b, double* out) {
+    launch_dot_partials(st, a, b, (size_t)(n + 1) * (n + 1), pb.part, POIS_PARTS);
+    launch_sum_to(st, pb.part, POIS_PARTS, out);
+}
+
+}  // namespace
+
+extern "C" {
+
+int mtomg_poisson_solve(mtomg_ctx* c, int n, int n_pre, int n_post, double omega, double rel_tol, int max_iter,
+                        const double* f, double* u, mtomg_stats* stats) {
+    if (!c) return MTOMG_BAD_INPUT;
+    if (n < 4 || n > 8192 || (n & (n - 1))) return fail(c, MTOMG_BAD_INPUT, "n must be a power of two in [4, 8192]");
+    if (n_pre < 0 || n_pre > 8 || n_post < 0 || n_post > 8) return fail(c, MTOMG_BAD_INPUT, "n_pre, n_post must be in [0, 8]");
+    if (!(omega > 0.0 && omega <= 1.0)) return fail(c, MTOMG_BAD_INPUT, "omega must be in (0, 1]");
+    if (!(rel_tol > 0.0) || max_iter < 0) return fail(c, MTOMG_BAD_INPUT, "rel_tol must be > 0, max_iter >= 0");
+    if (!f || !u || !stats) return fail(c, MTOMG_BAD_INPUT, "f, u (device) and stats (host) are required");
+    if (f == u) return fail(c, MTOMG_BAD_INPUT, "u must not alias f");
+    int L = 0;
+    while ((2 << L) <= n) ++L;   // levels down to the 2 x 2 grid: n = 2^L
+    hipStream_t st = c->stream;
+    const size_t need = pois_layout(n, L, nullptr, nullptr);
+    if (need > c->pois_bytes) {
+        HIPCHK(c, hipStreamSynchronize(st));
+        if (c->pois_buf) HIPCHK(c, hipFree(c->pois_buf));
+        c->pois_buf = nullptr;
+        c->pois_bytes = 0;
+        HIPCHK(c, hipMalloc(&c->pois_buf, need));
+        c->pois_bytes = need;
+    }
+    if (!c->pois_host) HIPCHK(c, hipHostMalloc(&c->pois_host, 8 * sizeof(double)));
+    PoisBufs pb;
+    pois_layout(n, L, &pb, reinterpret_cast<char*>(c->pois_buf));
+    const size_t N = (size_t)(n + 1) * (n + 1);
+    double* sc = pb.sc;   // [0] ||f||^2, [1] / [2] r.z of alternate iterations, [3] p.q, [4] ||r||^2
+    double* hs = c->pois_host;
+    hipEvent_t e0 = c->ev_solve[0], e1 = c->ev_solve[1];
+    HIPCHK(c, hipEventRecord(e0, st));
+    // u = 0, r = f on the interior (Algorithm 2 from a zero start)
+    launch_fill<double>(st, u, N, 0.0);
+    launch_pois_residual(st, n, f, nullptr, pb.r);
+    pois_dot(st, pb, n, pb.r, pb.r, sc + 0);
+    const int fine = L - 1;
+    auto read_scalars = [&]() -> int {
+        HIPCHK(c, hipMemcpyAsync(hs, sc, 5 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        return MTOMG_OK;
+    };
+    int rc = read_scalars();
+    if (rc) return rc;
+    const double ff = hs[0];
+    int status = MTOMG_OK, it = 0, cycles = 0;
+    double rr = ff;
+    if (ff > 0.0 && max_iter > 0) {
+        pois_cycle(st, pb, fine, pb.r, pb.z, n_pre, n_post, omega);
+        ++cycles;
+        pois_dot(st, pb, n, pb.r, pb.z, sc + 1);
+        launch_pois_xpby(st, n, pb.z, nullptr, nullptr, pb.p);
+        status = MTOMG_NOT_CONVERGED;
+        for (it = 1; it <= max_iter; ++it) {
+            double* rz = sc + 1 + ((it - 1) & 1);   // r_{it-1}.z_{it-1}
+            double* rz_next = sc + 1 + (it & 1);
+            launch_pois_apply(st, n, pb.p, pb.q);
+            pois_dot(st, pb, n, pb.p, pb.q, sc + 3);
+            launch_pois_axpy(st, n, rz, sc + 3, 1.0, pb.p, u);
+            launch_pois_axpy(st, n, rz, sc + 3, -1.0, pb.q, pb.r);
+            pois_dot(st, pb, n, pb.r, pb.r, sc + 4);
+            // the next cycle and direction are queued before the host looks
+            pois_cycle(st, pb, fine, pb.r, pb.z, n_pre, n_post, omega);
+            ++cycles;
+            pois_dot(st, pb, n, pb.r, pb.z, rz_next);
+            LAUNCHCHK(c);
+            rc = read_scalars();
+            if (rc) return rc;
+            rr = hs[4];
+            if (!std::isfinite(rr) || !std::isfinite(hs[3])) { status = MTOMG_NAN; break; }
+            if (!(hs[3] > 0.0)) { status = MTOMG_BREAKDOWN; break; }
+            if (rr <= rel_tol * rel_tol * ff) { status = MTOMG_OK; break; }
+            if (!(hs[1 + (it & 1)] > 0.0)) { status = MTOMG_BREAKDOWN; break; }
+            launch_pois_xpby(st, n, pb.z, rz_next, rz, pb.p);
+        }
+        if (it > max_iter) it = max_iter;
+    }
+    // true residual ||f - K u|| at exit
+    launch_pois_residual(st, n, f, u, pb.res[fine]);
+    pois_dot(st, pb, n, pb.res[fine], pb.res[fine], sc + 4);
+    HIPCHK(c, hipEventRecord(e1, st));
+    LAUNCHCHK(c);
+    rc = read_scalars();
+    if (rc) return rc;
+    float ms = 0.0f;
+    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+    mtomg_stats s{};
+    s.status = status;
+    s.iters = it;
+    s.vcycles = cycles;
+    s.n_dof = (n - 1) * (n - 1);
+    s.relres_rec = ff > 0.0 ? std::sqrt(rr / ff) : 0.0;
+    s.relres_true = ff > 0.0 ? std::sqrt(hs[4] / ff) : 0.0;
+    s.t_setup_ms = 0.0;
+    s.t_solve_ms = ms;
+    s.model_bytes = 0.0;
+    *stats = s;
+    return status;
 }
 
 const char* mtomg_status_string(int s) {

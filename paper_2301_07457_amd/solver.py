@@ -146,6 +146,20 @@ class PCGMGSolver:
                               a.data_ptr(), o.data_ptr())
         return out
 
+    def poisson_solve(self, f: torch.Tensor, rel_tol: float = 1e-8, max_iter: int = 1000, n_pre: int = 2,
+                      n_post: int = 2, omega: float = 0.6):
+        """mtomg_poisson_solve: the Poisson model problem of Section 5.1 on an
+        n x n grid (n a power of two).  f: nodal loads [n+1][n+1].  Returns
+        (u [n+1][n+1], stats dict); needs no design."""
+        fd = f.to(self.device, torch.float64).contiguous()
+        n = fd.shape[0] - 1
+        if tuple(fd.shape) != (n + 1, n + 1):
+            raise ValueError("f must be [n+1, n+1]")
+        u = torch.empty_like(fd)
+        _, st = _lib.mtomg_poisson_solve(self.ctx, n, n_pre, n_post, omega, rel_tol, max_iter, fd.data_ptr(),
+                                         u.data_ptr())
+        return u, st
+
     def U(self, design: int = 0) -> torch.Tensor:
         return self.designs[design]["U"]
 

@@ -1,0 +1,90 @@
+"""The Poisson model problem of Section 5.1 on the GPU (mtomg_poisson_solve).
+
+Against the oracle (oracle/poisson.py): the solution matches the direct
+solve to 1e-6 and the iteration count the oracle's pCGMG with the same
+cycle (within 1), from 4^2 to 256^2 (the paper's meshes, levels 2 .. 7)
+and for several sweep counts; boundary loads are ignored and boundary
+values are 0.  At 1024^2 and 2048^2 the exact solution sin(pi x) sin(pi y)
+bounds the error at the discretisation's O(h^2), and the iteration count
+stays that of the small meshes.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import poisson
+from tests.gpu_util import rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def solver():
+    from paper_2301_07457_amd import PCGMGSolver
+    return PCGMGSolver(max_designs=1)
+
+
+def full_load(n, source):
+    F = np.zeros((n + 1, n + 1))
+    F[1:-1, 1:-1] = poisson.load(n, source).reshape(n - 1, n - 1)
+    return F
+
+
+@pytest.mark.parametrize("n", [4, 16, 32, 64, 128, 256])
+def test_matches_oracle(solver, n):
+    L = int(np.log2(n))
+    F = full_load(n, np.ones((n + 1, n + 1)))
+    F_junk = F.copy()
+    F_junk[0, :] = F_junk[-1, :] = F_junk[:, 0] = F_junk[:, -1] = 7.0    # boundary loads are ignored
+    u, st = solver.poisson_solve(torch.from_numpy(F_junk), 1e-8, 1000)
+    u = u.cpu().numpy()
+    assert st["status"] == 0 and st["relres_true"] <= 1.05e-8, st
+    assert np.all(u[0, :] == 0) and np.all(u[-1, :] == 0) and np.all(u[:, 0] == 0) and np.all(u[:, -1] == 0)
+    ref = poisson.solve_direct(n, F[1:-1, 1:-1].ravel())
+    assert rel(u[1:-1, 1:-1].ravel(), ref) <= 1e-6
+    o = poisson.solve_mgpcg(n, L, F[1:-1, 1:-1].ravel(), rel_tol=1e-8)
+    assert abs(st["iters"] - o.iters) <= 1, (st["iters"], o.iters)
+    print(f"[poisson] n={n} L={L} iters={st['iters']} (oracle {o.iters}) {st['t_solve_ms']:.3f} ms")
+
+
+@pytest.mark.parametrize("pre,post,omega", [(1, 1, 0.6), (3, 3, 0.6), (2, 2, 0.8), (0, 2, 0.6)])
+def test_sweep_counts(solver, pre, post, omega):
+    n = 64
+    rng = np.random.default_rng(pre * 10 + post)
+    F = full_load(n, rng.standard_normal((n + 1, n + 1)))
+    u, st = solver.poisson_solve(torch.from_numpy(F), 1e-8, 1000, pre, post, omega)
+    assert st["status"] == 0, st
+    o = poisson.solve_mgpcg(n, 6, F[1:-1, 1:-1].ravel(), omega, pre, post, rel_tol=1e-8)
+    assert abs(st["iters"] - o.iters) <= 1, (st["iters"], o.iters)
+    ref = poisson.solve_direct(n, F[1:-1, 1:-1].ravel())
+    assert rel(u.cpu().numpy()[1:-1, 1:-1].ravel(), ref) <= 1e-6
+
+
+@pytest.mark.parametrize("n", [1024, 2048])
+def test_large_meshes_discretisation_error(solver, n):
+    """Loads integrated exactly (the hat function against sin(pi x) gives
+    sin(pi x_i) 2 (1 - cos(pi h)) / (pi^2 h)); the nodal error of Q4 is then
+    (pi^2 / 12) h^2 to leading order."""
+    h = 1.0 / n
+    x = np.linspace(0.0, 1.0, n + 1)
+    X, Y = np.meshgrid(x, x)
+    exact = np.sin(np.pi * X) * np.sin(np.pi * Y)
+    g = np.sin(np.pi * x) * 2.0 * (1.0 - np.cos(np.pi * h)) / (np.pi ** 2 * h)
+    F = 2 * np.pi ** 2 * np.outer(g, g)
+    u, st = solver.poisson_solve(torch.from_numpy(F), 1e-10, 1000)
+    assert st["status"] == 0 and st["relres_true"] <= 1.05e-10, st
+    err = np.abs(u.cpu().numpy() - exact).max()
+    assert err <= 1.0 / n ** 2, err          # O(h^2) with a constant below 1
+    assert st["iters"] <= 12, st["iters"]
+    print(f"[poisson] n={n} iters={st['iters']} max error {err:.2e} {st['t_solve_ms']:.2f} ms")
+
+
+def test_zero_load_and_bad_input(solver):
+    u, st = solver.poisson_solve(torch.zeros((17, 17), dtype=torch.float64), 1e-8, 100)
+    assert st["status"] == 0 and st["iters"] == 0 and torch.all(u == 0)
+    for n in (2, 6, 24):
+        with pytest.raises(RuntimeError):
+            solver.poisson_solve(torch.zeros((n + 1, n + 1), dtype=torch.float64), 1e-8, 100)
+    with pytest.raises(RuntimeError):
+        solver.poisson_solve(torch.zeros((17, 17), dtype=torch.float64), 1e-8, 100, omega=1.5)
