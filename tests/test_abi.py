@@ -40,3 +40,27 @@ def test_binding_names_match_header():
     # a null context is rejected without touching the GPU
     assert lib.mtomg_solve(None, 1e-8, 10, 0, None) == _lib.MTOMG_BAD_INPUT
     assert lib.mtomg_workspace_bytes(None) == 0
+
+
+def header_enum(prefix):
+    txt = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    return {m.group(1): int(m.group(2)) for m in re.finditer(prefix + r"([A-Z0-9_]+)\s*=\s*(-?\d+)", txt)}
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmtomg.so not built")
+def test_binding_enums_match_header():
+    from paper_2301_07457_amd import _lib
+    assert _lib.OPTIONS == header_enum("MTOMG_OPT_")
+    assert _lib.FILTERS == header_enum("MTOMG_FILTER_")
+    assert _lib.KERNELS == header_enum("MTOMG_KERNEL_")
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmtomg.so not built")
+def test_null_context_is_rejected_by_every_context_call():
+    from paper_2301_07457_amd import _lib
+    lib = _lib.load()
+    bad = _lib.MTOMG_BAD_INPUT
+    assert lib.mtomg_set_option(None, 0, 1) == bad
+    assert lib.mtomg_filter(None, 8, 8, 1, 2.0, 0, 1e-3, None, None, None) == bad
+    assert lib.mtomg_poisson_solve(None, 16, 2, 2, 0.6, 1e-8, 10, None, None, None) == bad
+    assert lib.mtomg_compliance_and_grad(None, 0, None, None) == bad
