@@ -11,7 +11,8 @@
  * smoothing (Section 2.3) and a direct Cholesky solve (Algorithm 3) on the
  * coarsest grid; the stiffness follows Eqs. (5)-(10).  mtomg_filter adds
  * the cone filter that an optimisation loop applies to the densities and
- * sensitivities (Section 4).
+ * sensitivities (Section 4), and mtomg_poisson_solve the Poisson model
+ * problem of Section 5.1.
  *
  * Conventions shared by every entry point:
  *   - Node (i, j), i = 0..nelx, j = 0..nely, stores its two displacement

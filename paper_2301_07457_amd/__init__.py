@@ -2,7 +2,8 @@
 
 The compute path is libmtomg.so (HIP, gfx950) behind the C ABI in
 include/mtomg.h; ``solver`` wraps it with torch tensors and an autograd
-function.  Importing this package does not load the library; the first
+function (``PCGMGSolver`` also exposes the cone filter and the Poisson
+model problem of Section 5.1).  Importing this package does not load the library; the first
 solver object does, and fails loudly if it is not built.
 """
 

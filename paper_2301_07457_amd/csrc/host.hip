@@ -1583,7 +1583,7 @@ int mtomg_poisson_solve(mtomg_ctx* c, int n, int n_pre, int n_post, double omega
     int rc = read_scalars();
     if (rc) return rc;
     const double ff = hs[0];
-    int status = MTOMG_OK, it = 0, cycles = 0;
+    int status = ff > 0.0 ? MTOMG_NOT_CONVERGED : MTOMG_OK, it = 0, cycles = 0;
     double rr = ff;
     if (ff > 0.0 && max_iter > 0) {
         pois_cycle(st, pb, fine, pb.r, pb.z, n_pre, n_post, omega);
