@@ -388,7 +388,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this solver runs on one GPU; multi-GPU runs are not supported "
-              "(independent designs shard trivially, see DESIGN.md)", file=sys.stderr)
+              "(independent designs would shard over GPUs with no communication)", file=sys.stderr)
         sys.exit(2)
 
     if args.cycle_sweep:
