@@ -111,3 +111,34 @@ def test_mgpcg_on_random_cone_wall():
     assert err <= 1e-6
     assert mg.c[0] == pytest.approx(ref.c[0], rel=1e-7)
     np.testing.assert_allclose(mg.dcdx, ref.dcdx, rtol=1e-5, atol=1e-9 * np.abs(ref.dcdx).max())
+
+
+def _cycle_matrix(H, l, gamma):
+    N = H.levels[l].K.shape[0]
+    return np.column_stack([multigrid.cycle(H, l, e, None, 0.6, 2, 2, gamma) for e in np.eye(N)])
+
+
+def test_wcycle_coarse_correction_is_two_visits():
+    """gamma = 2: the coarse problem is visited twice, the second visit from
+    the first one's result.  A cycle from a start U is the affine map
+    U + M (F - K U), so two visits give (2 M - M K M) Fc with M the coarse
+    level's own W-cycle matrix; the level above is that coarse correction
+    between two damped Jacobi sweeps before and after (written here with
+    plain matrices)."""
+    H, _ = _hier(8, 3, 21)
+    top = H.levels[2]
+    Kc = H.levels[1].K.toarray()
+    Mc = _cycle_matrix(H, 1, 2)
+    C = 2 * Mc - Mc @ Kc @ Mc                     # two visits from zero
+    K = top.K.toarray()
+    P = top.P.toarray()
+    S = np.eye(K.shape[0]) - 0.6 * (K / top.diag[:, None])   # one sweep's error map
+    I = np.eye(K.shape[0])
+    pre = (I - S @ S) @ np.linalg.inv(K)          # two sweeps from zero
+    # U = pre F; U += P C P^T (F - K U); two post-sweeps: U <- S U + (I - S) K^-1 F
+    Kinv = np.linalg.inv(K)
+    M_coarse = pre + P @ C @ P.T @ (I - K @ pre)
+    M = S @ S @ M_coarse + (I - S @ S) @ Kinv
+    np.testing.assert_allclose(_cycle_matrix(H, 2, 2), M, atol=1e-10 * np.abs(M).max())
+    # and the V-cycle differs (one visit: C would be Mc alone)
+    assert np.abs(_cycle_matrix(H, 2, 1) - M).max() > 1e-3 * np.abs(M).max()
