@@ -17,7 +17,11 @@ unknown) and meshes 16^2 .. 256^2 (levels 3 .. 7).  Written out plainly:
   form ``multigrid.cycle`` consumes, so the multigrid cycle and PCG are the
   oracle's own (Algorithms 1 and 2).
 Node values are [n+1][n+1] arrays (row j, column i) where a full field is
-meant, interior vectors elsewhere.
+meant, interior vectors elsewhere.  Every function is pinned by
+tests/test_oracle_poisson.py: hand-computed element matrices, the 9-point
+stencil, second-order convergence to a closed-form solution, Galerkin
+operators equal to the coarse discretisation, a symmetric positive definite
+cycle and mesh-independent iteration counts.
 """
 
 from __future__ import annotations
