@@ -53,3 +53,28 @@ def test_batched_workload_layout():
     assert [(p.nelx, p.levels) for p in probs] == [(128, 4), (384, 5), (768, 6)]
     assert all(p.F.shape == (4, p.nely + 1, p.nelx + 1, 2) for p in probs)
     assert all(p.nelx % 2 ** (p.levels - 1) == 0 and p.nelx >> (p.levels - 1) <= 32 for p in probs)
+
+
+def test_binary_contrast_recipe():
+    p = make_problem("wall256", n=64, levels=3)
+    x = p.x
+    assert x.shape == (64, 64, 3)
+    assert set(np.unique(x)) <= {0.0, 1.0}
+    s = x.sum(axis=2)
+    assert np.all(s[0] == 1) and np.all(s[-1] == 1)         # loaded and clamped rows solid
+    assert 0.4 < s[1:-1].mean() < 0.6                        # half of the rest
+    assert p.fd_elements.shape == (64, 2) and p.fd_zero_pairs.shape == (8, 2)
+    # FD pairs sit on solid elements, on their own phase
+    e, k = p.fd_elements[:, 0], p.fd_elements[:, 1]
+    assert np.all(x.reshape(-1, 3)[e, k] == 1.0)
+
+
+def test_near_binary_recipe_spans_top_to_bottom():
+    from scipy import ndimage
+    p = make_problem("wall2048", n=128, levels=4)
+    x = p.x
+    assert x.shape == (128, 128, 4)
+    assert set(np.round(np.unique(x), 6)) <= {1e-3, round(1 - 3e-3, 6)}
+    solid = x.max(axis=2) > 0.5
+    lab, _ = ndimage.label(solid)
+    assert np.intersect1d(lab[0][lab[0] > 0], lab[-1][lab[-1] > 0]).size > 0
