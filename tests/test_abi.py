@@ -64,3 +64,20 @@ def test_null_context_is_rejected_by_every_context_call():
     assert lib.mtomg_filter(None, 8, 8, 1, 2.0, 0, 1e-3, None, None, None) == bad
     assert lib.mtomg_poisson_solve(None, 16, 2, 2, 0.6, 1e-8, 10, None, None, None) == bad
     assert lib.mtomg_compliance_and_grad(None, 0, None, None) == bad
+
+
+def test_header_is_plain_c(tmp_path):
+    """The boundary header compiles as pedantic C99 (no C++ or torch types)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if not gcc:
+        pytest.skip("gcc not available")
+    src = tmp_path / "use.c"
+    src.write_text('#include "mtomg.h"\n'
+                   "int main(void) { mtomg_stats s; mtomg_ctx *c = 0; (void)s; (void)c;\n"
+                   "  return MTOMG_OPT_GAMMA + MTOMG_FILTER_SENSITIVITY + MTOMG_FP32MG; }\n")
+    r = subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I",
+                        os.path.join(ROOT, "include"), "-c", str(src), "-o", str(tmp_path / "use.o")],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
