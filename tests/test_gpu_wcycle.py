@@ -148,3 +148,20 @@ def test_gamma_option_rejects_other_values():
     for bad in (0, 3, -1):
         with pytest.raises(RuntimeError):
             s.set_option("GAMMA", bad)
+
+
+@pytest.mark.parametrize("levels", [4, 5, 6, 7, 8])
+@pytest.mark.parametrize("gamma", [1, 2])
+def test_level_and_cycle_sweep_iterations_match_oracle(levels, gamma):
+    """The sweep of bench.py --cycle-sweep at 128^2 (coarsest 16^2 down to
+    1 element): FP64 cycle, iterations within 1 of the oracle's pCGMG with
+    the same levels and cycle index."""
+    from workloads import make_problem
+    p = make_problem("wall1024", n=128, levels=levels, mixed=False)
+    o = solve.solve_mgpcg(p.nelx, p.nely, p.x, p.E_phase, p.E_min, p.penal, p.nu, p.F, levels,
+                          rel_tol=1e-8, grad=False, gamma=gamma)
+    s = gpu_solver(p, "fp64")
+    s.set_option("GAMMA", gamma)
+    st = s.solve(1e-8, 1000)[0]
+    assert st["status"] == 0 and st["relres_true"] <= 1.05e-8, st
+    assert abs(st["iters"] - o.iters[0]) <= 1, (levels, gamma, st["iters"], o.iters)
