@@ -178,7 +178,8 @@ int mtomg_compliance_and_grad(mtomg_ctx *ctx, int design, double *c, double *dcd
  * x, in, out: device [nely][nelx][m] FP64; x is read by the sensitivity
  * filter only (densities of the same phases), gmin > 0 keeps void elements
  * finite there (1e-3 is usual).  0 < rf <= 16; rf <= 1 leaves only the
- * element itself.  out must not alias in or x.  Asynchronous on the
+ * element itself.  At most 2^22 columns, 2^20 rows and 2^30 elements.
+ * out must not alias in or x.  Asynchronous on the
  * context's stream; needs no design.  Returns BAD_INPUT for invalid
  * arguments. */
 enum { MTOMG_FILTER_DENSITY = 0, MTOMG_FILTER_DENSITY_ADJOINT = 1, MTOMG_FILTER_SENSITIVITY = 2 };

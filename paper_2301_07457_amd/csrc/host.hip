@@ -1426,8 +1426,9 @@ int mtomg_compliance_and_grad(mtomg_ctx* c, int design, double* cout, double* dc
 int mtomg_filter(mtomg_ctx* c, int nelx, int nely, int m, double rf, int mode, double gmin, const double* x,
                  const double* in, double* out) {
     if (!c) return MTOMG_BAD_INPUT;
-    if (nelx < 1 || nely < 1 || nely > (1 << 20) || (long)nelx * nely > (1L << 30))
-        return fail(c, MTOMG_BAD_INPUT, "filter grid must be 1 .. 2^20 element rows, at most 2^30 elements");
+    if (nelx < 1 || nely < 1 || nelx > (1 << 22) || nely > (1 << 20) || (long)nelx * nely > (1L << 30))
+        return fail(c, MTOMG_BAD_INPUT,
+                    "filter grid must have 1 .. 2^22 columns, 1 .. 2^20 rows and at most 2^30 elements");
     if (m < 1 || m > MAX_PHASES) return fail(c, MTOMG_BAD_INPUT, "m must be in [1, 8]");
     if (!(rf > 0.0 && rf <= FILTER_MAX_RF)) return fail(c, MTOMG_BAD_INPUT, "rf must be in (0, 16]");
     if (mode != MTOMG_FILTER_DENSITY && mode != MTOMG_FILTER_DENSITY_ADJOINT && mode != MTOMG_FILTER_SENSITIVITY)
