@@ -797,6 +797,16 @@ double model_bytes(const Design& d) {
     return bytes;
 }
 
+// The dense coarsest matrix K_0 of a design from its level-0 moments, and
+// its factorisation flags reset to {0, 1, 0, 0} (positive definite so far,
+// factor this design).  The dense block factorisation overwrites K_0 with
+// its trailing updates, so a factorisation that runs again needs this first.
+void assemble_coarsest(hipStream_t st, Design& d) {
+    launch_fill<double>(st, d.A0, (size_t)d.np0 * d.np0, 0.0);
+    launch_assemble_dense(st, false, level_op<double>(d, 0), make_mat<double>(d, d.omega), d.A0, d.np0,
+                          d.chol_status);
+}
+
 // Coarsest factorisation (Algorithm 3 and the explicit inverse) of every
 // design whose densities changed since its last factorisation, on stream
 // st: one launch sequence per group, designs not flagged skip it.  The
@@ -1363,10 +1373,7 @@ int mtomg_set_densities(mtomg_ctx* c, int design, const double* x) {
         launch_moments_tree(st, l + 1 == f, P.op64, P.nx, P.ny, T, n, out);
         l -= n;
     }
-    launch_fill<double>(st, d.A0, (size_t)d.np0 * d.np0, 0.0);
-    // also status = {0, 1, 0, 0}: positive definite so far, factor this design
-    launch_assemble_dense(st, false, level_op<double>(d, 0), make_mat<double>(d, d.omega), d.A0, d.np0,
-                          d.chol_status);
+    assemble_coarsest(st, d);
     LAUNCHCHK(c);
     HIPCHK(c, hipEventRecord(d.ev[1], st));
     d.x_dev = x;
@@ -1680,14 +1687,15 @@ int mtomg_set_option(mtomg_ctx* c, int option, int value) {
         }
         case MTOMG_OPT_DENSE_FACTOR: {
             c->dense_factor = value != 0;
-            // factorisations queued by set_densities run again with the new choice
+            // factorisations queued by set_densities run again with the new
+            // choice, from a freshly assembled K_0 (the dense sequence
+            // overwrites the matrix it factors)
             HIPCHK(c, hipStreamSynchronize(c->side_stream));
             c->fac_inflight = false;
             for (Design& d : c->d) {
                 if (!(d.has_dens && d.needs_factor && d.fac_launched)) continue;
                 d.fac_launched = false;
-                launch_fill<int>(c->stream, d.chol_status, 1, 0);
-                launch_fill<int>(c->stream, d.chol_status + 1, 1, 1);
+                assemble_coarsest(c->stream, d);
             }
             LAUNCHCHK(c);
             return MTOMG_OK;

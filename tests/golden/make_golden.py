@@ -46,13 +46,8 @@ def make(name: str):
     n_nodes = (p.nelx + 1) * (p.nely + 1)
     nodes, elems, phases = sample_indices(n_nodes, p.nelx * p.nely, p.m, 12345)
     Uf = U.reshape(-1, 2)
-    # gradient only at the sampled elements: -p x^(p-1) (E_i - E_min) u_e^T K0 u_e
-    KE = fe.element_stiffness(p.nu)
-    dofs = fe.element_dof_map(p.nelx, p.nely)[elems]
-    ue = U.ravel()[dofs]
-    w = np.einsum("ea,ab,eb->e", ue, KE, ue)
-    xs = p.x.reshape(-1, p.m)[elems, phases]
-    g = -p.penal * np.power(xs, p.penal - 1) * (p.E_phase[phases] - p.E_min) * w
+    # the oracle's gradient (Eq. 6 and the sensitivity step of Section 4), sampled
+    g = fe.compliance_gradient(p.x, U, p.E_phase, p.E_min, p.penal, p.nu).reshape(-1, p.m)[elems, phases]
     out = {
         "workload": name,
         "source": "oracle/solve.py solve_mgpcg (FP64 scipy, pCGMG) to relative residual 1e-11",

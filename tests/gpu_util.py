@@ -20,10 +20,27 @@ def nodal_of(vf: np.ndarray, nx: int, ny: int) -> np.ndarray:
 
 
 def rel(a, b):
+    """||a - b||_2 / ||b||_2."""
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     d = np.linalg.norm(b)
     return np.linalg.norm(a - b) / (d if d > 0 else 1.0)
+
+
+def rel_max(a, b):
+    """max_k |a_k - b_k| / max_k |b_k|: an element-wise bar, which a
+    2-norm bar does not give (a wrong value at one node of a large vector
+    hardly moves the 2-norm)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    d = np.max(np.abs(b)) if b.size else 0.0
+    return float(np.max(np.abs(a - b)) / (d if d > 0 else 1.0)) if b.size else 0.0
+
+
+def relerr(a, b):
+    """The larger of rel(a, b) and rel_max(a, b): a parity test asserting
+    relerr(a, b) <= tol holds both the 2-norm and the element-wise bar."""
+    return max(rel(a, b), rel_max(a, b))
 
 
 class OracleLevels:

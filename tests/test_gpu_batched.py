@@ -14,7 +14,7 @@ import pytest
 import torch
 
 from oracle import solve
-from tests.gpu_util import rel
+from tests.gpu_util import rel, relerr
 from workloads import Problem
 from workloads.square_wall import batched_designs, density_gaussian_sum, four_load_cases
 
@@ -66,10 +66,10 @@ def test_batched_systems_match_oracle(batch):
             assert st["status"] == 0 and st["relres_true"] <= 1.05e-8, (k, q, st)
         U = s.U(k).cpu().numpy()
         for q in range(4):
-            assert rel(U[q], ref.U[q]) <= 1e-6, (k, q)
+            assert relerr(U[q], ref.U[q]) <= 1e-6, (k, q)
         c, dc = s.compliance_and_grad(k)
         np.testing.assert_allclose(c.cpu().numpy(), ref.c, rtol=1e-7)
-        assert rel(dc.cpu().numpy(), ref.dcdx) <= 1e-5
+        assert relerr(dc.cpu().numpy(), ref.dcdx) <= 1e-5
         print(f"[batched] design {k} {p.nelx}x{p.nely} iters={[st['iters'] for st in stats[4*k:4*k+4]]}")
 
 
@@ -103,7 +103,7 @@ def test_design_without_densities_is_untouched():
     stats = s.solve(1e-8, 1000)
     assert len(stats) == 8 and all(st["status"] == 0 for st in stats)
     ref = solve.solve_direct(b.nelx, b.nely, b.x, b.E_phase, b.E_min, b.penal, b.nu, b.F)
-    assert rel(s.U(1).cpu().numpy(), ref.U) <= 1e-6
+    assert relerr(s.U(1).cpu().numpy(), ref.U) <= 1e-6
 
 
 def test_graphs_on_and_off_agree(batch):
@@ -136,7 +136,7 @@ def test_config4_shapes_small_slice():
     for k in range(3):
         p = probs[k]
         ref = solve.solve_direct(p.nelx, p.nely, p.x, p.E_phase, p.E_min, p.penal, p.nu, p.F)
-        assert rel(s.U(k).cpu().numpy(), ref.U) <= 1e-6
+        assert relerr(s.U(k).cpu().numpy(), ref.U) <= 1e-6
     print(f"[config4 slice] solve {stats[0]['t_solve_ms']:.2f} ms, iters "
           f"{sorted(set(st['iters'] for st in stats))}")
 
@@ -156,7 +156,7 @@ def test_non_spd_design_reports_breakdown_and_spares_the_group():
     assert [st["status"] for st in stats[:4]] == [-3] * 4
     assert all(st["status"] == 0 and st["relres_true"] <= 1e-8 for st in stats[4:])
     ref = solve.solve_direct(a.nelx, a.nely, a.x, a.E_phase, a.E_min, a.penal, a.nu, a.F)
-    assert rel(s.U(1).cpu().numpy(), ref.U) <= 1e-6
+    assert relerr(s.U(1).cpu().numpy(), ref.U) <= 1e-6
     # new valid densities clear the failure
     s.set_densities(0, torch.from_numpy(a.x))
     stats = s.solve(1e-8, 1000)
@@ -178,7 +178,7 @@ def test_non_spd_single_design_reports_breakdown():
     stats = s.solve(1e-8, 1000)
     assert all(st["status"] == 0 and st["relres_true"] <= 1e-8 for st in stats)
     ref = solve.solve_direct(a.nelx, a.nely, a.x, a.E_phase, a.E_min, a.penal, a.nu, a.F)
-    assert rel(s.U(0).cpu().numpy(), ref.U) <= 1e-6
+    assert relerr(s.U(0).cpu().numpy(), ref.U) <= 1e-6
 
 
 def test_densities_set_twice_before_a_solve():
@@ -194,4 +194,4 @@ def test_densities_set_twice_before_a_solve():
     stats = s.solve(1e-8, 1000)
     assert all(st["status"] == 0 for st in stats)
     ref = solve.solve_direct(b.nelx, b.nely, b.x, b.E_phase, b.E_min, b.penal, b.nu, b.F)
-    assert rel(s.U(0).cpu().numpy(), ref.U) <= 1e-6
+    assert relerr(s.U(0).cpu().numpy(), ref.U) <= 1e-6

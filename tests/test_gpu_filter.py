@@ -13,7 +13,7 @@ import pytest
 import torch
 
 from oracle import cone_filter as cf
-from tests.gpu_util import rel
+from tests.gpu_util import rel, relerr
 
 pytestmark = pytest.mark.gpu
 
@@ -45,7 +45,7 @@ def test_filter_matches_oracle(solver, nx, ny, m, rf, mode):
     g = rng.standard_normal((ny, nx, m))
     want = oracle(mode, x, g, rf)
     got = solver.filter(torch.from_numpy(g), rf, mode, torch.from_numpy(x)).cpu().numpy()
-    assert rel(got, want) < 1e-13, (mode, rel(got, want))
+    assert relerr(got, want) < 1e-13, (mode, rel(got, want))
     np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-12 * np.abs(want).max())
 
 

@@ -28,7 +28,7 @@ import pytest
 import torch
 
 from oracle import fe, solve
-from tests.gpu_util import gpu_solver, rel
+from tests.gpu_util import gpu_solver, rel, relerr
 from workloads import make_problem
 
 pytestmark = pytest.mark.gpu
@@ -54,10 +54,10 @@ def test_wall256_fp64_matches_direct_solve(wall256):
     st = s.solve(1e-10, 20000)[0]
     assert st["status"] == 0, st
     U = s.U(0).cpu().numpy()
-    assert rel(U, ref.U) <= 1e-6
+    assert relerr(U, ref.U) <= 1e-6
     c, dc = s.compliance_and_grad(0)
     assert c.item() == pytest.approx(ref.c[0], rel=1e-7)
-    assert rel(dc.cpu().numpy(), ref.dcdx) <= 1e-5
+    assert relerr(dc.cpu().numpy(), ref.dcdx) <= 1e-5
     print(f"[wall256] iters={st['iters']} relres={st['relres_true']:.2e} err={rel(U, ref.U):.2e}")
 
 
@@ -152,12 +152,12 @@ def test_fullsize_fp32_cycle_against_oracle_samples(name):
     U = s.U(0).cpu().numpy()
     Uf = U.reshape(-1, 2)
     un = np.array(gold["u_nodes"])
-    assert rel(Uf[gold["nodes"]], un) <= 1e-6
+    assert relerr(Uf[gold["nodes"]], un) <= 1e-6
     assert np.linalg.norm(U) == pytest.approx(gold["u_norm"], rel=1e-6)
     c, dc = s.compliance_and_grad(0)
     assert c.item() == pytest.approx(gold["compliance"], rel=1e-7)
     g = dc[0].cpu().numpy().reshape(-1, p.m)[gold["grad_elems"], gold["grad_phases"]]
-    assert rel(g, gold["grad"]) <= 1e-5
+    assert relerr(g, gold["grad"]) <= 1e-5
     # oracle energy identity on the GPU displacements
     E = fe.interpolate_modulus(p.x, p.E_phase, p.E_min, p.penal)
     energy = np.sum(E * fe.element_energies(U[0], p.nelx, p.nely, p.nu))
@@ -195,10 +195,10 @@ def test_nearbinary_small_matches_direct_solve():
         assert st["status"] == 0 and st["relres_true"] <= 1e-8, (prec, st)
         st = s.solve(1e-10, 20000)[0]
         assert st["status"] == 0 and st["relres_true"] <= 1e-10, (prec, st)
-        assert rel(s.U(0).cpu().numpy(), ref.U) <= 1e-6
+        assert relerr(s.U(0).cpu().numpy(), ref.U) <= 1e-6
         c, dc = s.compliance_and_grad(0)
         assert c.item() == pytest.approx(ref.c[0], rel=1e-7)
-        assert rel(dc.cpu().numpy(), ref.dcdx) <= 1e-5
+        assert relerr(dc.cpu().numpy(), ref.dcdx) <= 1e-5
         print(f"[near-binary 128] {prec} iters={st['iters']}")
 
 
@@ -279,7 +279,7 @@ def test_nearbinary2048_converges_with_oracle_properties(nearbinary2048, prec):
     # u_e^T K0 u_e cancels for near-rigid elements (large u, tiny strain):
     # the kernel's strain/stress form and the oracle's 8x8 product round
     # differently there, by ~1e-11 relative
-    assert rel(dc.reshape(-1, p.m)[els, ph], want) <= 1e-9
+    assert relerr(dc.reshape(-1, p.m)[els, ph], want) <= 1e-9
 
 
 def test_nearbinary2048_precisions_agree(nearbinary2048):

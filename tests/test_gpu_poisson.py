@@ -14,7 +14,7 @@ import pytest
 import torch
 
 from oracle import poisson
-from tests.gpu_util import rel
+from tests.gpu_util import rel, relerr
 
 pytestmark = pytest.mark.gpu
 
@@ -42,7 +42,7 @@ def test_matches_oracle(solver, n):
     assert st["status"] == 0 and st["relres_true"] <= 1.05e-8, st
     assert np.all(u[0, :] == 0) and np.all(u[-1, :] == 0) and np.all(u[:, 0] == 0) and np.all(u[:, -1] == 0)
     ref = poisson.solve_direct(n, F[1:-1, 1:-1].ravel())
-    assert rel(u[1:-1, 1:-1].ravel(), ref) <= 1e-6
+    assert relerr(u[1:-1, 1:-1].ravel(), ref) <= 1e-6
     o = poisson.solve_mgpcg(n, L, F[1:-1, 1:-1].ravel(), rel_tol=1e-8)
     assert abs(st["iters"] - o.iters) <= 1, (st["iters"], o.iters)
     print(f"[poisson] n={n} L={L} iters={st['iters']} (oracle {o.iters}) {st['t_solve_ms']:.3f} ms")
@@ -58,7 +58,7 @@ def test_sweep_counts(solver, pre, post, omega):
     o = poisson.solve_mgpcg(n, 6, F[1:-1, 1:-1].ravel(), omega, pre, post, rel_tol=1e-8)
     assert abs(st["iters"] - o.iters) <= 1, (st["iters"], o.iters)
     ref = poisson.solve_direct(n, F[1:-1, 1:-1].ravel())
-    assert rel(u.cpu().numpy()[1:-1, 1:-1].ravel(), ref) <= 1e-6
+    assert relerr(u.cpu().numpy()[1:-1, 1:-1].ravel(), ref) <= 1e-6
 
 
 @pytest.mark.parametrize("n", [1024, 2048])

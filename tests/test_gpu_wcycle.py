@@ -15,7 +15,7 @@ import pytest
 import torch
 
 from oracle import multigrid, solve
-from tests.gpu_util import OracleLevels, free_of, gpu_solver, rel
+from tests.gpu_util import OracleLevels, free_of, gpu_solver, rel, relerr
 from workloads import Problem, load_top_traction
 
 pytestmark = pytest.mark.gpu
@@ -58,7 +58,7 @@ def test_w_cycle_every_level_matches_oracle(sweeps, prec):
         b = rnd_nodal(rng, nx, ny)
         want = multigrid.cycle(o.H, l, free_of(b, nx), None, prob.omega, n_pre, n_post, gamma=2)
         got = cycle_gpu(s, prec, l, b)
-        assert rel(free_of(got, nx), want) < bar, (prec, sweeps, l)
+        assert relerr(free_of(got, nx), want) < bar, (prec, sweeps, l)
         # the V-cycle differs from it (the option is really in effect)
         v = multigrid.cycle(o.H, l, free_of(b, nx), None, prob.omega, n_pre, n_post, gamma=1)
         if l >= 2:
@@ -79,7 +79,7 @@ def test_w_cycle_deep_hierarchy(prec):
     b = rnd_nodal(rng, nx, ny)
     want = multigrid.cycle(o.H, L - 1, free_of(b, nx), None, prob.omega, 2, 2, gamma=2)
     got = cycle_gpu(s, prec, L - 1, b)
-    assert rel(free_of(got, nx), want) < (2e-11 if prec == "fp64" else 1e-5)
+    assert relerr(free_of(got, nx), want) < (2e-11 if prec == "fp64" else 1e-5)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32mg"])
@@ -98,7 +98,7 @@ def test_w_cycle_pcg_matches_oracle(prec):
     assert abs(st["iters"] - o.iters[0]) <= 1, (st["iters"], o.iters)
     assert st["iters"] <= st_v["iters"], (st["iters"], st_v["iters"])
     U = s.U(0).clone()
-    assert rel(U.cpu().numpy(), ref.U) <= 1e-6
+    assert relerr(U.cpu().numpy(), ref.U) <= 1e-6
     assert not torch.equal(U, U_v)
     # eager launches give the same bits as the captured graphs
     s.set_option("GRAPHS", 0)
