@@ -17,6 +17,9 @@ gradient multigrid method for multi-material topology optimization"):
                   optimisation loop (Section 4, radius rf of Table 2).
 * ``poisson``   — the Poisson model problem of Section 5.1 (scalar Q4,
                   zero boundary values) with its Galerkin hierarchy.
+* ``oc``        — the alternating active-phase optimality-criteria loop of
+                  Section 4 (pairs of phases in Gauss-Seidel order, each a
+                  binary sub-problem with a bisection on the multiplier).
 * ``solve``     — the plain definition u = K_ff^{-1} f_f by a direct solve,
                   and the oracle's own MG-preconditioned CG.
 
@@ -25,4 +28,4 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 and never imports it.
 """
 
-from . import cone_filter, fe, linalg, multigrid, poisson, solve  # noqa: F401
+from . import cone_filter, fe, linalg, multigrid, oc, poisson, solve  # noqa: F401
