@@ -54,7 +54,8 @@ def pair_bounds(ya: np.ndarray, s: np.ndarray, eps: float, move: float):
 
 
 def pair_candidate(ya, d, lo, hi, lam: float, eta: float) -> np.ndarray:
-    """y(lambda) = clamp(ya (max(0, -d) / lambda)^eta, lo, hi)."""
+    """y(lambda) = clamp(ya (max(0, -d) / lambda)^eta, lo, hi); lambda = inf
+    gives lo."""
     if lam <= 0.0:
         return np.where(-d > 0.0, hi, lo)
     return np.clip(ya * (np.maximum(0.0, -d) / lam) ** eta, lo, hi)
@@ -65,12 +66,14 @@ def pair_multiplier(ya, d, lo, hi, target: float, eta: float, rtol: float = 1e-1
     """lambda with sum_e y_e(lambda) = target, by bisection on [0, lambda_hi],
     lambda_hi the smallest multiplier that puts every element at lo.  The
     sum is non-increasing in lambda; a target above sum(y(0+)) drives
-    lambda to 0 (every element with d < 0 at hi), a target below sum(lo)
-    to lambda_hi (every element at lo)."""
+    lambda to 0 (every element with d < 0 at hi), a target at or below
+    sum(lo) gives lambda = inf (every element at lo, exactly)."""
     g = np.maximum(0.0, -d)
     lam_hi = float(np.max(g * (ya / lo) ** (1.0 / eta))) if g.size else 0.0
     if lam_hi <= 0.0:
         return 0.0
+    if target <= np.sum(lo):
+        return np.inf          # every element exactly at lo
     l1, l2 = 0.0, lam_hi
     for _ in range(max_steps):
         mid = 0.5 * (l1 + l2)
