@@ -49,7 +49,7 @@ enum {
                               /* above rel_tol; U holds the last iterate         */
     MTOMG_BREAKDOWN = -3,     /* p^T K p <= 0 or z^T r <= 0 inside PCG, or the   */
                               /* coarsest matrix is not positive definite        */
-    MTOMG_NAN = -4,           /* non-finite residual                             */
+    MTOMG_NAN = -4,           /* non-finite residual or non-finite densities     */
     MTOMG_WORKSPACE = -5,     /* workspace missing or too small                  */
     MTOMG_HIP_ERROR = -6,     /* a HIP runtime call failed                       */
     MTOMG_STATE = -7          /* call out of order (e.g. solve before set_grid)  */
@@ -62,7 +62,8 @@ enum { MTOMG_FP64 = 0, MTOMG_FP32MG = 1 };
 
 /* Per (design, load case) solve statistics. */
 typedef struct {
-    int32_t status;      /* MTOMG_OK / NOT_CONVERGED / BREAKDOWN / NAN        */
+    int32_t status;      /* MTOMG_OK / NOT_CONVERGED / BREAKDOWN / NAN, or    */
+                         /* BAD_INPUT for densities outside [0, 1]            */
     int32_t iters;       /* PCG iterations (updates of u), all runs            */
     int32_t vcycles;     /* preconditioner applications                        */
     int32_t n_dof;       /* 2 (nelx+1)(nely+1), clamped DOFs included          */
@@ -86,6 +87,10 @@ int mtomg_create(mtomg_ctx **ctx, int max_designs, void *hip_stream);
 int mtomg_destroy(mtomg_ctx *ctx);
 
 /* Describe design `design` (0 <= design < max_designs).
+ * The wall is the rectangle [0, nelx h] x [0, nely h] of square elements of
+ * side h and thickness 1.  There is no h argument: the plane-stress element
+ * stiffness of Eqs. (7)-(9) does not depend on the element size in 2D, so h
+ * enters only through the loads, which the caller gives as nodal forces F.
  *   nelx, nely   element counts; both divisible by 2^(levels-1), and the
  *                coarsest grid at most 32 x 32 elements
  *                (its dense inverse is kept in device memory).
@@ -93,7 +98,10 @@ int mtomg_destroy(mtomg_ctx *ctx);
  *   m, E_phase   number of solid phases and their moduli (host [m]), Eq. (5).
  *   E_min        modulus of the void phase, > 0.
  *   penal        SIMP exponent p >= 1 of Eq. (5).
- *   levels       number of grids of the hierarchy (Algorithm 1), >= 1.
+ *   levels       number of grids of the hierarchy (Algorithm 1), 2..14.
+ *                One grid is not accepted: its "cycle" would be the exact
+ *                coarsest solve of the whole system, a direct method
+ *                rather than the multigrid preconditioner.
  *   n_pre/n_post damped-Jacobi sweeps before/after the coarse correction
  *                (theta_1, theta_2 of Algorithm 1), 0..8; equal values
  *                keep the preconditioner symmetric (Section 2.2).
@@ -130,9 +138,12 @@ int mtomg_set_workspace(mtomg_ctx *ctx, void *dev, size_t bytes);
  * whose densities changed (one launch sequence for all of them).  Either way
  * the first coarse solve of the next solve waits for it.
  * x: device [nely][nelx][m] FP64 in [0, 1], read in stream order (keep it
- * alive until the work is done).  Asynchronous; a coarsest matrix that is
- * not positive definite is reported by the next solve (status BREAKDOWN
- * for every load case of the design). */
+ * alive until the work is done).  Asynchronous, so x is checked on the
+ * device, and the next solve reports the result for every load case of the
+ * design without extra synchronisation: BAD_INPUT if some density lies
+ * outside [0, 1], NAN if some density is not finite, BREAKDOWN if the
+ * coarsest matrix is not positive definite.  Such a design takes no further
+ * PCG runs after the first, and its U then holds no solution. */
 int mtomg_set_densities(mtomg_ctx *ctx, int design, const double *x);
 
 /* Solve every load case of every design that has densities: PCG
@@ -185,6 +196,58 @@ int mtomg_compliance_and_grad(mtomg_ctx *ctx, int design, double *c, double *dcd
 enum { MTOMG_FILTER_DENSITY = 0, MTOMG_FILTER_DENSITY_ADJOINT = 1, MTOMG_FILTER_SENSITIVITY = 2 };
 int mtomg_filter(mtomg_ctx *ctx, int nelx, int nely, int m, double rf, int mode, double gmin, const double *x,
                  const double *in, double *out);
+
+/* One binary sub-problem of the alternating active-phase optimality-criteria
+ * update (Section 4: pairs of active phases, Gauss-Seidel order; parameters
+ * of Table 2).  The paper does not write the update out; this is the
+ * reading implemented.  x holds the m solid phases, the void share
+ * 1 - sum_i x_i is implicit (phase index m) and has no sensitivity.  For
+ * phases a < b (b = m: the void), with s_e = x_{e,a} + x_{e,b} held fixed per
+ * element and the pair sensitivity d_e = g_{e,a} - g_{e,b}:
+ *   lo_e = max(eps, x_{e,a} - move),  hi_e = min(1, s_e - eps, x_{e,a} + move),
+ *   y_e(lambda) = clamp(x_{e,a} (max(0, -d_e) / lambda)^eta, lo_e, hi_e),
+ * with lambda > 0 chosen so that sum_e y_e = vol_a nelx nely (the volume of
+ * phase a); then x_{e,a} = y_e and x_{e,b} = s_e - y_e.  lambda is found on
+ * the device (Newton steps on the piecewise-linear volume sum, kept in a
+ * bracket); a target outside the reachable range puts every element at
+ * its lower (or every element with d_e < 0 at its upper) bound.
+ *   g:     device [nely][nelx][m] FP64, the (filtered) compliance gradient.
+ *   x:     device [nely][nelx][m] FP64, updated in place; every phase, void
+ *          included, must lie in [eps, 1] on entry and stays there.
+ *   vol_a: target volume fraction of phase a, in [0, 1].
+ *   move > 0, eta in (0, 2] (1/2 is usual), eps in (0, 1/(2(m+1))).
+ *   info:  host [4] or NULL: lambda, the largest |change| of x_{e,a},
+ *          sum y - target, and the number of passes (+ 0.5 if the pass
+ *          limit ended it before convergence); with info the call
+ *          synchronises, otherwise it is asynchronous.
+ * Uses a workspace the context allocates on first use.  Returns BAD_INPUT
+ * for invalid arguments. */
+int mtomg_oc_update(mtomg_ctx *ctx, int nelx, int nely, int m, int a, int b, const double *g, double vol_a,
+                    double move, double eta, double eps, double *x, double *info);
+
+/* One outer iteration of the alternating active-phase loop (Section 4) on
+ * design `design`, which must be the only design of its context with
+ * densities: for every pair (a, b), a < b, in the order (0,1), (0,2), ...,
+ * (0,m), (1,2), ..., (m-1,m), with the densities left by the previous pair,
+ * set_densities(x), a warm-started solve (from U) to rel_tol, compliance and
+ * gradient of every load case, the gradient summed over the load cases, the
+ * sensitivity filter of radius rf (floor gmin, mtomg_filter) on each solid
+ * phase, then mtomg_oc_update with the target vols[a].
+ *   vols:    host [m+1] target volume fractions, void last, summing to 1.
+ *   x:       device [nely][nelx][m], the densities, updated in place (every
+ *            phase, void included, in [eps, 1]).
+ *   c_pairs: host [m(m+1)/2], the compliance summed over load cases before
+ *            each pair's update.
+ *   change:  host, the largest change of any density (void included) over
+ *            the iteration; the loop stops when it is at most tol
+ *            (Table 2: 1e-3).
+ *   iters:   host [m(m+1)/2] or NULL: PCG iterations of each pair's solve
+ *            (the most over the load cases).
+ * A solve that does not reach rel_tol ends the step with its status.
+ * Blocks until done. */
+int mtomg_aap_step(mtomg_ctx *ctx, int design, const double *vols, double rf, double move, double eta, double eps,
+                   double gmin, double rel_tol, int max_iter, double *x, double *c_pairs, double *change,
+                   int *iters);
 
 /* The Poisson model problem of Section 5.1: -Laplace(u) = f on the unit
  * square with u = 0 on the whole boundary, bilinear (Q4) elements on an

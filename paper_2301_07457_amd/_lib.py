@@ -31,7 +31,8 @@ EXPORTS = ["mtomg_create", "mtomg_destroy", "mtomg_set_grid", "mtomg_workspace_b
            "mtomg_set_workspace", "mtomg_set_densities", "mtomg_solve",
            "mtomg_compliance_and_grad", "mtomg_status_string", "mtomg_last_error",
            "mtomg_debug_apply", "mtomg_profile_kernel", "mtomg_profile_read",
-           "mtomg_set_option", "mtomg_filter", "mtomg_poisson_solve"]
+           "mtomg_set_option", "mtomg_filter", "mtomg_poisson_solve", "mtomg_oc_update",
+           "mtomg_aap_step"]
 
 OPTIONS = dict(GRAPHS=0, BATCH=1, ROWS_FINE=2, ROWS_COARSE=3, DENSE_FACTOR=4, GAMMA=5)
 
@@ -95,6 +96,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mtomg_profile_kernel.argtypes = [vp, i]
     lib.mtomg_set_option.argtypes = [vp, i, i]
     lib.mtomg_filter.argtypes = [vp, i, i, i, d, i, d, dp, dp, dp]
+    lib.mtomg_oc_update.argtypes = [vp, i, i, i, i, i, dp, d, d, d, d, dp, ctypes.POINTER(d)]
+    lib.mtomg_aap_step.argtypes = [vp, i, ctypes.POINTER(d), d, d, d, d, d, d, i, dp, ctypes.POINTER(d),
+                                   ctypes.POINTER(d), ctypes.POINTER(i)]
     lib.mtomg_poisson_solve.argtypes = [vp, i, i, i, d, d, i, dp, dp, ctypes.POINTER(mtomg_stats)]
     lib.mtomg_profile_read.argtypes = [vp, ctypes.POINTER(d), i, ctypes.POINTER(i)]
     for name in EXPORTS:
@@ -150,8 +154,15 @@ def mtomg_set_densities(ctx, design, x_ptr):
 
 def mtomg_solve(ctx, rel_tol, max_iter, warm_start, n_systems):
     stats = (mtomg_stats * n_systems)()
+    for s in stats:
+        s.status = 1   # not a status code: marks entries the call did not write
     st = load().mtomg_solve(ctx, rel_tol, max_iter, int(warm_start), stats)
-    check(ctx, st, allow=(MTOMG_NOT_CONVERGED, MTOMG_BREAKDOWN, MTOMG_NAN))
+    # per-system outcomes come back in stats; BAD_INPUT is one of them only
+    # when some system reports it (invalid densities), else the call failed
+    per_system = (MTOMG_NOT_CONVERGED, MTOMG_BREAKDOWN, MTOMG_NAN)
+    if st == MTOMG_BAD_INPUT and any(s.status == MTOMG_BAD_INPUT for s in stats):
+        per_system = per_system + (MTOMG_BAD_INPUT,)
+    check(ctx, st, allow=per_system)
     return st, [s.as_dict() for s in stats]
 
 
@@ -205,3 +216,26 @@ def mtomg_filter(ctx, nelx: int, nely: int, m: int, rf: float, mode: str, gmin: 
     return check(ctx, load().mtomg_filter(ctx, nelx, nely, m, float(rf), FILTERS[mode], float(gmin),
                                           ctypes.c_void_p(x_ptr or None), ctypes.c_void_p(in_ptr or None),
                                           ctypes.c_void_p(out_ptr or None)))
+
+
+def mtomg_oc_update(ctx, nelx: int, nely: int, m: int, a: int, b: int, g_ptr: int, vol_a: float, move: float,
+                    eta: float, eps: float, x_ptr: int):
+    """Returns info: (lambda, largest change, sum - target, passes)."""
+    info = (ctypes.c_double * 4)()
+    check(ctx, load().mtomg_oc_update(ctx, nelx, nely, m, a, b, ctypes.c_void_p(g_ptr), float(vol_a), float(move),
+                                      float(eta), float(eps), ctypes.c_void_p(x_ptr), info))
+    return tuple(info)
+
+
+def mtomg_aap_step(ctx, design: int, vols, rf: float, move: float, eta: float, eps: float, gmin: float,
+                   rel_tol: float, max_iter: int, x_ptr: int):
+    """Returns (compliance before each pair, largest change, PCG iterations per pair)."""
+    m = len(vols) - 1
+    npairs = m * (m + 1) // 2
+    v = (ctypes.c_double * (m + 1))(*[float(t) for t in vols])
+    cp = (ctypes.c_double * npairs)()
+    ch = ctypes.c_double(0.0)
+    it = (ctypes.c_int * npairs)()
+    check(ctx, load().mtomg_aap_step(ctx, design, v, float(rf), float(move), float(eta), float(eps), float(gmin),
+                                     float(rel_tol), int(max_iter), ctypes.c_void_p(x_ptr), cp, ctypes.byref(ch), it))
+    return list(cp), ch.value, list(it)

@@ -36,6 +36,7 @@
 #include "../../include/mtomg.h"
 #include "filter_kernels.h"
 #include "kernels.h"
+#include "oc_kernels.h"
 #include "poisson_kernels.h"
 
 using namespace mtomg;
@@ -73,6 +74,8 @@ struct Design {
     bool needs_factor = false;   // densities set since the last factorisation
     bool fac_launched = false;   // its factorisation is queued on the side stream, not yet finalised
     bool fac_failed = false;     // coarsest matrix not positive definite
+    int dens_seq = 0;            // number of the last set_densities call (1 .. 2^29 - 1)
+    int x_code = 0;              // densities of that call: 0 valid, 1 outside [0, 1], 2 not finite
     int nelx = 0, nely = 0, m = 0, levels = 0, n_pre = 2, n_post = 2, precision = 0, n_cases = 1;
     double nu = 0.3, E_min = 1e-9, penal = 3.0, omega = 0.6;
     double E_phase[MAX_PHASES] = {};
@@ -81,7 +84,7 @@ struct Design {
     std::vector<LevelBufs> lev;   // 0 = coarsest
     int n0 = 0, np0 = 0;   // coarsest free DOFs, padded to the block size
     double *A0 = nullptr, *W0 = nullptr, *Ainv = nullptr, *Dinv = nullptr, *Lbuf = nullptr, *Sacc = nullptr;
-    int* chol_status = nullptr;   // [0] not positive definite, [1] factor pending
+    int* chol_status = nullptr;   // [0] not positive definite, [1] factor pending, [2] input check (k_interp)
     std::vector<CaseBufs> cases;
     const double* x_dev = nullptr;
     int group = -1, gidx = 0;     // group and position in it
@@ -162,6 +165,10 @@ struct mtomg_ctx {
     double* pois_buf = nullptr;           // mtomg_poisson_solve workspace
     size_t pois_bytes = 0;
     double* pois_host = nullptr;          // pinned copies of its scalars
+    double* oc_buf = nullptr;             // OC update and optimisation-step workspace (grown on demand)
+    size_t oc_bytes = 0;
+    double* oc_host = nullptr;            // pinned: compliance per pair and load case, change, state
+    size_t oc_host_bytes = 0;
     hipStream_t cap_stream = nullptr;     // capture stream (default priority)
     hipStream_t side_stream = nullptr;    // coarsest factorisations during a solve (default priority)
     hipEvent_t ev_fac[2] = {nullptr, nullptr};   // [0] main -> side, [1] side -> main
@@ -400,6 +407,8 @@ int ensure_workspace(mtomg_ctx* c) {
     layout_into(c->d, c->groups, reinterpret_cast<char*>(c->ws));
     int total = 0;
     for (Group& g : c->groups) {
+        // input-check words start at zero (k_interp only raises them)
+        launch_fill_strided(c->stream, c->d[g.designs[0]].chol_status + 2, g.ds, (int)g.designs.size(), 0);
         std::vector<const double*> F;
         std::vector<double*> U;
         for (int di : g.designs)
@@ -865,6 +874,8 @@ int factor_finalize(mtomg_ctx* c) {
                 HIPCHK(c, hipEventElapsedTime(&ms, d.ev[0], d.ev[1]));
                 d.t_setup_ms = ms + fac_ms;
                 d.fac_failed = c->host_chol[4 * (sys0 + k)] != 0;
+                const int xv = c->host_chol[4 * (sys0 + k) + 2];
+                d.x_code = (xv >> 2) == d.dens_seq ? (xv & 3) : 0;
                 d.needs_factor = false;
                 d.fac_launched = false;
             }
@@ -1099,7 +1110,7 @@ int solve_all(mtomg_ctx* c, double rel_tol, int max_iter, int warm, mtomg_stats*
         gsys0[gi] = n_sys;
         for (size_t k = 0; k < g.designs.size(); ++k) {
             const Design& d = c->d[g.designs[k]];
-            const int v = (d.has_dens && !d.fac_failed) ? 0 : ST_INACTIVE;
+            const int v = (d.has_dens && !d.fac_failed && !d.x_code) ? 0 : ST_INACTIVE;
             for (int q = 0; q < g.cpd; ++q) {
                 int* h = c->host_state + 4 * (n_sys + (int)k * g.cpd + q);
                 h[0] = v;
@@ -1136,7 +1147,8 @@ int solve_all(mtomg_ctx* c, double rel_tol, int max_iter, int warm, mtomg_stats*
             if (round == 0) first_round_most = std::max(first_round_most, iters[q]);
             for (int k = 0; k < 3; ++k) sums[3 * q + k] = c->host_sums[4 * q + k];
             const double ff = sums[3 * q];
-            const bool ok = (state[q] == 1 || state[q] == 2) && !c->d[sys_design[q]].fac_failed;
+            const Design& dq = c->d[sys_design[q]];
+            const bool ok = (state[q] == 1 || state[q] == 2) && !dq.fac_failed && !dq.x_code;
             if (ok && ff > 0.0 && sums[3 * q + 2] > tol2 * ff) {
                 again.push_back(q);
                 used = std::max(used, iters[q]);
@@ -1163,6 +1175,11 @@ int solve_all(mtomg_ctx* c, double rel_tol, int max_iter, int warm, mtomg_stats*
             o.n_dof = (int)(2 * d.lev[d.fine()].nodes());
             o.t_setup_ms = d.t_setup_ms;
             o.model_bytes = model_bytes(d);
+            if (d.x_code) {   // densities outside [0, 1] or not finite (checked by k_interp)
+                o.status = d.x_code == 2 ? MTOMG_NAN : MTOMG_BAD_INPUT;
+                worst = std::min(worst, o.status);
+                continue;
+            }
             if (d.fac_failed) {
                 o.status = MTOMG_BREAKDOWN;
                 worst = std::min(worst, (int)MTOMG_BREAKDOWN);
@@ -1243,6 +1260,8 @@ int mtomg_destroy(mtomg_ctx* c) {
     if (c->filt_host) hipHostFree(c->filt_host);
     if (c->pois_buf) hipFree(c->pois_buf);
     if (c->pois_host) hipHostFree(c->pois_host);
+    if (c->oc_buf) hipFree(c->oc_buf);
+    if (c->oc_host) hipHostFree(c->oc_host);
     for (hipEvent_t& e : c->prof.ev)
         if (e) hipEventDestroy(e);
     delete c;
@@ -1348,7 +1367,10 @@ int mtomg_set_densities(mtomg_ctx* c, int design, const double* x) {
     HIPCHK(c, hipEventRecord(d.ev[0], st));
     const int f = d.fine();
     LevelBufs& Lf = d.lev[f];
-    launch_interp(st, x, phases_of(d), Lf.nx * Lf.ny, Lf.op64, d.mixed() ? Lf.op32 : nullptr);
+    d.dens_seq = d.dens_seq % ((1 << 29) - 1) + 1;
+    d.x_code = 0;
+    launch_interp(st, x, phases_of(d), Lf.nx * Lf.ny, Lf.op64, d.mixed() ? Lf.op32 : nullptr, d.chol_status + 2,
+                  d.dens_seq);
     // coarse moments, up to five levels per launch (tiles of 16 x 16 elements
     // or the largest power of two dividing the level; 1 falls back to one
     // launch per level)
@@ -1646,13 +1668,159 @@ int mtomg_poisson_solve(mtomg_ctx* c, int n, int n_pre, int n_post, double omega
     return status;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Device workspace of the OC calls, grown on demand (never shrunk).
+int oc_reserve(mtomg_ctx* c, size_t bytes, size_t host_bytes) {
+    if (bytes > c->oc_bytes) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (c->oc_buf) HIPCHK(c, hipFree(c->oc_buf));
+        c->oc_buf = nullptr;
+        c->oc_bytes = 0;
+        HIPCHK(c, hipMalloc(&c->oc_buf, bytes));
+        c->oc_bytes = bytes;
+    }
+    if (host_bytes > c->oc_host_bytes) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (c->oc_host) HIPCHK(c, hipHostFree(c->oc_host));
+        c->oc_host = nullptr;
+        c->oc_host_bytes = 0;
+        HIPCHK(c, hipHostMalloc((void**)&c->oc_host, host_bytes, hipHostMallocDefault));
+        c->oc_host_bytes = host_bytes;
+    }
+    return MTOMG_OK;
+}
+
+const char* oc_args_error(int nelx, int nely, int m, int a, int b, double vol_a, double move, double eta,
+                          double eps) {
+    if (nelx < 1 || nely < 1 || (long)nelx * nely > (1L << 30)) return "grid must have 1 .. 2^30 elements";
+    if (m < 1 || m > MAX_PHASES) return "m must be in [1, 8]";
+    if (!(a >= 0 && a < b && b <= m)) return "phases must satisfy 0 <= a < b <= m (b = m: the void)";
+    if (!(vol_a >= 0.0 && vol_a <= 1.0)) return "volume fraction must be in [0, 1]";
+    if (!(move > 0.0 && std::isfinite(move))) return "move must be finite and > 0";
+    if (!(eta > 0.0 && eta <= 2.0)) return "eta must be in (0, 2]";
+    if (!(eps > 0.0 && eps < 0.5 / (m + 1))) return "eps must be in (0, 1 / (2 (m + 1)))";
+    return nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mtomg_oc_update(mtomg_ctx* c, int nelx, int nely, int m, int a, int b, const double* g, double vol_a,
+                    double move, double eta, double eps, double* x, double* info) {
+    if (!c) return MTOMG_BAD_INPUT;
+    if (const char* msg = oc_args_error(nelx, nely, m, a, b, vol_a, move, eta, eps))
+        return fail(c, MTOMG_BAD_INPUT, msg);
+    if (!g || !x) return fail(c, MTOMG_BAD_INPUT, "g and x must be device pointers");
+    if (g == x) return fail(c, MTOMG_BAD_INPUT, "g must not alias x");
+    const int n_e = nelx * nely;
+    const size_t nd = oc_scratch_doubles(n_e);
+    int rc = oc_reserve(c, nd * sizeof(double) + sizeof(OcState) + 256, sizeof(OcState));
+    if (rc) return rc;
+    double* scratch = c->oc_buf;
+    OcState* state = reinterpret_cast<OcState*>(scratch + nd);
+    const OcPair op{n_e, m, a, b, eta, move, eps, vol_a * n_e};
+    launch_oc_pair(c->stream, op, g, x, scratch, state);
+    LAUNCHCHK(c);
+    if (info) {
+        HIPCHK(c, hipMemcpyAsync(c->oc_host, state, sizeof(OcState), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        const OcState* hs = reinterpret_cast<const OcState*>(c->oc_host);
+        info[0] = hs->lambda;
+        info[1] = hs->change;
+        info[2] = hs->S - op.target;
+        info[3] = hs->passes + (hs->done ? 0.0 : 0.5);
+    }
+    return MTOMG_OK;
+}
+
+int mtomg_aap_step(mtomg_ctx* c, int design, const double* vols, double rf, double move, double eta, double eps,
+                   double gmin, double rel_tol, int max_iter, double* x, double* c_pairs, double* change,
+                   int* iters) {
+    int rc = check_design(c, design, false);
+    if (rc) return rc;
+    Design& d = c->d[design];
+    if (!vols || !x || !c_pairs || !change) return fail(c, MTOMG_BAD_INPUT, "vols, x, c_pairs and change are required");
+    for (int k = 0; k < (int)c->d.size(); ++k)
+        if (k != design && c->d[k].has_grid && c->d[k].has_dens)
+            return fail(c, MTOMG_BAD_INPUT, "the optimised design must be the only design of its context with densities");
+    double vsum = 0.0;
+    for (int i = 0; i <= d.m; ++i) {
+        if (!(vols[i] >= 0.0 && vols[i] <= 1.0)) return fail(c, MTOMG_BAD_INPUT, "volume fractions must be in [0, 1]");
+        vsum += vols[i];
+    }
+    if (std::fabs(vsum - 1.0) > 1e-12) return fail(c, MTOMG_BAD_INPUT, "volume fractions (void last) must sum to 1");
+    if (const char* msg = oc_args_error(d.nelx, d.nely, d.m, 0, 1, vols[0], move, eta, eps))
+        return fail(c, MTOMG_BAD_INPUT, msg);
+    if (!(rf > 0.0 && rf <= FILTER_MAX_RF)) return fail(c, MTOMG_BAD_INPUT, "rf must be in (0, 16]");
+    if (!(gmin > 0.0 && std::isfinite(gmin))) return fail(c, MTOMG_BAD_INPUT, "gmin must be finite and > 0");
+    const int n_e = d.nelx * d.nely, m = d.m, nc = d.n_cases;
+    const size_t ne_m = (size_t)n_e * m;
+    const int npairs = m * (m + 1) / 2;
+    // device: OC scratch | state | dcdx [nc][n_e][m] | gsum | gfilt | x0 | c [nc] | change partials | change
+    const size_t nd = oc_scratch_doubles(n_e);
+    const size_t off_state = nd;
+    const size_t off_dc = off_state + (sizeof(OcState) + 7) / 8;
+    const size_t off_gs = off_dc + (size_t)nc * ne_m;
+    const size_t off_gf = off_gs + ne_m;
+    const size_t off_x0 = off_gf + ne_m;
+    const size_t off_c = off_x0 + ne_m;
+    const size_t off_cp = off_c + nc;
+    const size_t off_ch = off_cp + OC_BLOCKS;
+    const size_t total = off_ch + 1;
+    rc = oc_reserve(c, total * sizeof(double), ((size_t)npairs * nc + 1) * sizeof(double));
+    if (rc) return rc;
+    double* B = c->oc_buf;
+    OcState* state = reinterpret_cast<OcState*>(B + off_state);
+    double* hc = c->oc_host;
+    hipStream_t st = c->stream;
+    HIPCHK(c, hipMemcpyAsync(B + off_x0, x, ne_m * sizeof(double), hipMemcpyDeviceToDevice, st));
+    std::vector<mtomg_stats> stats(nc);
+    int pair = 0;
+    for (int a = 0; a < m; ++a) {
+        for (int b = a + 1; b <= m; ++b, ++pair) {
+            rc = mtomg_set_densities(c, design, x);
+            if (rc) return rc;
+            rc = solve_all(c, rel_tol, max_iter, 1, stats.data());
+            if (rc != MTOMG_OK) return rc == MTOMG_HIP_ERROR ? rc : fail(c, rc, std::string("solve in the OC step: ") + mtomg_status_string(rc));
+            if (iters) {
+                iters[pair] = 0;
+                for (const mtomg_stats& o : stats) iters[pair] = std::max(iters[pair], (int)o.iters);
+            }
+            rc = mtomg_compliance_and_grad(c, design, B + off_c, B + off_dc);
+            if (rc) return rc;
+            HIPCHK(c, hipMemcpyAsync(hc + (size_t)pair * nc, B + off_c, nc * sizeof(double), hipMemcpyDeviceToHost, st));
+            launch_sum_cases(st, B + off_dc, nc, ne_m, B + off_gs);
+            rc = mtomg_filter(c, d.nelx, d.nely, m, rf, MTOMG_FILTER_SENSITIVITY, gmin, x, B + off_gs, B + off_gf);
+            if (rc) return rc;
+            const OcPair op{n_e, m, a, b, eta, move, eps, vols[a] * n_e};
+            launch_oc_pair(st, op, B + off_gf, x, B, state);
+            LAUNCHCHK(c);
+        }
+    }
+    launch_oc_change(st, B + off_x0, x, n_e, m, B + off_cp, B + off_ch);
+    HIPCHK(c, hipMemcpyAsync(hc + (size_t)npairs * nc, B + off_ch, sizeof(double), hipMemcpyDeviceToHost, st));
+    LAUNCHCHK(c);
+    HIPCHK(c, hipStreamSynchronize(st));
+    for (int k = 0; k < npairs; ++k) {
+        double sum = 0.0;
+        for (int q = 0; q < nc; ++q) sum += hc[(size_t)k * nc + q];
+        c_pairs[k] = sum;
+    }
+    *change = hc[(size_t)npairs * nc];
+    return MTOMG_OK;
+}
+
 const char* mtomg_status_string(int s) {
     switch (s) {
         case MTOMG_OK: return "ok";
-        case MTOMG_BAD_INPUT: return "bad input";
+        case MTOMG_BAD_INPUT: return "bad input (an argument, or densities outside [0, 1])";
         case MTOMG_NOT_CONVERGED: return "not converged (max_iter reached)";
         case MTOMG_BREAKDOWN: return "breakdown (p^T K p <= 0 or z^T r <= 0, or coarsest matrix not SPD)";
-        case MTOMG_NAN: return "non-finite residual";
+        case MTOMG_NAN: return "non-finite residual or densities";
         case MTOMG_WORKSPACE: return "workspace missing or too small";
         case MTOMG_HIP_ERROR: return "HIP runtime error";
         case MTOMG_STATE: return "call out of order";

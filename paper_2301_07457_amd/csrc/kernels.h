@@ -121,7 +121,9 @@ struct Phases {
     int m;
     double E_min, penal;
 };
-void launch_interp(hipStream_t st, const double* x, Phases ph, int n_e, double* E64, float* E32);
+// flag: the design's input-check word (see k_interp); seq: this call's number (0 .. 2^29 - 1)
+void launch_interp(hipStream_t st, const double* x, Phases ph, int n_e, double* E64, float* E32, int* flag,
+                   int seq);
 void launch_moments_from_fine(hipStream_t st, const double* E64, int nxf, int nyf, double* mom64,
                               float* mom32);
 void launch_moments_coarsen(hipStream_t st, const double* momf, int nxf, int nyf, double* mom64,

@@ -23,14 +23,24 @@ __device__ __forceinline__ double powp(double x, double p) {
     return pow(x, p);
 }
 
+// Element moduli (Eq. 5).  Densities outside [0, 1] (code 1) or not finite
+// (code 2) are reported in *flag as (seq << 2) | code by an atomic maximum,
+// so a later reader can tell this call's report from an older one and a
+// non-finite entry outranks an out-of-range one; valid inputs write nothing.
 __global__ void k_interp(const double* __restrict__ x, Phases ph, int n_e, double* __restrict__ E64,
-                         float* __restrict__ E32) {
+                         float* __restrict__ E32, int* __restrict__ flag, int seq) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n_e) return;
     double E = ph.E_min;
-    for (int k = 0; k < ph.m; ++k) E += powp(x[(size_t)e * ph.m + k], ph.penal) * ph.dE[k];
+    int code = 0;
+    for (int k = 0; k < ph.m; ++k) {
+        const double v = x[(size_t)e * ph.m + k];
+        if (!(v >= 0.0 && v <= 1.0)) code = max(code, isfinite(v) ? 1 : 2);
+        E += powp(v, ph.penal) * ph.dE[k];
+    }
     E64[e] = E;
     if (E32) E32[e] = (float)E;
+    if (code && flag) atomicMax(flag, (seq << 2) | code);
 }
 
 __global__ void k_moments_from_fine(const double* __restrict__ E, int nxf, int nyf, double* __restrict__ m64,
@@ -143,8 +153,6 @@ __global__ void k_assemble_dense(LevelOp<double> op, Mat<double> mat, double* __
         // positive definite so far; factor this design at the next opportunity
         status[0] = 0;
         status[1] = 1;
-        status[2] = 0;
-        status[3] = 0;
     }
     const int node = t / 9, o = t % 9;
     if (node >= (nx + 1) * ny) return;
@@ -895,8 +903,9 @@ __global__ __launch_bounds__(WG_THREADS) void k_sums(SumJob job, double* __restr
 // ---------------------------------------------------------------------------
 static inline unsigned blocks_for(size_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
 
-void launch_interp(hipStream_t st, const double* x, Phases ph, int n_e, double* E64, float* E32) {
-    hipLaunchKernelGGL(k_interp, dim3(blocks_for(n_e, 256)), dim3(256), 0, st, x, ph, n_e, E64, E32);
+void launch_interp(hipStream_t st, const double* x, Phases ph, int n_e, double* E64, float* E32, int* flag,
+                   int seq) {
+    hipLaunchKernelGGL(k_interp, dim3(blocks_for(n_e, 256)), dim3(256), 0, st, x, ph, n_e, E64, E32, flag, seq);
 }
 void launch_moments_from_fine(hipStream_t st, const double* E64, int nxf, int nyf, double* m64, float* m32) {
     const int n = (nxf / 2) * (nyf / 2);

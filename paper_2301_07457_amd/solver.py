@@ -146,6 +146,47 @@ class PCGMGSolver:
                               a.data_ptr(), o.data_ptr())
         return out
 
+    def oc_update(self, x: torch.Tensor, g: torch.Tensor, a: int, b: int, vol_a: float, move: float = 0.2,
+                  eta: float = 0.5, eps: float = 1e-3):
+        """mtomg_oc_update: one binary OC sub-problem on phases a < b (b = m:
+        the void) of the densities x [nely][nelx][m] (CUDA float64, updated
+        in place) with the filtered gradient g.  Returns (lambda, largest
+        change, volume sum - target, passes)."""
+        ny, nx, m = x.shape
+        if not (x.is_cuda and x.dtype == torch.float64 and x.is_contiguous()):
+            raise ValueError("x must be a contiguous CUDA float64 tensor (updated in place)")
+        gd = g.to(self.device, torch.float64).contiguous()
+        return _lib.mtomg_oc_update(self.ctx, nx, ny, m, a, b, gd.data_ptr(), vol_a, move, eta, eps, x.data_ptr())
+
+    def aap_step(self, design: int, x: torch.Tensor, vols, rf: float = 8.0, move: float = 0.2, eta: float = 0.5,
+                 eps: float = 1e-3, gmin: float = 1e-3, rel_tol: float = 1e-8, max_iter: int = 1000):
+        """mtomg_aap_step: one outer iteration of the alternating active-phase
+        loop on `design` (every pair: solve, gradient, sensitivity filter,
+        OC update).  x [nely][nelx][m] is updated in place and stays the
+        design's densities.  Returns (compliance before each pair, largest
+        change, PCG iterations per pair)."""
+        info = self.designs[design]
+        if not (x.is_cuda and x.dtype == torch.float64 and x.is_contiguous()):
+            raise ValueError("x must be a contiguous CUDA float64 tensor (updated in place)")
+        if tuple(x.shape) != (info["nely"], info["nelx"], info["m"]):
+            raise ValueError("x must be [nely, nelx, m]")
+        info["x"] = x
+        self._ensure_workspace()
+        return _lib.mtomg_aap_step(self.ctx, design, list(vols), rf, move, eta, eps, gmin, rel_tol, max_iter,
+                                   x.data_ptr())
+
+    def optimize(self, design: int, x: torch.Tensor, vols, tol: float = 1e-3, max_outer: int = 100, **kw):
+        """Outer iterations of aap_step until the largest density change is
+        at most tol (Table 2) or max_outer; returns the per-iteration
+        (compliance list, change) history."""
+        hist = []
+        for _ in range(max_outer):
+            cs, ch, _ = self.aap_step(design, x, vols, **kw)
+            hist.append((cs, ch))
+            if ch <= tol:
+                break
+        return hist
+
     def poisson_solve(self, f: torch.Tensor, rel_tol: float = 1e-8, max_iter: int = 1000, n_pre: int = 2,
                       n_post: int = 2, omega: float = 0.6):
         """mtomg_poisson_solve: the Poisson model problem of Section 5.1 on an

@@ -16,7 +16,7 @@ import torch
 from oracle import solve
 from tests.gpu_util import rel, relerr
 from workloads import Problem
-from workloads.square_wall import batched_designs, density_gaussian_sum, four_load_cases
+from workloads.square_wall import density_gaussian_sum, four_load_cases
 
 pytestmark = pytest.mark.gpu
 
@@ -119,32 +119,70 @@ def test_graphs_on_and_off_agree(batch):
         assert torch.equal(U0[k], s.U(k))
 
 
-def test_config4_shapes_small_slice():
-    """Three designs of each config-4 size (128^2 L4, 384^2 L5, 768^2 L6)
-    with four load cases: every system converges to the residual bar and
-    the 128^2 ones match the oracle."""
+SLICE = (0, 1, 2, 16, 17, 18, 32, 33, 34)   # designs of the 48-design workload: 3 per size
+
+
+@pytest.fixture(scope="module")
+def config4_slice():
+    """Nine designs of the batched workload itself (three each at 128^2,
+    384^2 and 768^2, four load cases each) and their oracle references: the
+    direct solve for designs 0-2 and 16, the stored direct-solve samples of
+    design 32 (tests/golden/make_golden.py batch32)."""
+    import json
+    import os
+    from workloads import batched_design
+    probs = [batched_design(d) for d in SLICE]
+    refs = {}
+    for k in (0, 1, 2, 3):
+        p = probs[k]
+        print(f"[config4 slice] oracle direct solve {p.name} ({p.nelx}^2)", flush=True)
+        refs[k] = solve.solve_direct(p.nelx, p.nely, p.x, p.E_phase, p.E_min, p.penal, p.nu, p.F)
+    path = os.path.join(os.path.dirname(__file__), "golden", "batch32_samples.json")
+    gold = json.load(open(path))
+    return probs, refs, gold
+
+
+@pytest.mark.parametrize("pair", __import__("paper_2301_07457_amd").PCGMGSolver.AUTOTUNE_CANDIDATES,
+                         ids=lambda t: f"rows{t[0]}-{t[1]}")
+def test_config4_slice_matches_oracle(config4_slice, pair):
+    """The batched workload's shapes in one solve, with each tile pair the
+    autotuner may pick: every system reaches the residual bar; the 128^2
+    designs and a 384^2 design match the oracle's direct solve (u element
+    by element, compliance, gradient) in all four load cases, and a 768^2
+    design its stored direct-solve samples."""
     from paper_2301_07457_amd import PCGMGSolver
-    probs = batched_designs(per_size=3)
+    from tests.test_gpu_fullsize import check_against_samples
+    probs, refs, gold = config4_slice
     s = PCGMGSolver(max_designs=len(probs))
     for k, p in enumerate(probs):
         add(s, k, p, "fp32mg")
+    s.set_option("ROWS_FINE", pair[0])
+    s.set_option("ROWS_COARSE", pair[1])
     for k, p in enumerate(probs):
         s.set_densities(k, torch.from_numpy(p.x))
     stats = s.solve(1e-8, 1000)
     assert len(stats) == 4 * len(probs)
-    assert all(st["status"] == 0 and st["relres_true"] <= 1.05e-8 for st in stats)
-    for k in range(3):
-        p = probs[k]
-        ref = solve.solve_direct(p.nelx, p.nely, p.x, p.E_phase, p.E_min, p.penal, p.nu, p.F)
-        assert relerr(s.U(k).cpu().numpy(), ref.U) <= 1e-6
-    print(f"[config4 slice] solve {stats[0]['t_solve_ms']:.2f} ms, iters "
+    assert all(st["status"] == 0 and st["relres_true"] <= 1.05e-8 for st in stats), stats
+    for k, ref in refs.items():
+        c, dc = s.compliance_and_grad(k)
+        assert relerr(s.U(k).cpu().numpy(), ref.U) <= 1e-6, k
+        np.testing.assert_allclose(c.cpu().numpy(), ref.c, rtol=1e-7)
+        assert relerr(dc.cpu().numpy(), ref.dcdx) <= 1e-5, k
+    k32 = SLICE.index(32)
+    p = probs[k32]
+    U = s.U(k32).cpu().numpy()
+    c, dc = s.compliance_and_grad(k32)
+    for case in range(4):
+        check_against_samples(gold, p, s, case, U[case], c[case].item(), dc[case].cpu().numpy())
+    print(f"[config4 slice {pair}] solve {stats[0]['t_solve_ms']:.2f} ms, iters "
           f"{sorted(set(st['iters'] for st in stats))}")
 
 
-def test_non_spd_design_reports_breakdown_and_spares_the_group():
-    """x = -1 gives negative moduli: the coarsest matrix is not positive
-    definite, which the deferred factorisation reports as BREAKDOWN for each
-    load case of that design, while a valid design of the same group solves."""
+def test_invalid_design_reports_bad_input_and_spares_the_group():
+    """x = -1 lies outside [0, 1] (and gives negative moduli, so the coarsest
+    matrix is not positive definite either): the device-side input check
+    reports BAD_INPUT for each load case of that design, while a valid
+    design of the same group solves."""
     from paper_2301_07457_amd import PCGMGSolver
     a = make(64, 64, 3, 2201)
     s = PCGMGSolver(max_designs=2)
@@ -153,7 +191,7 @@ def test_non_spd_design_reports_breakdown_and_spares_the_group():
     s.set_densities(0, torch.from_numpy(-np.ones_like(a.x)))
     s.set_densities(1, torch.from_numpy(a.x))
     stats = s.solve(1e-8, 200)
-    assert [st["status"] for st in stats[:4]] == [-3] * 4
+    assert [st["status"] for st in stats[:4]] == [-1] * 4
     assert all(st["status"] == 0 and st["relres_true"] <= 1e-8 for st in stats[4:])
     ref = solve.solve_direct(a.nelx, a.nely, a.x, a.E_phase, a.E_min, a.penal, a.nu, a.F)
     assert relerr(s.U(1).cpu().numpy(), ref.U) <= 1e-6
@@ -163,17 +201,17 @@ def test_non_spd_design_reports_breakdown_and_spares_the_group():
     assert all(st["status"] == 0 for st in stats)
 
 
-def test_non_spd_single_design_reports_breakdown():
+def test_invalid_single_design_reports_bad_input():
     """A design alone in its group starts its factorisation inside
-    set_densities; a non-positive-definite coarsest matrix is still reported
-    as BREAKDOWN for each load case, and valid densities clear it."""
+    set_densities; invalid densities are still reported (BAD_INPUT for each
+    load case), and valid densities clear it."""
     from paper_2301_07457_amd import PCGMGSolver
     a = make(64, 64, 3, 2301)
     s = PCGMGSolver(max_designs=1)
     add(s, 0, a, "fp32mg")
     s.set_densities(0, torch.from_numpy(-np.ones_like(a.x)))
     stats = s.solve(1e-8, 200)
-    assert [st["status"] for st in stats] == [-3] * 4
+    assert [st["status"] for st in stats] == [-1] * 4
     s.set_densities(0, torch.from_numpy(a.x))
     stats = s.solve(1e-8, 1000)
     assert all(st["status"] == 0 and st["relres_true"] <= 1e-8 for st in stats)

@@ -234,6 +234,16 @@ def test_factor_option_switch_refactors_a_fresh_matrix(shape):
     s.set_option("DENSE_FACTOR", 1)
     s.set_densities(0, torch.from_numpy(p.x))
     s.set_option("DENSE_FACTOR", 0)
-    st = s.solve(1e-10, 2000)[0]
-    assert st["status"] == 0, st
+    # 40% void at E_min = 1e-9: a relative residual of 1e-10 still leaves
+    # ~5e-6 element-wise error (the oracle's own pCGMG measures the same),
+    # so solve to 1e-12, or to the FP64 floor just above it
+    st = s.solve(1e-12, 5000)[0]
+    assert st["status"] in (0, -2) and st["relres_true"] <= 2e-11, st
     assert relerr(s.U(0).cpu().numpy(), ref.U) <= 1e-6
+    # and bit for bit what a solver that never switched computes
+    f = PCGMGSolver(max_designs=1)
+    f.add_design(0, nx, ny, torch.from_numpy(p.F), list(p.E_phase), p.E_min, p.penal, p.nu, L, 2, 2, 0.6, "fp64")
+    f.set_option("DENSE_FACTOR", 0)
+    f.set_densities(0, torch.from_numpy(p.x))
+    stf = f.solve(1e-12, 5000)[0]
+    assert stf["iters"] == st["iters"] and torch.equal(f.U(0), s.U(0))

@@ -193,3 +193,63 @@ def test_autotune_picks_a_candidate_and_keeps_parity():
     st = s.solve(1e-8, 1000)[0]
     assert st["status"] == 0 and st["relres_true"] <= 1e-8
     assert relerr(s.U(0).cpu().numpy(), ref.U) <= 1e-6
+
+
+@pytest.fixture(scope="module")
+def wall576():
+    """The 1024^2 workload's recipe at 576^2, 6 grids (coarsest 18^2): its
+    second-finest level (288^2, 83,521 nodes) is above both fusion
+    thresholds, so the solve takes every kernel path of the 1024^2 solve
+    (unfused restriction and single post-smoother below the finest level,
+    fused restriction + pre-smoothing and paired post-smoothers further
+    down)."""
+    p = make_problem("wall1024", n=576, levels=6)
+    print("[wall576] oracle direct solve", flush=True)
+    return p, oracle_direct(p)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32mg"])
+@pytest.mark.parametrize("pair", __import__("paper_2301_07457_amd").PCGMGSolver.AUTOTUNE_CANDIDATES,
+                         ids=lambda t: f"rows{t[0]}-{t[1]}")
+def test_every_autotune_tile_pair_matches_oracle(wall576, pair, prec):
+    """Each (fine, coarse) rows-per-wave pair the autotuner may pick gives the
+    oracle's solution, compliance and gradient."""
+    p, ref = wall576
+    s = gpu_solver(p, prec)
+    s.set_option("ROWS_FINE", pair[0])
+    s.set_option("ROWS_COARSE", pair[1])
+    st = s.solve(1e-8, 1000)[0]
+    assert st["status"] == 0 and st["relres_true"] <= 1.05e-8, st
+    assert relerr(s.U(0).cpu().numpy(), ref.U) <= 1e-6
+    c, dc = s.compliance_and_grad(0)
+    np.testing.assert_allclose(c.cpu().numpy(), ref.c, rtol=1e-7)
+    assert relerr(dc.cpu().numpy(), ref.dcdx) <= 1e-5
+    print(f"[tiles {pair}] {prec} iters={st['iters']} solve_ms={st['t_solve_ms']:.2f}")
+
+
+@pytest.mark.parametrize("bad,want", [(float("nan"), -4), (float("inf"), -4), (1.5, -1), (-1.0, -1),
+                                      (1.0 + 2.0 ** -52, -1)],
+                         ids=["nan", "inf", "1.5", "-1", "1+ulp"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32mg"])
+def test_invalid_density_is_reported_by_the_solve(bad, want, prec):
+    """One density outside [0, 1] (BAD_INPUT) or not finite (NAN): the
+    device-side check of set_densities is reported by the next solve for the
+    design's load case, a second solve on the same densities reports it
+    again, and valid densities clear it."""
+    from paper_2301_07457_amd import _lib
+    p = make_problem("wall64")
+    x = p.x.copy()
+    x[5, 7, 1] = bad
+    s = gpu_solver(p, prec)
+    s.set_densities(0, torch.from_numpy(x))
+    for _ in range(2):
+        st = s.solve(1e-8, 200)[0]
+        assert st["status"] == want, st
+    assert _lib.mtomg_last_error(s.ctx) == _lib.mtomg_status_string(want)
+    s.set_densities(0, torch.from_numpy(p.x))
+    st = s.solve(1e-8, 1000)[0]
+    assert st["status"] == 0 and st["relres_true"] <= 1.05e-8, st
+    x[5, 7, 1] = 1.0   # the bounds themselves are valid
+    x[0, 0, 0] = 0.0
+    s.set_densities(0, torch.from_numpy(x))
+    assert s.solve(1e-8, 1000)[0]["status"] == 0

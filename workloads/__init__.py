@@ -18,6 +18,7 @@ from .square_wall import (  # noqa: F401
     load_point,
     load_left_traction,
     make_problem,
+    batched_design,
     batched_designs,
     PHYSICS,
 )

@@ -271,17 +271,19 @@ def make_problem(name: str, n: Optional[int] = None, levels: Optional[int] = Non
     return prob
 
 
+def batched_design(d: int, sizes: Sequence[int] = (128, 384, 768), per_size: int = 16,
+                   levels: Sequence[int] = (4, 5, 6)) -> Problem:
+    """Design d of ``batched_designs`` (same sizes and per_size), built alone."""
+    if not 0 <= d < per_size * len(sizes):
+        raise IndexError(f"design {d} out of range")
+    n, lv = sizes[d // per_size], levels[d // per_size]
+    x = density_gaussian_sum(n, n, 1000 + d)
+    ph = _phys()
+    return Problem(f"batch{d}", n, n, x, np.array(ph["E_phase"]), ph["E_min"], ph["penal"], ph["nu"],
+                   four_load_cases(n, n), lv, mixed=True, seed=1000 + d)
+
+
 def batched_designs(sizes: Sequence[int] = (128, 384, 768), per_size: int = 16,
                     levels: Sequence[int] = (4, 5, 6)) -> List[Problem]:
     """Many independent smooth 3-phase designs, four load cases each."""
-    out = []
-    d = 0
-    for n, lv in zip(sizes, levels):
-        for _ in range(per_size):
-            x = density_gaussian_sum(n, n, 1000 + d)
-            ph = _phys()
-            out.append(Problem(f"batch{d}", n, n, x, np.array(ph["E_phase"]), ph["E_min"],
-                               ph["penal"], ph["nu"], four_load_cases(n, n), lv, mixed=True,
-                               seed=1000 + d))
-            d += 1
-    return out
+    return [batched_design(d, sizes, per_size, levels) for d in range(per_size * len(sizes))]
