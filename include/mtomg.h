@@ -197,6 +197,24 @@ enum { MTOMG_FILTER_DENSITY = 0, MTOMG_FILTER_DENSITY_ADJOINT = 1, MTOMG_FILTER_
 int mtomg_filter(mtomg_ctx *ctx, int nelx, int nely, int m, double rf, int mode, double gmin, const double *x,
                  const double *in, double *out);
 
+/* mtomg_filter for callers that cannot allocate device or host memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same filter and the same kernels, with the weight table
+ * held in a statically allocated device array of 1,985 doubles (15.9 KB,
+ * the table of the largest radius, rf = 16) instead of a per-context
+ * buffer.  Needs no context: work is ordered on hip_stream (a hipStream_t,
+ * NULL = the null stream) of the current device.  Each call rebuilds the
+ * table for its rf on the device and then filters, allocating nothing.
+ * Every call on one GPU shares that GPU's table: calls that overlap in time
+ * on one GPU (different streams, or several host threads) race and must be
+ * serialised by the caller; calls ordered on one stream are safe.  Each GPU
+ * keeps its copy until the process ends.  Arguments, layouts and limits as
+ * mtomg_filter (rf beyond 16 is rejected).  Returns MTOMG_OK, BAD_INPUT for
+ * invalid arguments (there is no context to hold a message), or HIP_ERROR
+ * if the launch fails.  Asynchronous. */
+int mtomg_filter_noalloc(void *hip_stream, int nelx, int nely, int m, double rf, int mode, double gmin,
+                         const double *x, const double *in, double *out);
+
 /* One binary sub-problem of the alternating active-phase optimality-criteria
  * update (Section 4: pairs of active phases, Gauss-Seidel order; parameters
  * of Table 2).  The paper does not write the update out; this is the

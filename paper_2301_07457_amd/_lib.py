@@ -31,8 +31,8 @@ EXPORTS = ["mtomg_create", "mtomg_destroy", "mtomg_set_grid", "mtomg_workspace_b
            "mtomg_set_workspace", "mtomg_set_densities", "mtomg_solve",
            "mtomg_compliance_and_grad", "mtomg_status_string", "mtomg_last_error",
            "mtomg_debug_apply", "mtomg_profile_kernel", "mtomg_profile_read",
-           "mtomg_set_option", "mtomg_filter", "mtomg_poisson_solve", "mtomg_oc_update",
-           "mtomg_aap_step"]
+           "mtomg_set_option", "mtomg_filter", "mtomg_poisson_solve", "mtomg_filter_noalloc",
+           "mtomg_oc_update", "mtomg_aap_step"]
 
 OPTIONS = dict(GRAPHS=0, BATCH=1, ROWS_FINE=2, ROWS_COARSE=3, DENSE_FACTOR=4, GAMMA=5)
 
@@ -96,6 +96,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mtomg_profile_kernel.argtypes = [vp, i]
     lib.mtomg_set_option.argtypes = [vp, i, i]
     lib.mtomg_filter.argtypes = [vp, i, i, i, d, i, d, dp, dp, dp]
+    lib.mtomg_filter_noalloc.argtypes = [vp, i, i, i, d, i, d, dp, dp, dp]
     lib.mtomg_oc_update.argtypes = [vp, i, i, i, i, i, dp, d, d, d, d, dp, ctypes.POINTER(d)]
     lib.mtomg_aap_step.argtypes = [vp, i, ctypes.POINTER(d), d, d, d, d, d, d, i, dp, ctypes.POINTER(d),
                                    ctypes.POINTER(d), ctypes.POINTER(i)]
@@ -216,6 +217,13 @@ def mtomg_filter(ctx, nelx: int, nely: int, m: int, rf: float, mode: str, gmin: 
     return check(ctx, load().mtomg_filter(ctx, nelx, nely, m, float(rf), FILTERS[mode], float(gmin),
                                           ctypes.c_void_p(x_ptr or None), ctypes.c_void_p(in_ptr or None),
                                           ctypes.c_void_p(out_ptr or None)))
+
+
+def mtomg_filter_noalloc(stream: int, nelx: int, nely: int, m: int, rf: float, mode: str, gmin: float, x_ptr: int,
+                         in_ptr: int, out_ptr: int):
+    return check(None, load().mtomg_filter_noalloc(ctypes.c_void_p(stream or None), nelx, nely, m, float(rf),
+                                                   FILTERS[mode], float(gmin), ctypes.c_void_p(x_ptr or None),
+                                                   ctypes.c_void_p(in_ptr or None), ctypes.c_void_p(out_ptr or None)))
 
 
 def mtomg_oc_update(ctx, nelx: int, nely: int, m: int, a: int, b: int, g_ptr: int, vol_a: float, move: float,

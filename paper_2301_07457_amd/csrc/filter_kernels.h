@@ -22,6 +22,14 @@ int filter_radius_cells(double rf);
 // row-major).
 void filter_table(double rf, double* tab);
 
+// Device address of this GPU's statically allocated weight table
+// (FILTER_TAB_MAX doubles, shared by every call on the GPU until the process
+// ends); looked up on the first call per device, with that device current.
+hipError_t filter_static_table(double** tab);
+
+// filter_table(rf) written into tab (device) by a kernel on st.
+void launch_filter_table(hipStream_t st, double rf, double* tab);
+
 // in, x, out: device [ny][nx][m] FP64; x is read by FILTER_SENSITIVITY only;
 // tab: device copy of filter_table(rf).  Asynchronous on st.
 void launch_cone_filter(hipStream_t st, int nx, int ny, int m, double rf, int mode, double gmin, const double* tab,

@@ -23,6 +23,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 namespace mtomg {
 
@@ -153,6 +154,69 @@ void filter_table(double rf, double* tab) {
     }
     for (int a = 1; a < W1; ++a)
         for (int b = 0; b < W1; ++b) P[a * W1 + b] += P[(a - 1) * W1 + b];
+}
+
+// ---------------------------------------------------------------------------
+// The weight table in static device memory, for callers that cannot allocate
+// ---------------------------------------------------------------------------
+namespace {
+
+// One table of the largest radius per GPU, held until the process ends.
+// Host code must not pass this name to a kernel (on the host it is a
+// stand-in, not a device address): filter_static_table() returns the
+// device address of this GPU's copy.
+static __device__ __align__(256) double scratch[FILTER_TAB_MAX];
+
+constexpr int MAX_DEVICES = 64;
+double* scratch_ptr[MAX_DEVICES] = {};
+std::mutex scratch_mu;
+
+// filter_table(rf) built on the device, in the host's operation order
+// (same weights, same running sums), by one workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void k_filter_table(double rf, int R, double* __restrict__ tab) {
+    const int W = 2 * R + 1, W1 = W + 1;
+    double* w = tab;
+    double* P = tab + W * W;
+    const int t = threadIdx.x;
+    if (t < W * W) {
+        const int di = t / W - R, dj = t % W - R;
+        w[t] = fmax(0.0, rf - sqrt((double)(di * di + dj * dj)));
+    }
+    __syncthreads();
+    if (t < W1) {   // running sums along stencil row a = t
+        double s = 0.0;
+        P[t * W1] = 0.0;
+        for (int b = 0; b < W; ++b) {
+            if (t > 0) s += w[b * W + (t - 1)];
+            P[t * W1 + b + 1] = s;
+        }
+    }
+    __syncthreads();
+    if (t < W1)     // then down column b = t
+        for (int a = 1; a < W1; ++a) P[a * W1 + t] += P[(a - 1) * W1 + t];
+}
+
+}  // namespace
+
+hipError_t filter_static_table(double** tab) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        // this device's copy of the array, looked up once with the device current
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        scratch_ptr[dev] = static_cast<double*>(ptr);
+    }
+    *tab = scratch_ptr[dev];
+    return hipSuccess;
+}
+
+void launch_filter_table(hipStream_t st, double rf, double* tab) {
+    hipLaunchKernelGGL(k_filter_table, dim3(1), dim3(1024), 0, st, rf, filter_radius_cells(rf), tab);
 }
 
 void launch_cone_filter(hipStream_t st, int nx, int ny, int m, double rf, int mode, double gmin, const double* tab,

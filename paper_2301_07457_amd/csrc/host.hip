@@ -1452,23 +1452,38 @@ int mtomg_compliance_and_grad(mtomg_ctx* c, int design, double* cout, double* dc
     return MTOMG_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Argument check shared by both filter entry points: nullptr if valid.
+const char* filter_args_error(int nelx, int nely, int m, double rf, int mode, double gmin, const double* x,
+                              const double* in, const double* out) {
+    if (nelx < 1 || nely < 1 || nelx > (1 << 22) || nely > (1 << 20) || (long)nelx * nely > (1L << 30))
+        return "filter grid must have 1 .. 2^22 columns, 1 .. 2^20 rows and at most 2^30 elements";
+    if (m < 1 || m > MAX_PHASES) return "m must be in [1, 8]";
+    if (!(rf > 0.0 && rf <= FILTER_MAX_RF)) return "rf must be in (0, 16]";
+    if (mode != MTOMG_FILTER_DENSITY && mode != MTOMG_FILTER_DENSITY_ADJOINT && mode != MTOMG_FILTER_SENSITIVITY)
+        return "unknown filter mode";
+    if (!in || !out) return "in and out must be device pointers";
+    if (in == out) return "out must not alias in";
+    if (mode == MTOMG_FILTER_SENSITIVITY) {
+        if (!x) return "the sensitivity filter needs the densities x";
+        if (x == out) return "out must not alias x";
+        if (!(gmin > 0.0 && std::isfinite(gmin))) return "gmin must be finite and > 0";
+    }
+    return nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
 int mtomg_filter(mtomg_ctx* c, int nelx, int nely, int m, double rf, int mode, double gmin, const double* x,
                  const double* in, double* out) {
     if (!c) return MTOMG_BAD_INPUT;
-    if (nelx < 1 || nely < 1 || nelx > (1 << 22) || nely > (1 << 20) || (long)nelx * nely > (1L << 30))
-        return fail(c, MTOMG_BAD_INPUT,
-                    "filter grid must have 1 .. 2^22 columns, 1 .. 2^20 rows and at most 2^30 elements");
-    if (m < 1 || m > MAX_PHASES) return fail(c, MTOMG_BAD_INPUT, "m must be in [1, 8]");
-    if (!(rf > 0.0 && rf <= FILTER_MAX_RF)) return fail(c, MTOMG_BAD_INPUT, "rf must be in (0, 16]");
-    if (mode != MTOMG_FILTER_DENSITY && mode != MTOMG_FILTER_DENSITY_ADJOINT && mode != MTOMG_FILTER_SENSITIVITY)
-        return fail(c, MTOMG_BAD_INPUT, "unknown filter mode");
-    if (!in || !out) return fail(c, MTOMG_BAD_INPUT, "in and out must be device pointers");
-    if (in == out) return fail(c, MTOMG_BAD_INPUT, "out must not alias in");
-    if (mode == MTOMG_FILTER_SENSITIVITY) {
-        if (!x) return fail(c, MTOMG_BAD_INPUT, "the sensitivity filter needs the densities x");
-        if (x == out) return fail(c, MTOMG_BAD_INPUT, "out must not alias x");
-        if (!(gmin > 0.0 && std::isfinite(gmin))) return fail(c, MTOMG_BAD_INPUT, "gmin must be finite and > 0");
-    }
+    if (const char* msg = filter_args_error(nelx, nely, m, rf, mode, gmin, x, in, out))
+        return fail(c, MTOMG_BAD_INPUT, msg);
     if (!c->filt_tab) {
         HIPCHK(c, hipMalloc(&c->filt_tab, FILTER_TAB_MAX * sizeof(double)));
         HIPCHK(c, hipHostMalloc(&c->filt_host, FILTER_TAB_MAX * sizeof(double)));
@@ -1484,6 +1499,17 @@ int mtomg_filter(mtomg_ctx* c, int nelx, int nely, int m, double rf, int mode, d
     launch_cone_filter(c->stream, nelx, nely, m, rf, mode, gmin, c->filt_tab, x, in, out);
     LAUNCHCHK(c);
     return MTOMG_OK;
+}
+
+int mtomg_filter_noalloc(void* hip_stream, int nelx, int nely, int m, double rf, int mode, double gmin,
+                         const double* x, const double* in, double* out) {
+    if (filter_args_error(nelx, nely, m, rf, mode, gmin, x, in, out)) return MTOMG_BAD_INPUT;
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    double* tab = nullptr;
+    if (filter_static_table(&tab) != hipSuccess) return MTOMG_HIP_ERROR;
+    launch_filter_table(st, rf, tab);
+    launch_cone_filter(st, nelx, nely, m, rf, mode, gmin, tab, x, in, out);
+    return hipGetLastError() == hipSuccess ? MTOMG_OK : MTOMG_HIP_ERROR;
 }
 
 }  // extern "C"
