@@ -56,16 +56,18 @@ def measured_traffic():
 
 
 def copy_calibration(mib: int, reps: int = 3):
-    """A plain device-to-device copy of known size, for scaling the
+    """A plain device-to-device copy of known size (the library's k_copy
+    streaming kernel, one untimed pass + `reps`), for scaling the
     FETCH_SIZE / WRITE_SIZE counters to bytes."""
     import torch
-    n = mib * (1 << 20) // 4
-    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    from paper_2301_07457_amd import PCGMGSolver, _lib
+    s = PCGMGSolver(max_designs=1)
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
-    for _ in range(reps):
-        b.copy_(a)
+    _lib.mtomg_stream_probe(s.ctx, "COPY", a.data_ptr(), b.data_ptr(), 0, n, reps)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes_each_way": n * 4, "reps": reps}))
+    print(json.dumps({"copy_bytes_each_way": n * 8, "dispatches": reps + 1}))
 
 
 def cpu_baseline_worker(n: int, levels: int, warmup: int, runs: int):
@@ -166,31 +168,29 @@ def oracle_error(name, case, U, c, dc, m):
     }
 
 
-def stream_copy_gbs(mib: int = 1024, reps: int = 20) -> float:
-    """Device-to-device copy bandwidth (bytes read + bytes written per
-    second) of a plain torch copy of `mib` MiB, the practical HBM ceiling
-    for a streaming kernel on this GPU."""
+def stream_ceiling(mib: int = 1024, reps: int = 20):
+    """The practical HBM ceiling: the library's hand-written streaming kernels
+    (mtomg_stream_probe: 16-byte loads and stores, 8 workgroups per compute
+    unit) over arrays of `mib` MiB each, device time per pass from HIP
+    events; GB/s counts bytes read + bytes written."""
     import torch
-    n = mib * (1 << 20) // 4
-    a = torch.ones(n, dtype=torch.float32, device="cuda")
-    b = torch.empty_like(a)
-    for _ in range(3):
-        b.copy_(a)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    secs = e0.elapsed_time(e1) * 1e-3 / reps
-    del a, b
-    return 2 * n * 4 / secs / 1e9
+    from paper_2301_07457_amd import PCGMGSolver, _lib
+    s = PCGMGSolver(max_designs=1)
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.ones_like(a)
+    c = torch.ones_like(a)
+    out = {}
+    for kind, nbytes in (("READ", 8 * n), ("COPY", 16 * n), ("TRIAD", 24 * n)):
+        ms = _lib.mtomg_stream_probe(s.ctx, kind, a.data_ptr(), b.data_ptr(), c.data_ptr(), n, reps)
+        out[kind.lower() + "_gbs"] = nbytes / (ms * 1e-3) / 1e9
+    del a, b, c
+    return out
 
 
 def gpu_run(prob, precision, steps, warmup, profile_kernel=None, tiles=None):
-    """Time `steps` steps; the tiles (rows per wave on the finest / coarse
-    grids) are autotuned first unless given.  Returns the solver, per-step
+    """Time `steps` steps; the tiles (rows per wave: the ROWS_* options) are
+    autotuned first unless given as a dict.  Returns the solver, per-step
     stats, elapsed seconds, profiled durations, U and (tiles, timings)."""
     import torch
     from paper_2301_07457_amd import PCGMGSolver
@@ -202,11 +202,12 @@ def gpu_run(prob, precision, steps, warmup, profile_kernel=None, tiles=None):
     s.set_densities(0, x)
     tune = None
     if tiles is None:
-        tiles, t = s.autotune(1e-8, 1000)
-        tune = {f"{a},{b}": round(v, 4) for (a, b), v in t.items()}
+        _, t = s.autotune(1e-8, 1000)
+        tiles = dict(s.tuned)
+        tune = {(f"{k[0]},{k[1]}" if isinstance(k, tuple) else k): round(v, 4) for k, v in t.items()}
     else:
-        s.set_option("ROWS_FINE", tiles[0])
-        s.set_option("ROWS_COARSE", tiles[1])
+        for name, v in tiles.items():
+            s.set_option(name, v)
 
     last = {}
 
@@ -261,7 +262,8 @@ def batched_run(steps, warmup, per_size=16):
     xs = [torch.from_numpy(p.x).cuda() for p in probs]
     for k, x in enumerate(xs):
         s.set_densities(k, x)
-    tiles, tune = s.autotune(1e-8, 1000, repeats=1)
+    _, tune = s.autotune(1e-8, 1000, repeats=1)
+    tiles = dict(s.tuned)
 
     def step():
         for k, x in enumerate(xs):
@@ -303,8 +305,8 @@ def batched_run(steps, warmup, per_size=16):
         "relres_true_max": max(st["relres_true"] for st in last),
         "all_ok": all(st["status"] == 0 for st in last),
         "error_vs_oracle_design32": err,
-        "tiles": {"rows_fine": tiles[0], "rows_coarse": tiles[1],
-                  "autotune_solve_ms": {f"{a},{b}": round(v, 3) for (a, b), v in tune.items()}},
+        "tiles": {"rows": tiles, "autotune_solve_ms": {(f"{k[0]},{k[1]}" if isinstance(k, tuple) else k): round(v, 3)
+                                                      for k, v in tune.items()}},
     }
 
 
@@ -443,8 +445,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--breakdown", action="store_true", help="add per-kernel average times")
     ap.add_argument("--no-batched", action="store_true", help="skip the 48-design batched workload")
-    ap.add_argument("--tiles", default=None, metavar="RF,RC",
-                    help="rows per wave on the finest / coarse grids instead of autotuning (0 = library choice)")
+    ap.add_argument("--tiles", default=None, metavar="RF,RC[,RCG,R1,R2]",
+                    help="rows per wave instead of autotuning (0 = library choice): finest grid, coarse grids, "
+                         "and optionally the outer-CG apply and the first two grids below the finest")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain copy of MIB MiB (counter calibration)")
     ap.add_argument("--cycle-sweep", action="store_true",
@@ -489,7 +492,10 @@ def main():
     n_elem = prob.nelx * prob.nely
 
     # timed pass: graph-replayed iterations, nothing instrumented
-    fixed = tuple(int(v) for v in args.tiles.split(",")) if args.tiles else None
+    fixed = None
+    if args.tiles:
+        vals = [int(v) for v in args.tiles.split(",")]
+        fixed = dict(zip(("ROWS_FINE", "ROWS_COARSE", "ROWS_CG", "ROWS_LEVEL1", "ROWS_LEVEL2"), vals))
     s, stats, elapsed, _, U32, (tiles, tune) = gpu_run(prob, "fp32mg", args.steps, args.warmup, tiles=fixed)
     iters_total = sum(st["iters"] for st in stats)
     value = n_dof * iters_total / elapsed
@@ -537,7 +543,7 @@ def main():
             "setup_ms": setup_ms,
             "relres_true": stats[-1]["relres_true"],
             "error_vs_oracle": err32,
-            "tiles": {"rows_fine": tiles[0], "rows_coarse": tiles[1], "autotune_solve_ms": tune},
+            "tiles": {"rows": tiles, "autotune_solve_ms": tune},
         },
         "roofline": {
             "kernel": "k_cg_apply (FP64 p-update + stiffness apply + p.q)",
@@ -555,9 +561,10 @@ def main():
             "eager_pass_ms_per_step": 1e3 * elapsed_r / args.steps,
         },
     }
-    copy_gbs = stream_copy_gbs()
-    out["roofline"]["stream_copy_gbs"] = copy_gbs
-    out["roofline"]["frac_of_stream_copy"] = achieved / copy_gbs
+    ceil = stream_ceiling()
+    best = max(ceil["copy_gbs"], ceil["triad_gbs"])
+    out["roofline"]["stream_ceiling_gbs"] = ceil
+    out["roofline"]["frac_of_stream_ceiling"] = achieved / best
     if not args.no_fp64:
         s64, stats64, el64, _, U64, (tiles64, _) = gpu_run(prob, "fp64", max(3, args.steps // 2), 1)
         it64 = sum(st["iters"] for st in stats64)
@@ -570,7 +577,7 @@ def main():
             "error_vs_oracle": (oracle_error(golden, 0, U64[0].cpu().numpy(), s64.last_c[0].item(),
                                              s64.last_dc[0].cpu().numpy(), prob.m)
                                 if golden else "parity unpinned (no oracle samples at this size)"),
-            "tiles": {"rows_fine": tiles64[0], "rows_coarse": tiles64[1]},
+            "tiles": {"rows": tiles64},
         }
         out["fp32mg_vs_fp64_solve_speedup"] = out["fp64_cycle"]["solve_ms"] / solve_ms
         out["fp32mg_vs_fp64_rel_diff_u"] = float(torch.linalg.norm(U32 - U64) / torch.linalg.norm(U64))

@@ -324,9 +324,19 @@ const char *mtomg_last_error(const mtomg_ctx *ctx);
  *     runs once.  A W-cycle visits level l 2^(L-1-l) times per
  *     preconditioner application (L levels), so it pays only where the
  *     V-cycle needs many more iterations.  Changing it drops the captured
- *     graphs and the iteration-count history (MTOMG_OPT_BATCH). */
+ *     graphs and the iteration-count history (MTOMG_OPT_BATCH).
+ *   MTOMG_OPT_RESTARTS (default 4; 0..64): how many times a system whose
+ *     true residual fails the confirmation restarts PCG from its current u
+ *     (within max_iter in total).
+ *   MTOMG_OPT_ROWS_CG (default 0 = automatic, as for the sweeps; 1, 2, 4
+ *     or 8): node rows per wave of the outer-CG stiffness apply,
+ *     independent of MTOMG_OPT_ROWS_FINE.
+ *   MTOMG_OPT_ROWS_LEVEL + k, k = 1..13 (default 0 = MTOMG_OPT_ROWS_COARSE;
+ *     1, 2, 4 or 8): rows per wave on the grid k levels below the finest.
+ *   The ROWS options re-plan every design, as MTOMG_OPT_ROWS_FINE does. */
 enum { MTOMG_OPT_GRAPHS = 0, MTOMG_OPT_BATCH = 1, MTOMG_OPT_ROWS_FINE = 2, MTOMG_OPT_ROWS_COARSE = 3,
-       MTOMG_OPT_DENSE_FACTOR = 4, MTOMG_OPT_GAMMA = 5 };
+       MTOMG_OPT_DENSE_FACTOR = 4, MTOMG_OPT_GAMMA = 5, MTOMG_OPT_RESTARTS = 6, MTOMG_OPT_ROWS_CG = 7,
+       MTOMG_OPT_ROWS_LEVEL = 16 };
 int mtomg_set_option(mtomg_ctx *ctx, int option, int value);
 
 /* Profiling: time every launch of one solver kernel during the following
@@ -350,6 +360,20 @@ enum {
 };
 int mtomg_profile_kernel(mtomg_ctx *ctx, int kernel);
 int mtomg_profile_read(mtomg_ctx *ctx, double *ms, int cap, int *launches);
+
+/* Practical HBM ceiling for the roofline of the bandwidth-bound kernels:
+ * time `reps` back-to-back passes of a hand-written streaming kernel over n
+ * doubles (16-byte loads and stores, 8 workgroups per compute unit) with
+ * HIP events on the context's stream, after one untimed pass.
+ *   MTOMG_PROBE_READ:  reads a (8 n bytes); writes one double per workgroup
+ *                      into b.
+ *   MTOMG_PROBE_COPY:  b = a (16 n bytes).
+ *   MTOMG_PROBE_TRIAD: a = b + 3 c (24 n bytes).
+ * a, b, c: device arrays of n doubles, 16-byte aligned (c used by TRIAD
+ * only); n even and at least 2^20.  *ms (host): device time per pass.
+ * Blocks until done. */
+enum { MTOMG_PROBE_READ = 0, MTOMG_PROBE_COPY = 1, MTOMG_PROBE_TRIAD = 2 };
+int mtomg_stream_probe(mtomg_ctx *ctx, int kind, double *a, double *b, double *c, size_t n, int reps, double *ms);
 
 /* Test hook: run one internal operator of level `level` (0 = coarsest,
  * levels-1 = finest) of a design whose densities are set.  Vectors are

@@ -32,11 +32,21 @@ EXPORTS = ["mtomg_create", "mtomg_destroy", "mtomg_set_grid", "mtomg_workspace_b
            "mtomg_compliance_and_grad", "mtomg_status_string", "mtomg_last_error",
            "mtomg_debug_apply", "mtomg_profile_kernel", "mtomg_profile_read",
            "mtomg_set_option", "mtomg_filter", "mtomg_poisson_solve", "mtomg_filter_noalloc",
-           "mtomg_oc_update", "mtomg_aap_step"]
+           "mtomg_oc_update", "mtomg_aap_step", "mtomg_stream_probe"]
 
-OPTIONS = dict(GRAPHS=0, BATCH=1, ROWS_FINE=2, ROWS_COARSE=3, DENSE_FACTOR=4, GAMMA=5)
+OPTIONS = dict(GRAPHS=0, BATCH=1, ROWS_FINE=2, ROWS_COARSE=3, DENSE_FACTOR=4, GAMMA=5, RESTARTS=6, ROWS_CG=7,
+               ROWS_LEVEL=16)
+
+
+def option_code(name: str) -> int:
+    """Option number: a name of OPTIONS, or ROWS_LEVEL<k> for MTOMG_OPT_ROWS_LEVEL + k."""
+    if name.startswith("ROWS_LEVEL") and name != "ROWS_LEVEL":
+        return OPTIONS["ROWS_LEVEL"] + int(name[len("ROWS_LEVEL"):])
+    return OPTIONS[name]
 
 FILTERS = dict(DENSITY=0, DENSITY_ADJOINT=1, SENSITIVITY=2)
+
+PROBES = dict(READ=0, COPY=1, TRIAD=2)
 
 KERNELS = dict(NONE=0, CG_APPLY=1, FINE_PRESMOOTH=2, FINE_RESTRICT=3, FINE_POST=4, FINE_POST_DOT=5,
                COARSE_SOLVE=6)
@@ -97,6 +107,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mtomg_set_option.argtypes = [vp, i, i]
     lib.mtomg_filter.argtypes = [vp, i, i, i, d, i, d, dp, dp, dp]
     lib.mtomg_filter_noalloc.argtypes = [vp, i, i, i, d, i, d, dp, dp, dp]
+    lib.mtomg_stream_probe.argtypes = [vp, i, dp, dp, dp, sz, i, ctypes.POINTER(d)]
     lib.mtomg_oc_update.argtypes = [vp, i, i, i, i, i, dp, d, d, d, d, dp, ctypes.POINTER(d)]
     lib.mtomg_aap_step.argtypes = [vp, i, ctypes.POINTER(d), d, d, d, d, d, d, i, dp, ctypes.POINTER(d),
                                    ctypes.POINTER(d), ctypes.POINTER(i)]
@@ -198,7 +209,7 @@ def mtomg_profile_read(ctx, cap: int = 4096):
 
 
 def mtomg_set_option(ctx, option: str, value: int):
-    return check(ctx, load().mtomg_set_option(ctx, OPTIONS[option], int(value)))
+    return check(ctx, load().mtomg_set_option(ctx, option_code(option), int(value)))
 
 
 def mtomg_poisson_solve(ctx, n: int, n_pre: int, n_post: int, omega: float, rel_tol: float, max_iter: int,
@@ -247,3 +258,11 @@ def mtomg_aap_step(ctx, design: int, vols, rf: float, move: float, eta: float, e
     check(ctx, load().mtomg_aap_step(ctx, design, v, float(rf), float(move), float(eta), float(eps), float(gmin),
                                      float(rel_tol), int(max_iter), ctypes.c_void_p(x_ptr), cp, ctypes.byref(ch), it))
     return list(cp), ch.value, list(it)
+
+
+def mtomg_stream_probe(ctx, kind: str, a_ptr: int, b_ptr: int, c_ptr: int, n: int, reps: int = 20) -> float:
+    """Device ms per pass of the READ / COPY / TRIAD streaming kernel over n doubles."""
+    ms = ctypes.c_double(0.0)
+    check(ctx, load().mtomg_stream_probe(ctx, PROBES[kind], ctypes.c_void_p(a_ptr), ctypes.c_void_p(b_ptr),
+                                         ctypes.c_void_p(c_ptr or None), n, reps, ctypes.byref(ms)))
+    return ms.value

@@ -21,7 +21,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libmtomg.so")
 OBJDIR = os.path.join(HERE, "_build")
 SOURCES = ["sweep_kernels.hip", "setup_kernels.hip", "filter_kernels.hip", "poisson_kernels.hip", "oc_kernels.hip",
-           "host.hip"]
+           "probe_kernels.hip", "host.hip"]
 ARCH = "gfx950"
 
 

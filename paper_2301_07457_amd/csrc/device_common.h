@@ -247,6 +247,7 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ p, int
     return out[0];
 }
 
+
 // ---------------------------------------------------------------------------
 // tile mapping: consecutive tiles land on the same XCD (workgroups are
 // dispatched round-robin over the 8 XCDs), so vertical and horizontal halo

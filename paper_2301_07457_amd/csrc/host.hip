@@ -38,6 +38,7 @@
 #include "kernels.h"
 #include "oc_kernels.h"
 #include "poisson_kernels.h"
+#include "probe_kernels.h"
 
 using namespace mtomg;
 
@@ -158,6 +159,9 @@ struct mtomg_ctx {
     bool use_graphs = true;
     bool dense_factor = false;   // coarsest factorisation by the dense block sequence
     int rows_fine = 0, rows_coarse = 0;   // rows per wave overrides (0 = automatic)
+    int rows_cg = 0;                      // rows per wave of the outer-CG apply (0 = automatic)
+    int rows_depth[16] = {};              // per grid k levels below the finest (0 = rows_coarse)
+    int max_restarts = 4;                 // PCG restarts after a failed true-residual check
     int gamma = 1;                        // cycle index of Algorithm 1: 1 V-cycle, 2 W-cycle
     double* filt_tab = nullptr;           // device weight table of mtomg_filter (FILTER_TAB_MAX doubles)
     double* filt_host = nullptr;          // pinned staging copy of it
@@ -231,11 +235,10 @@ Sweep make_sweep(int cols, int wout, int rows_total, int R = 0) {
     return s;
 }
 
-void plan_level(LevelBufs& L, int R = 0) {
-    // The outer-CG apply streams the most bytes per node; 8 rows per wave
-    // keep more loads in flight, as long as that still leaves >= 2048 waves.
-    const int strips = (L.nx + 1 + 61) / 62;
-    const int Rcg = R > 0 ? R : ((long)strips * ((L.ny + 1 + 7) / 8) >= 2048 ? 8 : 0);
+void plan_level(LevelBufs& L, int R = 0, int Rcg = 0) {
+    // The outer-CG apply has its own knob (Rcg), not R.  Automatic choice as
+    // for the sweeps: at 1024^2, 4 rows per wave measured 19.8 us per launch
+    // against 21.4 us with 8 (fewer waves in flight).
     L.sw_cg = make_sweep(L.nx + 1, 62, L.ny + 1, Rcg);
     L.sw_apply = make_sweep(L.nx + 1, 62, L.ny + 1, R);
     L.sw_post = L.sw_apply;
@@ -248,6 +251,15 @@ void plan_level(LevelBufs& L, int R = 0) {
 }
 
 
+
+// Rows per wave of every level of a design from the context's knobs.
+void plan_design(const int rows_fine, const int rows_coarse, const int rows_cg, const int* rows_depth, Design& d) {
+    for (int l = 0; l < d.levels; ++l) {
+        const int k = d.levels - 1 - l;   // levels below the finest
+        const int R = k == 0 ? rows_fine : (rows_depth[k] ? rows_depth[k] : rows_coarse);
+        plan_level(d.lev[l], R, k == 0 ? rows_cg : 0);
+    }
+}
 
 // ----------------------------------------------------------------------------
 // workspace layout (bump allocation; a null base only measures)
@@ -290,11 +302,12 @@ void layout_case_slab(const Design& d, CaseBufs& c, Bump& B) {
     const size_t nf = Lf.nodes() * 2;
     const int np = std::max({Lf.sw_apply.n_tiles, Lf.sw_cg.n_tiles, Lf.sw_pre.n_tiles, Lf.sw_post.n_tiles,
                              Lf.sw_post2.n_tiles, 1});
+    // partial-sum arrays: n partials and, for z.r and p.q, their total after them
     for (int k = 0; k < 2; ++k) {
         c.r[k] = B.take<double>(nf);
         c.p[k] = B.take<double>(nf);
-        c.zr[k] = B.take<double>(np);
-        c.pq[k] = B.take<double>(np);
+        c.zr[k] = B.take<double>(np + 1);
+        c.pq[k] = B.take<double>(np + 1);
         c.rr[k] = B.take<double>(np);
     }
     c.q = B.take<double>(nf);
@@ -730,6 +743,9 @@ void fine_cycle(CycleCtx<T>& cx, int it, double tol2) {
     coarse_correction<T>(cx, f - 1, pre_done);
     post_chain<T>(cx, f, d.n_pre > 0 ? cur : nullptr, (const T*)c.e[f - 1], bfine, (T*)c.z, cur == t0 ? t1 : t0,
                   cur, true, c.r[nxt], c.zr[it < 0 ? 0 : nxt]);
+    // z.r once, for the next CG apply (which would otherwise re-sum the
+    // partials in every workgroup) and pre-smoother
+    launch_partial_total(cx.st, c.zr[it < 0 ? 0 : nxt], d.zr_tiles(), cx.conv, cx.bt);
 }
 
 template <typename T>
@@ -1083,8 +1099,7 @@ int pcg_round(mtomg_ctx* c, const std::vector<int>& gsys0, double tol2, int max_
 // updated residual; at exit the true FP64 residual f - K u is formed, and a
 // system whose true residual is still above the tolerance (the two drift
 // apart over thousands of iterations at high contrast) restarts PCG from
-// its current iterate, up to MAX_RESTARTS times within max_iter in total.
-constexpr int MAX_RESTARTS = 4;
+// its current iterate, up to c->max_restarts times within max_iter in total.
 int solve_all(mtomg_ctx* c, double rel_tol, int max_iter, int warm, mtomg_stats* stats) {
     // Coarsest factorisations of designs with new densities run on the side
     // stream, overlapped with the start of the first run (initial residual
@@ -1126,7 +1141,7 @@ int solve_all(mtomg_ctx* c, double rel_tol, int max_iter, int warm, mtomg_stats*
     float total_ms = 0.f;
     int first_round_most = 0;
     int budget = max_iter, warm_r = warm;
-    for (int round = 0; round <= MAX_RESTARTS; ++round) {
+    for (int round = 0; round <= c->max_restarts; ++round) {
         float ms = 0.f;
         rc = pcg_round(c, gsys0, tol2, budget, warm_r, &ms, round == 0 ? wait_fac : nullptr);
         if (rc) return rc;
@@ -1154,7 +1169,7 @@ int solve_all(mtomg_ctx* c, double rel_tol, int max_iter, int warm, mtomg_stats*
                 used = std::max(used, iters[q]);
             }
         }
-        if (again.empty() || round == MAX_RESTARTS || used >= max_iter) break;
+        if (again.empty() || round == c->max_restarts || used >= max_iter) break;
         for (int q = 0; q < n_sys; ++q) {
             int* h = c->host_state + 4 * q;
             h[0] = ST_INACTIVE;
@@ -1309,8 +1324,8 @@ int mtomg_set_grid(mtomg_ctx* c, int design, int nelx, int nely, double nu, int 
         const int sh = levels - 1 - l;
         d.lev[l].nx = nelx >> sh;
         d.lev[l].ny = nely >> sh;
-        plan_level(d.lev[l], l == levels - 1 ? c->rows_fine : c->rows_coarse);
     }
+    plan_design(c->rows_fine, c->rows_coarse, c->rows_cg, c->rows_depth, d);
     d.n0 = 2 * (d.lev[0].nx + 1) * d.lev[0].ny;
     d.np0 = (d.n0 + COARSE_NB - 1) / COARSE_NB * COARSE_NB;
     d.cases.assign(n_cases, CaseBufs());
@@ -1862,16 +1877,26 @@ int mtomg_set_option(mtomg_ctx* c, int option, int value) {
         case MTOMG_OPT_GRAPHS:
             c->use_graphs = value != 0;
             return MTOMG_OK;
+        case MTOMG_OPT_RESTARTS:
+            if (value < 0 || value > 64) return fail(c, MTOMG_BAD_INPUT, "restarts must be in [0, 64]");
+            c->max_restarts = value;
+            return MTOMG_OK;
         case MTOMG_OPT_ROWS_FINE:
-        case MTOMG_OPT_ROWS_COARSE: {
+        case MTOMG_OPT_ROWS_COARSE:
+        case MTOMG_OPT_ROWS_CG:
+        default: {
+            const bool depth = option >= MTOMG_OPT_ROWS_LEVEL + 1 && option <= MTOMG_OPT_ROWS_LEVEL + 13;
+            if (!depth && option != MTOMG_OPT_ROWS_FINE && option != MTOMG_OPT_ROWS_COARSE && option != MTOMG_OPT_ROWS_CG)
+                return fail(c, MTOMG_BAD_INPUT, "unknown option");
             if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8)
                 return fail(c, MTOMG_BAD_INPUT, "rows per wave must be 0 (automatic), 1, 2, 4 or 8");
-            (option == MTOMG_OPT_ROWS_FINE ? c->rows_fine : c->rows_coarse) = value;
+            if (depth) c->rows_depth[option - MTOMG_OPT_ROWS_LEVEL] = value;
+            else if (option == MTOMG_OPT_ROWS_CG) c->rows_cg = value;
+            else (option == MTOMG_OPT_ROWS_FINE ? c->rows_fine : c->rows_coarse) = value;
             hipStreamSynchronize(c->stream);
             hipStreamSynchronize(c->side_stream);
             drop_graphs(c);
-            for (Design& d : c->d)
-                for (int l = 0; l < d.levels; ++l) plan_level(d.lev[l], l == d.levels - 1 ? c->rows_fine : c->rows_coarse);
+            for (Design& d : c->d) plan_design(c->rows_fine, c->rows_coarse, c->rows_cg, c->rows_depth, d);
             // partial-sum buffers are sized by the tile counts: re-lay out the workspace
             c->laid_out = false;
             for (Design& d : c->d) d.has_dens = false;
@@ -1908,9 +1933,29 @@ int mtomg_set_option(mtomg_ctx* c, int option, int value) {
             c->batch = value;
             c->last_iters = 0;
             return MTOMG_OK;
-        default:
-            return fail(c, MTOMG_BAD_INPUT, "unknown option");
     }
+}
+
+int mtomg_stream_probe(mtomg_ctx* c, int kind, double* a, double* b, double* cc, size_t n, int reps, double* ms) {
+    if (!c) return MTOMG_BAD_INPUT;
+    if (kind != MTOMG_PROBE_READ && kind != MTOMG_PROBE_COPY && kind != MTOMG_PROBE_TRIAD)
+        return fail(c, MTOMG_BAD_INPUT, "unknown probe kind");
+    if (n < (1u << 20) || n % 2) return fail(c, MTOMG_BAD_INPUT, "n must be even and at least 2^20");
+    if (reps < 1 || reps > 1000 || !ms) return fail(c, MTOMG_BAD_INPUT, "reps must be in [1, 1000] and ms given");
+    for (const double* p : {(const double*)a, (const double*)b, (const double*)(kind == MTOMG_PROBE_TRIAD ? cc : a)})
+        if (!p || (reinterpret_cast<uintptr_t>(p) & 15)) return fail(c, MTOMG_BAD_INPUT, "arrays must be 16-byte aligned device pointers");
+    const int blocks = probe_blocks();
+    hipStream_t st = c->stream;
+    launch_probe(st, kind, a, b, cc, n, blocks);   // warm-up
+    HIPCHK(c, hipEventRecord(c->ev_solve[0], st));
+    for (int k = 0; k < reps; ++k) launch_probe(st, kind, a, b, cc, n, blocks);
+    HIPCHK(c, hipEventRecord(c->ev_solve[1], st));
+    LAUNCHCHK(c);
+    HIPCHK(c, hipEventSynchronize(c->ev_solve[1]));
+    float t = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&t, c->ev_solve[0], c->ev_solve[1]));
+    *ms = (double)t / reps;
+    return MTOMG_OK;
 }
 
 int mtomg_profile_kernel(mtomg_ctx* c, int kernel) {

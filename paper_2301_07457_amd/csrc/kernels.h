@@ -47,7 +47,7 @@ struct CgRhs {
     float* r32;
     const double* zr;
     int n_zr;
-    const double* pq;
+    double* pq;   // partials of p.q; the kernel stores their total after them
     int n_pq;
     double* rr_out;
     int update;
@@ -69,6 +69,8 @@ struct ConvCheck {
 // own dispatch (profiling); both events must exist.
 void time_next_launch(hipEvent_t start, hipEvent_t stop);
 
+// p[n] = the sum of the partials p[0 .. n-1] (fixed order), per system.
+void launch_partial_total(hipStream_t st, double* p, int n, const int* conv, const Batch& bt = Batch{});
 template <typename TZ>
 void launch_cg_apply(hipStream_t st, LevelOp<double> op, Mat<double> mat, Sweep sw, const TZ* z,
                      const double* p_old, double* p_new, double* x, double* q, const double* zr_cur,

@@ -814,21 +814,59 @@ __global__ void k_cast_f32(const double* __restrict__ a, float* __restrict__ b, 
         b[k] = (float)a[k];
 }
 
-// dc/dx_{e,i} = -p x^(p-1) (E_i - E_min) u_e^T K^0 u_e, one thread per element.
-__global__ void k_grad(const double* __restrict__ U, const double* __restrict__ x, Phases ph, Mat<double> mat,
-                       int nx, int ny, double* __restrict__ dcdx) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= nx * ny) return;
-    const int i = e % nx, j = e / nx;
-    const V2<double> u0 = load_node(U, nx, ny, i, j), u1 = load_node(U, nx, ny, i + 1, j);
-    const V2<double> u2 = load_node(U, nx, ny, i + 1, j + 1), u3 = load_node(U, nx, ny, i, j + 1);
-    V2<double> f0, f1, f2, f3;
-    elem_force(mom_const<double>(1.0), mat, u0, u1, u2, u3, f0, f1, f2, f3);
-    const double w = (u0.x * f0.x + u0.y * f0.y) + (u1.x * f1.x + u1.y * f1.y) +
-                     (u2.x * f2.x + u2.y * f2.y) + (u3.x * f3.x + u3.y * f3.y);
-    for (int k = 0; k < ph.m; ++k) {
-        const double xv = x[(size_t)e * ph.m + k];
-        dcdx[(size_t)e * ph.m + k] = -ph.penal * powp(xv, ph.penal - 1.0) * ph.dE[k] * w;
+// dc/dx_{e,i} = -p x^(p-1) (E_i - E_min) u_e^T K^0 u_e.
+// A wave owns 63 element columns (64 node columns, lane l at node column
+// i0 + l) and GRAD_ROWS element rows.  It issues the loads of its
+// GRAD_ROWS + 1 node rows first, then marches up: element (i, j) takes nodes
+// (i, j) and (i, j+1) from its own lane and (i+1, .) from the next lane (DPP),
+// so every node row is read once per wave instead of by the four elements
+// around it.  The m phases of a row's 63 elements are contiguous in x and
+// dc/dx: the outputs go through LDS and leave as whole coalesced stores,
+// the densities come in the same way.  Consecutive tiles share an XCD
+// (xcd_tile), so the one halo row between row chunks hits L2.
+constexpr int GRAD_ROWS = 8, GRAD_COLS = 63;
+__global__ __launch_bounds__(WG_THREADS) void k_grad(const double* __restrict__ U, const double* __restrict__ x,
+                                                    Phases ph, Mat<double> mat, int nx, int ny, int n_strips,
+                                                    int n_tiles, double* __restrict__ dcdx) {
+    __shared__ double stage[WAVES_PER_WG][GRAD_COLS * 8];
+    const int tile = xcd_tile(n_tiles);
+    if (tile >= n_tiles) return;
+    const int lane = lane_id(), w = wave_id();
+    const int strip = tile % n_strips;
+    const int j0 = ((tile / n_strips) * WAVES_PER_WG + w) * GRAD_ROWS;
+    const int i0 = strip * GRAD_COLS, i = i0 + lane;
+    const int ne = min(GRAD_COLS, nx - i0);          // elements of this strip
+    const int m = ph.m, nm = ne * m;
+    double* buf = stage[w];
+    V2<double> un[GRAD_ROWS + 1];
+#pragma unroll
+    for (int s = 0; s <= GRAD_ROWS; ++s) un[s] = load_node(U, nx, ny, i, j0 + s);
+    V2<double> right_lo = from_right(un[0]);
+#pragma unroll
+    for (int s = 0; s < GRAD_ROWS; ++s) {
+        const int j = j0 + s;
+        if (j >= ny) break;                            // uniform over the wave
+        const V2<double> right_hi = from_right(un[s + 1]);
+        V2<double> f0, f1, f2, f3;
+        elem_force(mom_const<double>(1.0), mat, un[s], right_lo, right_hi, un[s + 1], f0, f1, f2, f3);
+        const double we = (un[s].x * f0.x + un[s].y * f0.y) + (right_lo.x * f1.x + right_lo.y * f1.y) +
+                          (right_hi.x * f2.x + right_hi.y * f2.y) + (un[s + 1].x * f3.x + un[s + 1].y * f3.y);
+        right_lo = right_hi;
+        // the row's densities, coalesced, into LDS; each lane takes its element's
+        const size_t base = ((size_t)j * nx + i0) * m;
+        for (int k = lane; k < nm; k += WAVE) buf[k] = x[base + k];
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        if (lane < ne)
+            for (int k = 0; k < m; ++k) {
+                const double xv = buf[lane * m + k];
+                buf[lane * m + k] = -ph.penal * powp(xv, ph.penal - 1.0) * ph.dE[k] * we;
+            }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        for (int k = lane; k < nm; k += WAVE) dcdx[base + k] = buf[k];
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     }
 }
 
@@ -986,7 +1024,11 @@ void launch_cast_f32(hipStream_t st, const double* a, float* b, size_t n) {
 }
 void launch_grad(hipStream_t st, const double* U, const double* x, Phases ph, Mat<double> mat, int nx, int ny,
                  double* dcdx) {
-    hipLaunchKernelGGL(k_grad, dim3(blocks_for((size_t)nx * ny, 256)), dim3(256), 0, st, U, x, ph, mat, nx, ny, dcdx);
+    const int n_strips = (nx + GRAD_COLS - 1) / GRAD_COLS;
+    const int chunks = (ny + GRAD_ROWS - 1) / GRAD_ROWS;
+    const int n_tiles = n_strips * ((chunks + WAVES_PER_WG - 1) / WAVES_PER_WG);
+    const int grid = (n_tiles + 7) / 8 * 8;   // whole rounds over the 8 XCDs (xcd_tile)
+    hipLaunchKernelGGL(k_grad, dim3(grid), dim3(WG_THREADS), 0, st, U, x, ph, mat, nx, ny, n_strips, n_tiles, dcdx);
 }
 void launch_dot_partials(hipStream_t st, const double* a, const double* b, size_t n, double* partials, int n_part) {
     hipLaunchKernelGGL(k_dot_partials, dim3(n_part), dim3(WG_THREADS), 0, st, a, b, n, partials);

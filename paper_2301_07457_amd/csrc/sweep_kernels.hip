@@ -40,6 +40,21 @@ __device__ __forceinline__ TileInfo tile_info(const Sweep& s, int n_rows) {
 }
 
 // ===========================================================================
+// Total of a sweep's n partial sums, stored after them (p[n]) for the
+// kernels that need it at their start: one workgroup per system, the fixed
+// order of sum_partials.  Systems whose state word is not 0 are skipped
+// (their producer did not run).
+// ===========================================================================
+__global__ __launch_bounds__(WG_THREADS) void k_partial_total(double* __restrict__ p, int n, const int* conv,
+                                                              Batch bt) {
+    const SysOff so = sys_off(bt);
+    if (load_state(at(conv, so.c)) != 0) return;
+    p = at(p, so.c);
+    const double s = sum_partials(p, n);
+    if (threadIdx.x == 0) p[n] = s;
+}
+
+// ===========================================================================
 // Outer CG: p = z + beta p_old, x += alpha_prev p_old, q = K p, partial p.q
 // mode 0: iteration i >= 1; mode 1: first iteration (beta = 0, no x update);
 // mode 2: only the pending x update (after the last iteration); mode 3: the
@@ -84,15 +99,12 @@ __global__ __launch_bounds__(WG_THREADS) void k_cg_apply(
 
     double alpha_prev = 0.0, beta = 0.0, rho_prev = 1.0, rho_cur = 0.0;
     if (mode != 1) {
-        // rho_{i-1}, p_{i-1}.q_{i-1} and rho_i in one pass (rho_i is unused
-        // by the final-only modes; its partials are valid memory there)
-        const double* ps[3] = {zr_prev, pq_prev, zr_cur};
-        const int ns[3] = {n_zr, n_pq, n_zr};
-        double sv[3];
-        sum_partials_k<3>(ps, ns, sv);
-        rho_prev = sv[0];
-        alpha_prev = rho_prev / sv[1];
-        rho_cur = sv[2];
+        // rho_{i-1}, p_{i-1}.q_{i-1} and rho_i: totals stored after the
+        // partials by their producers (rho_i is unused by the final-only
+        // modes; its slot is valid memory there)
+        rho_prev = zr_prev[n_zr];
+        alpha_prev = rho_prev / pq_prev[n_pq];
+        rho_cur = zr_cur[n_zr];
     }
     if (final_only) {
         if (out_lane) {
@@ -298,11 +310,11 @@ __global__ __launch_bounds__(WG_THREADS) void k_presmooth(
     double alpha = 0.0;
     if constexpr (CG) {
         if (cg.update) {
-            const double* ps[2] = {cg.zr, cg.pq};
-            const int ns[2] = {cg.n_zr, cg.n_pq};
-            double sv[2];
-            sum_partials_k<2>(ps, ns, sv);
-            const double rho = sv[0], pq = sv[1];
+            // rho from its producer's total; p.q summed here from the CG
+            // apply's partials, and its total stored for the next CG apply
+            const double rho = cg.zr[cg.n_zr];
+            const double pq = sum_partials(cg.pq, cg.n_pq);
+            if (blockIdx.x == 0 && threadIdx.x == 0) cg.pq[cg.n_pq] = pq;
             alpha = rho / pq;
             if (!(pq > 0.0) || !(rho > 0.0) || !isfinite(alpha)) {
                 if (blockIdx.x == 0 && threadIdx.x == 0) *cg.conv_rw = isfinite(alpha) ? 3 : 4;
@@ -1197,6 +1209,10 @@ static inline dim3 grid_of(const Sweep& s, const Batch& bt = Batch{}) {
         case 4: { constexpr int RR = 4; CALL; } break; \
         default: { constexpr int RR = 8; CALL; } break; \
     }
+
+void launch_partial_total(hipStream_t st, double* p, int n, const int* conv, const Batch& bt) {
+    MTOMG_LAUNCH(k_partial_total, dim3(1, bt.n), dim3(WG_THREADS), 0, st, p, n, conv, bt);
+}
 
 template <typename TZ>
 void launch_cg_apply(hipStream_t st, LevelOp<double> op, Mat<double> mat, Sweep sw, const TZ* z,

@@ -69,7 +69,7 @@ class PCGMGSolver:
     def set_option(self, name: str, value: int):
         """mtomg_set_option; re-plans the workspace when the launch geometry changes."""
         _lib.mtomg_set_option(self.ctx, name, value)
-        if name in ("ROWS_FINE", "ROWS_COARSE"):
+        if name.startswith("ROWS"):
             self.workspace = None
             self._ensure_workspace()
 
@@ -84,27 +84,52 @@ class PCGMGSolver:
                     _lib.mtomg_set_densities(self.ctx, d, info["x"].data_ptr())
 
     AUTOTUNE_CANDIDATES = ((0, 0), (2, 1), (4, 1), (4, 2), (8, 1), (8, 2))
+    AUTOTUNE_CG_ROWS = (4, 8)
+    AUTOTUNE_LEVEL_ROWS = (1, 2, 4)
 
-    def autotune(self, rel_tol: float = 1e-8, max_iter: int = 1000, candidates=None, repeats: int = 2):
+    def _time_solve(self, rel_tol, max_iter, repeats):
+        self.solve(rel_tol, max_iter)
+        return min(self.solve(rel_tol, max_iter)[0]["t_solve_ms"] for _ in range(repeats))
+
+    def autotune(self, rel_tol: float = 1e-8, max_iter: int = 1000, candidates=None, repeats: int = 2,
+                 per_kernel: bool = True):
         """Tile autotuner: time the solve of the designs as they are now for
         each (ROWS_FINE, ROWS_COARSE) pair of rows per wave (0 = the
-        library's own choice), keep the fastest and return
-        (best pair, {pair: ms}).  Densities must be set; the densities are
-        reloaded for every candidate (the launch geometry changes the
-        workspace), and each candidate's time is its best of `repeats`
+        library's own choice) and keep the fastest; then, with per_kernel,
+        the rows of the outer-CG apply (ROWS_CG) and, one grid at a time,
+        the rows of the two grids below the finest (ROWS_LEVEL1, ROWS_LEVEL2),
+        keeping each choice only if it is faster.  Returns (best pair,
+        {setting: ms}); every kept setting is in self.tuned.  Densities must
+        be set; they are reloaded for every candidate (the launch geometry
+        changes the workspace), and each time is the best of `repeats`
         solves after one warm-up solve."""
         if any(info["x"] is None for info in self.designs.values()):
             raise ValueError("autotune needs densities for every design")
+        for name in ("ROWS_CG", "ROWS_LEVEL1", "ROWS_LEVEL2"):
+            self.set_option(name, 0)
         timings = {}
         for rf, rc in (candidates or self.AUTOTUNE_CANDIDATES):
             self.set_option("ROWS_FINE", rf)
             self.set_option("ROWS_COARSE", rc)
-            self.solve(rel_tol, max_iter)
-            ms = min(self.solve(rel_tol, max_iter)[0]["t_solve_ms"] for _ in range(repeats))
-            timings[(rf, rc)] = ms
+            timings[(rf, rc)] = self._time_solve(rel_tol, max_iter, repeats)
         best = min(timings, key=timings.get)
         self.set_option("ROWS_FINE", best[0])
         self.set_option("ROWS_COARSE", best[1])
+        self.tuned = {"ROWS_FINE": best[0], "ROWS_COARSE": best[1], "ROWS_CG": 0, "ROWS_LEVEL1": 0,
+                      "ROWS_LEVEL2": 0}
+        if per_kernel:
+            best_ms = timings[best]
+            for name, values in (("ROWS_CG", self.AUTOTUNE_CG_ROWS), ("ROWS_LEVEL1", self.AUTOTUNE_LEVEL_ROWS),
+                                 ("ROWS_LEVEL2", self.AUTOTUNE_LEVEL_ROWS)):
+                keep = 0
+                for v in values:
+                    self.set_option(name, v)
+                    ms = self._time_solve(rel_tol, max_iter, repeats)
+                    timings[f"{name}={v}"] = ms
+                    if ms < best_ms:
+                        best_ms, keep = ms, v
+                self.set_option(name, keep)
+                self.tuned[name] = keep
         return best, timings
 
     def set_densities(self, design: int, x: torch.Tensor):

@@ -53,6 +53,7 @@ def test_binding_enums_match_header():
     assert _lib.OPTIONS == header_enum("MTOMG_OPT_")
     assert _lib.FILTERS == header_enum("MTOMG_FILTER_")
     assert _lib.KERNELS == header_enum("MTOMG_KERNEL_")
+    assert _lib.PROBES == header_enum("MTOMG_PROBE_")
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libmtomg.so not built")

@@ -188,7 +188,11 @@ def test_autotune_picks_a_candidate_and_keeps_parity():
     s = gpu_solver(p, "fp32mg")
     cands = ((0, 0), (1, 1), (2, 2), (4, 1))
     best, timings = s.autotune(1e-8, 1000, candidates=cands, repeats=1)
-    assert best in cands and set(timings) == set(cands)
+    assert best in cands and set(cands) <= set(timings)
+    # then the outer-CG apply and the two grids below the finest, one knob at a time
+    assert {"ROWS_CG=4", "ROWS_CG=8", "ROWS_LEVEL1=1", "ROWS_LEVEL2=4"} <= set(timings)
+    assert s.tuned["ROWS_FINE"] == best[0] and s.tuned["ROWS_COARSE"] == best[1]
+    assert s.tuned["ROWS_CG"] in (0, 4, 8) and s.tuned["ROWS_LEVEL1"] in (0, 1, 2, 4)
     assert all(t > 0 for t in timings.values())
     st = s.solve(1e-8, 1000)[0]
     assert st["status"] == 0 and st["relres_true"] <= 1e-8
@@ -253,3 +257,32 @@ def test_invalid_density_is_reported_by_the_solve(bad, want, prec):
     x[0, 0, 0] = 0.0
     s.set_densities(0, torch.from_numpy(x))
     assert s.solve(1e-8, 1000)[0]["status"] == 0
+
+
+@pytest.mark.parametrize("prec,cg,l1,l2", [("fp32mg", 1, 1, 1), ("fp32mg", 2, 2, 2), ("fp32mg", 4, 4, 4),
+                                           ("fp32mg", 8, 8, 8), ("fp64", 8, 4, 2)],
+                         ids=lambda v: str(v))
+def test_per_kernel_and_per_level_rows_match_oracle(wall576, prec, cg, l1, l2):
+    """The autotuner's per-kernel knobs: rows per wave of the outer-CG apply
+    (ROWS_CG) and of the two grids below the finest (ROWS_LEVEL1/2), every
+    value each may take, give the oracle's solution."""
+    p, ref = wall576
+    s = gpu_solver(p, prec)
+    s.set_option("ROWS_CG", cg)
+    s.set_option("ROWS_LEVEL1", l1)
+    s.set_option("ROWS_LEVEL2", l2)
+    st = s.solve(1e-8, 1000)[0]
+    assert st["status"] == 0 and st["relres_true"] <= 1.05e-8, st
+    assert relerr(s.U(0).cpu().numpy(), ref.U) <= 1e-6
+    c, dc = s.compliance_and_grad(0)
+    np.testing.assert_allclose(c.cpu().numpy(), ref.c, rtol=1e-7)
+    assert relerr(dc.cpu().numpy(), ref.dcdx) <= 1e-5
+
+
+def test_option_values_are_checked():
+    from paper_2301_07457_amd import PCGMGSolver, _lib
+    s = PCGMGSolver()
+    for name, v in (("RESTARTS", -1), ("RESTARTS", 65), ("ROWS_CG", 3), ("ROWS_LEVEL1", 16), ("ROWS_LEVEL14", 2)):
+        with pytest.raises(_lib.MtomgError):
+            _lib.mtomg_set_option(s.ctx, name, v)
+    _lib.mtomg_set_option(s.ctx, "RESTARTS", 10)
