@@ -412,6 +412,62 @@ def poisson_run(sizes=(16, 32, 64, 128, 256, 1024, 2048), reps=5):
             "rows": rows}
 
 
+def oc_run(n=1024, levels=7, steps=2):
+    """The alternating active-phase OC loop (Section 4) on the square wall with
+    the moduli and volume fractions of Table 2 (E = 9, 3, 1, void 1e-9;
+    V = 0.16, 0.08, 0.08, 0.68), rf = 8, FP32 cycle: device-synchronised
+    wall time of one outer iteration (six pairs, each set_densities + warm
+    solve to 1e-8 + gradient + sensitivity filter + pair update) after one
+    warm-up iteration from the uniform start, and the pair update alone
+    (HIP events around 10 calls on a resident state)."""
+    import numpy as np
+    import torch
+    from paper_2301_07457_amd import PCGMGSolver
+    from workloads import load_top_traction
+    vols = [0.16, 0.08, 0.08, 0.68]
+    E = [9.0, 3.0, 1.0]
+    F = torch.from_numpy(load_top_traction(n, n)[None])
+    s = PCGMGSolver(max_designs=1)
+    s.add_design(0, n, n, F, E, 1e-9, 3.0, 0.3, levels, 2, 2, 0.6, "fp32mg")
+    x = torch.tensor(vols[:3], dtype=torch.float64, device="cuda").expand(n, n, 3).contiguous()
+    s.aap_step(0, x, vols, rf=8.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = [s.aap_step(0, x, vols, rf=8.0) for _ in range(steps)]
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    # the pair update alone: phases (0, 3) of the current state, a fixed gradient
+    g = -torch.rand((n, n, 3), dtype=torch.float64, device="cuda") - 0.1
+    xs = x.clone()
+    s.oc_update(xs, g, 0, 3, vols[0])
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    info = s.oc_update(xs, g, 0, 3, vols[0])
+    e0.record()
+    for _ in range(10):
+        xs.copy_(x)
+        s.oc_update(xs, g, 0, 3, vols[0], info=False)
+    e1.record()
+    torch.cuda.synchronize()
+    # the copy of x is timed too: subtract it
+    e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e2.record()
+    for _ in range(10):
+        xs.copy_(x)
+    e3.record()
+    torch.cuda.synchronize()
+    upd_ms = (e0.elapsed_time(e1) - e2.elapsed_time(e3)) / 10
+    return {
+        "workload": (f"square wall {n}x{n}, Table 2 moduli and volume fractions, rf = 8, FP32 cycle in FP64 CG "
+                     f"to 1e-8 (warm-started), {levels} levels; one outer iteration = 6 phase pairs"),
+        "ms_per_outer_iteration": 1e3 * el,
+        "compliance_before_each_pair": hist[-1][0],
+        "change": hist[-1][1],
+        "pcg_iterations_per_pair": hist[-1][2],
+        "pair_update_ms": upd_ms,
+        "pair_update_newton_passes": info[3],
+    }
+
+
 def kernel_breakdown(prob, precision):
     """Average device ms per launch of each finest-grid kernel over one solve."""
     import torch
@@ -445,6 +501,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--breakdown", action="store_true", help="add per-kernel average times")
     ap.add_argument("--no-batched", action="store_true", help="skip the 48-design batched workload")
+    ap.add_argument("--no-oc", action="store_true", help="skip the OC loop timing")
     ap.add_argument("--tiles", default=None, metavar="RF,RC[,RCG,R1,R2]",
                     help="rows per wave instead of autotuning (0 = library choice): finest grid, coarse grids, "
                          "and optionally the outer-CG apply and the first two grids below the finest")
@@ -587,6 +644,8 @@ def main():
     if args.breakdown:
         out["kernel_avg_us_fp32mg"] = kernel_breakdown(prob, "fp32mg")
     out["filter"] = filter_run()
+    if not args.no_oc:
+        out["oc"] = oc_run()
     out["poisson"] = poisson_run()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = run_cpu_baseline(args.n, args.levels)

@@ -238,12 +238,13 @@ def mtomg_filter_noalloc(stream: int, nelx: int, nely: int, m: int, rf: float, m
 
 
 def mtomg_oc_update(ctx, nelx: int, nely: int, m: int, a: int, b: int, g_ptr: int, vol_a: float, move: float,
-                    eta: float, eps: float, x_ptr: int):
-    """Returns info: (lambda, largest change, sum - target, passes)."""
-    info = (ctypes.c_double * 4)()
+                    eta: float, eps: float, x_ptr: int, want_info: bool = True):
+    """Returns info (lambda, largest change, sum - target, passes), or None
+    without want_info (then the call is asynchronous)."""
+    info = (ctypes.c_double * 4)() if want_info else None
     check(ctx, load().mtomg_oc_update(ctx, nelx, nely, m, a, b, ctypes.c_void_p(g_ptr), float(vol_a), float(move),
                                       float(eta), float(eps), ctypes.c_void_p(x_ptr), info))
-    return tuple(info)
+    return tuple(info) if want_info else None
 
 
 def mtomg_aap_step(ctx, design: int, vols, rf: float, move: float, eta: float, eps: float, gmin: float,

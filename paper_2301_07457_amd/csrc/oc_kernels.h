@@ -13,9 +13,10 @@
 // is continuous, piecewise linear and non-decreasing in t, so the root is
 // found by Newton steps on S, kept inside a shrinking bracket (a geometric
 // bisection step wherever Newton would leave it).  Every pass reads q, lo,
-// hi once (24 B per element) and sums in a fixed order; the last workgroup
-// to finish a pass (an arrival counter) reduces the partial sums and sets
-// the next candidate, so the host only queues passes.
+// hi once (24 B per element) and sums in a fixed order; a one-workgroup
+// kernel after it reduces the per-workgroup sums and sets the next
+// candidate, so the host only queues passes (those after convergence exit
+// at once).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -25,8 +26,9 @@ namespace mtomg {
 // Workgroups of every OC pass (a grid-stride loop covers larger grids).
 constexpr int OC_BLOCKS = 1024;
 constexpr int OC_THREADS = 256;
-// Passes queued per pair update; a converged state makes the rest return at once.
-constexpr int OC_MAX_PASSES = 48;
+// Newton passes queued per pair update; a converged state makes the rest
+// return at once (3 to 6 passes are typical).
+constexpr int OC_MAX_PASSES = 24;
 
 // Device state of one pair update.
 struct OcState {
@@ -35,7 +37,7 @@ struct OcState {
     double change;          // largest |alpha_a new - old| (set by the apply pass)
     double lambda;          // final multiplier
     int done, passes;       // converged; passes run
-    unsigned int count;     // arrival counter of the current pass (reset by the last block)
+    unsigned int count;     // unused (keeps the layout of 64 bytes)
     int pad;
 };
 

@@ -1,14 +1,15 @@
 // Optimality-criteria pair update of the alternating active-phase loop
 // (Section 4); the arithmetic is described in oc_kernels.h.
 //
-// Passes.  k_oc_prep forms q, lo, hi per element and the bracket of t;
-// k_oc_newton (queued OC_MAX_PASSES times) evaluates S(t) and its slope
-// sum_{lo < q t < hi} q, and its last workgroup picks the next t; k_oc_apply
-// writes the pair.  Each of the OC_BLOCKS workgroups owns a fixed, strided
-// set of elements and writes one partial record; the workgroup that arrives
-// last (an atomic counter) sums the records in block order, so every pass
-// is deterministic.  Partial records and the state cross workgroups (and
-// XCDs) through agent-scope atomic loads and stores plus device fences.
+// Passes.  k_oc_prep forms q, lo, hi per element and per-workgroup partial
+// records for the bracket of t; k_oc_bracket (one workgroup) reduces them
+// and sets the first candidate.  Each Newton pass is k_oc_eval (S(t) and
+// its slope sum_{lo < q t < hi} q, per-workgroup records) and k_oc_next
+// (one workgroup: reduce, new bracket and candidate); k_oc_apply writes the
+// pair and k_oc_finish records the largest change and lambda.  Each of the
+// OC_BLOCKS workgroups owns a fixed, strided set of elements and the
+// one-workgroup kernels sum the records in block order, so every pass is
+// deterministic; the records cross workgroups only at kernel boundaries.
 #include <math.h>
 
 #include <algorithm>
@@ -21,30 +22,6 @@ namespace mtomg {
 namespace {
 
 constexpr int REC = 8;   // doubles per partial record
-
-__device__ __forceinline__ void st_agent(double* p, double v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double ld_agent(const double* p) {
-    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Publish this workgroup's record (already stored by thread 0) and report
-// whether it is the last workgroup of the pass; that one resets the counter.
-__device__ __forceinline__ bool arrive_last(OcState* s) {
-    __shared__ int last;
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned prev = atomicAdd(&s->count, 1u);
-        last = prev == gridDim.x - 1;
-        if (last) {
-            __threadfence();
-            __hip_atomic_store(&s->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
-    __syncthreads();
-    return last != 0;
-}
 
 // Fixed-order sums (or min / max) of the records' fields, by the whole block.
 __device__ __forceinline__ double block_min(double v) {
@@ -64,42 +41,30 @@ __device__ __forceinline__ double block_max(double v) { return -block_min(-v); }
 // Sum over records 0 .. nrec-1 of field f: thread t adds records t, t + 256, ...
 __device__ __forceinline__ double records_sum(const double* part, int nrec, int f) {
     double v = 0.0;
-    for (int k = threadIdx.x; k < nrec; k += OC_THREADS) v += ld_agent(part + (size_t)k * REC + f);
+    for (int k = threadIdx.x; k < nrec; k += OC_THREADS) v += part[(size_t)k * REC + f];
     return block_sum(v);
 }
 __device__ __forceinline__ double records_min(const double* part, int nrec, int f) {
     double v = INFINITY;
-    for (int k = threadIdx.x; k < nrec; k += OC_THREADS) v = fmin(v, ld_agent(part + (size_t)k * REC + f));
+    for (int k = threadIdx.x; k < nrec; k += OC_THREADS) v = fmin(v, part[(size_t)k * REC + f]);
     return block_min(v);
 }
 __device__ __forceinline__ double records_max(const double* part, int nrec, int f) {
     double v = 0.0;
-    for (int k = threadIdx.x; k < nrec; k += OC_THREADS) v = fmax(v, ld_agent(part + (size_t)k * REC + f));
+    for (int k = threadIdx.x; k < nrec; k += OC_THREADS) v = fmax(v, part[(size_t)k * REC + f]);
     return block_max(v);
 }
 
 __device__ __forceinline__ double eta_pow(double v, double eta) { return eta == 0.5 ? sqrt(v) : pow(v, eta); }
 
-__global__ void k_oc_init(OcState* s) {
-    s->t = s->tl = s->th = s->S = 0.0;
-    s->change = 0.0;
-    s->lambda = 0.0;
-    s->done = 0;
-    s->passes = 0;
-    s->count = 0u;
-    s->pad = 0;
-}
-
 // q, lo, hi per element; records: min lo/q, max hi/q (q > 0), sum lo,
-// sum (q > 0 ? hi : lo), sum q.  The last block sets the bracket and the
-// first candidate, or finishes at once when the target lies outside
-// [S(0), S(inf)].
+// sum (q > 0 ? hi : lo), sum q.
 __global__ __launch_bounds__(OC_THREADS) void k_oc_prep(OcPair op, const double* __restrict__ g,
                                                         const double* __restrict__ x, double* __restrict__ q,
                                                         double* __restrict__ lo, double* __restrict__ hi,
-                                                        double* __restrict__ part, OcState* s) {
+                                                        double* __restrict__ part) {
     double tmin = INFINITY, tmax = 0.0, slo = 0.0, shi = 0.0, sq = 0.0;
-    for (int e = blockIdx.x * OC_THREADS + threadIdx.x; e < op.n_e; e += OC_BLOCKS * OC_THREADS) {
+    for (int e = blockIdx.x * OC_THREADS + threadIdx.x; e < op.n_e; e += gridDim.x * OC_THREADS) {
         const double* xe = x + (size_t)e * op.m;
         const double ya = xe[op.a];
         double yb;
@@ -134,20 +99,25 @@ __global__ __launch_bounds__(OC_THREADS) void k_oc_prep(OcPair op, const double*
     slo = block_sum(slo);
     shi = block_sum(shi);
     sq = block_sum(sq);
-    double* rec = part + (size_t)blockIdx.x * REC;
     if (threadIdx.x == 0) {
-        st_agent(rec + 0, tmin);
-        st_agent(rec + 1, tmax);
-        st_agent(rec + 2, slo);
-        st_agent(rec + 3, shi);
-        st_agent(rec + 4, sq);
+        double* rec = part + (size_t)blockIdx.x * REC;
+        rec[0] = tmin;
+        rec[1] = tmax;
+        rec[2] = slo;
+        rec[3] = shi;
+        rec[4] = sq;
     }
-    if (!arrive_last(s)) return;
-    const double tl = records_min(part, gridDim.x, 0);
-    const double thv = records_max(part, gridDim.x, 1);
-    const double Slo = records_sum(part, gridDim.x, 2);
-    const double Shi = records_sum(part, gridDim.x, 3);
-    const double Sq = records_sum(part, gridDim.x, 4);
+}
+
+// One workgroup: the bracket and the first candidate, or the answer at once
+// when the target lies outside [S(0), S(inf)].
+__global__ __launch_bounds__(OC_THREADS) void k_oc_bracket(OcPair op, const double* __restrict__ part, int nrec,
+                                                           OcState* s) {
+    const double tl = records_min(part, nrec, 0);
+    const double thv = records_max(part, nrec, 1);
+    const double Slo = records_sum(part, nrec, 2);
+    const double Shi = records_sum(part, nrec, 3);
+    const double Sq = records_sum(part, nrec, 4);
     if (threadIdx.x == 0) {
         double t = 0.0;
         int done = 0;
@@ -163,35 +133,47 @@ __global__ __launch_bounds__(OC_THREADS) void k_oc_prep(OcPair op, const double*
         s->tl = tl;
         s->th = thv;
         s->t = t;
+        s->S = 0.0;
+        s->change = 0.0;
+        s->lambda = 0.0;
         s->done = done;
         s->passes = 0;
+        s->count = 0u;
+        s->pad = 0;
     }
 }
 
-// One Newton pass: S(t) and the slope; the last block updates the bracket
-// and the candidate.
-__global__ __launch_bounds__(OC_THREADS) void k_oc_newton(OcPair op, const double* __restrict__ q,
-                                                          const double* __restrict__ lo,
-                                                          const double* __restrict__ hi,
-                                                          double* __restrict__ part, OcState* s) {
+// One Newton pass: S(t) and the slope per workgroup ...
+__global__ __launch_bounds__(OC_THREADS) void k_oc_eval(OcPair op, const double* __restrict__ q,
+                                                        const double* __restrict__ lo,
+                                                        const double* __restrict__ hi,
+                                                        double* __restrict__ part, const OcState* s) {
     if (s->done) return;
     const double t = s->t;
     double S = 0.0, D = 0.0;
-    for (int e = blockIdx.x * OC_THREADS + threadIdx.x; e < op.n_e; e += OC_BLOCKS * OC_THREADS) {
-        const double v = q[e] * t, l = lo[e], h = hi[e];
+    for (int e = blockIdx.x * OC_THREADS + threadIdx.x; e < op.n_e; e += gridDim.x * OC_THREADS) {
+        const double qe = q[e], v = qe * t, l = lo[e], h = hi[e];
         S += fmin(fmax(v, l), h);
-        if (v > l && v < h) D += q[e];
+        if (v > l && v < h) D += qe;
     }
     S = block_sum(S);
     D = block_sum(D);
-    double* rec = part + (size_t)blockIdx.x * REC;
     if (threadIdx.x == 0) {
-        st_agent(rec + 0, S);
-        st_agent(rec + 1, D);
+        double* rec = part + (size_t)blockIdx.x * REC;
+        rec[0] = S;
+        rec[1] = D;
     }
-    if (!arrive_last(s)) return;
-    S = records_sum(part, gridDim.x, 0);
-    D = records_sum(part, gridDim.x, 1);
+}
+
+// ... and one workgroup reduces them and picks the next candidate: the
+// Newton step if it stays strictly inside the bracket, else the geometric
+// middle of the bracket.
+__global__ __launch_bounds__(OC_THREADS) void k_oc_next(OcPair op, const double* __restrict__ part, int nrec,
+                                                        OcState* s) {
+    if (s->done) return;
+    const double t = s->t;
+    const double S = records_sum(part, nrec, 0);
+    const double D = records_sum(part, nrec, 1);
     if (threadIdx.x == 0) {
         double tl = s->tl, th = s->th;
         s->S = S;
@@ -213,15 +195,15 @@ __global__ __launch_bounds__(OC_THREADS) void k_oc_newton(OcPair op, const doubl
     }
 }
 
-// y = clamp(q t, lo, hi) into phase a, s - y into phase b; the last block
-// records the largest change and lambda = t^(-1/eta).
+// y = clamp(q t, lo, hi) into phase a, s - y into phase b; per-workgroup
+// largest change ...
 __global__ __launch_bounds__(OC_THREADS) void k_oc_apply(OcPair op, const double* __restrict__ q,
                                                          const double* __restrict__ lo,
                                                          const double* __restrict__ hi, double* __restrict__ x,
-                                                         double* __restrict__ part, OcState* s) {
+                                                         double* __restrict__ part, const OcState* s) {
     const double t = s->t;
     double ch = 0.0;
-    for (int e = blockIdx.x * OC_THREADS + threadIdx.x; e < op.n_e; e += OC_BLOCKS * OC_THREADS) {
+    for (int e = blockIdx.x * OC_THREADS + threadIdx.x; e < op.n_e; e += gridDim.x * OC_THREADS) {
         double* xe = x + (size_t)e * op.m;
         const double ya = xe[op.a];
         const double y = fmin(fmax(q[e] * t, lo[e]), hi[e]);
@@ -230,11 +212,15 @@ __global__ __launch_bounds__(OC_THREADS) void k_oc_apply(OcPair op, const double
         ch = fmax(ch, fabs(y - ya));
     }
     ch = block_max(ch);
-    double* rec = part + (size_t)blockIdx.x * REC;
-    if (threadIdx.x == 0) st_agent(rec + 0, ch);
-    if (!arrive_last(s)) return;
-    const double v = records_max(part, gridDim.x, 0);
+    if (threadIdx.x == 0) part[(size_t)blockIdx.x * REC] = ch;
+}
+
+// ... and one workgroup records the largest change and lambda = t^(-1/eta).
+__global__ __launch_bounds__(OC_THREADS) void k_oc_finish(OcPair op, const double* __restrict__ part, int nrec,
+                                                          OcState* s) {
+    const double v = records_max(part, nrec, 0);
     if (threadIdx.x == 0) {
+        const double t = s->t;
         s->change = v;
         s->lambda = t > 0.0 ? pow(t, -1.0 / op.eta) : INFINITY;
     }
@@ -287,11 +273,14 @@ void launch_oc_pair(hipStream_t st, const OcPair& op, const double* g, double* x
     double* hi = lo + op.n_e;
     double* part = hi + op.n_e;
     const int nb = blocks_for(op.n_e);
-    hipLaunchKernelGGL(k_oc_init, dim3(1), dim3(1), 0, st, state);
-    hipLaunchKernelGGL(k_oc_prep, dim3(nb), dim3(OC_THREADS), 0, st, op, g, x, q, lo, hi, part, state);
-    for (int k = 0; k < OC_MAX_PASSES; ++k)
-        hipLaunchKernelGGL(k_oc_newton, dim3(nb), dim3(OC_THREADS), 0, st, op, q, lo, hi, part, state);
+    hipLaunchKernelGGL(k_oc_prep, dim3(nb), dim3(OC_THREADS), 0, st, op, g, x, q, lo, hi, part);
+    hipLaunchKernelGGL(k_oc_bracket, dim3(1), dim3(OC_THREADS), 0, st, op, part, nb, state);
+    for (int k = 0; k < OC_MAX_PASSES; ++k) {
+        hipLaunchKernelGGL(k_oc_eval, dim3(nb), dim3(OC_THREADS), 0, st, op, q, lo, hi, part, state);
+        hipLaunchKernelGGL(k_oc_next, dim3(1), dim3(OC_THREADS), 0, st, op, part, nb, state);
+    }
     hipLaunchKernelGGL(k_oc_apply, dim3(nb), dim3(OC_THREADS), 0, st, op, q, lo, hi, x, part, state);
+    hipLaunchKernelGGL(k_oc_finish, dim3(1), dim3(OC_THREADS), 0, st, op, part, nb, state);
 }
 
 void launch_sum_cases(hipStream_t st, const double* in, int n_cases, size_t n, double* out) {

@@ -172,16 +172,18 @@ class PCGMGSolver:
         return out
 
     def oc_update(self, x: torch.Tensor, g: torch.Tensor, a: int, b: int, vol_a: float, move: float = 0.2,
-                  eta: float = 0.5, eps: float = 1e-3):
+                  eta: float = 0.5, eps: float = 1e-3, info: bool = True):
         """mtomg_oc_update: one binary OC sub-problem on phases a < b (b = m:
         the void) of the densities x [nely][nelx][m] (CUDA float64, updated
         in place) with the filtered gradient g.  Returns (lambda, largest
-        change, volume sum - target, passes)."""
+        change, volume sum - target, passes), or None with info=False (then
+        nothing synchronises)."""
         ny, nx, m = x.shape
         if not (x.is_cuda and x.dtype == torch.float64 and x.is_contiguous()):
             raise ValueError("x must be a contiguous CUDA float64 tensor (updated in place)")
         gd = g.to(self.device, torch.float64).contiguous()
-        return _lib.mtomg_oc_update(self.ctx, nx, ny, m, a, b, gd.data_ptr(), vol_a, move, eta, eps, x.data_ptr())
+        return _lib.mtomg_oc_update(self.ctx, nx, ny, m, a, b, gd.data_ptr(), vol_a, move, eta, eps, x.data_ptr(),
+                                    info)
 
     def aap_step(self, design: int, x: torch.Tensor, vols, rf: float = 8.0, move: float = 0.2, eta: float = 0.5,
                  eps: float = 1e-3, gmin: float = 1e-3, rel_tol: float = 1e-8, max_iter: int = 1000):

@@ -72,7 +72,7 @@ def test_pair_update_matches_oracle(ny, nx, a, b, scale):
     assert np.array_equal(got[..., a].ravel()[firm], want[..., a].ravel()[firm])
     if np.any(active == 0):
         assert info[0] == pytest.approx(lam, rel=1e-8)
-    assert info[3] < 48, info         # converged within the pass limit
+    assert info[3] == int(info[3]) and info[3] < 24, info   # converged within the pass limit
 
 
 @pytest.mark.parametrize("vol", [0.0, 1.0])
@@ -132,3 +132,24 @@ def test_aap_step_matches_oracle(n, rf):
         assert ch == pytest.approx(ch_or, abs=1e-6)
         for k in range(3):
             assert got[..., k].mean() == pytest.approx(vols[k], rel=1e-10)
+
+
+def test_aap_step_sums_load_cases_like_the_oracle():
+    """Four load cases (top traction, corner and midpoint point loads, left
+    shear): the step's objective and gradient are the sums over the cases,
+    as in the oracle's loop."""
+    from paper_2301_07457_amd import PCGMGSolver
+    from workloads import four_load_cases
+    n = 32
+    p = table2_wall(n)
+    p.F = four_load_cases(n, n)
+    vols = [0.16, 0.08, 0.08, 0.68]
+    x_or = oc.initial_design(n, n, vols)
+    s = PCGMGSolver(max_designs=1)
+    s.add_design(0, n, n, torch.from_numpy(p.F), list(p.E_phase), p.E_min, p.penal, p.nu, p.levels, 2, 2, 0.6, "fp64")
+    xt = torch.from_numpy(x_or.copy()).cuda()
+    x_or, cs_or, ch_or = oc.aap_iteration(p, x_or, vols, rf=2.0)
+    cs, ch, iters = s.aap_step(0, xt, vols, rf=2.0, rel_tol=1e-11, max_iter=2000)
+    np.testing.assert_allclose(cs, cs_or, rtol=1e-8)
+    assert np.max(np.abs(xt.cpu().numpy() - x_or)) <= 1e-6
+    assert ch == pytest.approx(ch_or, abs=1e-6)

@@ -17,6 +17,7 @@ from .square_wall import (  # noqa: F401
     load_top_traction,
     load_point,
     load_left_traction,
+    four_load_cases,
     make_problem,
     batched_design,
     batched_designs,
