@@ -502,6 +502,7 @@ def main():
     ap.add_argument("--breakdown", action="store_true", help="add per-kernel average times")
     ap.add_argument("--no-batched", action="store_true", help="skip the 48-design batched workload")
     ap.add_argument("--no-oc", action="store_true", help="skip the OC loop timing")
+    ap.add_argument("--no-cycle-sweep", action="store_true", help="skip the level / cycle-index sweep")
     ap.add_argument("--tiles", default=None, metavar="RF,RC[,RCG,R1,R2]",
                     help="rows per wave instead of autotuning (0 = library choice): finest grid, coarse grids, "
                          "and optionally the outer-CG apply and the first two grids below the finest")
@@ -647,6 +648,11 @@ def main():
     if not args.no_oc:
         out["oc"] = oc_run()
     out["poisson"] = poisson_run()
+    if not args.no_cycle_sweep:
+        # levels and cycle index at the bench mesh (Section 2.1), one timed step per setting
+        out["cycle_sweep"] = {"workload": (f"square wall {args.n}x{args.n}, smooth 3-phase densities, FP32 cycle, "
+                                           f"rel.res 1e-8, new densities per step, library tiles"),
+                              "rows": cycle_sweep(args.n, "fp32mg", reps=1)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = run_cpu_baseline(args.n, args.levels)
     print(json.dumps(out))

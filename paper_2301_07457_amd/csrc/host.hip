@@ -169,6 +169,8 @@ struct mtomg_ctx {
     double* pois_buf = nullptr;           // mtomg_poisson_solve workspace
     size_t pois_bytes = 0;
     double* pois_host = nullptr;          // pinned copies of its scalars
+    hipGraphExec_t pois_exec = nullptr;   // two Poisson PCG iterations (parities 1, 2)
+    std::vector<double> pois_key;         // what pois_exec was captured for
     double* oc_buf = nullptr;             // OC update and optimisation-step workspace (grown on demand)
     size_t oc_bytes = 0;
     double* oc_host = nullptr;            // pinned: compliance per pair and load case, change, state
@@ -1275,6 +1277,7 @@ int mtomg_destroy(mtomg_ctx* c) {
     if (c->filt_host) hipHostFree(c->filt_host);
     if (c->pois_buf) hipFree(c->pois_buf);
     if (c->pois_host) hipHostFree(c->pois_host);
+    if (c->pois_exec) hipGraphExecDestroy(c->pois_exec);
     if (c->oc_buf) hipFree(c->oc_buf);
     if (c->oc_host) hipHostFree(c->oc_host);
     for (hipEvent_t& e : c->prof.ev)
@@ -1545,6 +1548,7 @@ struct PoisBufs {
     double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
     double* part = nullptr;   // 64 dot-product partials
     double* sc = nullptr;     // scalars: ff, rz[2], pq, rr
+    int* state = nullptr;     // [0] 0 running / 1 converged / 3 breakdown / 4 not finite, [1] iterations
 };
 
 constexpr int POIS_PARTS = 64;
@@ -1565,8 +1569,11 @@ size_t pois_layout(int n, int L, PoisBufs* pb, char* base) {
     }
     const size_t N = (size_t)(n + 1) * (n + 1);
     double* r = take(N); double* z = take(N); double* p = take(N); double* q = take(N);
-    double* part = take(POIS_PARTS); double* sc = take(8);
-    if (pb) { pb->r = r; pb->z = z; pb->p = p; pb->q = q; pb->part = part; pb->sc = sc; }
+    double* part = take(POIS_PARTS); double* sc = take(8); double* state = take(1);
+    if (pb) {
+        pb->r = r; pb->z = z; pb->p = p; pb->q = q; pb->part = part; pb->sc = sc;
+        pb->state = reinterpret_cast<int*>(state);
+    }
     return off;
 }
 
@@ -1648,9 +1655,29 @@ int mtomg_poisson_solve(mtomg_ctx* c, int n, int n_pre, int n_post, double omega
     const int fine = L - 1;
     auto read_scalars = [&]() -> int {
         HIPCHK(c, hipMemcpyAsync(hs, sc, 5 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipMemcpyAsync(hs + 6, pb.state, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipStreamSynchronize(st));
         return MTOMG_OK;
     };
+    const double tol2 = rel_tol * rel_tol;
+    // PCG iteration k (k >= 1): the device tests it, and once its state word
+    // is set the updates of u, r and p that follow do nothing, so whole
+    // batches of iterations are queued between host reads
+    auto iteration = [&](hipStream_t s2, int k) {
+        double* rz = sc + 1 + ((k - 1) & 1);   // r_{k-1}.z_{k-1}
+        double* rz_next = sc + 1 + (k & 1);
+        launch_pois_apply(s2, n, pb.p, pb.q);
+        pois_dot(s2, pb, n, pb.p, pb.q, sc + 3);
+        launch_pois_axpy(s2, n, rz, sc + 3, 1.0, pb.p, u, pb.state);
+        launch_pois_axpy(s2, n, rz, sc + 3, -1.0, pb.q, pb.r, pb.state);
+        pois_dot(s2, pb, n, pb.r, pb.r, sc + 4);
+        launch_pois_check(s2, sc, tol2, pb.state);
+        pois_cycle(s2, pb, fine, pb.r, pb.z, n_pre, n_post, omega);
+        pois_dot(s2, pb, n, pb.r, pb.z, rz_next);
+        launch_pois_check_rz(s2, rz_next, pb.state);
+        launch_pois_xpby(s2, n, pb.z, rz_next, rz, pb.p, pb.state);
+    };
+    launch_fill_strided(st, pb.state, sizeof(int), 2, 0);
     int rc = read_scalars();
     if (rc) return rc;
     const double ff = hs[0];
@@ -1658,33 +1685,58 @@ int mtomg_poisson_solve(mtomg_ctx* c, int n, int n_pre, int n_post, double omega
     double rr = ff;
     if (ff > 0.0 && max_iter > 0) {
         pois_cycle(st, pb, fine, pb.r, pb.z, n_pre, n_post, omega);
-        ++cycles;
         pois_dot(st, pb, n, pb.r, pb.z, sc + 1);
-        launch_pois_xpby(st, n, pb.z, nullptr, nullptr, pb.p);
-        status = MTOMG_NOT_CONVERGED;
-        for (it = 1; it <= max_iter; ++it) {
-            double* rz = sc + 1 + ((it - 1) & 1);   // r_{it-1}.z_{it-1}
-            double* rz_next = sc + 1 + (it & 1);
-            launch_pois_apply(st, n, pb.p, pb.q);
-            pois_dot(st, pb, n, pb.p, pb.q, sc + 3);
-            launch_pois_axpy(st, n, rz, sc + 3, 1.0, pb.p, u);
-            launch_pois_axpy(st, n, rz, sc + 3, -1.0, pb.q, pb.r);
-            pois_dot(st, pb, n, pb.r, pb.r, sc + 4);
-            // the next cycle and direction are queued before the host looks
-            pois_cycle(st, pb, fine, pb.r, pb.z, n_pre, n_post, omega);
-            ++cycles;
-            pois_dot(st, pb, n, pb.r, pb.z, rz_next);
+        launch_pois_xpby(st, n, pb.z, nullptr, nullptr, pb.p, nullptr);
+        // two iterations (k = 1, 2: both parities) in one graph, replayed
+        // for every later pair; captured again when the arguments change
+        const std::vector<double> key{(double)n, (double)n_pre, (double)n_post, omega, tol2,
+                                      (double)reinterpret_cast<uintptr_t>(u),
+                                      (double)reinterpret_cast<uintptr_t>(c->pois_buf)};
+        if (!c->pois_exec || c->pois_key != key) {
+            if (c->pois_exec) HIPCHK(c, hipGraphExecDestroy(c->pois_exec));
+            c->pois_exec = nullptr;
+            hipStream_t cs = c->cap_stream;
+            HIPCHK(c, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            iteration(cs, 1);
+            iteration(cs, 2);
+            hipGraph_t g = nullptr;
+            HIPCHK(c, hipStreamEndCapture(cs, &g));
+            const hipError_t e = hipGraphInstantiate(&c->pois_exec, g, nullptr, nullptr, 0);
+            hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                c->pois_exec = nullptr;
+                return fail(c, MTOMG_HIP_ERROR, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+            }
+            c->pois_key = key;
+        }
+        int launched = 0, batch = 4;
+        while (launched < max_iter) {
+            const int nb = std::min(batch, max_iter - launched);
+            for (int k = 0; k < nb;) {
+                if (nb - k >= 2) {
+                    HIPCHK(c, hipGraphLaunch(c->pois_exec, st));
+                    k += 2;
+                } else {
+                    iteration(st, 1);   // one of parity 1; the next batch starts a pair again
+                    k += 1;
+                    launched += 1;
+                    break;
+                }
+            }
+            launched = std::min(max_iter, launched + (nb & ~1));
             LAUNCHCHK(c);
             rc = read_scalars();
             if (rc) return rc;
-            rr = hs[4];
-            if (!std::isfinite(rr) || !std::isfinite(hs[3])) { status = MTOMG_NAN; break; }
-            if (!(hs[3] > 0.0)) { status = MTOMG_BREAKDOWN; break; }
-            if (rr <= rel_tol * rel_tol * ff) { status = MTOMG_OK; break; }
-            if (!(hs[1 + (it & 1)] > 0.0)) { status = MTOMG_BREAKDOWN; break; }
-            launch_pois_xpby(st, n, pb.z, rz_next, rz, pb.p);
+            const int* hst = reinterpret_cast<const int*>(hs + 6);
+            if (hst[0] != 0) break;
+            batch = std::min(2 * batch, 16);
         }
-        if (it > max_iter) it = max_iter;
+        const int* hst = reinterpret_cast<const int*>(hs + 6);
+        it = hst[1];
+        cycles = it + 1;
+        rr = hs[4];
+        status = hst[0] == 1 ? MTOMG_OK : hst[0] == 3 ? MTOMG_BREAKDOWN : hst[0] == 4 ? MTOMG_NAN
+                                                                                     : MTOMG_NOT_CONVERGED;
     }
     // true residual ||f - K u|| at exit
     launch_pois_residual(st, n, f, u, pb.res[fine]);

@@ -22,10 +22,17 @@ void launch_pois_restrict(hipStream_t st, int nc, const double* rf, double* bc);
 void launch_pois_prolong_add(hipStream_t st, int nc, const double* ec, double* uf);
 // 2 x 2 coarsest grid: its one unknown e = b / (8/3); boundary entries 0.
 void launch_pois_coarse(hipStream_t st, const double* b, double* e);
-// y += sa (num / den) x (num, den device scalars), every node.
+// y += sa (num / den) x (num, den device scalars), every node; nothing when
+// *state != 0 (state may be null).
 void launch_pois_axpy(hipStream_t st, int n, const double* num, const double* den, double sa, const double* x,
-                      double* y);
-// p = z + (num / den) p (num, den device scalars; den == nullptr: p = z).
-void launch_pois_xpby(hipStream_t st, int n, const double* z, const double* num, const double* den, double* p);
+                      double* y, const int* state);
+// p = z + (num / den) p (num, den device scalars; den == nullptr: p = z);
+// nothing when *state != 0 (state may be null).
+void launch_pois_xpby(hipStream_t st, int n, const double* z, const double* num, const double* den, double* p,
+                      const int* state);
+// The PCG tests on the device: sc = {f.f, r.z, r.z, p.q, r.r}; state[0]
+// (0 running, 1 converged, 3 breakdown, 4 not finite), state[1] iterations.
+void launch_pois_check(hipStream_t st, const double* sc, double tol2, int* state);
+void launch_pois_check_rz(hipStream_t st, const double* rz, int* state);
 
 }  // namespace mtomg

@@ -94,7 +94,8 @@ __global__ void k_pois_coarse(const double* __restrict__ b, double* __restrict__
 }
 
 __global__ void k_pois_axpy(int n, const double* __restrict__ num, const double* __restrict__ den, double sa,
-                            const double* __restrict__ x, double* __restrict__ y) {
+                            const double* __restrict__ x, double* __restrict__ y, const int* state) {
+    if (state && *state != 0) return;
     const int id = blockIdx.x * PT + threadIdx.x;
     const int w = n + 1;
     if (id >= w * w) return;
@@ -102,11 +103,31 @@ __global__ void k_pois_axpy(int n, const double* __restrict__ num, const double*
 }
 
 __global__ void k_pois_xpby(int n, const double* __restrict__ z, const double* __restrict__ num,
-                            const double* __restrict__ den, double* __restrict__ p) {
+                            const double* __restrict__ den, double* __restrict__ p, const int* state) {
+    if (state && *state != 0) return;
     const int id = blockIdx.x * PT + threadIdx.x;
     const int w = n + 1;
     if (id >= w * w) return;
     p[id] = den ? z[id] + (*num / *den) * p[id] : z[id];
+}
+
+// Convergence and breakdown tests of one PCG iteration on the device
+// (state[0]: 0 running, 1 converged, 3 breakdown, 4 not finite; state[1]:
+// iterations whose update of u ran).  After the update: count it, then stop
+// on a non-finite p.q or r.r, on p.q <= 0, or on r.r <= tol2 f.f.
+__global__ void k_pois_check(const double* __restrict__ sc, double tol2, int* __restrict__ state) {
+    if (threadIdx.x != 0 || state[0] != 0) return;
+    const double ff = sc[0], pq = sc[3], rr = sc[4];
+    state[1] += 1;
+    if (!isfinite(rr) || !isfinite(pq)) state[0] = 4;
+    else if (!(pq > 0.0)) state[0] = 3;
+    else if (rr <= tol2 * ff) state[0] = 1;
+}
+
+// After the next preconditioner application: breakdown on r.z <= 0.
+__global__ void k_pois_check_rz(const double* __restrict__ rz, int* __restrict__ state) {
+    if (threadIdx.x != 0 || state[0] != 0) return;
+    if (!(*rz > 0.0)) state[0] = isfinite(*rz) ? 3 : 4;
 }
 
 inline dim3 grid_of(int n) { return dim3((unsigned)(((size_t)(n + 1) * (n + 1) + PT - 1) / PT)); }
@@ -132,11 +153,18 @@ void launch_pois_coarse(hipStream_t st, const double* b, double* e) {
     hipLaunchKernelGGL(k_pois_coarse, dim3(1), dim3(64), 0, st, b, e);
 }
 void launch_pois_axpy(hipStream_t st, int n, const double* num, const double* den, double sa, const double* x,
-                      double* y) {
-    hipLaunchKernelGGL(k_pois_axpy, grid_of(n), dim3(PT), 0, st, n, num, den, sa, x, y);
+                      double* y, const int* state) {
+    hipLaunchKernelGGL(k_pois_axpy, grid_of(n), dim3(PT), 0, st, n, num, den, sa, x, y, state);
 }
-void launch_pois_xpby(hipStream_t st, int n, const double* z, const double* num, const double* den, double* p) {
-    hipLaunchKernelGGL(k_pois_xpby, grid_of(n), dim3(PT), 0, st, n, z, num, den, p);
+void launch_pois_xpby(hipStream_t st, int n, const double* z, const double* num, const double* den, double* p,
+                      const int* state) {
+    hipLaunchKernelGGL(k_pois_xpby, grid_of(n), dim3(PT), 0, st, n, z, num, den, p, state);
+}
+void launch_pois_check(hipStream_t st, const double* sc, double tol2, int* state) {
+    hipLaunchKernelGGL(k_pois_check, dim3(1), dim3(64), 0, st, sc, tol2, state);
+}
+void launch_pois_check_rz(hipStream_t st, const double* rz, int* state) {
+    hipLaunchKernelGGL(k_pois_check_rz, dim3(1), dim3(64), 0, st, rz, state);
 }
 
 }  // namespace mtomg
