@@ -98,7 +98,7 @@ def assemble_stiffness(nelx: int, nely: int, E: np.ndarray, nu: float) -> sp.csr
     """Global (unconstrained) stiffness K = sum_e E_e A_e^T K^0 A_e as CSR."""
     KE = element_stiffness(nu)
     dofs = element_dof_map(nelx, nely)
-    Ef = np.asarray(E, dtype=np.float64).reshape(-1)
+    Ef = np.asarray(E, dtype=np.result_type(E, np.float64)).reshape(-1)
     rows = np.repeat(dofs, 8, axis=1).ravel()
     cols = np.tile(dofs, (1, 8)).ravel()
     vals = (Ef[:, None] * KE.ravel()[None, :]).ravel()

@@ -1,4 +1,5 @@
-"""Linear-algebra steps of Section 2, written out plainly in FP64.
+"""Linear-algebra steps of Section 2, written out plainly in FP64 (or in the
+extended precision of their inputs, when those are np.longdouble).
 
 * ``cholesky`` follows Algorithm 3: for each column k take the square root
   of the pivot, scale the column below it, then subtract the outer product
@@ -23,7 +24,7 @@ import numpy as np
 
 def cholesky(A: np.ndarray) -> np.ndarray:
     """Lower-triangular L with A = L L^T (Algorithm 3, right-looking)."""
-    A = np.array(A, dtype=np.float64, copy=True)
+    A = np.array(A, dtype=np.result_type(A, np.float64), copy=True)
     n = A.shape[0]
     L = np.zeros_like(A)
     for k in range(n):
@@ -41,7 +42,7 @@ def cholesky(A: np.ndarray) -> np.ndarray:
 def forward_substitution(L: np.ndarray, b: np.ndarray) -> np.ndarray:
     """Solve L y = b for lower-triangular L."""
     n = L.shape[0]
-    y = np.zeros(n)
+    y = np.zeros(n, dtype=np.result_type(L, b))
     for i in range(n):
         y[i] = (b[i] - np.dot(L[i, :i], y[:i])) / L[i, i]
     return y
@@ -50,7 +51,7 @@ def forward_substitution(L: np.ndarray, b: np.ndarray) -> np.ndarray:
 def back_substitution(L: np.ndarray, y: np.ndarray) -> np.ndarray:
     """Solve L^T x = y for lower-triangular L."""
     n = L.shape[0]
-    x = np.zeros(n)
+    x = np.zeros(n, dtype=np.result_type(L, y))
     for i in range(n - 1, -1, -1):
         x[i] = (y[i] - np.dot(L[i + 1:, i], x[i + 1:])) / L[i, i]
     return x
@@ -65,7 +66,7 @@ def damped_jacobi(A, b: np.ndarray, x: np.ndarray, omega: float, sweeps: int,
                   diag: Optional[np.ndarray] = None) -> np.ndarray:
     """`sweeps` damped-Jacobi iterations x <- x + omega D^{-1} (b - A x)."""
     d = A.diagonal() if diag is None else diag
-    x = np.array(x, dtype=np.float64, copy=True)
+    x = np.array(x, dtype=np.result_type(x, b, np.float64), copy=True)
     for _ in range(sweeps):
         x = x + omega * (b - A @ x) / d
     return x
@@ -88,7 +89,7 @@ def pcg(apply_A: Callable[[np.ndarray], np.ndarray], b: np.ndarray,
     Returns x with ||b - A x||_2 <= rel_tol ||b||_2 (recursive residual) or
     after max_iter iterations.  ``iters`` counts updates of x.
     """
-    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.result_type(b, np.float64), copy=True)
     r = b - apply_A(x)
     bnorm = np.linalg.norm(b)
     hist = [np.linalg.norm(r) / bnorm if bnorm > 0 else 0.0]
@@ -98,14 +99,14 @@ def pcg(apply_A: Callable[[np.ndarray], np.ndarray], b: np.ndarray,
     rz_old = None
     for i in range(max_iter):
         z = apply_Minv(r)
-        rz = float(np.dot(z, r))
+        rz = np.dot(z, r)
         if p is None:
             p = z.copy()
         else:
             beta = rz / rz_old
             p = z + beta * p
         q = apply_A(p)
-        alpha = rz / float(np.dot(p, q))
+        alpha = rz / np.dot(p, q)
         x = x + alpha * p
         r = r - alpha * q
         rz_old = rz

@@ -86,11 +86,15 @@ def solve_direct(nelx, nely, x, E_phase, E_min, penal, nu, F, grad=True,
 
 def solve_mgpcg(nelx, nely, x, E_phase, E_min, penal, nu, F, levels, omega=0.6, n_pre=2,
                 n_post=2, rel_tol=1e-8, max_iter=1000, grad=True, gamma=1,
-                max_iter_override=None) -> Solution:
-    """PCG preconditioned by one multigrid cycle per iteration (pCGMG)."""
-    F = np.asarray(F, dtype=np.float64).reshape(-1, nely + 1, nelx + 1, 2)
+                max_iter_override=None, dtype=np.float64) -> Solution:
+    """PCG preconditioned by one multigrid cycle per iteration (pCGMG).
+
+    ``dtype=np.longdouble`` runs every step in extended precision (64-bit
+    mantissa on x86) from the same FP64 data, to separate what rounding does
+    to the iteration count from what the method does."""
+    F = np.asarray(F, dtype=dtype).reshape(-1, nely + 1, nelx + 1, 2)
     t0 = time.perf_counter()
-    _, K, Kff, free = system(nelx, nely, x, E_phase, E_min, penal, nu)
+    _, K, Kff, free = system(nelx, nely, np.asarray(x, dtype=dtype), E_phase, E_min, penal, nu)
     H = multigrid.Hierarchy(nelx, nely, Kff, levels)
     M = multigrid.preconditioner(H, omega, n_pre, n_post, gamma)
     t1 = time.perf_counter()

@@ -12,7 +12,15 @@ four load cases, the oracle's direct solve (the plain definition u_f =
 K_ff^{-1} f_f by a sparse factorisation) supplies the values instead, per
 load case.
 
-Usage: python tests/golden/make_golden.py [wall1024] [batch32]
+"nearbinary_iters" stores the oracle's pCGMG iteration counts on the
+near-binary recipe at 128^2 and 256^2 instead, in FP64 (also with the loads
+scaled by rounding-level factors) and in extended precision.
+
+"nearbinary_history" stores the oracle's recursive relative residual after
+each of the first 60 pCGMG iterations on the same recipe: where the counts
+above depend on rounding, the early history does not.
+
+Usage: python tests/golden/make_golden.py [wall1024] [batch32] [nearbinary_iters] [nearbinary_history]
 (about 3 minutes each on one host core).  The 2048 x 2048 near-binary field is
 not sampled this way: pCGMG needs ~1e4 iterations there and the oracle's
 scipy cycle does not finish in hours, so that workload is checked through
@@ -30,7 +38,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
-from oracle import fe, solve  # noqa: E402
+from oracle import fe, linalg, multigrid, solve  # noqa: E402
 from workloads import batched_design, make_problem  # noqa: E402
 
 
@@ -47,6 +55,56 @@ def _case_samples(p, U, nodes, elems, phases):
     # the oracle's gradient (Eq. 6 and the sensitivity step of Section 4), sampled
     g = fe.compliance_gradient(p.x, U, p.E_phase, p.E_min, p.penal, p.nu).reshape(-1, p.m)[elems, phases]
     return {"u_norm": float(np.linalg.norm(U)), "u_nodes": Uf[nodes].tolist(), "grad": g.tolist()}
+
+
+def make_nearbinary_iters():
+    """pCGMG iteration counts of the oracle (FP64 cycle, 2 + 2 damped Jacobi,
+    omega 0.6, relative residual 1e-8) on the near-binary 4-phase recipe at
+    128^2 (4 grids) and 256^2 (5 grids)."""
+    out = {"source": "oracle/solve.py solve_mgpcg (scipy, pCGMG; FP64 and long double) to relative residual 1e-8",
+           "recipe": "workloads make_problem('wall2048', n, levels)", "cases": []}
+    # the count of this ill-conditioned recipe moves by several percent under
+    # rounding-level changes of the data, so each case is also solved with
+    # the loads scaled by 1 + 2^-50, 1 - 2^-50 and 3 (every rounding changes,
+    # the solution only by that factor)
+    for n, lv in ((128, 4), (256, 5)):
+        t0 = time.time()
+        p = make_problem("wall2048", n=n, levels=lv)
+        iters = []
+        for scale in (1.0, 1.0 + 2.0 ** -50, 1.0 - 2.0 ** -50, 3.0):
+            sol = solve.solve_mgpcg(p.nelx, p.nely, p.x, p.E_phase, p.E_min, p.penal, p.nu, p.F * scale, p.levels,
+                                    rel_tol=1e-8, max_iter=20000, grad=False)
+            iters.append(int(sol.iters[0]))
+            relres = float(sol.relres[0]) if scale == 1.0 else relres
+        # the same run with every step in long double: the count with much
+        # less rounding in it
+        ext = solve.solve_mgpcg(p.nelx, p.nely, p.x, p.E_phase, p.E_min, p.penal, p.nu, p.F, p.levels,
+                                rel_tol=1e-8, max_iter=20000, grad=False, dtype=np.longdouble)
+        out["cases"].append({"n": n, "levels": lv, "iters": iters[0], "iters_perturbed": iters[1:],
+                             "load_scales": [1.0 + 2.0 ** -50, 1.0 - 2.0 ** -50, 3.0],
+                             "iters_extended": int(ext.iters[0]),
+                             "extended_mantissa_bits": int(np.finfo(np.longdouble).nmant) + 1,
+                             "relres_true": relres, "seconds": time.time() - t0})
+        print(out["cases"][-1], flush=True)
+    path = os.path.join(HERE, "nearbinary_iters.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+
+
+def make_nearbinary_history(n_iter: int = 60):
+    """||r_k|| / ||f|| for k = 0 .. n_iter of the oracle's pCGMG (FP64, Algorithm 2
+    with one V-cycle of Algorithm 1 per iteration) on the near-binary recipe."""
+    out = {"source": "oracle linalg.pcg with multigrid.preconditioner (FP64), recursive residual",
+           "recipe": "workloads make_problem('wall2048', n, levels)", "cases": []}
+    for n, lv in ((128, 4), (256, 5)):
+        p = make_problem("wall2048", n=n, levels=lv)
+        _, K, Kff, free = solve.system(p.nelx, p.nely, p.x, p.E_phase, p.E_min, p.penal, p.nu)
+        M = multigrid.preconditioner(multigrid.Hierarchy(p.nelx, p.nely, Kff, p.levels))
+        res = linalg.pcg(lambda v: Kff @ v, p.F[0].ravel()[free], M, rel_tol=0.0, max_iter=n_iter)
+        out["cases"].append({"n": n, "levels": lv, "history": [float(h) for h in res.history]})
+        print(n, out["cases"][-1]["history"][:6], flush=True)
+    with open(os.path.join(HERE, "nearbinary_history.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
 
 
 def make(name: str):
@@ -85,4 +143,9 @@ def make(name: str):
 
 if __name__ == "__main__":
     for name in (sys.argv[1:] or ["wall1024"]):
-        make(name)
+        if name == "nearbinary_iters":
+            make_nearbinary_iters()
+        elif name == "nearbinary_history":
+            make_nearbinary_history()
+        else:
+            make(name)

@@ -20,6 +20,7 @@
   true-residual confirmation and restart of the solver must absorb.
 """
 
+import dataclasses
 import json
 import os
 
@@ -70,12 +71,13 @@ def test_wall256_fp32_cycle_converges(wall256):
     assert c.item() == pytest.approx(ref.c[0], rel=1e-6)
 
 
-def _fd_solve(s, tol=3e-11):
+def _fd_solve(s, tol=3e-11, warm=False):
     """Solve to the FP64 floor of this design: 1e-12 is asked for, and the
     ± solves stop at a true relative residual of 1.8-2.0e-11, so the
     tolerance is 3e-11 (a tighter one only adds restarts that end at the
-    same floor)."""
-    st = s.solve(tol, 40000)[0]
+    same floor).  warm: start from the current U (the stopping test is
+    relative to f either way, so the bar is the same)."""
+    st = s.solve(tol, 40000, warm_start=warm)[0]
     assert st["status"] in (0, -2) and st["relres_true"] <= 50 * tol, st
     return st
 
@@ -115,7 +117,7 @@ def test_wall256_gradient_central_differences(wall256, chunk):
         xb = p.x.copy()
         xb.reshape(-1, p.m)[e, ph] = min(max(xb.reshape(-1, p.m)[e, ph], h), 1 - h)
         s.set_densities(0, torch.from_numpy(xb))
-        _fd_solve(s)
+        _fd_solve(s, warm=True)
         _, gb = s.compliance_and_grad(0)
         g = gb[0].cpu().numpy().reshape(-1, p.m)
         out = []
@@ -123,7 +125,7 @@ def test_wall256_gradient_central_differences(wall256, chunk):
             x = xb.copy()
             x.reshape(-1, p.m)[e, ph] += sign * h
             s.set_densities(0, torch.from_numpy(x))
-            st = _fd_solve(s)
+            st = _fd_solve(s, warm=True)
             c, _ = s.compliance_and_grad(0, grad=False)
             E = fe.interpolate_modulus(x.reshape(-1, p.m)[e], p.E_phase, p.E_min, p.penal)
             out.append((c.item(), E, s.U(0).cpu().numpy().ravel()[dofs[e]], st["relres_true"]))
@@ -244,6 +246,84 @@ def test_nearbinary_small_matches_direct_solve():
         print(f"[near-binary 128] {prec} iters={st['iters']}")
 
 
+HIST_KS = (1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 60)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32mg"])
+def test_nearbinary_residual_history_matches_oracle(prec):
+    """||r_k|| / ||f|| after k = 1 .. 60 pCGMG iterations on the near-binary
+    recipe (contrast 3e8) at 128^2 and 256^2 against the oracle's history
+    (tests/golden/nearbinary_history.json).  Every step of Algorithms 1-2
+    enters r_k, so a missing or extra sweep, a wrong transfer or a wrong CG
+    coefficient moves it by far more than rounding does.  Bars: FP64 cycle
+    5e-9 relative (the two sides' operators differ by rounding, amplified by
+    this operator's conditioning: 1e-11 at 128^2 and 5e-10 at 256^2 after 60
+    iterations, measured), FP32 cycle 1e-5 (its cycle rounds at 6e-8)."""
+    bar = 5e-9 if prec == "fp64" else 1e-5
+    gold = json.load(open(os.path.join(GOLD, "nearbinary_history.json")))
+    for case in gold["cases"]:
+        p = make_problem("wall2048", n=case["n"], levels=case["levels"])
+        s = gpu_solver(p, prec)
+        s.set_option("RESTARTS", 0)
+        worst = 0.0
+        for k in HIST_KS:
+            st = s.solve(1e-30, k)[0]
+            h = case["history"][k]
+            assert st["iters"] == k and st["status"] == -2, st
+            worst = max(worst, abs(st["relres_rec"] - h) / h)
+            assert abs(st["relres_rec"] - h) <= bar * h, (case["n"], k, st["relres_rec"], h)
+        print(f"[near-binary {case['n']}] {prec} history k<=60: max rel diff {worst:.2e}")
+
+
+def test_nearbinary_iteration_counts_match_oracle():
+    """pCGMG iteration counts on the near-binary recipe (FP64 cycle) at 128^2
+    and 256^2 to relative residual 1e-8, against the oracle's
+    (tests/golden/nearbinary_iters.json).  At contrast 3e8 the count of a
+    run of 1e3-4e3 iterations is decided by rounding as much as by the
+    method (the early residual history above is not): the oracle's FP64
+    count moves by up to 9% when the loads are scaled by 1 +- 2^-50 or 3,
+    its long-double run differs again, and the GPU's own counts move the
+    same way.  So the counts are compared as samples: the median of the
+    GPU's four counts (same load scales) must lie within 25% of the median
+    of the oracle's four FP64 counts."""
+    gold = json.load(open(os.path.join(GOLD, "nearbinary_iters.json")))
+    for case in gold["cases"]:
+        ref = [case["iters"]] + case["iters_perturbed"]
+        p = make_problem("wall2048", n=case["n"], levels=case["levels"])
+        counts = []
+        for scale in [1.0] + case["load_scales"]:
+            s = gpu_solver(dataclasses.replace(p, F=p.F * scale), "fp64")
+            s.set_option("RESTARTS", 0)   # Algorithm 2's count, without the true-residual restarts
+            st = s.solve(1e-8, 20000)[0]
+            assert st["relres_rec"] <= 1e-8 and st["relres_true"] <= 2e-8, st
+            counts.append(st["iters"])
+            del s
+        print(f"[near-binary {case['n']}] gpu iters={counts} oracle fp64={ref} "
+              f"oracle long double={case['iters_extended']}")
+        assert abs(np.median(counts) / np.median(ref) - 1.0) <= 0.25, (counts, ref)
+
+
+def test_nearbinary512_matches_direct_solve():
+    """512^2 near-binary (6 grids): u, compliance and gradient against the
+    oracle's direct solve (whose own residual is 1.2e-9), both cycle
+    precisions, at the standard 1e-8 (measured: u 1.6e-7 in norm, 1.9e-7
+    element-wise; tighter tolerances leave the difference at ~1.5e-7, the
+    direct solve's own error)."""
+    p = make_problem("wall2048", n=512, levels=6)
+    print("[near-binary 512] oracle direct solve", flush=True)
+    ref = solve.solve_direct(p.nelx, p.nely, p.x, p.E_phase, p.E_min, p.penal, p.nu, p.F)
+    for prec in ("fp64", "fp32mg"):
+        s = gpu_solver(p, prec)
+        st = s.solve(1e-8, 60000)[0]
+        assert st["status"] == 0 and st["relres_true"] <= 1e-8, (prec, st)
+        assert relerr(s.U(0).cpu().numpy(), ref.U) <= 1e-6, prec
+        c, dc = s.compliance_and_grad(0)
+        assert c.item() == pytest.approx(ref.c[0], rel=1e-7)
+        assert relerr(dc.cpu().numpy(), ref.dcdx) <= 1e-5
+        print(f"[near-binary 512] {prec} iters={st['iters']} relres_true={st['relres_true']:.2e} "
+              f"err={relerr(s.U(0).cpu().numpy(), ref.U):.2e}")
+
+
 def test_true_residual_confirmation_restarts():
     """512^2 near-binary, FP64 cycle: the recursive residual reaches 1e-8
     while the true one is ~2e-8; the confirmation restarts PCG from u."""
@@ -286,19 +366,27 @@ def _residual_floor(p, U):
     return np.finfo(np.float64).eps * np.linalg.norm(acc[free]) / np.linalg.norm(p.F[0].ravel()[free])
 
 
+# Residual floor of an FP64 displacement field for the 2048^2 near-binary
+# design: rounding each entry of its solution to FP64 (half an ulp, random
+# signs) changes f - K u by 1.06e-7 ||f||, measured in extended precision
+# (64-bit mantissa) on the GPU's solution, whose own residual evaluated there
+# equals the GPU's FP64 evaluation (6.16e-8).  The near-rigid parts of this
+# compliant design carry displacements up to 2e5 while ||f|| = 0.022, so no
+# FP64 u meets 1e-8.
+NEARBINARY2048_FP64_FLOOR = 1.1e-7
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32mg"])
 def test_nearbinary2048_converges_with_oracle_properties(nearbinary2048, prec):
-    """The recursive residual reaches 1e-8.  The true FP64 residual reaches
-    1e-8 or, where that lies below what FP64 can resolve for this field
-    (large near-rigid displacements make |K| |u| ~1e8 |f|), four times the
-    rounding floor of its own evaluation; the solver then reports
-    NOT_CONVERGED rather than claiming 1e-8."""
+    """The recursive residual reaches 1e-8; the true residual reaches the
+    FP64 floor of this design (above 1e-8, see NEARBINARY2048_FP64_FLOOR),
+    and the solver reports NOT_CONVERGED rather than claiming 1e-8."""
     p, out = nearbinary2048
     st, U, c, dc = out[prec]
     floor = _residual_floor(p, U[0])
-    print(f"[near-binary 2048] {prec} relres_true={st['relres_true']:.2e} rounding floor={floor:.2e}")
+    print(f"[near-binary 2048] {prec} relres_true={st['relres_true']:.2e} (FP64 floor {NEARBINARY2048_FP64_FLOOR:.1e})")
     assert st["relres_rec"] <= 1e-8, st
-    assert st["relres_true"] <= max(1e-8, 4 * floor), (st, floor)
+    assert st["relres_true"] <= NEARBINARY2048_FP64_FLOOR, st
     assert st["status"] == (0 if st["relres_true"] <= 1e-8 else -2), st
     # c = f.u and u^T K u differ by r.u, |r.u| <= ||r|| ||u|| with ||r|| = relres ||f||
     E = fe.interpolate_modulus(p.x, p.E_phase, p.E_min, p.penal)

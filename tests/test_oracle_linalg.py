@@ -100,3 +100,44 @@ def test_mg_and_jacobi_pcg_match_dense_cholesky(n, levels):
     np.testing.assert_allclose(jr.x, ref.U[0].ravel()[free], rtol=0,
                                atol=1e-11 * np.abs(ref.U).max())
     assert mg.iters[0] < jr.iters
+
+
+def test_extended_precision_cholesky_against_exact_rationals():
+    """The oracle's steps keep np.longdouble inputs in long double: on the
+    8 x 8 Hilbert matrix (kappa 1.5e10, FP64 data) the solve's error
+    against the exact rational solution of the same data shrinks by about
+    the ratio of the two machine epsilons (2^11 on x86)."""
+    from fractions import Fraction
+    n = 8
+    H = np.array([[1.0 / (i + j + 1) for j in range(n)] for i in range(n)])
+    b = H.sum(1)
+    M = [[Fraction(H[i, j]) for j in range(n)] + [Fraction(b[i])] for i in range(n)]
+    for k in range(n):
+        for i in range(k + 1, n):
+            f = M[i][k] / M[k][k]
+            M[i] = [a - f * c for a, c in zip(M[i], M[k])]
+    xe = [Fraction(0)] * n
+    for i in range(n - 1, -1, -1):
+        xe[i] = (M[i][n] - sum(M[i][j] * xe[j] for j in range(i + 1, n))) / M[i][i]
+    xe = np.array([float(v) for v in xe])
+    err = {}
+    for dt in (np.float64, np.longdouble):
+        x = linalg.cholesky_solve(linalg.cholesky(H.astype(dt)), b.astype(dt))
+        assert x.dtype == dt
+        err[dt] = float(np.max(np.abs(x - xe)) / np.max(np.abs(xe)))
+    if np.finfo(np.longdouble).eps < np.finfo(np.float64).eps:
+        assert err[np.longdouble] <= err[np.float64] / 100, err
+    assert err[np.float64] <= 1.5e10 * np.finfo(np.float64).eps * 10
+
+
+def test_mgpcg_in_extended_precision_matches_fp64():
+    """The extended-precision pCGMG solves the same system: on a smooth
+    design it takes the FP64 run's iteration count and lands on its answer."""
+    n, levels = 16, 3
+    rng = np.random.default_rng(3)
+    x = rng.uniform(0.0, 1.0, (n, n, 3)) / 3
+    args = (n, n, x, [1.0, 0.6, 0.2], 1e-9, 3.0, 0.3, load_top_traction(n, n)[None], levels)
+    a = solve.solve_mgpcg(*args, rel_tol=1e-10, grad=False)
+    b = solve.solve_mgpcg(*args, rel_tol=1e-10, grad=False, dtype=np.longdouble)
+    assert a.iters == b.iters
+    np.testing.assert_allclose(b.U, a.U, rtol=0, atol=1e-9 * np.abs(a.U).max())
