@@ -187,24 +187,22 @@ __device__ __forceinline__ double block_sum(double v) {
 }
 
 // Sums of K partial arrays (p[q] holds n[q] >= 1 entries, n[q] used) in a
-// fixed order, identical in every block that calls it: thread t adds
+// fixed order, identical in every block that computes them: thread t adds
 // entries t, t + WG_THREADS, ... in increasing order, then the wave and
-// workgroup trees of block_sum.  Loads are issued eight per thread and
-// array at a time, all before the first add (out-of-range slots load a
-// valid entry and are not added), and the K reductions share one barrier
-// pair.  Requires all threads of the block to call.
+// workgroup trees of block_sum.  Loads go out eight per thread and array at
+// a time, all before the first add (out-of-range slots load a valid entry
+// and are not added), and the K reductions share one barrier pair.
+// issue() sends the first eight loads per thread and array; a kernel calls
+// it before its own tile loads, so the two latencies overlap, and finish()
+// later (all threads of the block).
 template <int K>
-__device__ __forceinline__ void sum_partials_k(const double* const (&p)[K], const int (&n)[K], double (&out)[K]) {
-    constexpr int U = 8;
-    double s[K];
-    int nmax = 0;
-#pragma unroll
-    for (int q = 0; q < K; ++q) {
-        s[q] = 0.0;
-        nmax = max(nmax, n[q]);
-    }
-    for (int base = 0; base < nmax; base += U * WG_THREADS) {
-        double v[K][U];
+struct PartialSums {
+    static constexpr int U = 8;
+    const double* p[K];
+    int n[K];
+    double v[K][U];
+
+    __device__ __forceinline__ void load_chunk(int base) {
 #pragma unroll
         for (int q = 0; q < K; ++q)
 #pragma unroll
@@ -212,6 +210,18 @@ __device__ __forceinline__ void sum_partials_k(const double* const (&p)[K], cons
                 const int k = base + threadIdx.x + u * WG_THREADS;
                 v[q][u] = p[q][max(min(k, n[q] - 1), 0)];
             }
+    }
+
+    __device__ __forceinline__ void issue(const double* const (&ps)[K], const int (&ns)[K]) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            p[q] = ps[q];
+            n[q] = ns[q];
+        }
+        load_chunk(0);
+    }
+
+    __device__ __forceinline__ void add_chunk(int base, double (&s)[K]) const {
 #pragma unroll
         for (int q = 0; q < K; ++q)
 #pragma unroll
@@ -220,22 +230,52 @@ __device__ __forceinline__ void sum_partials_k(const double* const (&p)[K], cons
                 s[q] = (k < n[q]) ? s[q] + v[q][u] : s[q];
             }
     }
-    __shared__ double red[K][WAVES_PER_WG];
+
+    __device__ __forceinline__ void finish(double (&out)[K]) {
+        double s[K];
+        int nmax = 0;
 #pragma unroll
-    for (int q = 0; q < K; ++q) s[q] = wave_sum(s[q]);
-    __syncthreads();
-    if (lane_id() == 0) {
+        for (int q = 0; q < K; ++q) {
+            s[q] = 0.0;
+            nmax = max(nmax, n[q]);
+        }
+        // the values issue() loaded enter here and no earlier: without this
+        // the compiler may hoist the first adds (and their wait for the
+        // loads) above the caller's tile loads, serialising the two
 #pragma unroll
-        for (int q = 0; q < K; ++q) red[q][wave_id()] = s[q];
+        for (int q = 0; q < K; ++q)
+#pragma unroll
+            for (int u = 0; u < U; ++u) asm volatile("" : "+v"(v[q][u]) : : "memory");
+        add_chunk(0, s);   // the chunk issue() loaded, outside the loop
+        for (int base = U * WG_THREADS; base < nmax; base += U * WG_THREADS) {
+            load_chunk(base);
+            add_chunk(base, s);
+        }
+        __shared__ double red[K][WAVES_PER_WG];
+#pragma unroll
+        for (int q = 0; q < K; ++q) s[q] = wave_sum(s[q]);
+        __syncthreads();
+        if (lane_id() == 0) {
+#pragma unroll
+            for (int q = 0; q < K; ++q) red[q][wave_id()] = s[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            double t = 0.0;
+#pragma unroll
+            for (int w = 0; w < WAVES_PER_WG; ++w) t += red[q][w];
+            out[q] = t;
+        }
     }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < K; ++q) {
-        double t = 0.0;
-#pragma unroll
-        for (int w = 0; w < WAVES_PER_WG; ++w) t += red[q][w];
-        out[q] = t;
-    }
+};
+
+// The sums of PartialSums in one call.  Requires all threads of the block.
+template <int K>
+__device__ __forceinline__ void sum_partials_k(const double* const (&p)[K], const int (&n)[K], double (&out)[K]) {
+    PartialSums<K> ps;
+    ps.issue(p, n);
+    ps.finish(out);
 }
 
 // Sum of n >= 1 partials in a fixed order; identical in every block that calls it.

@@ -171,6 +171,7 @@ struct mtomg_ctx {
     double* pois_host = nullptr;          // pinned copies of its scalars
     hipGraphExec_t pois_exec = nullptr;   // two Poisson PCG iterations (parities 1, 2)
     std::vector<double> pois_key;         // what pois_exec was captured for
+    int pois_last_n = 0, pois_last_iters = 0;   // the previous Poisson solve (first batch hint)
     double* oc_buf = nullptr;             // OC update and optimisation-step workspace (grown on demand)
     size_t oc_bytes = 0;
     double* oc_host = nullptr;            // pinned: compliance per pair and load case, change, state
@@ -1709,31 +1710,43 @@ int mtomg_poisson_solve(mtomg_ctx* c, int n, int n_pre, int n_post, double omega
             }
             c->pois_key = key;
         }
-        int launched = 0, batch = 4;
+        // Batches of iterations between host reads: the first is the
+        // previous count at this size (or one pair), the next ones are
+        // predicted from the residual's reduction over the last batch, so a
+        // converged solve queues few iterations that do nothing.
+        int launched = 0;
+        int batch = c->pois_last_n == n && c->pois_last_iters > 0 ? c->pois_last_iters : 2;
+        double prev_rel = 1.0;   // ||r_0|| / ||f||
         while (launched < max_iter) {
             const int nb = std::min(batch, max_iter - launched);
-            for (int k = 0; k < nb;) {
-                if (nb - k >= 2) {
-                    HIPCHK(c, hipGraphLaunch(c->pois_exec, st));
-                    k += 2;
-                } else {
-                    iteration(st, 1);   // one of parity 1; the next batch starts a pair again
-                    k += 1;
-                    launched += 1;
-                    break;
-                }
+            int k = 0;
+            if (launched & 1) {   // the next iteration has parity 2
+                iteration(st, 2);
+                ++k;
             }
-            launched = std::min(max_iter, launched + (nb & ~1));
+            for (; nb - k >= 2; k += 2) HIPCHK(c, hipGraphLaunch(c->pois_exec, st));
+            if (k < nb) iteration(st, 1);
+            launched += nb;
             LAUNCHCHK(c);
             rc = read_scalars();
             if (rc) return rc;
             const int* hst = reinterpret_cast<const int*>(hs + 6);
             if (hst[0] != 0) break;
-            batch = std::min(2 * batch, 16);
+            const double rel = std::sqrt(std::max(hs[4], 0.0) / ff);
+            if (rel > 0.0 && rel < prev_rel) {
+                const double rate = std::pow(rel / prev_rel, 1.0 / nb);
+                const double need = std::ceil(std::log(rel_tol / rel) / std::log(rate));
+                batch = (int)std::min(16.0, std::max(1.0, need));
+            } else {
+                batch = std::min(2 * nb, 16);
+            }
+            prev_rel = rel;
         }
         const int* hst = reinterpret_cast<const int*>(hs + 6);
         it = hst[1];
         cycles = it + 1;
+        c->pois_last_n = n;
+        c->pois_last_iters = it;
         rr = hs[4];
         status = hst[0] == 1 ? MTOMG_OK : hst[0] == 3 ? MTOMG_BREAKDOWN : hst[0] == 4 ? MTOMG_NAN
                                                                                      : MTOMG_NOT_CONVERGED;

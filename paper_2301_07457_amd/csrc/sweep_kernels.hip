@@ -307,13 +307,38 @@ __global__ __launch_bounds__(WG_THREADS) void k_presmooth(
     const bool out_lane = lane >= HL && lane < HL + WOUT && i <= nx;
     const bool node_col = i >= 0 && i <= nx;
 
-    double alpha = 0.0;
+    double rr = 0.0;
+    // right-hand side rows j0-1 .. j0+R, element rows j0-2 .. j0+R
+    V2<T> br[R + 2];
+    Mom<T> me[R + 3];
     if constexpr (CG) {
+        // the loads of the CG apply's p.q partials go out first, then the
+        // tile's (every wave, rows clamped), then the block sums p.q:
+        // alpha = rho / p.q, rho from its producer's total; the p.q total
+        // is stored for the next CG apply
+        PartialSums<1> pqs;
         if (cg.update) {
-            // rho from its producer's total; p.q summed here from the CG
-            // apply's partials, and its total stored for the next CG apply
+            const double* ps[1] = {cg.pq};
+            const int ns[1] = {cg.n_pq};
+            pqs.issue(ps, ns);
+        }
+        __builtin_amdgcn_sched_barrier(0);   // the partials' loads ahead of the tile's
+        // q is loaded whether or not it is used (the initial cycle leaves r
+        // alone): a load under a branch would be waited for at the join
+        V2<double> ro[R + 2], qr[R + 2];
+#pragma unroll
+        for (int s = 0; s < R + 2; ++s) ro[s] = load_node(cg.r_old, nx, ny, i, t.j0 - 1 + s);
+#pragma unroll
+        for (int s = 0; s < R + 2; ++s) qr[s] = load_node(cg.q, nx, ny, i, t.j0 - 1 + s);
+#pragma unroll
+        for (int s = 0; s < R + 3; ++s) me[s] = load_elem<T, FINE>(op, i, t.j0 - 2 + s);
+        __builtin_amdgcn_sched_barrier(0);
+        double alpha = 0.0;
+        if (cg.update) {
             const double rho = cg.zr[cg.n_zr];
-            const double pq = sum_partials(cg.pq, cg.n_pq);
+            double pqv[1];
+            pqs.finish(pqv);
+            const double pq = pqv[0];
             if (blockIdx.x == 0 && threadIdx.x == 0) cg.pq[cg.n_pq] = pq;
             alpha = rho / pq;
             if (!(pq > 0.0) || !(rho > 0.0) || !isfinite(alpha)) {
@@ -322,22 +347,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_presmooth(
             }
             if (blockIdx.x == 0 && threadIdx.x == 0) *cg.iters += 1;
         }
-    }
-    double rr = 0.0;
-    if (t.j0 < t.j1) {
-        // right-hand side rows j0-1 .. j0+R, element rows j0-2 .. j0+R
-        V2<T> br[R + 2];
-        Mom<T> me[R + 3];
-        if constexpr (CG) {
-            V2<double> ro[R + 2], qr[R + 2];
-#pragma unroll
-            for (int s = 0; s < R + 2; ++s) ro[s] = load_node(cg.r_old, nx, ny, i, t.j0 - 1 + s);
-            if (cg.update) {
-#pragma unroll
-                for (int s = 0; s < R + 2; ++s) qr[s] = load_node(cg.q, nx, ny, i, t.j0 - 1 + s);
-            }
-#pragma unroll
-            for (int s = 0; s < R + 3; ++s) me[s] = load_elem<T, FINE>(op, i, t.j0 - 2 + s);
+        if (t.j0 < t.j1) {
 #pragma unroll
             for (int s = 0; s < R + 2; ++s) {
                 V2<double> rv = ro[s];
@@ -360,7 +370,9 @@ __global__ __launch_bounds__(WG_THREADS) void k_presmooth(
                 }
                 br[s] = V2<T>{(T)rv.x, (T)rv.y};
             }
-        } else {
+        }
+    } else {
+        if (t.j0 < t.j1) {
 #pragma unroll
             for (int s = 0; s < R + 2; ++s) br[s] = load_node(b, nx, ny, i, t.j0 - 1 + s);
 #pragma unroll
@@ -370,6 +382,8 @@ __global__ __launch_bounds__(WG_THREADS) void k_presmooth(
                 if (cst != 0) return;
             }
         }
+    }
+    if (t.j0 < t.j1) {
         if (t.j0 == 0 && out_lane) store_node(u_out, nx, i, 0, V2<T>{T(0), T(0)});
 
         V2<T> d0, d1, d2, d3;
@@ -418,6 +432,26 @@ __global__ __launch_bounds__(WG_THREADS) void k_presmooth(
     }
 }
 
+// The outer PCG's convergence test of Algorithm 2 on the device, from the
+// partials of ||r||^2 and ||f||^2 (fixed order, the same bits in every
+// block): issue_check sends the partials' loads (before the caller's tile
+// loads), converged_or_bad sums them; block 0 records 1 (converged) or 4
+// (not finite) in the state word and every block returns whether to stop.
+// All threads of the block call both.
+__device__ __forceinline__ void issue_check(const ConvCheck& chk, PartialSums<2>& ps) {
+    const double* p[2] = {chk.rr, chk.ff};
+    const int n[2] = {chk.n_rr, chk.n_ff};
+    ps.issue(p, n);
+}
+__device__ __forceinline__ bool converged_or_bad(const ConvCheck& chk, PartialSums<2>& ps) {
+    double sv[2];
+    ps.finish(sv);
+    const double rr = sv[0], ff = sv[1];
+    const int code = !(rr == rr) ? 4 : rr <= chk.tol2 * ff ? 1 : 0;
+    if (code != 0 && blockIdx.x == 0 && threadIdx.x == 0) *chk.conv_rw = code;
+    return code != 0;
+}
+
 // ===========================================================================
 // Residual and restriction: rc = P^T (b - K u) onto the next coarser grid
 // (full weighting: weights 1, 1/2, 1/4 from the 3x3 fine neighbourhood of
@@ -430,13 +464,15 @@ __global__ __launch_bounds__(WG_THREADS) void k_presmooth(
 // Residual restriction rc = P^T (b - K u) of one wave's tile: coarse rows
 // j0 .. j1-1 (j0 < j1) of strip `strip` (60 fine columns; even lanes own
 // the coarse columns).  store(I, J, v) receives every coarse node of the
-// tile (J = 0, the clamped row, with v = 0).  With `abort` the wave returns
-// once its loads are issued (a latency-bound caller overlaps the state
-// read with them).
-template <typename T, bool FINE, int R, typename Store>
+// tile (J = 0, the clamped row, with v = 0); a wave with j0 >= j1 loads
+// (clamped rows) and stores nothing.  pre() runs before the loads and
+// abort() once they are issued, by every wave of the block: the wave
+// returns if abort() says so (the caller overlaps the state read or the
+// convergence test with the loads).
+template <typename T, bool FINE, int R, typename Pre, typename Abort, typename Store>
 __device__ __forceinline__ void restrict_tile(const LevelOp<T>& op, const Mat<T>& mat, int strip, int j0, int j1,
-                                              const T* __restrict__ b, const T* __restrict__ u, bool abort,
-                                              Store store) {
+                                              const T* __restrict__ b, const T* __restrict__ u, Pre pre,
+                                              Abort abort, Store store) {
     const int nx = op.nx, ny = op.ny;
     const int ncx = nx / 2;
     constexpr int HL = 2, WOUT = 60;
@@ -450,14 +486,16 @@ __device__ __forceinline__ void restrict_tile(const LevelOp<T>& op, const Mat<T>
     V2<T> ur[NF + 2], br[NF];
     Mom<T> me[NF + 1];
     const T* uu = u ? u : b;   // u == null reads zeros, without a branch
+    pre();
+    __builtin_amdgcn_sched_barrier(0);   // pre()'s loads ahead of the tile's
 #pragma unroll
     for (int s = 0; s < NF + 2; ++s) ur[s] = load_node(uu, nx, ny, i, jf0 - 1 + s, u != nullptr);
 #pragma unroll
     for (int s = 0; s < NF; ++s) br[s] = load_node(b, nx, ny, i, jf0 + s);
 #pragma unroll
     for (int s = 0; s < NF + 1; ++s) me[s] = load_elem<T, FINE>(op, i, jf0 - 1 + s);
-    if constexpr (!FINE) __builtin_amdgcn_sched_barrier(0);   // latency-bound: one batch of loads
-    if (abort) return;
+    __builtin_amdgcn_sched_barrier(0);   // one batch of loads ahead of abort()
+    if (abort()) return;
     V2<T> f0, f1, f2, f3;
     V2<T> ur_lo = from_right(ur[0]), ur_hi = from_right(ur[1]);
     elem_force<FINE>(me[0], mat, ur[0], ur_lo, ur_hi, ur[1], f0, f1, f2, f3);
@@ -511,24 +549,19 @@ __global__ __launch_bounds__(WG_THREADS) void k_restrict(
     const int ncx = nx / 2, ncy = ny / 2;
     const TileInfo t = tile_info<R>(sw, ncy + 1);
     if (!t.block_ok) return;
-    if constexpr (CHECK) {
-        const double* ps[2] = {chk.rr, chk.ff};
-        const int ns[2] = {chk.n_rr, chk.n_ff};
-        double sv[2];
-        sum_partials_k<2>(ps, ns, sv);
-        const double rr = sv[0], ff = sv[1];
-        const bool done = rr <= chk.tol2 * ff;
-        if (!(rr == rr)) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) *chk.conv_rw = 4;
-            return;
-        }
-        if (done) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) *chk.conv_rw = 1;
-            return;
-        }
+    // with CHECK every wave runs the tile's loads and the block-wide test
+    if constexpr (!CHECK) {
+        if (t.j0 >= t.j1) return;
     }
-    if (t.j0 >= t.j1) return;
-    restrict_tile<T, FINE, R>(op, mat, t.strip, t.j0, t.j1, b, u, !FINE && !CHECK && cst != 0,
+    PartialSums<2> cps;
+    restrict_tile<T, FINE, R>(op, mat, t.strip, t.j0, t.j1, b, u,
+                              [&]() {
+                                  if constexpr (CHECK) issue_check(chk, cps);
+                              },
+                              [&]() {
+                                  if constexpr (CHECK) return converged_or_bad(chk, cps);
+                                  else return !FINE && cst != 0;
+                              },
                               [&](int I, int J, const V2<T>& v) { store_node(rc, ncx, I, J, v); });
 }
 
@@ -571,23 +604,11 @@ __global__ __launch_bounds__(WG_THREADS) void k_restrict_pre(
     const int ncx = opc.nx, ncy = opc.ny;
     const TileInfo t = tile_info<R>(sw, ncy + 1);
     if (!t.block_ok) return;
-    if constexpr (CHECK) {
-        const double* ps[2] = {chk.rr, chk.ff};
-        const int ns[2] = {chk.n_rr, chk.n_ff};
-        double sv[2];
-        sum_partials_k<2>(ps, ns, sv);
-        const double rr = sv[0], ff = sv[1];
-        const bool done = rr <= chk.tol2 * ff;
-        if (!(rr == rr)) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) *chk.conv_rw = 4;
-            return;
-        }
-        if (done) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) *chk.conv_rw = 1;
-            return;
-        }
+    // with CHECK every wave runs phase A's loads and the block-wide test (a
+    // wave without rows stores nothing)
+    if constexpr (!CHECK) {
+        if (t.j0 >= t.j1) return;
     }
-    if (t.j0 >= t.j1) return;
     constexpr int CHL = 2, CWOUT = 28;
     const int lane = lane_id();
     const int Ib = t.strip * CWOUT - CHL;      // coarse column of coarse lane 0
@@ -597,6 +618,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_restrict_pre(
     const int ic = Ib + cl;
     // phase B's coarse element rows j0-2 .. j0+R, loaded with phase A's data
     Mom<T> mc[R + 3];
+    PartialSums<2> cps;   // the convergence test's partials (CHECK)
 
     // ---- phase A: fine lane l <-> fine column 2 Ib + l
     {
@@ -607,6 +629,8 @@ __global__ __launch_bounds__(WG_THREADS) void k_restrict_pre(
         V2<T> ur[NF + 2], br[NF];
         Mom<T> me[NF + 1];
         const T* uu = u ? u : b;   // u == null reads zeros, without a branch
+        if constexpr (CHECK) issue_check(chk, cps);
+        __builtin_amdgcn_sched_barrier(0);   // the partials' loads ahead of the tile's
 #pragma unroll
         for (int s = 0; s < NF + 2; ++s) ur[s] = load_node(uu, nx, ny, i, jf0 - 1 + s, u != nullptr);
 #pragma unroll
@@ -615,11 +639,11 @@ __global__ __launch_bounds__(WG_THREADS) void k_restrict_pre(
         for (int s = 0; s < NF + 1; ++s) me[s] = load_elem<T, FINE>(op, i, jf0 - 1 + s);
 #pragma unroll
         for (int s = 0; s < R + 3; ++s) mc[s] = load_elem<T, false>(opc, ic, t.j0 - 2 + s);
-        if constexpr (!FINE) {
-            __builtin_amdgcn_sched_barrier(0);   // latency-bound: one batch of loads
-            if constexpr (!CHECK) {
-                if (cst != 0) return;
-            }
+        __builtin_amdgcn_sched_barrier(0);   // one batch of loads ahead of the tests
+        if constexpr (CHECK) {
+            if (converged_or_bad(chk, cps)) return;
+        } else if constexpr (!FINE) {
+            if (cst != 0) return;
         }
         V2<T> f0, f1, f2, f3;
         V2<T> ur_lo = from_right(ur[0]), ur_hi = from_right(ur[1]);

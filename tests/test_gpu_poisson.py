@@ -48,6 +48,35 @@ def test_matches_oracle(solver, n):
     print(f"[poisson] n={n} L={L} iters={st['iters']} (oracle {o.iters}) {st['t_solve_ms']:.3f} ms")
 
 
+def test_batch_schedule_and_iteration_limits():
+    """The driver queues iterations in batches (the previous count at the
+    same size, else one pair, then as many as the residual's reduction rate
+    predicts; one graph replays a pair).  Whatever the schedule, the
+    iterates are those of Algorithm 2: a repeat solve is bitwise equal to
+    the first, and a solve stopped after k = 1, 2, 3 or 5 iterations
+    (odd counts start the next batch on the second iterate of a pair)
+    holds the oracle's k-th iterate."""
+    from paper_2301_07457_amd import PCGMGSolver
+    n, L = 128, 7
+    rng = np.random.default_rng(11)
+    F = full_load(n, rng.standard_normal((n + 1, n + 1)))
+    Ft = torch.from_numpy(F)
+    fresh = PCGMGSolver(max_designs=1)
+    u1, st1 = fresh.poisson_solve(Ft, 1e-8, 1000)
+    u2, st2 = fresh.poisson_solve(Ft, 1e-8, 1000)
+    assert st1["status"] == 0 and st1["iters"] == st2["iters"]
+    assert torch.equal(u1, u2)
+    for k in (1, 2, 3, 5):
+        u, st = fresh.poisson_solve(Ft, 1e-12, k)
+        assert st["status"] == -2 and st["iters"] == k, st
+        o = poisson.solve_mgpcg(n, L, F[1:-1, 1:-1].ravel(), rel_tol=0.0, max_iter=k)
+        assert relerr(u.cpu().numpy()[1:-1, 1:-1].ravel(), o.x) <= 1e-12, k
+        assert st["relres_rec"] == pytest.approx(o.history[-1], rel=1e-10)
+    # a full solve after the limited ones: the hint is the last count again
+    u3, st3 = fresh.poisson_solve(Ft, 1e-8, 1000)
+    assert st3["iters"] == st1["iters"] and torch.equal(u3, u1)
+
+
 @pytest.mark.parametrize("pre,post,omega", [(1, 1, 0.6), (3, 3, 0.6), (2, 2, 0.8), (0, 2, 0.6)])
 def test_sweep_counts(solver, pre, post, omega):
     n = 64
