@@ -333,10 +333,21 @@ const char *mtomg_last_error(const mtomg_ctx *ctx);
  *     independent of MTOMG_OPT_ROWS_FINE.
  *   MTOMG_OPT_ROWS_LEVEL + k, k = 1..13 (default 0 = MTOMG_OPT_ROWS_COARSE;
  *     1, 2, 4 or 8): rows per wave on the grid k levels below the finest.
- *   The ROWS options re-plan every design, as MTOMG_OPT_ROWS_FINE does. */
+ *   The ROWS options re-plan every design, as MTOMG_OPT_ROWS_FINE does.
+ *   MTOMG_OPT_FUSE_PRE (default 1): run the two pre-smoothing sweeps of a
+ *     level and the restriction of the residual they leave in one launch
+ *     (Section 2.3 steps fused; on the finest grid together with the CG
+ *     update of r, the convergence test then opening the level below)
+ *     where no other fusion of that level is used: n_pre = 2, the V-cycle,
+ *     and for the finest grid 3 levels or a grid two below the finest of
+ *     more than 32768 nodes.  0 launches the steps one by one.  Both take
+ *     the same operations per node in the same order; they differ by
+ *     rounding only (the compiler forms fused multiply-adds differently
+ *     in the two kernels, and the partial sums of ||r||^2 are grouped by
+ *     different tiles). */
 enum { MTOMG_OPT_GRAPHS = 0, MTOMG_OPT_BATCH = 1, MTOMG_OPT_ROWS_FINE = 2, MTOMG_OPT_ROWS_COARSE = 3,
        MTOMG_OPT_DENSE_FACTOR = 4, MTOMG_OPT_GAMMA = 5, MTOMG_OPT_RESTARTS = 6, MTOMG_OPT_ROWS_CG = 7,
-       MTOMG_OPT_ROWS_LEVEL = 16 };
+       MTOMG_OPT_FUSE_PRE = 8, MTOMG_OPT_ROWS_LEVEL = 16 };
 int mtomg_set_option(mtomg_ctx *ctx, int option, int value);
 
 /* Profiling: time every launch of one solver kernel during the following
@@ -352,8 +363,10 @@ int mtomg_set_option(mtomg_ctx *ctx, int option, int value);
 enum {
     MTOMG_KERNEL_NONE = 0,
     MTOMG_KERNEL_CG_APPLY = 1,        /* FP64 p update + K p + p.q (outer CG)      */
-    MTOMG_KERNEL_FINE_PRESMOOTH = 2,  /* r update + two Jacobi sweeps, finest grid */
-    MTOMG_KERNEL_FINE_RESTRICT = 3,   /* residual + restriction, finest grid       */
+    MTOMG_KERNEL_FINE_PRESMOOTH = 2,  /* r update + two Jacobi sweeps, finest grid
+                                         (+ residual restriction when fused)      */
+    MTOMG_KERNEL_FINE_RESTRICT = 3,   /* residual + restriction, finest grid
+                                         (no launch when fused, see FUSE_PRE)     */
     MTOMG_KERNEL_FINE_POST = 4,       /* prolongation + Jacobi sweep, finest grid  */
     MTOMG_KERNEL_FINE_POST_DOT = 5,   /* last Jacobi sweep + z.r, finest grid      */
     MTOMG_KERNEL_COARSE_SOLVE = 6     /* explicit-inverse coarsest solve           */
@@ -394,6 +407,10 @@ int mtomg_stream_probe(mtomg_ctx *ctx, int kind, double *a, double *b, double *c
  *   COARSE_SOLVE (level 0)
  *             in: b           out: K_0^{-1} b
  *   VCYCLE    in: b           out: MG_1^l(0, b) (Algorithm 1)
+ *   PRESMOOTH_RESTRICT (n_pre = 2)
+ *             in: b           out: P_l^T (b - K_l u) (a level l-1 vector)
+ *                               followed by u, two damped-Jacobi sweeps
+ *                               from 0 (the fused launch of FUSE_PRE)
  */
 enum {
     MTOMG_OP_APPLY = 0,
@@ -404,7 +421,8 @@ enum {
     MTOMG_OP_PROLONG_POSTSMOOTH = 5,
     MTOMG_OP_SMOOTH = 6,
     MTOMG_OP_COARSE_SOLVE = 7,
-    MTOMG_OP_VCYCLE = 8
+    MTOMG_OP_VCYCLE = 8,
+    MTOMG_OP_PRESMOOTH_RESTRICT = 9
 };
 int mtomg_debug_apply(mtomg_ctx *ctx, int design, int level, int op, const void *in, void *out);
 

@@ -25,7 +25,7 @@ MTOMG_FP64 = 0
 MTOMG_FP32MG = 1
 
 OPS = dict(APPLY=0, APPLY64=1, DIAG=2, PRESMOOTH=3, RESIDUAL_RESTRICT=4, PROLONG_POSTSMOOTH=5,
-           SMOOTH=6, COARSE_SOLVE=7, VCYCLE=8)
+           SMOOTH=6, COARSE_SOLVE=7, VCYCLE=8, PRESMOOTH_RESTRICT=9)
 
 EXPORTS = ["mtomg_create", "mtomg_destroy", "mtomg_set_grid", "mtomg_workspace_bytes",
            "mtomg_set_workspace", "mtomg_set_densities", "mtomg_solve",
@@ -35,7 +35,7 @@ EXPORTS = ["mtomg_create", "mtomg_destroy", "mtomg_set_grid", "mtomg_workspace_b
            "mtomg_oc_update", "mtomg_aap_step", "mtomg_stream_probe"]
 
 OPTIONS = dict(GRAPHS=0, BATCH=1, ROWS_FINE=2, ROWS_COARSE=3, DENSE_FACTOR=4, GAMMA=5, RESTARTS=6, ROWS_CG=7,
-               ROWS_LEVEL=16)
+               FUSE_PRE=8, ROWS_LEVEL=16)
 
 
 def option_code(name: str) -> int:

@@ -128,11 +128,20 @@ __device__ __forceinline__ void mom_accumulate_child(Mom<T>& P, const Mom<T>& c,
     P.m02 += T(0.0625) * (U * c.m00 + T(2) * U * c.m01 + c.m02);
 }
 
+// omega / d, the damped-Jacobi weight of a node.  In FP32 (the multigrid
+// cycle's precision there) by the hardware reciprocal (1 ulp) instead of the
+// correctly rounded division sequence (about ten instructions); in FP64 the
+// division itself.
+__device__ __forceinline__ float w_over(float omega, float d) { return omega * __builtin_amdgcn_rcpf(d); }
+__device__ __forceinline__ double w_over(double omega, double d) { return omega / d; }
+
 // ---------------------------------------------------------------------------
 // wave helpers
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
-__device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
+// the same for every lane of a wave: readfirstlane lets the compiler keep
+// row indices, masks and addresses derived from it in scalar registers
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 // Neighbour lanes by whole-wave DPP shifts (a VALU operand modifier, no
 // LDS round trip): from_left gives lane l the value of lane l-1 (lane 0

@@ -55,6 +55,7 @@ struct LevelBufs {
     Sweep sw_cg{};      // outer-CG apply (finest level)
     Sweep sw_post2{};   // two fused post-smoothing sweeps
     Sweep sw_rp{};      // restriction fused with the next level's pre-smoothing (coarse geometry)
+    Sweep sw_pr{};      // two pre-smoothing sweeps fused with the restriction (coarse geometry, <= 4 rows)
     size_t nodes() const { return (size_t)(nx + 1) * (ny + 1); }
 };
 
@@ -163,6 +164,7 @@ struct mtomg_ctx {
     int rows_depth[16] = {};              // per grid k levels below the finest (0 = rows_coarse)
     int max_restarts = 4;                 // PCG restarts after a failed true-residual check
     int gamma = 1;                        // cycle index of Algorithm 1: 1 V-cycle, 2 W-cycle
+    bool fuse_pre = true;                 // MTOMG_OPT_FUSE_PRE
     double* filt_tab = nullptr;           // device weight table of mtomg_filter (FILTER_TAB_MAX doubles)
     double* filt_host = nullptr;          // pinned staging copy of it
     double filt_rf = -1.0;                // radius the table holds
@@ -250,6 +252,8 @@ void plan_level(LevelBufs& L, int R = 0, int Rcg = 0) {
     if (L.nx % 2 == 0 && L.ny % 2 == 0) {
         L.sw_res = make_sweep(L.nx / 2 + 1, 30, L.ny / 2 + 1, R);
         L.sw_rp = make_sweep(L.nx / 2 + 1, 28, L.ny / 2 + 1, R);
+        L.sw_pr = make_sweep(L.nx / 2 + 1, 28, L.ny / 2 + 1, R);
+        if (L.sw_pr.rows > 4) L.sw_pr = make_sweep(L.nx / 2 + 1, 28, L.ny / 2 + 1, 4);
     }
 }
 
@@ -304,7 +308,7 @@ void layout_case_slab(const Design& d, CaseBufs& c, Bump& B) {
     const LevelBufs& Lf = d.lev[d.fine()];
     const size_t nf = Lf.nodes() * 2;
     const int np = std::max({Lf.sw_apply.n_tiles, Lf.sw_cg.n_tiles, Lf.sw_pre.n_tiles, Lf.sw_post.n_tiles,
-                             Lf.sw_post2.n_tiles, 1});
+                             Lf.sw_post2.n_tiles, Lf.sw_pr.n_tiles, 1});
     // partial-sum arrays: n partials and, for z.r and p.q, their total after them
     for (int k = 0; k < 2; ++k) {
         c.r[k] = B.take<double>(nf);
@@ -486,6 +490,7 @@ template <typename T> struct CycleCtx {
     Batch bt{};        // systems of every launch (pointers above are system 0's)
     hipEvent_t wait_coarse = nullptr;   // the coarse solve waits for it (coarsest factors ready)
     int gamma = 1;                      // coarse-grid visits per level (Algorithm 1)
+    bool fuse = true;                   // pre-smoothing fused with the restriction where it pays
     void begin(int id) { if (prof) prof->begin(id, st); }
     void end(int id) { if (prof) prof->end(id, st); }
 };
@@ -549,6 +554,29 @@ constexpr long FUSE_MAX_COARSE_NODES = 32768;
 // level l that each wave's prolongation needs, so they pay up to a level
 // l+1 of this many nodes summed over the systems of the launch.
 constexpr long PAIR_MAX_NODES = 70000;
+
+// Two pre-smoothing sweeps fused with the restriction (k_pre_restrict) on
+// level l of a V-cycle, where the restriction is not already fused with the
+// pre-smoothing of level l-1 (which removes more launches).
+template <typename T>
+bool use_pre_restrict(const CycleCtx<T>& cx, int l) {
+    const Design& d = *cx.d;
+    const bool rp = l - 1 >= 1 && (long)d.lev[l - 1].nodes() * cx.bt.n <= FUSE_MAX_COARSE_NODES;
+    return cx.fuse && cx.gamma == 1 && d.n_pre == 2 && l >= 1 && !rp;
+}
+// The finest grid's pre-smoothing, restriction and CG update in one launch.
+// The convergence test then moves to the first launch on the level below,
+// which must be a k_pre_restrict too: level f-2 is the coarsest or too big
+// for the restriction-presmoothing fusion for any number of systems.
+bool fine_fused(bool fuse, int gamma, const Design& d) {
+    if (!fuse || gamma != 1 || d.levels < 3 || d.n_pre != 2) return false;
+    return d.levels == 3 || (long)d.lev[d.fine() - 2].nodes() > FUSE_MAX_COARSE_NODES;
+}
+// partial sums of ||r||^2 of a PCG iteration: from the fused launch or k_presmooth
+int rr_tiles(bool fuse, int gamma, const Design& d) {
+    const LevelBufs& L = d.lev[d.fine()];
+    return fine_fused(fuse, gamma, d) ? L.sw_pr.n_tiles : L.sw_pre.n_tiles;
+}
 template <typename T>
 bool restrict_down(CycleCtx<T>& cx, int l, const T* b, const T* u, bool check, const ConvCheck& chk) {
     Design& d = *cx.d;
@@ -572,7 +600,7 @@ bool restrict_down(CycleCtx<T>& cx, int l, const T* b, const T* u, bool check, c
 // iterate of each level stays in u2 or u4 (which one depends on the number
 // of sweeps only), so a captured launch sequence is the same every time.
 template <typename T>
-void coarse_cycle(CycleCtx<T>& cx, int top, bool top_pre) {
+void coarse_cycle(CycleCtx<T>& cx, int top, bool top_pre, const ConvCheck* chk) {
     Design& d = *cx.d;
     CaseBufs& c = *cx.c;
     ConvCheck nochk{};
@@ -584,6 +612,15 @@ void coarse_cycle(CycleCtx<T>& cx, int top, bool top_pre) {
         T* t0 = (T*)c.u2[l];
         T* t1 = (T*)c.u4[l];
         T* cur = t0;
+        if (!pre_done && use_pre_restrict(cx, l)) {
+            // with chk (top level below a fused finest grid) the convergence test runs here
+            const bool check = chk && l == top;
+            launch_pre_restrict<T>(cx.st, false, false, check, level_op<T>(d, l), make_mat<T>(d, d.omega),
+                                   d.lev[l].sw_pr, b, t0, (T*)c.b[l - 1], nocg, check ? *chk : nochk, cx.conv,
+                                   cx.bt);
+            pre[l] = t0;
+            continue;
+        }
         if (d.n_pre > 0) {
             if (!pre_done)
                 launch_presmooth<T>(cx.st, false, false, level_op<T>(d, l), make_mat<T>(d, d.omega), d.lev[l].sw_pre,
@@ -692,9 +729,9 @@ void w_visit(CycleCtx<T>& cx, int l, bool from_e, bool pre_done) {
 // top .. 0 of Algorithm 1 with cycle index cx.gamma (the V-cycle visits
 // each level once, the W-cycle visits level top twice and recurses).
 template <typename T>
-void coarse_correction(CycleCtx<T>& cx, int top, bool top_pre) {
+void coarse_correction(CycleCtx<T>& cx, int top, bool top_pre, const ConvCheck* chk = nullptr) {
     if (cx.gamma == 1) {
-        coarse_cycle<T>(cx, top, top_pre);
+        coarse_cycle<T>(cx, top, top_pre, chk);
         return;
     }
     w_visit<T>(cx, top, false, top_pre);
@@ -728,6 +765,26 @@ void fine_cycle(CycleCtx<T>& cx, int it, double tol2) {
     T* t0 = (T*)c.u2[f];
     T* t1 = (T*)c.u4[f];
     const T* bfine = d.mixed() ? (const T*)(void*)c.r32 : (const T*)(void*)c.r[nxt];
+    if (fine_fused(cx.fuse, cx.gamma, d)) {
+        // pre-smoothing, restriction and the CG update of r in one launch;
+        // the convergence test on its ||r||^2 partials opens level f-1
+        cx.begin(MTOMG_KERNEL_FINE_PRESMOOTH);
+        launch_pre_restrict<T>(cx.st, true, true, false, level_op<T>(d, f), make_mat<T>(d, d.omega), L.sw_pr,
+                               nullptr, t0, (T*)c.b[f - 1], cg, ConvCheck{}, cx.conv, cx.bt);
+        cx.end(MTOMG_KERNEL_FINE_PRESMOOTH);
+        ConvCheck chk{};
+        chk.rr = c.rr[nxt];
+        chk.n_rr = it < 0 ? L.sw_apply.n_tiles : L.sw_pr.n_tiles;
+        chk.ff = c.ff;
+        chk.n_ff = L.sw_apply.n_tiles;
+        chk.tol2 = tol2;
+        chk.conv_rw = c.state;
+        coarse_correction<T>(cx, f - 1, false, &chk);
+        post_chain<T>(cx, f, t0, (const T*)c.e[f - 1], bfine, (T*)c.z, t1, t0, true, c.r[nxt],
+                      c.zr[it < 0 ? 0 : nxt]);
+        launch_partial_total(cx.st, c.zr[it < 0 ? 0 : nxt], d.zr_tiles(), cx.conv, cx.bt);
+        return;
+    }
     cx.begin(MTOMG_KERNEL_FINE_PRESMOOTH);
     launch_presmooth<T>(cx.st, true, true, level_op<T>(d, f), make_mat<T>(d, d.omega), L.sw_pre, nullptr, t0,
                         std::min(d.n_pre, 2), cg, cx.conv, cx.bt);
@@ -784,6 +841,7 @@ int debug_vcycle(mtomg_ctx* ctx, Design& d, CaseBufs& cb, hipStream_t st, int le
     ConvCheck nochk{};
     CycleCtx<T> cx{&d, &cb, st, nullptr};
     cx.gamma = ctx->gamma;
+    cx.fuse = ctx->fuse_pre;
     T* t0 = (T*)cb.u2[level];
     T* t1 = (T*)cb.u4[level];
     T* cur = t0;
@@ -928,6 +986,7 @@ CycleCtx<T> group_cycle(mtomg_ctx* c, Group& g, hipStream_t st, Prof* prof) {
     CycleCtx<T> cx{&d0, &d0.cases[0], st, d0.cases[0].state, prof};
     cx.bt = g.batch();
     cx.gamma = c->gamma;
+    cx.fuse = c->fuse_pre;
     return cx;
 }
 
@@ -1025,7 +1084,7 @@ int pcg_round(mtomg_ctx* c, const std::vector<int>& gsys0, double tol2, int max_
             launch_residual(st, level_op<double>(d, d.fine()), make_mat<double>(d, d.omega), L.sw_apply, nullptr,
                             nullptr, 1, nullptr, cb.trr, nullptr, cb.state, bt);
             launch_solve_sums(st, cb.ff, L.sw_apply.n_tiles, cb.rr[0], cb.rr[1], L.sw_apply.n_tiles,
-                              L.sw_pre.n_tiles, cb.trr, cb.state, cb.sums, bt);
+                              rr_tiles(c->fuse_pre, c->gamma, d), cb.trr, cb.state, cb.sums, bt);
         }
         LAUNCHCHK(c);
         HIPCHK(c, hipEventRecord(c->ev_solve[1], st));
@@ -1942,6 +2001,11 @@ int mtomg_set_option(mtomg_ctx* c, int option, int value) {
         case MTOMG_OPT_GRAPHS:
             c->use_graphs = value != 0;
             return MTOMG_OK;
+        case MTOMG_OPT_FUSE_PRE:
+            hipStreamSynchronize(c->stream);
+            c->fuse_pre = value != 0;
+            drop_graphs(c);   // the captured iteration launches other kernels now
+            return MTOMG_OK;
         case MTOMG_OPT_RESTARTS:
             if (value < 0 || value > 64) return fail(c, MTOMG_BAD_INPUT, "restarts must be in [0, 64]");
             c->max_restarts = value;
@@ -2083,6 +2147,14 @@ int mtomg_debug_apply(mtomg_ctx* c, int design, int level, int op, const void* i
                 launch_presmooth<T>(st, fine, false, opT, mat, L.sw_pre, vin, t0, std::min(d.n_pre, 2), nocg, nullptr);
                 T* cur = pre_chain_extra<T>(cx, level, t0, vin, t0, t1);
                 HIPCHK(c, hipMemcpyAsync(vout, cur, n * sizeof(T), hipMemcpyDeviceToDevice, st));
+                break;
+            }
+            case MTOMG_OP_PRESMOOTH_RESTRICT: {
+                if (level == 0) return fail(c, MTOMG_BAD_INPUT, "no restriction from the coarsest level");
+                if (d.n_pre != 2) return fail(c, MTOMG_BAD_INPUT, "the fused pre-smoothing runs two sweeps (n_pre = 2)");
+                const size_t nc = 2 * d.lev[level - 1].nodes();
+                launch_pre_restrict<T>(st, fine, false, false, opT, mat, L.sw_pr, vin, vout + nc, vout, nocg, nochk,
+                                       nullptr);
                 break;
             }
             case MTOMG_OP_RESIDUAL_RESTRICT:

@@ -87,6 +87,15 @@ template <typename T>
 void launch_restrict(hipStream_t st, bool fine, bool check, LevelOp<T> op, Mat<T> mat, Sweep sw,
                      const T* b, const T* u, T* rc, const ConvCheck& chk, const int* conv,
                      const Batch& bt = Batch{});
+// two pre-smoothing sweeps from zero on level l and the restriction of the
+// residual they leave: u_out = S(S(0)), rc = P^T (b - K u_out); with cgmode
+// b is the outer residual updated from cg (finest grid), with check the
+// outer PCG's convergence test (chk) runs first; geometry: 28 coarse
+// columns per strip, at most 4 rows per wave
+template <typename T>
+void launch_pre_restrict(hipStream_t st, bool fine, bool cgmode, bool check, LevelOp<T> op, Mat<T> mat, Sweep sw,
+                         const T* b, T* u_out, T* rc, const CgRhs& cg, const ConvCheck& chk, const int* conv,
+                         const Batch& bt = Batch{});
 // restriction to level l-1 fused with its first (up to two) pre-smoothing
 // sweeps; op / opc: levels l and l-1; geometry: 28 coarse columns per strip
 template <typename T>

@@ -399,7 +399,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_presmooth(
             dcarry = d3 + from_left(d2);
             const V2<T> bk = br[s];
             const bool kok = node_col && k >= 1 && k <= ny;
-            const V2<T> wD{mat.omega / D.x, mat.omega / D.y};   // w D^-1, reused by the second sweep
+            const V2<T> wD{w_over(mat.omega, D.x), w_over(mat.omega, D.y)};   // w D^-1, reused by the second sweep
             const V2<T> u1{kok ? bk.x * wD.x : T(0), kok ? bk.y * wD.y : T(0)};
             const V2<T> u1r = from_right(u1);
             if (s >= 1) {
@@ -703,7 +703,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_restrict_pre(
         dcarry = d3 + from_left(d2);
         const V2<T> bk = br[s];
         const bool kok = node_col && k >= 1 && k <= ncy;
-        const V2<T> wD{mat.omega / D.x, mat.omega / D.y};   // w D^-1, reused by the second sweep
+        const V2<T> wD{w_over(mat.omega, D.x), w_over(mat.omega, D.y)};   // w D^-1, reused by the second sweep
         const V2<T> u1{kok ? bk.x * wD.x : T(0), kok ? bk.y * wD.y : T(0)};
         const V2<T> u1r = from_right(u1);
         if (s >= 1) {
@@ -844,8 +844,8 @@ __global__ __launch_bounds__(WG_THREADS) void k_post(
             if (out_lane && j < t.j1) {
                 if (j >= 1) {
                     V2<T> uo;
-                    uo.x = vr[s + 1].x + mat.omega * (br[s].x - fs.x) / D.x;
-                    uo.y = vr[s + 1].y + mat.omega * (br[s].y - fs.y) / D.y;
+                    uo.x = vr[s + 1].x + (br[s].x - fs.x) * w_over(mat.omega, D.x);
+                    uo.y = vr[s + 1].y + (br[s].y - fs.y) * w_over(mat.omega, D.y);
                     store_node(u_out, nx, i, j, uo);
                     if constexpr (DOT) dot += (double)uo.x * rr64[s].x + (double)uo.y * rr64[s].y;
                 } else {
@@ -857,6 +857,224 @@ __global__ __launch_bounds__(WG_THREADS) void k_post(
     if constexpr (DOT) {
         const double s = block_sum(dot);
         if (threadIdx.x == 0) zr_out[t.tile] = s;
+    }
+}
+
+// ===========================================================================
+// Two pre-smoothing sweeps from zero and the restriction of the residual
+// they leave, in one pass: u1 = w D^-1 b, u2 = u1 + w D^-1 (b - K u1),
+// rc = P^T (b - K u2).  u2 is stored (the post-smoother starts from it);
+// u1 and the residual stay in registers.  With CG (finest grid inside PCG)
+// b is the outer residual updated on the fly, r_new = r_old - alpha q, as
+// in k_presmooth (r_new, its FP32 copy and partial ||r_new||^2 stored).
+// With CHECK the outer PCG's convergence test on the partials of
+// ||r||^2 (from the finest grid's launch) comes first, overlapped with the
+// tile's loads.  Per node the operations and their order are those of
+// k_presmooth followed by k_restrict (the two agree to rounding: the
+// compiler contracts multiply-adds differently in each kernel).
+// Geometry: lane l <-> node column i = 56 strip - 4 + l.  A wave owns the
+// coarse rows j0 .. j1-1 and the coarse columns 28 strip .. 28 strip + 27,
+// i.e. the fine columns 56 strip .. 56 strip + 55 (lanes 4..59) and fine
+// rows 2 j0 .. 2 j1 - 1, and marches over the node rows 2 j0 - 3 ..
+// 2 j0 + 2R + 1 (NS = 2R + 5): the diagonal, hence u1, is valid on lanes
+// 1..63 (lane 0 lacks its left element), u2 on 2..62, the residual on
+// 3..61 and its horizontal full weighting on 4..60.  Step s forms u1 on
+// node row k = 2 j0 - 3 + s, u2 on row k-1 and the residual on row k-2;
+// the coarse row (k-3)/2 is complete when k-2 is odd.
+// ===========================================================================
+template <typename T, bool FINE, bool CG, bool CHECK, int R>
+__global__ __launch_bounds__(WG_THREADS) void k_pre_restrict(
+    LevelOp<T> op, Mat<T> mat, Sweep sw, const T* __restrict__ b, T* __restrict__ u_out, T* __restrict__ rc,
+    CgRhs cg, ConvCheck chk, const int* conv, Batch bt) {
+    constexpr int NS = 2 * R + 5;
+    const SysOff so = sys_off(bt);
+    conv = at(conv, so.c);
+    op.data = at(op.data, so.d);
+    b = at(b, so.c);
+    u_out = at(u_out, so.c);
+    rc = at(rc, so.c);
+    if constexpr (CG) {
+        cg.r_old = at(cg.r_old, so.c);
+        cg.q = at(cg.q, so.c);
+        cg.r_new = at(cg.r_new, so.c);
+        cg.r32 = at(cg.r32, so.c);
+        cg.zr = at(cg.zr, so.c);
+        cg.pq = at(cg.pq, so.c);
+        cg.rr_out = at(cg.rr_out, so.c);
+        cg.conv_rw = at(cg.conv_rw, so.c);
+        cg.iters = at(cg.iters, so.c);
+    }
+    if constexpr (CHECK) {
+        chk.rr = at(chk.rr, so.c);
+        chk.ff = at(chk.ff, so.c);
+        chk.conv_rw = at(chk.conv_rw, so.c);
+    }
+    const int cst = load_state(conv);
+    if constexpr (CG) {
+        if (cst == 1 && blockIdx.x == 0 && threadIdx.x == 0) *cg.conv_rw = 2;
+    }
+    if constexpr (FINE || CG || CHECK) {
+        if (cst != 0) return;
+    }
+    const int nx = op.nx, ny = op.ny;
+    const int ncx = nx / 2, ncy = ny / 2;
+    const TileInfo t = tile_info<R>(sw, ncy + 1);
+    if (!t.block_ok) return;
+    // a wave without rows (t.j0 >= t.j1) runs along and stores nothing: the
+    // block-wide sums need every wave
+    constexpr int HL = 4, WOUT = 56;
+    const int lane = lane_id();
+    const int i = t.strip * WOUT - HL + lane;
+    const bool node_col = i >= 0 && i <= nx;
+    const bool own_col = lane >= HL && lane < HL + WOUT && i <= nx;
+    const bool out_lane = own_col && !(i & 1);   // even fine column 2I <-> coarse column I
+    const int I = i >> 1;
+    const int base = 2 * t.j0 - 3;               // node row of step 0
+    const int fr0 = 2 * t.j0, fr1 = min(2 * t.j1 - 1, ny);   // owned fine rows
+
+    PartialSums<1> pqs;
+    PartialSums<2> cps;
+    if constexpr (CG) {
+        if (cg.update) {
+            const double* ps[1] = {cg.pq};
+            const int ns[1] = {cg.n_pq};
+            pqs.issue(ps, ns);
+        }
+    }
+    if constexpr (CHECK) issue_check(chk, cps);
+    __builtin_amdgcn_sched_barrier(0);   // the partials' loads ahead of the tile's
+    // right-hand side rows base .. base+NS-1, element rows base-1 .. base+NS-1
+    V2<T> br[NS];
+    Mom<T> me[NS + 1];
+    V2<double> ro[CG ? NS : 1], qr[CG ? NS : 1];
+    if constexpr (CG) {
+        // q is loaded whether or not it is used, as in k_presmooth
+#pragma unroll
+        for (int s = 0; s < NS; ++s) ro[s] = load_node(cg.r_old, nx, ny, i, base + s);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) qr[s] = load_node(cg.q, nx, ny, i, base + s);
+    } else {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) br[s] = load_node(b, nx, ny, i, base + s);
+    }
+#pragma unroll
+    for (int s = 0; s < NS + 1; ++s) me[s] = load_elem<T, FINE>(op, i, base - 1 + s);
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (CHECK) {
+        if (converged_or_bad(chk, cps)) return;
+    } else if constexpr (!FINE && !CG) {
+        if (cst != 0) return;
+    }
+
+    double rr = 0.0;
+    if constexpr (CG) {
+        double alpha = 0.0;
+        if (cg.update) {
+            const double rho = cg.zr[cg.n_zr];
+            double pqv[1];
+            pqs.finish(pqv);
+            const double pq = pqv[0];
+            if (blockIdx.x == 0 && threadIdx.x == 0) cg.pq[cg.n_pq] = pq;
+            alpha = rho / pq;
+            if (!(pq > 0.0) || !(rho > 0.0) || !isfinite(alpha)) {
+                if (blockIdx.x == 0 && threadIdx.x == 0) *cg.conv_rw = isfinite(alpha) ? 3 : 4;
+                return;
+            }
+            if (blockIdx.x == 0 && threadIdx.x == 0) *cg.iters += 1;
+        }
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            V2<double> rv = ro[s];
+            if (cg.update) {
+                rv.x -= alpha * qr[s].x;
+                rv.y -= alpha * qr[s].y;
+            }
+            const int jj = base + s;
+            if (own_col && jj >= fr0 && jj <= fr1) {
+                if (jj >= 1) {
+                    if (cg.update) {
+                        store_node(cg.r_new, nx, i, jj, rv);
+                        rr += rv.x * rv.x + rv.y * rv.y;
+                    }
+                    if constexpr (sizeof(T) == 4) store_node(cg.r32, nx, i, jj, V2<float>{(float)rv.x, (float)rv.y});
+                } else {
+                    if (cg.update) store_node(cg.r_new, nx, i, jj, V2<double>{0.0, 0.0});
+                    if constexpr (sizeof(T) == 4) store_node(cg.r32, nx, i, jj, V2<float>{0.f, 0.f});
+                }
+            }
+            br[s] = V2<T>{(T)rv.x, (T)rv.y};
+        }
+    }
+
+    V2<T> d0, d1, d2, d3;
+    elem_diag<FINE>(me[0], mat, d0, d1, d2, d3);
+    V2<T> dcarry = d3 + from_left(d2);
+    V2<T> fcarry{T(0), T(0)}, gcarry{T(0), T(0)};
+    V2<T> u1_prev{T(0), T(0)}, u1r_prev{T(0), T(0)}, wD_prev{T(0), T(0)};
+    V2<T> u2_prev{T(0), T(0)}, u2r_prev{T(0), T(0)};
+    V2<T> h_m1{T(0), T(0)}, h_m2{T(0), T(0)};
+    bool kok_prev = false;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int k = base + s;
+        // stage A: the diagonal of node row k (element rows k-1, k) and u1 there
+        elem_diag<FINE>(me[s + 1], mat, d0, d1, d2, d3);
+        const V2<T> D = dcarry + d0 + from_left(d1);
+        dcarry = d3 + from_left(d2);
+        const V2<T> bk = br[s];
+        const bool kok = node_col && k >= 1 && k <= ny;
+        const V2<T> wD{w_over(mat.omega, D.x), w_over(mat.omega, D.y)};   // w D^-1, reused by the second sweep
+        const V2<T> u1{kok ? bk.x * wD.x : T(0), kok ? bk.y * wD.y : T(0)};
+        const V2<T> u1r = from_right(u1);
+        if (s >= 1) {
+            // stage B: element row k-1 on u1 completes K u1 at node row k-1 -> u2 there
+            V2<T> f0, f1, f2, f3;
+            elem_force<FINE>(me[s], mat, u1_prev, u1r_prev, u1r, u1, f0, f1, f2, f3);
+            const V2<T> fs = fcarry + f0 + from_left(f1);
+            fcarry = f3 + from_left(f2);
+            const int jr = k - 1;
+            const V2<T> bp = br[s - 1];
+            const V2<T> u2{kok_prev ? u1_prev.x + (bp.x - fs.x) * wD_prev.x : T(0),
+                           kok_prev ? u1_prev.y + (bp.y - fs.y) * wD_prev.y : T(0)};
+            if (own_col && jr >= fr0 && jr <= fr1) store_node(u_out, nx, i, jr, u2);
+            const V2<T> u2r = from_right(u2);
+            if (s >= 2) {
+                // stage C: element row k-2 on u2 completes K u2 at node row j = k-2 -> residual
+                V2<T> g0, g1, g2, g3;
+                elem_force<FINE>(me[s - 1], mat, u2_prev, u2r_prev, u2r, u2, g0, g1, g2, g3);
+                const V2<T> ku = gcarry + g0 + from_left(g1);
+                gcarry = g3 + from_left(g2);
+                const int j = k - 2;
+                const bool jok = node_col && j >= 1 && j <= ny;
+                const V2<T> bj = br[s - 2];
+                const V2<T> res{jok ? bj.x - ku.x : T(0), jok ? bj.y - ku.y : T(0)};
+                const V2<T> rl = from_left(res), rrt = from_right(res);
+                const V2<T> h{res.x + T(0.5) * (rl.x + rrt.x), res.y + T(0.5) * (rl.y + rrt.y)};
+                // stage D: j = 2J + 1 (s even) completes coarse row J from fine rows 2J-1 .. 2J+1
+                if ((s & 1) == 0 && s >= 6) {
+                    const int J = t.j0 - 3 + s / 2;
+                    if (out_lane && J < t.j1) {
+                        V2<T> v{h_m1.x + T(0.5) * (h_m2.x + h.x), h_m1.y + T(0.5) * (h_m2.y + h.y)};
+                        if (J == 0) v = V2<T>{T(0), T(0)};
+                        store_node(rc, ncx, I, J, v);
+                    }
+                }
+                h_m2 = h_m1;
+                h_m1 = h;
+            }
+            u2_prev = u2;
+            u2r_prev = u2r;
+        }
+        u1_prev = u1;
+        u1r_prev = u1r;
+        wD_prev = wD;
+        kok_prev = kok;
+    }
+    if constexpr (CG) {
+        if (cg.update) {
+            const double s = block_sum(rr);
+            if (threadIdx.x == 0) cg.rr_out[t.tile] = s;
+        }
     }
 }
 
@@ -890,7 +1108,7 @@ __device__ __forceinline__ void post2_stages(const Mat<T>& mat, const V2<T>* vr,
         dc1 = d3 + from_left(d2);
         const bool kok = node_col && k >= 1 && k <= ny;
         const V2<T> bk = br[s - 1];
-        const V2<T> wD{mat.omega / D.x, mat.omega / D.y};   // w D^-1, reused by the second stage
+        const V2<T> wD{w_over(mat.omega, D.x), w_over(mat.omega, D.y)};   // w D^-1, reused by the second stage
         const V2<T> u1{kok ? vr[s].x + (bk.x - F.x) * wD.x : T(0),
                        kok ? vr[s].y + (bk.y - F.y) * wD.y : T(0)};
         const V2<T> u1r = from_right(u1);
@@ -1226,6 +1444,14 @@ static inline dim3 grid_of(const Sweep& s, const Batch& bt = Batch{}) {
     return dim3(8 * ((s.n_tiles + 7) / 8), bt.n);
 }
 
+// rows per wave of k_pre_restrict: at most 4 (it holds 2R + 5 node rows)
+#define MTOMG_ROWS4_SWITCH(R_, CALL)              \
+    switch (R_) {                                 \
+        case 1: { constexpr int RR = 1; CALL; } break; \
+        case 2: { constexpr int RR = 2; CALL; } break; \
+        default: { constexpr int RR = 4; CALL; } break; \
+    }
+
 #define MTOMG_ROWS_SWITCH(R_, CALL)               \
     switch (R_) {                                 \
         case 1: { constexpr int RR = 1; CALL; } break; \
@@ -1285,6 +1511,21 @@ void launch_restrict(hipStream_t st, bool fine, bool check, LevelOp<T> op, Mat<T
     else if (fine) MTOMG_RES(true, false)
     else MTOMG_RES(false, false)
 #undef MTOMG_RES
+}
+
+template <typename T>
+void launch_pre_restrict(hipStream_t st, bool fine, bool cgmode, bool check, LevelOp<T> op, Mat<T> mat, Sweep sw,
+                         const T* b, T* u_out, T* rc, const CgRhs& cg, const ConvCheck& chk, const int* conv,
+                         const Batch& bt) {
+#define MTOMG_PR(F, C, K)                                                                             \
+    MTOMG_ROWS4_SWITCH(sw.rows, MTOMG_LAUNCH((k_pre_restrict<T, F, C, K, RR>), grid_of(sw, bt),          \
+                                             dim3(WG_THREADS), 0, st, op, mat, sw, b, u_out, rc, cg, chk, \
+                                             conv, bt))
+    if (cgmode) MTOMG_PR(true, true, false)
+    else if (fine) MTOMG_PR(true, false, false)
+    else if (check) MTOMG_PR(false, false, true)
+    else MTOMG_PR(false, false, false)
+#undef MTOMG_PR
 }
 
 template <typename T>
@@ -1366,6 +1607,8 @@ void launch_coarse_solve(hipStream_t st, const double* Ainv, int n0, int ld, int
                                       int, const CgRhs&, const int*, const Batch&);                \
     template void launch_restrict<T>(hipStream_t, bool, bool, LevelOp<T>, Mat<T>, Sweep, const T*,    \
                                      const T*, T*, const ConvCheck&, const int*, const Batch&);    \
+    template void launch_pre_restrict<T>(hipStream_t, bool, bool, bool, LevelOp<T>, Mat<T>, Sweep, const T*, \
+                                         T*, T*, const CgRhs&, const ConvCheck&, const int*, const Batch&); \
     template void launch_restrict_pre<T>(hipStream_t, bool, bool, LevelOp<T>, LevelOp<T>, Mat<T>, Sweep,  \
                                          const T*, const T*, T*, T*, int, const ConvCheck&, const int*, \
                                          const Batch&);                                            \

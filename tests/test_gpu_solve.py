@@ -203,10 +203,11 @@ def test_autotune_picks_a_candidate_and_keeps_parity():
 def wall576():
     """The 1024^2 workload's recipe at 576^2, 6 grids (coarsest 18^2): its
     second-finest level (288^2, 83,521 nodes) is above both fusion
-    thresholds, so the solve takes every kernel path of the 1024^2 solve
-    (unfused restriction and single post-smoother below the finest level,
-    fused restriction + pre-smoothing and paired post-smoothers further
-    down)."""
+    thresholds (single post-smoother there, fused restriction +
+    pre-smoothing and paired post-smoothers further down).  The grid two
+    below the finest (144^2) is small enough for the restriction-presmoothing
+    fusion, so the finest grid runs its pre-smoothing and restriction as
+    separate launches (the fused path of 1024^2 is tested at 768^2)."""
     p = make_problem("wall1024", n=576, levels=6)
     print("[wall576] oracle direct solve", flush=True)
     return p, oracle_direct(p)
@@ -277,6 +278,43 @@ def test_per_kernel_and_per_level_rows_match_oracle(wall576, prec, cg, l1, l2):
     c, dc = s.compliance_and_grad(0)
     np.testing.assert_allclose(c.cpu().numpy(), ref.c, rtol=1e-7)
     assert relerr(dc.cpu().numpy(), ref.dcdx) <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32mg"])
+def test_fused_presmoothing_matches_separate_launches_and_oracle(prec):
+    """MTOMG_OPT_FUSE_PRE on design 32 of the batched workload (768^2, 6
+    grids, four load cases): the grid two below the finest has 37,249 nodes,
+    so, as at 1024^2, the finest grid's CG update, pre-smoothing and
+    restriction run in one launch, the convergence test opens the 384^2
+    grid with its own fused launch, and the 192^2 grid keeps the
+    restriction-presmoothing fusion.  Against the separate launches (which
+    round differently only through the compiler's multiply-add contraction):
+    the same iteration counts and displacements within the oracle bar;
+    against the oracle: its stored direct-solve samples
+    (tests/golden/batch32_samples.json)."""
+    import json
+    import os
+    from tests.test_gpu_fullsize import check_against_samples
+    from workloads import batched_design
+    p = batched_design(32)
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "batch32_samples.json")))
+    out = {}
+    for fuse in (1, 0):
+        s = gpu_solver(p, prec)
+        s.set_option("FUSE_PRE", fuse)
+        stats = s.solve(1e-8, 1000)
+        assert all(st["status"] == 0 and st["relres_true"] <= 1.05e-8 for st in stats), stats
+        out[fuse] = ([st["iters"] for st in stats], s.U(0).clone(), s)
+        print(f"[fuse_pre={fuse}] {prec} iters={out[fuse][0]} solve_ms={stats[0]['t_solve_ms']:.2f}")
+    assert out[1][0] == out[0][0]
+    d = relerr(out[1][1].cpu().numpy(), out[0][1].cpu().numpy())
+    print(f"[fuse_pre] {prec} fused vs separate: relerr(u) {d:.2e}")
+    assert d <= 1e-6
+    s = out[1][2]
+    U = out[1][1].cpu().numpy()
+    c, dc = s.compliance_and_grad(0)
+    for case in range(4):
+        check_against_samples(gold, p, s, case, U[case], c[case].item(), dc[case].cpu().numpy())
 
 
 def test_option_values_are_checked():
