@@ -313,7 +313,8 @@ def batched_run(steps, warmup, per_size=16):
 def cycle_sweep(n, precision, reps=3):
     """Levels and cycle index at a fixed mesh (Section 2.1: the number of
     levels and gamma of Algorithm 1): for every admissible L (coarsest grid
-    from 32^2 down to 1 element per side) and gamma in (1, 2), the smooth
+    from the library's 8192-element limit down to 1 element per side) and
+    gamma in (1, 2), the smooth
     3-phase wall at n^2 solved to 1e-8 from new densities.  Per setting:
     iterations, set_densities time, solve time (device time of the solve
     call, the overlapped coarsest factorisation included), time per
@@ -324,7 +325,9 @@ def cycle_sweep(n, precision, reps=3):
     from paper_2301_07457_amd import PCGMGSolver
     from workloads import make_problem
     rows = []
-    L_min = max(2, int(np.ceil(np.log2(n / 32))) + 1)
+    L_min = 2
+    while (n >> (L_min - 1)) ** 2 > 8192:
+        L_min += 1
     L_max = int(np.log2(n)) + 1
     for L in range(L_min, L_max + 1):
         prob = make_problem("wall1024", n=n, levels=L, mixed=precision == "fp32mg")
@@ -352,6 +355,52 @@ def cycle_sweep(n, precision, reps=3):
             print(f"[cycle sweep] n={n} L={L} gamma={gamma}: {rows[-1]}", file=sys.stderr, flush=True)
             del s
     return rows
+
+
+PAPER_MESHES = ((32, 32), (32, 64), (64, 64), (64, 128), (128, 128), (128, 256))
+
+
+def paper_mesh_sweep(reps=3):
+    """The meshes of the paper's level study (Tables 3-5: 32 x 32 ... 128 x
+    256) with every level count from the two-grid method (l = 2) to a
+    1-element coarsest side: one solve of the wall with smooth 3-phase
+    densities to 1e-8, FP64 V-cycle (the paper's pCGMG), per setting the
+    iterations, the set_densities time and the solve time (device time; the
+    coarsest factorisation, overlapped with the start of the solve, is in
+    it), medians over `reps` steps after one warm-up.  A single solve, not
+    the paper's whole optimisation runs."""
+    import numpy as np
+    import torch
+    from paper_2301_07457_amd import PCGMGSolver
+    from workloads import Problem, density_gaussian_sum, load_top_traction
+    rows = []
+    for nx, ny in PAPER_MESHES:
+        x = density_gaussian_sum(nx, ny, 2)
+        F = torch.from_numpy(load_top_traction(nx, ny)[None])
+        xt = torch.from_numpy(x).cuda()
+        L = 2
+        while (min(nx, ny) >> (L - 1)) >= 1 and min(nx, ny) % (1 << (L - 1)) == 0:
+            if (nx >> (L - 1)) * (ny >> (L - 1)) <= 8192:
+                s = PCGMGSolver(max_designs=1)
+                s.add_design(0, nx, ny, F, [1.0, 0.6, 0.2], 1e-9, 3.0, 0.3, L, 2, 2, 0.6, "fp64")
+                sts = []
+                for k in range(reps + 1):
+                    s.set_densities(0, xt)
+                    st = s.solve(1e-8, 2000)[0]
+                    if k > 0:
+                        sts.append(st)
+                torch.cuda.synchronize()
+                rows.append({"mesh": f"{nx}x{ny}", "levels": L, "coarsest": f"{nx >> (L - 1)}x{ny >> (L - 1)}",
+                             "iters": sts[-1]["iters"],
+                             "setup_ms": round(float(np.median([t["t_setup_ms"] for t in sts])), 4),
+                             "solve_ms": round(float(np.median([t["t_solve_ms"] for t in sts])), 4),
+                             "status": sts[-1]["status"], "relres_true": sts[-1]["relres_true"]})
+                print(f"[paper meshes] {rows[-1]}", file=sys.stderr, flush=True)
+                del s
+            L += 1
+    return {"workload": "square wall, smooth 3-phase densities (seed 2), FP64 V-cycle (2+2 damped Jacobi, "
+                        "omega 0.6), rel.res 1e-8, the meshes of the paper's Tables 3-5",
+            "rows": rows}
 
 
 def filter_run(n=1024, m=3, rf=8.0, reps=20):
@@ -503,6 +552,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 48-design batched workload")
     ap.add_argument("--no-oc", action="store_true", help="skip the OC loop timing")
     ap.add_argument("--no-cycle-sweep", action="store_true", help="skip the level / cycle-index sweep")
+    ap.add_argument("--no-paper-meshes", action="store_true", help="skip the level sweep on the paper's meshes")
     ap.add_argument("--tiles", default=None, metavar="RF,RC[,RCG,R1,R2]",
                     help="rows per wave instead of autotuning (0 = library choice): finest grid, coarse grids, "
                          "and optionally the outer-CG apply and the first two grids below the finest")
@@ -648,6 +698,8 @@ def main():
     if not args.no_oc:
         out["oc"] = oc_run()
     out["poisson"] = poisson_run()
+    if not args.no_paper_meshes:
+        out["paper_meshes"] = paper_mesh_sweep()
     if not args.no_cycle_sweep:
         # levels and cycle index at the bench mesh (Section 2.1), one timed step per setting
         out["cycle_sweep"] = {"workload": (f"square wall {args.n}x{args.n}, smooth 3-phase densities, FP32 cycle, "

@@ -92,8 +92,11 @@ int mtomg_destroy(mtomg_ctx *ctx);
  * stiffness of Eqs. (7)-(9) does not depend on the element size in 2D, so h
  * enters only through the loads, which the caller gives as nodal forces F.
  *   nelx, nely   element counts; both divisible by 2^(levels-1), and the
- *                coarsest grid at most 32 x 32 elements
- *                (its dense inverse is kept in device memory).
+ *                coarsest grid at most 8192 elements (e.g. 64 x 128): its
+ *                FP64 factorisation and explicit inverse are kept in
+ *                device memory, about 5 n0^2 doubles of workspace for its
+ *                n0 = 2 (nx0 + 1) ny0 free DOFs (11 GB at 64 x 128; up to
+ *                24 x 24 elements a banded factorisation needs less work).
  *   nu           Poisson ratio of the plane-stress law, Eq. (8), in [0, 0.5).
  *   m, E_phase   number of solid phases and their moduli (host [m]), Eq. (5).
  *   E_min        modulus of the void phase, > 0.

@@ -1355,8 +1355,8 @@ int mtomg_set_grid(mtomg_ctx* c, int design, int nelx, int nely, double nu, int 
     const int s = 1 << (levels - 1);
     if (nelx < s || nely < s || nelx % s || nely % s)
         return fail(c, MTOMG_BAD_INPUT, "nelx and nely must be positive multiples of 2^(levels-1)");
-    if (nelx / s > 32 || nely / s > 32)
-        return fail(c, MTOMG_BAD_INPUT, "coarsest grid larger than 32 x 32 elements; add levels");
+    if ((long)(nelx / s) * (nely / s) > MAX_COARSE_ELEMS)
+        return fail(c, MTOMG_BAD_INPUT, "coarsest grid larger than 8192 elements; add levels");
     if ((long)(nelx + 1) * (nely + 1) > (1L << 30)) return fail(c, MTOMG_BAD_INPUT, "grid too large");
     if (!(nu >= 0.0 && nu < 0.5)) return fail(c, MTOMG_BAD_INPUT, "nu must be in [0, 0.5)");
     if (m < 1 || m > MAX_PHASES || !E_phase) return fail(c, MTOMG_BAD_INPUT, "m must be in [1, 8] with E_phase given");

@@ -150,6 +150,10 @@ struct MomLevels {
 void launch_moments_tree(hipStream_t st, bool from_e, const double* src, int nxs, int nys, int T, int nlev,
                          const MomLevels& out);
 constexpr int COARSE_NB = 32;   // block size of the coarse factorisation
+constexpr int COARSE_LDS_MAX = 4096;   // coarsest DOFs whose right-hand side the coarse solve stages in LDS
+// Largest coarsest grid (elements): its dense FP64 factorisation and explicit
+// inverse take 5 n0^2 doubles of workspace (11 GB at 64 x 128 elements).
+constexpr long MAX_COARSE_ELEMS = 8192;
 // also sets status = {0, 1, 0, 0} when given (factor this design)
 void launch_assemble_dense(hipStream_t st, bool fine, LevelOp<double> op, Mat<double> mat, double* A, int ld,
                            int* status = nullptr);

@@ -1358,8 +1358,10 @@ __global__ __launch_bounds__(WG_THREADS) void k_apply(LevelOp<T> op, Mat<T> mat,
 // Coarsest direct solve e = K_0^{-1} b with the explicit FP64 inverse of
 // the Cholesky factorisation (row-major n0 x n0 over the free DOFs, which
 // are the nodal DOFs of rows j >= 1 in order).  One wave per matrix row.
+// With LDS the workgroup stages b in LDS first (n0 doubles); without, for
+// large coarsest grids, every wave reads b from memory (through L2).
 // ===========================================================================
-template <typename T>
+template <typename T, bool LDS>
 __global__ __launch_bounds__(WG_THREADS) void k_coarse_solve(const double* __restrict__ Ainv, int n0,
                                                              int ld, int nx0, const T* __restrict__ b,
                                                              T* __restrict__ e, const int* conv, Batch bt) {
@@ -1380,21 +1382,25 @@ __global__ __launch_bounds__(WG_THREADS) void k_coarse_solve(const double* __res
     double va[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) va[u] = a[min(lane_id() + u * WAVE, n0 - 1)];
-    for (int base = 0; base < n0; base += U * WG_THREADS) {
-        T v[U];
+    if constexpr (LDS) {
+        for (int base = 0; base < n0; base += U * WG_THREADS) {
+            T v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = b[off + min(base + (int)threadIdx.x + u * WG_THREADS, n0 - 1)];
-        if (base == 0 && cst != 0) return;   // uniform over the block (one system)
+            for (int u = 0; u < U; ++u) v[u] = b[off + min(base + (int)threadIdx.x + u * WG_THREADS, n0 - 1)];
+            if (base == 0 && cst != 0) return;   // uniform over the block (one system)
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int k = base + threadIdx.x + u * WG_THREADS;
-            if (k < n0) sb[k] = (double)v[u];
+            for (int u = 0; u < U; ++u) {
+                const int k = base + threadIdx.x + u * WG_THREADS;
+                if (k < n0) sb[k] = (double)v[u];
+            }
         }
+    } else {
+        if (cst != 0) return;
     }
     if (blockIdx.x == 0) {
         for (int k = threadIdx.x; k < off; k += WG_THREADS) e[k] = T(0);
     }
-    __syncthreads();
+    if constexpr (LDS) __syncthreads();
     if (row >= n0) return;
     // s = sum over k = lane, lane + 64, ... of a[k] b[k], in that order
     double s = 0.0;
@@ -1410,7 +1416,8 @@ __global__ __launch_bounds__(WG_THREADS) void k_coarse_solve(const double* __res
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int k = base + lane_id() + u * WAVE;
-            s = (k < n0) ? s + v[u] * sb[min(k, n0 - 1)] : s;
+            const double bk = LDS ? sb[min(k, n0 - 1)] : (double)b[off + min(k, n0 - 1)];
+            s = (k < n0) ? s + v[u] * bk : s;
         }
     }
     s = wave_sum(s);
@@ -1598,8 +1605,13 @@ template <typename T>
 void launch_coarse_solve(hipStream_t st, const double* Ainv, int n0, int ld, int nx0, const T* b, T* e,
                          const int* conv, const Batch& bt) {
     const int nblk = (n0 + WAVES_PER_WG - 1) / WAVES_PER_WG;
-    MTOMG_LAUNCH((k_coarse_solve<T>), dim3(nblk, bt.n), dim3(WG_THREADS), n0 * sizeof(double), st, Ainv,
-                       n0, ld, nx0, b, e, conv, bt);
+    // b staged in LDS up to 32 KB; larger coarsest grids read it through L2
+    if (n0 <= COARSE_LDS_MAX)
+        MTOMG_LAUNCH((k_coarse_solve<T, true>), dim3(nblk, bt.n), dim3(WG_THREADS), n0 * sizeof(double), st, Ainv,
+                     n0, ld, nx0, b, e, conv, bt);
+    else
+        MTOMG_LAUNCH((k_coarse_solve<T, false>), dim3(nblk, bt.n), dim3(WG_THREADS), 0, st, Ainv, n0, ld, nx0, b,
+                     e, conv, bt);
 }
 
 #define MTOMG_INST(T)                                                                              \

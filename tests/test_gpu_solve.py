@@ -133,6 +133,28 @@ def test_bad_inputs_are_rejected():
         s.add_design(0, 256, 256, torch.zeros((1, 257, 257, 2)), [1.0], levels=2)  # coarsest too big
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32mg"])
+@pytest.mark.parametrize("nx,ny", [(96, 48), (128, 64)])
+def test_two_grids_with_large_coarsest_match_oracle(nx, ny, prec):
+    """Two grids (the paper's l = 2) with a coarsest grid beyond 32 x 32
+    elements, factorised by the dense block sequence: 48 x 24 (2,352 DOFs;
+    the coarse solve stages its right-hand side in LDS) and 64 x 32 (4,160
+    DOFs; read through L2).  u against the oracle's direct solve; at 96 x 48
+    also the iteration count against the oracle's two-grid pCGMG."""
+    p = rand_prob(nx, ny, 2, nx + ny)
+    ref = oracle_direct(p)
+    s = gpu_solver(p, prec)
+    st = s.solve(1e-8, 1000)[0]
+    assert st["status"] == 0 and st["relres_true"] <= 1.05e-8, st
+    assert relerr(s.U(0).cpu().numpy(), ref.U) <= 1e-6
+    if nx == 96 and prec == "fp64":
+        o = solve.solve_mgpcg(p.nelx, p.nely, p.x, p.E_phase, p.E_min, p.penal, p.nu, p.F, 2, rel_tol=1e-8,
+                              grad=False)
+        assert abs(st["iters"] - o.iters[0]) <= 1, (st["iters"], o.iters)
+    print(f"[two grids {nx}x{ny}] {prec} iters={st['iters']} setup_ms={st['t_setup_ms']:.2f} "
+          f"solve_ms={st['t_solve_ms']:.2f}")
+
+
 def test_autograd_function_matches_oracle_gradient():
     from paper_2301_07457_amd import ComplianceFn
     p = rand_prob(64, 64, 3, 13)

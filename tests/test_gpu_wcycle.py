@@ -165,3 +165,28 @@ def test_level_and_cycle_sweep_iterations_match_oracle(levels, gamma):
     st = s.solve(1e-8, 1000)[0]
     assert st["status"] == 0 and st["relres_true"] <= 1.05e-8, st
     assert abs(st["iters"] - o.iters[0]) <= 1, (levels, gamma, st["iters"], o.iters)
+
+
+# The paper's meshes (Tables 3-5: 32 x 32, 32 x 64, 64 x 64 and, below, the
+# larger ones in bench.py) with every level count from the two-grid method up
+PAPER_MESHES = [(32, 32, l) for l in range(2, 7)] + [(32, 64, l) for l in range(2, 7)] + \
+               [(64, 64, l) for l in range(2, 8)]
+
+
+@pytest.mark.parametrize("nx,ny,levels", PAPER_MESHES, ids=lambda v: str(v))
+def test_paper_meshes_every_level_count_match_oracle(nx, ny, levels):
+    """Levels l = 2 (two grids, coarsest 16 x 16 to 32 x 32) up to a 1-element
+    coarsest side on the paper's smaller meshes, smooth 3-phase densities:
+    FP64 cycle, iterations within 1 of the oracle's pCGMG with the same
+    levels, u against the oracle's direct solve."""
+    from workloads import Problem, density_gaussian_sum, load_top_traction
+    x = density_gaussian_sum(nx, ny, 2)
+    p = Problem("paper", nx, ny, x, np.array([1.0, 0.6, 0.2]), 1e-9, 3.0, 0.3, load_top_traction(nx, ny)[None],
+                levels)
+    o = solve.solve_mgpcg(p.nelx, p.nely, p.x, p.E_phase, p.E_min, p.penal, p.nu, p.F, levels,
+                          rel_tol=1e-8, grad=False)
+    s = gpu_solver(p, "fp64")
+    st = s.solve(1e-8, 1000)[0]
+    assert st["status"] == 0 and st["relres_true"] <= 1.05e-8, st
+    assert abs(st["iters"] - o.iters[0]) <= 1, (st["iters"], o.iters)
+    assert relerr(s.U(0).cpu().numpy(), o.U) <= 1e-6
