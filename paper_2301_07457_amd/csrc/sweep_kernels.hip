@@ -944,21 +944,24 @@ __global__ __launch_bounds__(WG_THREADS) void k_pre_restrict(
     if constexpr (CHECK) issue_check(chk, cps);
     __builtin_amdgcn_sched_barrier(0);   // the partials' loads ahead of the tile's
     // right-hand side rows base .. base+NS-1, element rows base-1 .. base+NS-1
+    // loads in the order the march uses them (row s: its right-hand side and
+    // the element row above it), so the first steps can start while the
+    // later rows are still arriving (loads complete in order)
     V2<T> br[NS];
     Mom<T> me[NS + 1];
     V2<double> ro[CG ? NS : 1], qr[CG ? NS : 1];
-    if constexpr (CG) {
-        // q is loaded whether or not it is used, as in k_presmooth
+    me[0] = load_elem<T, FINE>(op, i, base - 1);
 #pragma unroll
-        for (int s = 0; s < NS; ++s) ro[s] = load_node(cg.r_old, nx, ny, i, base + s);
-#pragma unroll
-        for (int s = 0; s < NS; ++s) qr[s] = load_node(cg.q, nx, ny, i, base + s);
-    } else {
-#pragma unroll
-        for (int s = 0; s < NS; ++s) br[s] = load_node(b, nx, ny, i, base + s);
+    for (int s = 0; s < NS; ++s) {
+        if constexpr (CG) {
+            // q is loaded whether or not it is used, as in k_presmooth
+            ro[s] = load_node(cg.r_old, nx, ny, i, base + s);
+            qr[s] = load_node(cg.q, nx, ny, i, base + s);
+        } else {
+            br[s] = load_node(b, nx, ny, i, base + s);
+        }
+        me[s + 1] = load_elem<T, FINE>(op, i, base + s);
     }
-#pragma unroll
-    for (int s = 0; s < NS + 1; ++s) me[s] = load_elem<T, FINE>(op, i, base - 1 + s);
     __builtin_amdgcn_sched_barrier(0);
     if constexpr (CHECK) {
         if (converged_or_bad(chk, cps)) return;
@@ -967,8 +970,8 @@ __global__ __launch_bounds__(WG_THREADS) void k_pre_restrict(
     }
 
     double rr = 0.0;
+    double alpha = 0.0;
     if constexpr (CG) {
-        double alpha = 0.0;
         if (cg.update) {
             const double rho = cg.zr[cg.n_zr];
             double pqv[1];
@@ -982,8 +985,10 @@ __global__ __launch_bounds__(WG_THREADS) void k_pre_restrict(
             }
             if (blockIdx.x == 0 && threadIdx.x == 0) *cg.iters += 1;
         }
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
+    }
+    // CG: r_new = r_old - alpha q on row s (stored on owned rows), b = its FP32 value
+    auto cg_row = [&](int s) {
+        if constexpr (CG) {
             V2<double> rv = ro[s];
             if (cg.update) {
                 rv.x -= alpha * qr[s].x;
@@ -1004,7 +1009,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_pre_restrict(
             }
             br[s] = V2<T>{(T)rv.x, (T)rv.y};
         }
-    }
+    };
 
     V2<T> d0, d1, d2, d3;
     elem_diag<FINE>(me[0], mat, d0, d1, d2, d3);
@@ -1017,6 +1022,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_pre_restrict(
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const int k = base + s;
+        cg_row(s);
         // stage A: the diagonal of node row k (element rows k-1, k) and u1 there
         elem_diag<FINE>(me[s + 1], mat, d0, d1, d2, d3);
         const V2<T> D = dcarry + d0 + from_left(d1);

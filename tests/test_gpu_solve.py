@@ -339,6 +339,36 @@ def test_fused_presmoothing_matches_separate_launches_and_oracle(prec):
         check_against_samples(gold, p, s, case, U[case], c[case].item(), dc[case].cpu().numpy())
 
 
+@pytest.mark.parametrize("pair", [tuple(t) + (0,) for t in
+                                  __import__("paper_2301_07457_amd").PCGMGSolver.AUTOTUNE_CANDIDATES] +
+                         [(0, 0, 1), (0, 0, 2), (0, 0, 4)],
+                         ids=lambda t: f"rows{t[0]}-{t[1]}-level1-{t[2]}")
+def test_fused_presmoothing_every_tile_pair_matches_oracle(pair):
+    """The fused path at 768^2 (design 32 of the batched workload, FP32
+    cycle) with each (fine, coarse) rows-per-wave pair the autotuner may
+    pick, and each rows-per-wave value of the grid below the finest: the
+    fused launches take 1, 2 or 4 rows per wave (at most 4), so every
+    instantiation the bench can run meets the oracle's stored direct-solve
+    samples."""
+    import json
+    import os
+    from tests.test_gpu_fullsize import check_against_samples
+    from workloads import batched_design
+    p = batched_design(32)
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "batch32_samples.json")))
+    s = gpu_solver(p, "fp32mg")
+    s.set_option("ROWS_FINE", pair[0])
+    s.set_option("ROWS_COARSE", pair[1])
+    s.set_option("ROWS_LEVEL1", pair[2])   # the fused launch with the convergence test
+    s.set_densities(0, torch.from_numpy(p.x))
+    stats = s.solve(1e-8, 1000)
+    assert all(st["status"] == 0 and st["relres_true"] <= 1.05e-8 for st in stats), stats
+    U = s.U(0).cpu().numpy()
+    c, dc = s.compliance_and_grad(0)
+    for case in range(4):
+        check_against_samples(gold, p, s, case, U[case], c[case].item(), dc[case].cpu().numpy())
+
+
 def test_option_values_are_checked():
     from paper_2301_07457_amd import PCGMGSolver, _lib
     s = PCGMGSolver()
