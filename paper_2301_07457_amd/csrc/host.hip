@@ -180,6 +180,8 @@ struct mtomg_ctx {
     size_t oc_host_bytes = 0;
     hipStream_t cap_stream = nullptr;     // capture stream (default priority)
     hipStream_t side_stream = nullptr;    // coarsest factorisations during a solve (default priority)
+    hipStream_t br_st[4] = {};            // concurrent branches of the shape groups (default priority; [0] unused)
+    hipEvent_t br_fork = nullptr, br_join[4] = {};
     hipEvent_t ev_fac[2] = {nullptr, nullptr};   // [0] main -> side, [1] side -> main
     bool fac_inflight = false;   // ev_fac[1] marks factorisations queued by set_densities
     int* host_chol = nullptr;             // pinned [cap][4]: coarsest-factor flags
@@ -990,21 +992,53 @@ CycleCtx<T> group_cycle(mtomg_ctx* c, Group& g, hipStream_t st, Prof* prof) {
     return cx;
 }
 
-// PCG iteration `it` of every group in `act` (mode as k_cg_apply)
-void run_iteration(mtomg_ctx* c, const std::vector<int>& act, hipStream_t st, int it, int mode, double tol2,
-                   Prof* prof) {
-    for (int gi : act) {
-        Group& g = c->groups[gi];
+// Shape groups of one solve run as up to MAX_BRANCHES concurrent branches:
+// forked from the solve stream by an event, joined back by one event per
+// branch (captured, they become parallel branches of the graph, which the
+// runtime executes concurrently).  Their latency-bound coarse levels then
+// overlap instead of queueing behind each other; a group's launches stay in
+// order on its branch, so every result is the same as in one stream.
+constexpr int MAX_BRANCHES = 4;
+int ensure_branches(mtomg_ctx* c) {
+    if (c->br_fork) return MTOMG_OK;
+    for (int b = 1; b < MAX_BRANCHES; ++b) {
+        HIPCHK(c, hipStreamCreateWithFlags(&c->br_st[b], hipStreamNonBlocking));
+        HIPCHK(c, hipEventCreateWithFlags(&c->br_join[b], hipEventDisableTiming));
+    }
+    HIPCHK(c, hipEventCreateWithFlags(&c->br_fork, hipEventDisableTiming));
+    return MTOMG_OK;
+}
+
+// PCG iteration `it` of every group in `act` (mode as k_cg_apply); one
+// stream while a kernel is being profiled (its events are in launch order)
+int run_iteration(mtomg_ctx* c, const std::vector<int>& act, hipStream_t st, int it, int mode, double tol2,
+                  Prof* prof) {
+    const int nb = (c->br_fork && c->prof.kernel == MTOMG_KERNEL_NONE)
+                       ? std::min<int>((int)act.size(), MAX_BRANCHES) : 1;
+    if (nb > 1) {
+        HIPCHK(c, hipEventRecord(c->br_fork, st));
+        for (int b = 1; b < nb; ++b) HIPCHK(c, hipStreamWaitEvent(c->br_st[b], c->br_fork, 0));
+    }
+    for (size_t k = 0; k < act.size(); ++k) {
+        Group& g = c->groups[act[k]];
+        hipStream_t gs = (nb > 1 && k % nb) ? c->br_st[k % nb] : st;
         if (c->d[g.designs[0]].mixed()) {
-            CycleCtx<float> cx = group_cycle<float>(c, g, st, prof);
+            CycleCtx<float> cx = group_cycle<float>(c, g, gs, prof);
             cg_step<float>(cx, it, mode);
             if (mode < 2) fine_cycle<float>(cx, it, tol2);
         } else {
-            CycleCtx<double> cx = group_cycle<double>(c, g, st, prof);
+            CycleCtx<double> cx = group_cycle<double>(c, g, gs, prof);
             cg_step<double>(cx, it, mode);
             if (mode < 2) fine_cycle<double>(cx, it, tol2);
         }
     }
+    if (nb > 1) {
+        for (int b = 1; b < nb; ++b) {
+            HIPCHK(c, hipEventRecord(c->br_join[b], c->br_st[b]));
+            HIPCHK(c, hipStreamWaitEvent(st, c->br_join[b], 0));
+        }
+    }
+    return MTOMG_OK;
 }
 
 // Capture iterations 1 and 2 (parities 1, 0) of every group in `act` into
@@ -1013,9 +1047,14 @@ int capture_pair(mtomg_ctx* c, const std::vector<int>& act, double tol2) {
     drop_graphs(c);
     hipStream_t cs = c->cap_stream;
     HIPCHK(c, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    for (int k = 1; k <= 2; ++k) run_iteration(c, act, cs, k, 0, tol2, nullptr);
+    int rc = MTOMG_OK;
+    for (int k = 1; k <= 2 && rc == MTOMG_OK; ++k) rc = run_iteration(c, act, cs, k, 0, tol2, nullptr);
     hipGraph_t g = nullptr;
     HIPCHK(c, hipStreamEndCapture(cs, &g));
+    if (rc) {
+        if (g) hipGraphDestroy(g);
+        return rc;
+    }
     const hipError_t e = hipGraphInstantiate(&c->pair_exec, g, nullptr, nullptr, 0);
     hipGraphDestroy(g);
     if (e != hipSuccess) {
@@ -1059,6 +1098,10 @@ int pcg_round(mtomg_ctx* c, const std::vector<int>& gsys0, double tol2, int max_
                                        4 * sizeof(int), 4 * sizeof(int), g.n_sys, hipMemcpyHostToDevice, st));
         }
     }
+    if (act.size() > 1) {
+        const int r2 = ensure_branches(c);
+        if (r2) return r2;
+    }
     HIPCHK(c, hipEventRecord(c->ev_solve[0], st));
     auto read_states = [&]() -> int {
         for (int gi : act) {
@@ -1074,7 +1117,10 @@ int pcg_round(mtomg_ctx* c, const std::vector<int>& gsys0, double tol2, int max_
     // none for mode < 0), the true residual f - K u and the per-system sums,
     // then one synchronisation for the state words and sums
     auto finish = [&](int it_done, int mode) -> int {
-        if (mode >= 0 && it_done > 0) run_iteration(c, act, st, it_done, mode, tol2, &c->prof);
+        if (mode >= 0 && it_done > 0) {
+            const int r2 = run_iteration(c, act, st, it_done, mode, tol2, &c->prof);
+            if (r2) return r2;
+        }
         for (int gi : act) {
             Group& g = c->groups[gi];
             Design& d = c->d[g.designs[0]];
@@ -1117,7 +1163,8 @@ int pcg_round(mtomg_ctx* c, const std::vector<int>& gsys0, double tol2, int max_
                     HIPCHK(c, hipGraphLaunch(c->pair_exec, st));
                     k += 2;
                 } else {
-                    run_iteration(c, act, st, k, k == 0 ? 1 : 0, tol2, &c->prof);
+                    const int r2 = run_iteration(c, act, st, k, k == 0 ? 1 : 0, tol2, &c->prof);
+                    if (r2) return r2;
                     ++k;
                 }
             }
@@ -1319,6 +1366,14 @@ int mtomg_destroy(mtomg_ctx* c) {
     if (c->side_stream) hipStreamSynchronize(c->side_stream);
     if (c->cap_stream) hipStreamDestroy(c->cap_stream);
     if (c->side_stream) hipStreamDestroy(c->side_stream);
+    for (int b = 1; b < MAX_BRANCHES; ++b) {
+        if (c->br_st[b]) {
+            hipStreamSynchronize(c->br_st[b]);
+            hipStreamDestroy(c->br_st[b]);
+        }
+        if (c->br_join[b]) hipEventDestroy(c->br_join[b]);
+    }
+    if (c->br_fork) hipEventDestroy(c->br_fork);
     for (hipEvent_t& e : c->ev_fac)
         if (e) hipEventDestroy(e);
     for (Design& d : c->d) {
