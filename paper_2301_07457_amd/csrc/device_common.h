@@ -337,6 +337,21 @@ __device__ __forceinline__ V2<T> load_node(const T* __restrict__ v, int nx, int 
     }
 }
 
+// The same load without the mask: the value at the clamped address, for
+// callers that select every use of it by the node's own validity anyway.
+template <typename T>
+__device__ __forceinline__ V2<T> load_node_clamped(const T* __restrict__ v, int nx, int ny, int i, int j) {
+    const int ic = min(max(i, 0), nx), jc = min(max(j, 1), ny);
+    const size_t n = (size_t)jc * (nx + 1) + ic;
+    if constexpr (sizeof(T) == 4) {
+        const float2 w = reinterpret_cast<const float2*>(v)[n];
+        return V2<T>{w.x, w.y};
+    } else {
+        const double2 w = reinterpret_cast<const double2*>(v)[n];
+        return V2<T>{w.x, w.y};
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ void store_node(T* __restrict__ v, int nx, int i, int j, V2<T> a) {
     const size_t n = (size_t)j * (nx + 1) + i;

@@ -950,15 +950,18 @@ __global__ __launch_bounds__(WG_THREADS) void k_pre_restrict(
     V2<T> br[NS];
     Mom<T> me[NS + 1];
     V2<double> ro[CG ? NS : 1], qr[CG ? NS : 1];
+    // (right-hand-side values off the grid are never used unselected: u1,
+    // u2 and the residual are selected by their node's validity, r_new is
+    // stored on owned grid nodes only; so they load unmasked)
     me[0] = load_elem<T, FINE>(op, i, base - 1);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         if constexpr (CG) {
             // q is loaded whether or not it is used, as in k_presmooth
-            ro[s] = load_node(cg.r_old, nx, ny, i, base + s);
-            qr[s] = load_node(cg.q, nx, ny, i, base + s);
+            ro[s] = load_node_clamped(cg.r_old, nx, ny, i, base + s);
+            qr[s] = load_node_clamped(cg.q, nx, ny, i, base + s);
         } else {
-            br[s] = load_node(b, nx, ny, i, base + s);
+            br[s] = load_node_clamped(b, nx, ny, i, base + s);
         }
         me[s + 1] = load_elem<T, FINE>(op, i, base + s);
     }
@@ -1184,11 +1187,13 @@ __global__ __launch_bounds__(WG_THREADS) void k_post2(
         for (int s = 0; s < R + 4; ++s) vr[s] = load_node(uin, nx, ny, i, t.j0 - 2 + s, u_in != nullptr);
         // fine rows j0-2 .. j0+R+1 = rows (j0-1)-1 .. (j0-1)+(R+2)
         if constexpr (PROLONG) load_prolongation<T, R + 2>(c0, c1, ec, ncx, ncy, I0, I1, t.j0 - 1);
+        // b and r are used only through u1 and the output, both selected by
+        // the node's validity: unmasked loads
 #pragma unroll
-        for (int s = 0; s < R + 2; ++s) br[s] = load_node(b, nx, ny, i, t.j0 - 1 + s);
+        for (int s = 0; s < R + 2; ++s) br[s] = load_node_clamped(b, nx, ny, i, t.j0 - 1 + s);
         if constexpr (DOT) {
 #pragma unroll
-            for (int s = 0; s < R; ++s) rr64[s] = load_node(r64, nx, ny, i, t.j0 + s);
+            for (int s = 0; s < R; ++s) rr64[s] = load_node_clamped(r64, nx, ny, i, t.j0 + s);
         }
 #pragma unroll
         for (int s = 0; s < R + 3; ++s) me[s] = load_elem<T, FINE>(op, i, t.j0 - 2 + s);
