@@ -1014,70 +1014,72 @@ __global__ __launch_bounds__(WG_THREADS) void k_pre_restrict(
         }
     };
 
+    // The march.  Step s forms u1 on node row base+s (stage A), u2 on row
+    // base+s-2 from u1 of earlier steps (stage B) and the residual on row
+    // base+s-4 from u2 of earlier steps (stage C): the three stages of a
+    // step do not depend on each other, so their instruction chains
+    // interleave.  Per-row values live in arrays indexed by the unrolled s.
     V2<T> d0, d1, d2, d3;
     elem_diag<FINE>(me[0], mat, d0, d1, d2, d3);
     V2<T> dcarry = d3 + from_left(d2);
     V2<T> fcarry{T(0), T(0)}, gcarry{T(0), T(0)};
-    V2<T> u1_prev{T(0), T(0)}, u1r_prev{T(0), T(0)}, wD_prev{T(0), T(0)};
-    V2<T> u2_prev{T(0), T(0)}, u2r_prev{T(0), T(0)};
+    V2<T> u1[NS], u1r[NS], wD[NS], u2[NS], u2r[NS];
+    bool kok[NS];
     V2<T> h_m1{T(0), T(0)}, h_m2{T(0), T(0)};
-    bool kok_prev = false;
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        const int k = base + s;
-        cg_row(s);
-        // stage A: the diagonal of node row k (element rows k-1, k) and u1 there
-        elem_diag<FINE>(me[s + 1], mat, d0, d1, d2, d3);
-        const V2<T> D = dcarry + d0 + from_left(d1);
-        dcarry = d3 + from_left(d2);
-        const V2<T> bk = br[s];
-        const bool kok = node_col && k >= 1 && k <= ny;
-        const V2<T> wD{w_over(mat.omega, D.x), w_over(mat.omega, D.y)};   // w D^-1, reused by the second sweep
-        const V2<T> u1{kok ? bk.x * wD.x : T(0), kok ? bk.y * wD.y : T(0)};
-        const V2<T> u1r = from_right(u1);
-        if (s >= 1) {
-            // stage B: element row k-1 on u1 completes K u1 at node row k-1 -> u2 there
+    for (int s = 0; s < NS + 2; ++s) {
+        if (s < NS) {
+            // stage A: the diagonal of node row base+s (element rows base+s-1,
+            // base+s) and u1 there
+            cg_row(s);
+            const int k = base + s;
+            elem_diag<FINE>(me[s + 1], mat, d0, d1, d2, d3);
+            const V2<T> D = dcarry + d0 + from_left(d1);
+            dcarry = d3 + from_left(d2);
+            kok[s] = node_col && k >= 1 && k <= ny;
+            wD[s] = V2<T>{w_over(mat.omega, D.x), w_over(mat.omega, D.y)};   // w D^-1, reused by the second sweep
+            u1[s] = V2<T>{kok[s] ? br[s].x * wD[s].x : T(0), kok[s] ? br[s].y * wD[s].y : T(0)};
+            u1r[s] = from_right(u1[s]);
+        }
+        if (s >= 2 && s <= NS) {
+            // stage B: element row base+q (q = s-2) on u1 rows q, q+1 completes
+            // K u1 at node row base+q -> u2 there
+            const int q = s - 2;
             V2<T> f0, f1, f2, f3;
-            elem_force<FINE>(me[s], mat, u1_prev, u1r_prev, u1r, u1, f0, f1, f2, f3);
+            elem_force<FINE>(me[q + 1], mat, u1[q], u1r[q], u1r[q + 1], u1[q + 1], f0, f1, f2, f3);
             const V2<T> fs = fcarry + f0 + from_left(f1);
             fcarry = f3 + from_left(f2);
-            const int jr = k - 1;
-            const V2<T> bp = br[s - 1];
-            const V2<T> u2{kok_prev ? u1_prev.x + (bp.x - fs.x) * wD_prev.x : T(0),
-                           kok_prev ? u1_prev.y + (bp.y - fs.y) * wD_prev.y : T(0)};
-            if (own_col && jr >= fr0 && jr <= fr1) store_node(u_out, nx, i, jr, u2);
-            const V2<T> u2r = from_right(u2);
-            if (s >= 2) {
-                // stage C: element row k-2 on u2 completes K u2 at node row j = k-2 -> residual
-                V2<T> g0, g1, g2, g3;
-                elem_force<FINE>(me[s - 1], mat, u2_prev, u2r_prev, u2r, u2, g0, g1, g2, g3);
-                const V2<T> ku = gcarry + g0 + from_left(g1);
-                gcarry = g3 + from_left(g2);
-                const int j = k - 2;
-                const bool jok = node_col && j >= 1 && j <= ny;
-                const V2<T> bj = br[s - 2];
-                const V2<T> res{jok ? bj.x - ku.x : T(0), jok ? bj.y - ku.y : T(0)};
-                const V2<T> rl = from_left(res), rrt = from_right(res);
-                const V2<T> h{res.x + T(0.5) * (rl.x + rrt.x), res.y + T(0.5) * (rl.y + rrt.y)};
-                // stage D: j = 2J + 1 (s even) completes coarse row J from fine rows 2J-1 .. 2J+1
-                if ((s & 1) == 0 && s >= 6) {
-                    const int J = t.j0 - 3 + s / 2;
-                    if (out_lane && J < t.j1) {
-                        V2<T> v{h_m1.x + T(0.5) * (h_m2.x + h.x), h_m1.y + T(0.5) * (h_m2.y + h.y)};
-                        if (J == 0) v = V2<T>{T(0), T(0)};
-                        store_node(rc, ncx, I, J, v);
-                    }
-                }
-                h_m2 = h_m1;
-                h_m1 = h;
-            }
-            u2_prev = u2;
-            u2r_prev = u2r;
+            const int jr = base + q;
+            u2[q] = V2<T>{kok[q] ? u1[q].x + (br[q].x - fs.x) * wD[q].x : T(0),
+                          kok[q] ? u1[q].y + (br[q].y - fs.y) * wD[q].y : T(0)};
+            if (own_col && jr >= fr0 && jr <= fr1) store_node(u_out, nx, i, jr, u2[q]);
+            u2r[q] = from_right(u2[q]);
         }
-        u1_prev = u1;
-        u1r_prev = u1r;
-        wD_prev = wD;
-        kok_prev = kok;
+        if (s >= 4) {
+            // stage C: element row base+p (p = s-4) on u2 rows p, p+1 completes
+            // K u2 at node row j = base+p -> residual
+            const int p = s - 4;
+            V2<T> g0, g1, g2, g3;
+            elem_force<FINE>(me[p + 1], mat, u2[p], u2r[p], u2r[p + 1], u2[p + 1], g0, g1, g2, g3);
+            const V2<T> ku = gcarry + g0 + from_left(g1);
+            gcarry = g3 + from_left(g2);
+            const int j = base + p;
+            const bool jok = node_col && j >= 1 && j <= ny;
+            const V2<T> res{jok ? br[p].x - ku.x : T(0), jok ? br[p].y - ku.y : T(0)};
+            const V2<T> rl = from_left(res), rrt = from_right(res);
+            const V2<T> h{res.x + T(0.5) * (rl.x + rrt.x), res.y + T(0.5) * (rl.y + rrt.y)};
+            // stage D: j = 2J + 1 (p even) completes coarse row J from fine rows 2J-1 .. 2J+1
+            if ((p & 1) == 0 && p >= 4) {
+                const int J = t.j0 - 2 + p / 2;
+                if (out_lane && J < t.j1) {
+                    V2<T> v{h_m1.x + T(0.5) * (h_m2.x + h.x), h_m1.y + T(0.5) * (h_m2.y + h.y)};
+                    if (J == 0) v = V2<T>{T(0), T(0)};
+                    store_node(rc, ncx, I, J, v);
+                }
+            }
+            h_m2 = h_m1;
+            h_m1 = h;
+        }
     }
     if constexpr (CG) {
         if (cg.update) {
