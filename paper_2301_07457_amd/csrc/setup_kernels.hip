@@ -816,55 +816,79 @@ __global__ void k_cast_f32(const double* __restrict__ a, float* __restrict__ b, 
 
 // dc/dx_{e,i} = -p x^(p-1) (E_i - E_min) u_e^T K^0 u_e.
 // A wave owns 63 element columns (64 node columns, lane l at node column
-// i0 + l) and GRAD_ROWS element rows.  It issues the loads of its
-// GRAD_ROWS + 1 node rows first, then marches up: element (i, j) takes nodes
-// (i, j) and (i, j+1) from its own lane and (i+1, .) from the next lane (DPP),
-// so every node row is read once per wave instead of by the four elements
-// around it.  The m phases of a row's 63 elements are contiguous in x and
-// dc/dx: the outputs go through LDS and leave as whole coalesced stores,
-// the densities come in the same way.  Consecutive tiles share an XCD
-// (xcd_tile), so the one halo row between row chunks hits L2.
-constexpr int GRAD_ROWS = 8, GRAD_COLS = 63;
+// i0 + l) and GRAD_ROWS element rows.  It issues every load first: its
+// GRAD_ROWS + 1 node rows of U and the densities of its element rows (the
+// M phases of a row's 63 elements are contiguous in x, so lane l takes
+// entries l, l + 64, ... of the row: M per lane).  Then it marches up:
+// element (i, j) takes nodes (i, j) and (i, j+1) from its own lane and
+// (i+1, .) from the next lane (DPP).  The densities and the outputs of a
+// row go through LDS, so both are read and written as whole coalesced
+// rows.  Consecutive tiles share an XCD (xcd_tile), so the one halo row
+// between row chunks hits L2.  Two rows per wave: at 1024^2 with three
+// phases the launch took 12.7 us, against 13.9 with four rows and 16.8
+// with eight, whose fewer workgroups hide less latency.
+constexpr int GRAD_COLS = 63, GRAD_ROWS = 2;
+template <int M>
 __global__ __launch_bounds__(WG_THREADS) void k_grad(const double* __restrict__ U, const double* __restrict__ x,
                                                     Phases ph, Mat<double> mat, int nx, int ny, int n_strips,
                                                     int n_tiles, double* __restrict__ dcdx) {
-    __shared__ double stage[WAVES_PER_WG][GRAD_COLS * 8];
+    constexpr int ROWS = GRAD_ROWS;
+    // 64 M per wave: every lane writes its M slots of a row, also past the
+    // strip's n_e M entries (values nobody stores), so no write is under a
+    // branch that the compiler could sink a load into
+    __shared__ double stage[WAVES_PER_WG][WAVE * M];
     const int tile = xcd_tile(n_tiles);
     if (tile >= n_tiles) return;
     const int lane = lane_id(), w = wave_id();
     const int strip = tile % n_strips;
-    const int j0 = ((tile / n_strips) * WAVES_PER_WG + w) * GRAD_ROWS;
+    const int j0 = ((tile / n_strips) * WAVES_PER_WG + w) * ROWS;
+    if (j0 >= ny) return;                            // a wave past the grid, before any load
     const int i0 = strip * GRAD_COLS, i = i0 + lane;
     const int ne = min(GRAD_COLS, nx - i0);          // elements of this strip
-    const int m = ph.m, nm = ne * m;
+    const int nm = ne * M;
     double* buf = stage[w];
-    V2<double> un[GRAD_ROWS + 1];
+    V2<double> un[ROWS + 1];
 #pragma unroll
-    for (int s = 0; s <= GRAD_ROWS; ++s) un[s] = load_node(U, nx, ny, i, j0 + s);
+    for (int s = 0; s <= ROWS; ++s) un[s] = load_node(U, nx, ny, i, j0 + s);
+    // densities of rows j0 .. j0+ROWS-1 (rows past the grid read the last
+    // row; nothing of them is stored), slot q of a row = its entry lane + 64 q
+    double xr[ROWS][M];
+#pragma unroll
+    for (int s = 0; s < ROWS; ++s) {
+        const size_t base = ((size_t)min(j0 + s, ny - 1) * nx + i0) * M;
+#pragma unroll
+        for (int q = 0; q < M; ++q) xr[s][q] = x[base + min(lane + q * WAVE, nm - 1)];
+    }
     V2<double> right_lo = from_right(un[0]);
 #pragma unroll
-    for (int s = 0; s < GRAD_ROWS; ++s) {
+    for (int s = 0; s < ROWS; ++s) {
         const int j = j0 + s;
-        if (j >= ny) break;                            // uniform over the wave
         const V2<double> right_hi = from_right(un[s + 1]);
         V2<double> f0, f1, f2, f3;
         elem_force(mom_const<double>(1.0), mat, un[s], right_lo, right_hi, un[s + 1], f0, f1, f2, f3);
         const double we = (un[s].x * f0.x + un[s].y * f0.y) + (right_lo.x * f1.x + right_lo.y * f1.y) +
                           (right_hi.x * f2.x + right_hi.y * f2.y) + (un[s + 1].x * f3.x + un[s + 1].y * f3.y);
         right_lo = right_hi;
-        // the row's densities, coalesced, into LDS; each lane takes its element's
-        const size_t base = ((size_t)j * nx + i0) * m;
-        for (int k = lane; k < nm; k += WAVE) buf[k] = x[base + k];
+        // the row's densities into LDS; each lane takes its element's
+#pragma unroll
+        for (int q = 0; q < M; ++q) buf[lane + q * WAVE] = xr[s][q];
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        if (lane < ne)
-            for (int k = 0; k < m; ++k) {
-                const double xv = buf[lane * m + k];
-                buf[lane * m + k] = -ph.penal * powp(xv, ph.penal - 1.0) * ph.dE[k] * we;
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const double xv = buf[lane * M + k];
+            buf[lane * M + k] = -ph.penal * powp(xv, ph.penal - 1.0) * ph.dE[k] * we;
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        if (j < ny) {                                  // uniform over the wave
+            const size_t base = ((size_t)j * nx + i0) * M;
+#pragma unroll
+            for (int q = 0; q < M; ++q) {
+                const int k = lane + q * WAVE;
+                if (k < nm) dcdx[base + k] = buf[k];
             }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        for (int k = lane; k < nm; k += WAVE) dcdx[base + k] = buf[k];
+        }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     }
@@ -1022,13 +1046,30 @@ void launch_cast_f32(hipStream_t st, const double* a, float* b, size_t n) {
     const unsigned nb = (unsigned)std::min<size_t>(blocks_for(n, 256), 4096);
     hipLaunchKernelGGL(k_cast_f32, dim3(nb), dim3(256), 0, st, a, b, n);
 }
-void launch_grad(hipStream_t st, const double* U, const double* x, Phases ph, Mat<double> mat, int nx, int ny,
-                 double* dcdx) {
+template <int M>
+void launch_grad_m(hipStream_t st, const double* U, const double* x, const Phases& ph, const Mat<double>& mat,
+                   int nx, int ny, double* dcdx) {
+    constexpr int ROWS = GRAD_ROWS;
     const int n_strips = (nx + GRAD_COLS - 1) / GRAD_COLS;
-    const int chunks = (ny + GRAD_ROWS - 1) / GRAD_ROWS;
+    const int chunks = (ny + ROWS - 1) / ROWS;
     const int n_tiles = n_strips * ((chunks + WAVES_PER_WG - 1) / WAVES_PER_WG);
     const int grid = (n_tiles + 7) / 8 * 8;   // whole rounds over the 8 XCDs (xcd_tile)
-    hipLaunchKernelGGL(k_grad, dim3(grid), dim3(WG_THREADS), 0, st, U, x, ph, mat, nx, ny, n_strips, n_tiles, dcdx);
+    hipLaunchKernelGGL(k_grad<M>, dim3(grid), dim3(WG_THREADS), 0, st, U, x, ph, mat, nx, ny, n_strips, n_tiles,
+                       dcdx);
+}
+// ph.m is 1 .. 8 (checked by set_grid)
+void launch_grad(hipStream_t st, const double* U, const double* x, Phases ph, Mat<double> mat, int nx, int ny,
+                 double* dcdx) {
+    switch (ph.m) {
+        case 1: launch_grad_m<1>(st, U, x, ph, mat, nx, ny, dcdx); break;
+        case 2: launch_grad_m<2>(st, U, x, ph, mat, nx, ny, dcdx); break;
+        case 3: launch_grad_m<3>(st, U, x, ph, mat, nx, ny, dcdx); break;
+        case 4: launch_grad_m<4>(st, U, x, ph, mat, nx, ny, dcdx); break;
+        case 5: launch_grad_m<5>(st, U, x, ph, mat, nx, ny, dcdx); break;
+        case 6: launch_grad_m<6>(st, U, x, ph, mat, nx, ny, dcdx); break;
+        case 7: launch_grad_m<7>(st, U, x, ph, mat, nx, ny, dcdx); break;
+        default: launch_grad_m<8>(st, U, x, ph, mat, nx, ny, dcdx); break;
+    }
 }
 void launch_dot_partials(hipStream_t st, const double* a, const double* b, size_t n, double* partials, int n_part) {
     hipLaunchKernelGGL(k_dot_partials, dim3(n_part), dim3(WG_THREADS), 0, st, a, b, n, partials);
