@@ -324,7 +324,7 @@ void layout_case_slab(const Design& d, CaseBufs& c, Bump& B) {
     c.r32 = mx ? B.take<float>(nf) : nullptr;
     c.ff = B.take<double>(np);
     c.trr = B.take<double>(np);
-    c.cpart = B.take<double>(256);
+    c.cpart = B.take<double>(DOT_PARTS_MAX);
     c.sums = B.take<double>(8);
     c.state = B.take<int>(4);
     c.b.assign(d.levels, nullptr);
@@ -1575,8 +1575,8 @@ int mtomg_compliance_and_grad(mtomg_ctx* c, int design, double* cout, double* dc
     const size_t nf = 2 * L.nodes();
     for (int k = 0; k < d.n_cases; ++k) {
         CaseBufs& cb = d.cases[k];
-        launch_dot_partials(st, cb.F, cb.U, nf, cb.cpart, 256);
-        launch_sum_to(st, cb.cpart, 256, cout + k);
+        launch_dot_partials(st, cb.F, cb.U, nf, cb.cpart, dot_parts(nf));
+        launch_sum_to(st, cb.cpart, dot_parts(nf), cout + k);
         if (dcdx)
             launch_grad(st, cb.U, d.x_dev, phases_of(d), make_mat<double>(d, d.omega), L.nx, L.ny,
                         dcdx + (size_t)k * L.nx * L.ny * d.m);
@@ -1666,8 +1666,6 @@ struct PoisBufs {
     int* state = nullptr;     // [0] 0 running / 1 converged / 3 breakdown / 4 not finite, [1] iterations
 };
 
-constexpr int POIS_PARTS = 64;
-
 size_t pois_layout(int n, int L, PoisBufs* pb, char* base) {
     size_t off = 0;
     auto take = [&](size_t count) -> double* {
@@ -1684,7 +1682,7 @@ size_t pois_layout(int n, int L, PoisBufs* pb, char* base) {
     }
     const size_t N = (size_t)(n + 1) * (n + 1);
     double* r = take(N); double* z = take(N); double* p = take(N); double* q = take(N);
-    double* part = take(POIS_PARTS); double* sc = take(8); double* state = take(1);
+    double* part = take(DOT_PARTS_MAX); double* sc = take(8); double* state = take(1);
     if (pb) {
         pb->r = r; pb->z = z; pb->p = p; pb->q = q; pb->part = part; pb->sc = sc;
         pb->state = reinterpret_cast<int*>(state);
@@ -1726,8 +1724,9 @@ void pois_cycle(hipStream_t st, const PoisBufs& pb, int l, const double* b, doub
 }
 
 void pois_dot(hipStream_t st, const PoisBufs& pb, int n, const double* a, const double* b, double* out) {
-    launch_dot_partials(st, a, b, (size_t)(n + 1) * (n + 1), pb.part, POIS_PARTS);
-    launch_sum_to(st, pb.part, POIS_PARTS, out);
+    const size_t N = (size_t)(n + 1) * (n + 1);
+    launch_dot_partials(st, a, b, N, pb.part, dot_parts(N));
+    launch_sum_to(st, pb.part, dot_parts(N), out);
 }
 
 }  // namespace

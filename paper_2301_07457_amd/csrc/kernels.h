@@ -179,6 +179,14 @@ void launch_grad(hipStream_t st, const double* U, const double* x, Phases ph, Ma
                  int ny, double* dcdx);
 void launch_dot_partials(hipStream_t st, const double* a, const double* b, size_t n, double* partials,
                          int n_part);
+// Partial count of a dot product of n terms: one workgroup per 2048 terms
+// (one batch of loads per thread), so a large vector gets enough workgroups
+// to keep the loads in flight, at most DOT_PARTS_MAX.
+constexpr int DOT_PARTS_MAX = 4096;
+inline int dot_parts(size_t n) {
+    const size_t k = (n + 2047) / 2048;
+    return (int)(k < 1 ? 1 : k > (size_t)DOT_PARTS_MAX ? (size_t)DOT_PARTS_MAX : k);
+}
 void launch_sum_to(hipStream_t st, const double* partials, int n, double* out);
 // out[0..] = sums of several partial arrays (one block)
 struct SumJob {
