@@ -195,6 +195,27 @@ __device__ __forceinline__ double block_sum(double v) {
     return s;
 }
 
+// Two block_sums sharing one barrier pair (each sum in block_sum's order).
+__device__ __forceinline__ void block_sum2(double& a, double& b) {
+    __shared__ double red[2][WAVES_PER_WG];
+    a = wave_sum(a);
+    b = wave_sum(b);
+    __syncthreads();
+    if (lane_id() == 0) {
+        red[0][wave_id()] = a;
+        red[1][wave_id()] = b;
+    }
+    __syncthreads();
+    double sa = 0.0, sb = 0.0;
+#pragma unroll
+    for (int w = 0; w < WAVES_PER_WG; ++w) {
+        sa += red[0][w];
+        sb += red[1][w];
+    }
+    a = sa;
+    b = sb;
+}
+
 // Sums of K partial arrays (p[q] holds n[q] >= 1 entries, n[q] used) in a
 // fixed order, identical in every block that computes them: thread t adds
 // entries t, t + WG_THREADS, ... in increasing order, then the wave and

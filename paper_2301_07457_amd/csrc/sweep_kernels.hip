@@ -212,51 +212,52 @@ __global__ __launch_bounds__(WG_THREADS) void k_residual(
     const int i = t.strip * WOUT - HL + lane;
     const bool out_lane = lane >= HL && lane < HL + WOUT && i <= nx;
     double rr = 0.0, ff = 0.0;
-    if (t.j0 < t.j1) {
-        V2<double> xr[R + 2], fr[R];
-        Mom<double> me[R + 1];
-        if (use_x) {
+    // every wave issues its loads, none under a branch (rows past the grid
+    // are masked); a cold start (use_x = 0) reads f, which is finite, in
+    // place of x under a zero mask, so U's old contents never enter
+    const double* xs = use_x ? x : f;
+    V2<double> xr[R + 2], fr[R];
+    Mom<double> me[R + 1];
 #pragma unroll
-            for (int s = 0; s < R + 2; ++s) xr[s] = load_node(x, nx, ny, i, t.j0 - 1 + s);
-        } else {
+    for (int s = 0; s < R + 2; ++s) xr[s] = load_node(xs, nx, ny, i, t.j0 - 1 + s, use_x != 0);
 #pragma unroll
-            for (int s = 0; s < R + 2; ++s) xr[s] = V2<double>{0.0, 0.0};
-        }
+    for (int s = 0; s < R; ++s) fr[s] = load_node(f, nx, ny, i, t.j0 + s);
 #pragma unroll
-        for (int s = 0; s < R; ++s) fr[s] = load_node(f, nx, ny, i, t.j0 + s);
+    for (int s = 0; s < R + 1; ++s) me[s] = load_elem<double, true>(op, i, t.j0 - 1 + s);
+    __builtin_amdgcn_sched_barrier(0);   // one batch of loads ahead of the arithmetic
+    // the arithmetic runs on every wave and its values are used without a
+    // branch (only the stores are conditional), so no load is sunk into one
+    V2<double> f0, f1, f2, f3;
+    V2<double> xr_lo = from_right(xr[0]), xr_hi = from_right(xr[1]);
+    elem_force<true>(me[0], mat, xr[0], xr_lo, xr_hi, xr[1], f0, f1, f2, f3);
+    V2<double> carry = f3 + from_left(f2);
 #pragma unroll
-        for (int s = 0; s < R + 1; ++s) me[s] = load_elem<double, true>(op, i, t.j0 - 1 + s);
-        V2<double> f0, f1, f2, f3;
-        V2<double> xr_lo = from_right(xr[0]), xr_hi = from_right(xr[1]);
-        elem_force<true>(me[0], mat, xr[0], xr_lo, xr_hi, xr[1], f0, f1, f2, f3);
-        V2<double> carry = f3 + from_left(f2);
-#pragma unroll
-        for (int s = 0; s < R; ++s) {
-            const int j = t.j0 + s;
-            xr_lo = xr_hi;
-            xr_hi = from_right(xr[s + 2]);
-            elem_force<true>(me[s + 1], mat, xr[s + 1], xr_lo, xr_hi, xr[s + 2], f0, f1, f2, f3);
-            const V2<double> kx = carry + f0 + from_left(f1);
-            carry = f3 + from_left(f2);
-            if (out_lane && j < t.j1) {
-                if (j >= 1) {
-                    const V2<double> rv = fr[s] - kx;
-                    if (r) store_node(r, nx, i, j, rv);
-                    if (!use_x) store_node(x, nx, i, j, V2<double>{0.0, 0.0});
-                    rr += rv.x * rv.x + rv.y * rv.y;
-                    ff += fr[s].x * fr[s].x + fr[s].y * fr[s].y;
-                } else {
-                    if (r) store_node(r, nx, i, j, V2<double>{0.0, 0.0});
-                    store_node(x, nx, i, j, V2<double>{0.0, 0.0});
-                }
+    for (int s = 0; s < R; ++s) {
+        const int j = t.j0 + s;
+        xr_lo = xr_hi;
+        xr_hi = from_right(xr[s + 2]);
+        elem_force<true>(me[s + 1], mat, xr[s + 1], xr_lo, xr_hi, xr[s + 2], f0, f1, f2, f3);
+        const V2<double> kx = carry + f0 + from_left(f1);
+        carry = f3 + from_left(f2);
+        const bool own = out_lane && j < t.j1;
+        const bool fre = own && j >= 1;
+        const V2<double> rv = fr[s] - kx;
+        rr += fre ? rv.x * rv.x + rv.y * rv.y : 0.0;
+        ff += fre ? fr[s].x * fr[s].x + fr[s].y * fr[s].y : 0.0;
+        if (own) {
+            if (j >= 1) {
+                if (r) store_node(r, nx, i, j, rv);
+                if (!use_x) store_node(x, nx, i, j, V2<double>{0.0, 0.0});
+            } else {
+                if (r) store_node(r, nx, i, j, V2<double>{0.0, 0.0});
+                store_node(x, nx, i, j, V2<double>{0.0, 0.0});
             }
         }
     }
-    const double srr = block_sum(rr);
-    const double sff = block_sum(ff);
+    block_sum2(rr, ff);
     if (threadIdx.x == 0) {
-        rr_out[t.tile] = srr;
-        if (ff_out) ff_out[t.tile] = sff;
+        rr_out[t.tile] = rr;
+        if (ff_out) ff_out[t.tile] = ff;
     }
 }
 
