@@ -49,7 +49,7 @@ def test_matches_oracle(solver, n):
 
 
 def test_batch_schedule_and_iteration_limits():
-    """The driver queues iterations in batches (the previous count at the
+    """The Poisson solve queues iterations in batches (the previous count at the
     same size, else one pair, then as many as the residual's reduction rate
     predicts; one graph replays a pair).  Whatever the schedule, the
     iterates are those of Algorithm 2: a repeat solve is bitwise equal to
